@@ -1,0 +1,11 @@
+"""FP64 CPU reference for regularized dipole sums (test infrastructure only).
+
+Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  The GPU library never calls it and shares no code
+with it.  See ``dps_oracle.c`` for what is computed and which passage of the
+paper each part follows.
+"""
+from .oracle import (  # noqa: F401
+    build, load, direct, direct_adjoint, Tree, rho, psi, rho_series,
+    psi_series, rho_closed, radial,
+)

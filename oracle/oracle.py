@@ -1,0 +1,214 @@
+"""ctypes wrapper of the FP64 reference (test infrastructure only).
+
+Inputs are the FP32 arrays both sides read; outputs are float64 NumPy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dps_oracle.c")
+_LIB = os.path.join(_HERE, "libdps_oracle.so")
+_lib = None
+
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_f64p = ct.POINTER(ct.c_double)
+
+
+def build(force: bool = True) -> str:
+    """Compile the reference with gcc (FP64, no floating-point contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ct.CDLL(_LIB)
+    vp = ct.c_void_p
+    lib.orc_rho.restype = ct.c_double
+    lib.orc_rho.argtypes = [ct.c_double]
+    lib.orc_psi.restype = ct.c_double
+    lib.orc_psi.argtypes = [ct.c_double]
+    for nm in ("orc_rho_series", "orc_psi_series", "orc_rho_closed"):
+        getattr(lib, nm).restype = ct.c_double
+        getattr(lib, nm).argtypes = [ct.c_double]
+    lib.orc_radial.restype = None
+    lib.orc_radial.argtypes = [ct.c_double, ct.c_double, _f64p, _f64p]
+    lib.orc_direct.restype = ct.c_int
+    lib.orc_direct.argtypes = [vp, vp, vp, vp, ct.c_int64, ct.c_int, vp, ct.c_int64, ct.c_double,
+                               vp, vp, vp, vp, ct.c_int]
+    lib.orc_direct_adjoint.restype = ct.c_int
+    lib.orc_direct_adjoint.argtypes = [vp, vp, vp, vp, ct.c_int64, ct.c_int, vp, ct.c_int64,
+                                       ct.c_double, vp, vp, vp, ct.c_int]
+    lib.orc_tree_build.restype = vp
+    lib.orc_tree_build.argtypes = [vp, vp, vp, ct.c_int64, ct.c_int]
+    lib.orc_tree_free.restype = None
+    lib.orc_tree_free.argtypes = [vp]
+    lib.orc_tree_set_attrs.restype = ct.c_int
+    lib.orc_tree_set_attrs.argtypes = [vp, vp, ct.c_int]
+    lib.orc_tree_num_nodes.restype = ct.c_int64
+    lib.orc_tree_num_nodes.argtypes = [vp]
+    lib.orc_tree_depth.restype = ct.c_int
+    lib.orc_tree_depth.argtypes = [vp]
+    lib.orc_tree_export.restype = ct.c_int
+    lib.orc_tree_export.argtypes = [vp] * 10
+    lib.orc_bh_query.restype = ct.c_int
+    lib.orc_bh_query.argtypes = [vp, vp, ct.c_int64, ct.c_float, ct.c_double, vp, vp, vp, vp, vp,
+                                 ct.c_int]
+    lib.orc_bh_adjoint.restype = ct.c_int
+    lib.orc_bh_adjoint.argtypes = [vp, vp, ct.c_int64, ct.c_float, ct.c_double, vp, vp, vp, vp,
+                                   vp, ct.c_int]
+    _lib = lib
+    return lib
+
+
+def _c32(a, shape_last=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if shape_last is not None and (a.ndim != 2 or a.shape[1] != shape_last):
+        raise ValueError(f"expected [n,{shape_last}] array, got {a.shape}")
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def rho(t): return load().orc_rho(float(t))
+def psi(t): return load().orc_psi(float(t))
+def rho_series(t): return load().orc_rho_series(float(t))
+def psi_series(t): return load().orc_psi_series(float(t))
+def rho_closed(t): return load().orc_rho_closed(float(t))
+
+
+def radial(r, eps):
+    """(kappa, lambda) = (rho(r/eps)/(4 pi r^3), psi(r/eps)/(4 pi r^5))."""
+    k, l = ct.c_double(), ct.c_double()
+    load().orc_radial(float(r), float(eps), ct.byref(k), ct.byref(l))
+    return k.value, l.value
+
+
+def direct(p, n, A, mu, x, eps, want_grad=True, nthreads=0):
+    """FP64 direct sum.  Returns dict f[Q,C], g[Q,C,3], sf[Q,C], sg[Q,C]."""
+    lib = load()
+    p, n, x = _c32(p, 3), _c32(n, 3), _c32(x, 3)
+    A = _c32(A).reshape(-1)
+    mu = _c32(mu)
+    if mu.ndim == 1:
+        mu = mu[:, None]
+    M, C, Q = p.shape[0], mu.shape[1], x.shape[0]
+    f = np.zeros((Q, C)); sf = np.zeros((Q, C)); sg = np.zeros((Q, C))
+    g = np.zeros((Q, C, 3)) if want_grad else None
+    rc = lib.orc_direct(_ptr(p), _ptr(n), _ptr(A), _ptr(mu), M, C, _ptr(x), Q, float(eps),
+                        _ptr(f), _ptr(g), _ptr(sf), _ptr(sg), int(nthreads))
+    if rc:
+        raise ValueError("orc_direct rejected its arguments")
+    return {"f": f, "g": g, "sf": sf, "sg": sg}
+
+
+def direct_adjoint(p, n, A, mu, x, eps, df, nthreads=0):
+    """Exact transpose of ``direct``: returns (dmu[M,C], dx[Q,3])."""
+    lib = load()
+    p, n, x = _c32(p, 3), _c32(n, 3), _c32(x, 3)
+    A = _c32(A).reshape(-1)
+    mu = _c32(mu)
+    if mu.ndim == 1:
+        mu = mu[:, None]
+    M, C, Q = p.shape[0], mu.shape[1], x.shape[0]
+    df = _c32(df).reshape(Q, C)
+    dmu = np.zeros((M, C)); dx = np.zeros((Q, 3))
+    rc = lib.orc_direct_adjoint(_ptr(p), _ptr(n), _ptr(A), _ptr(mu), M, C, _ptr(x), Q, float(eps),
+                                _ptr(df), _ptr(dmu), _ptr(dx), int(nthreads))
+    if rc:
+        raise ValueError("orc_direct_adjoint rejected its arguments")
+    return dmu, dx
+
+
+class Tree:
+    """Canonical octree + FP64 node dipoles + Barnes-Hut queries."""
+
+    def __init__(self, p, n, A, mu=None, leaf_size=16):
+        lib = load()
+        self._p = _c32(p, 3)
+        self._n = _c32(n, 3)
+        self._A = _c32(A).reshape(-1)
+        self.M = self._p.shape[0]
+        h = lib.orc_tree_build(_ptr(self._p), _ptr(self._n), _ptr(self._A), self.M, int(leaf_size))
+        if not h:
+            raise ValueError("orc_tree_build rejected its arguments")
+        self._h = ct.c_void_p(h)
+        self.N = int(lib.orc_tree_num_nodes(self._h))
+        self.depth = int(lib.orc_tree_depth(self._h))
+        self.C = 0
+        if mu is not None:
+            self.set_attrs(mu)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_tree_free(h)
+            self._h = None
+
+    def set_attrs(self, mu):
+        mu = _c32(mu)
+        if mu.ndim == 1:
+            mu = mu[:, None]
+        if mu.shape[0] != self.M:
+            raise ValueError("attribute rows must match the point count")
+        self.C = mu.shape[1]
+        if load().orc_tree_set_attrs(self._h, _ptr(mu), self.C):
+            raise ValueError("orc_tree_set_attrs rejected its arguments")
+
+    def export(self):
+        M, N, C = self.M, self.N, self.C
+        out = {
+            "codes_in": np.zeros(M, np.uint64), "codes": np.zeros(M, np.uint64),
+            "perm": np.zeros(M, np.uint32), "nodes": np.zeros((N, 6), np.int32),
+            "geom": np.zeros((N, 4), np.float32), "area": np.zeros(N),
+            "D": np.zeros((N, C, 3)) if C else None, "bounds": np.zeros(5),
+            "leaf_of": np.zeros(M, np.int32),
+        }
+        load().orc_tree_export(self._h, *[_ptr(out[k]) for k in
+                                          ("codes_in", "codes", "perm", "nodes", "geom", "area",
+                                           "D", "bounds", "leaf_of")])
+        return out
+
+    def query(self, x, beta, eps, want_grad=True, nthreads=0):
+        """Barnes-Hut forward.  Returns dict f, g, sf, sg, counts[Q,4]
+        (visited nodes, far-field nodes, leaves opened, near points)."""
+        x = _c32(x, 3)
+        Q, C = x.shape[0], self.C
+        f = np.zeros((Q, C)); sf = np.zeros((Q, C)); sg = np.zeros((Q, C))
+        g = np.zeros((Q, C, 3)) if want_grad else None
+        counts = np.zeros((Q, 4), np.int32)
+        rc = load().orc_bh_query(self._h, _ptr(x), Q, float(beta), float(eps), _ptr(f), _ptr(g),
+                                 _ptr(sf), _ptr(sg), _ptr(counts), int(nthreads))
+        if rc:
+            raise ValueError("orc_bh_query rejected its arguments")
+        return {"f": f, "g": g, "sf": sf, "sg": sg, "counts": counts}
+
+    def adjoint(self, x, beta, eps, df, nthreads=0):
+        """Barnes-Hut adjoint.  Returns dict dmu[M,C] (caller order), dx[Q,3],
+        sdmu[M,C], sdx[Q] (absolute scales for error normalisation)."""
+        x = _c32(x, 3)
+        Q, C, M = x.shape[0], self.C, self.M
+        df = _c32(df).reshape(Q, C)
+        dmu = np.zeros((M, C)); dx = np.zeros((Q, 3))
+        sdmu = np.zeros((M, C)); sdx = np.zeros(Q)
+        rc = load().orc_bh_adjoint(self._h, _ptr(x), Q, float(beta), float(eps), _ptr(df),
+                                   _ptr(dmu), _ptr(dx), _ptr(sdmu), _ptr(sdx), int(nthreads))
+        if rc:
+            raise ValueError("orc_bh_adjoint rejected its arguments")
+        return {"dmu": dmu, "dx": dx, "sdmu": sdmu, "sdx": sdx}

@@ -1,0 +1,20 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an AMD GPU (gfx950) and the built libdps.so")
+
+
+@pytest.fixture(scope="session")
+def orc():
+    """The FP64 reference, compiled once per session."""
+    import oracle
+    oracle.build(force=False)
+    return oracle

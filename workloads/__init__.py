@@ -1,0 +1,12 @@
+"""Seeded synthetic inputs for the regularized dipole-sum hot path.
+
+This package only draws input arrays (oriented point clouds, query points on
+camera rays, cotangents).  It contains none of the dipole-sum arithmetic, so
+both the FP64 reference in ``oracle/`` and the GPU library consume exactly the
+same FP32 bits without sharing any of the method's code.
+"""
+from .scenes import (  # noqa: F401
+    sphere_cloud, sphere_queries, sphere_probes, sfm_cloud, camera_rays,
+    ray_samples, tile_order, cotangents, sfm_camera, sfm_1m, fibonacci_sphere, CONFIGS,
+    SFM_1M_SURFACE, SFM_1M_OUTLIERS, SFM_8M_SURFACE, SFM_8M_OUTLIERS,
+)
