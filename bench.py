@@ -1,0 +1,243 @@
+#!/usr/bin/env python3
+"""Throughput of Barnes-Hut dipole-sum queries, forward + adjoint, on one GPU.
+
+Workload (sfm-1m): a 1,000,000-point SfM-like cloud (three noisy spheres / tori,
+5% outliers, jittered normals, C = 4 attribute channels), queried at the
+33,554,432 stratified samples of 512x512 camera rays x 128 samples, beta = 2,
+eps = 0.01414, leaf size 16.  All inputs are seeded synthetic arrays resident
+in HBM before timing starts.
+
+One step = one training iteration of the hot path: moment refit from the
+attributes (dps_set_attributes), primal query with gradients (dps_query), and
+the two-stage adjoint (dps_adjoint_zero / _accumulate / _finalize) with
+dL/df ~ N(0,1).  The tree itself is built once (points are fixed) and its
+build time is reported separately.  value = Q / (time per step).
+
+    python bench.py [--steps K] [--warmup W] [--storage fp32|bf16|both]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "dipole-sum queries/sec fwd+adjoint at 1M pts, beta=2, FP32 vs BF16-stored"
+BETA = 2.0
+EPS = math.sqrt(2.0) * 0.01
+LEAF = 16
+RES = 512
+SAMPLES = 128
+
+# Algorithmic FP32 operations per unit of work (FMA = 2, add / mul /
+# transcendental = 1), counted from the formulas the kernels evaluate:
+#   far test:          d = c - x (3), squares (3), sums (2), beta^2 r^2 (1), compare (1)
+#   far source, fwd:   d (3), rsqrt + r^-3 + kappa + lambda (6), per channel:
+#                      D.d (5), f += kappa s (2), lambda s (1), g += ... (3 x 4)
+#   near point, fwd:   d (3), r^2 (5), radial (6), An.d (5), kappa s, lambda s (2),
+#                      G = lambda s d - kappa An (9), per channel: f (2), g (6)
+#   far source, adj:   d (3), radial (6), E = sum w D (6C), E.d (5), dx (13),
+#                      per channel: w kappa d (4) + wavefront sum (3)
+#   near point, adj:   d (3), r^2 (5), radial (6), An.d (5), w.mu (2C), dx (16),
+#                      per channel: w kappa s (2) + wavefront sum (1)
+def flops_fwd(C):
+    return {"test": 10, "far": 9 + 20 * C, "near": 30 + 8 * C}
+
+
+def flops_adj(C):
+    return {"test": 10, "far": 27 + 13 * C, "near": 35 + 5 * C}
+
+
+MI355X_FP32_VECTOR_TFLOPS = 157.3   # published peak (packed FP32)
+MI355X_HBM_TBS = 8.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--storage", choices=["fp32", "bf16", "both"], default="both")
+    ap.add_argument("--res", type=int, default=RES, help="image side (rays = res^2)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only run a 1 GiB device fill + copy (calibrates HBM byte counters)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_inputs(res):
+    import numpy as np
+    import workloads
+    t0 = time.time()
+    p, n, A, attrs = workloads.sfm_cloud(workloads.SFM_1M_SURFACE, workloads.SFM_1M_OUTLIERS, 10)
+    eye = workloads.sfm_camera(11)
+    x = workloads.ray_samples(eye, res, res, SAMPLES, 12, order="tile")
+    df = workloads.cotangents(x.shape[0], attrs.shape[1], 17)
+    log(f"[bench] inputs generated in {time.time() - t0:.1f}s: M={p.shape[0]} Q={x.shape[0]}")
+    return p, n, A, attrs, x, df, np
+
+
+def time_storage(P, dev_in, storage, steps, warmup):
+    import torch
+    p, n, A, attrs, x, df = dev_in
+    Q, C = x.shape[0], attrs.shape[1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree = P.dps_build(p, n, A, attrs, leaf_size=LEAF, storage=storage)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    f = torch.empty((Q, C), device="cuda")
+    g = torch.empty((Q, C, 3), device="cuda")
+    dx = torch.empty((Q, 3), device="cuda")
+    dattrs = torch.empty((tree.M, C), device="cuda")
+    names = ["refit", "query", "adjoint_accumulate", "adjoint_finalize"]
+    ev = {k: [] for k in names}
+
+    def step(record):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        if record: e[0].record()
+        P.dps_set_attributes(tree, attrs)
+        if record: e[1].record()
+        P.dps_query(tree, x, BETA, EPS, f_out=f, g_out=g)
+        if record: e[2].record()
+        P.dps_adjoint_zero(tree)
+        P.dps_adjoint_accumulate(tree, x, BETA, EPS, df, dx_out=dx)
+        if record: e[3].record()
+        P.dps_adjoint_finalize(tree, dattrs_out=dattrs)
+        if record: e[4].record()
+        if record:
+            for i, k in enumerate(names):
+                ev[k].append((e[i], e[i + 1]))
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        step(True)
+    end.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    per = {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in ev.items()}
+    counts = P.dps_query_counts(tree, x, BETA)
+    csum = counts.to(torch.int64).sum(0).tolist()
+    info = P.dps_tree_info(tree)
+    P.dps_destroy(tree)
+    return {"ms_per_step": total_ms / steps, "build_ms": build_ms, "kernel_ms": per,
+            "counts_total": csum, "tree": info}
+
+
+def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
+    import oracle
+    oracle.build(force=False)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    T = oracle.Tree(p, n, A, attrs, LEAF)
+    rng = np.random.default_rng(18)
+
+    def run(k):
+        idx = np.sort(rng.choice(x.shape[0], size=k, replace=False))
+        xs, dfs = x[idx], df[idx]
+        t0 = time.perf_counter()
+        T.query(xs, BETA, EPS, nthreads=cores)
+        T.adjoint(xs, BETA, EPS, dfs, nthreads=cores)
+        return time.perf_counter() - t0
+
+    probe = 4096
+    dt = run(probe)
+    k = int(min(x.shape[0], max(probe, probe * seconds / max(dt, 1e-3))))
+    dt = run(k)
+    return {"value": k / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"{k} queries drawn (seed 18) from the {x.shape[0]}-query set; FP64 Barnes-Hut "
+                      f"forward (values+gradients) + adjoint on the full {p.shape[0]}-point tree, "
+                      f"{dt:.1f} s wall on {cores} threads; tree build excluded"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU design "
+              "(replicated tree, query sharding, one all-reduce of dL/dattrs) is not built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if args.copy_reference:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b = a.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": a.numel() * 4, "ok": bool(b[-1].item() == 1.0)}))
+        return
+    import paper_2405_16788_amd as P
+    P.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    p, n, A, attrs, x, df, np = make_inputs(args.res)
+    dev_in = [torch.from_numpy(a).cuda() for a in (p, n, A, attrs, x, df)]
+    Q, C = x.shape[0], attrs.shape[1]
+    storages = ["fp32", "bf16"] if args.storage == "both" else [args.storage]
+    res = {}
+    for st in storages:
+        log(f"[bench] timing storage={st}")
+        res[st] = time_storage(P, dev_in, st, args.steps, args.warmup)
+        log(f"[bench] {st}: {res[st]['ms_per_step']:.2f} ms/step, kernels {res[st]['kernel_ms']}")
+    main_st = "fp32" if "fp32" in res else storages[0]
+    r = res[main_st]
+    visits, nfar, leaves, near = r["counts_total"]
+    ffw, fad = flops_fwd(C), flops_adj(C)
+    fl_q = ffw["test"] * visits + ffw["far"] * nfar + ffw["near"] * near
+    fl_a = fad["test"] * visits + fad["far"] * nfar + fad["near"] * near
+    kq, ka = r["kernel_ms"]["query"], r["kernel_ms"]["adjoint_accumulate"]
+    dom, fl, ms = ("adjoint_accumulate", fl_a, ka) if ka >= kq else ("query", fl_q, kq)
+    achieved = fl / (ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": Q / (r["ms_per_step"] * 1e-3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"sfm-1m: {p.shape[0]} points, {args.res}x{args.res} rays x {SAMPLES} samples "
+                               f"= {Q} queries, C={C}, beta={BETA}, eps={EPS:.5f}, leaf {LEAF}",
+                   "storage": main_st, "step": "refit + query(values, gradients) + adjoint(zero, "
+                                               "accumulate, finalize)"},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": MI355X_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "flops_per_launch": fl, "avg_launch_ms": ms},
+        "per_query": {"nodes_visited": visits / Q, "far_nodes": nfar / Q, "leaves_opened": leaves / Q,
+                      "near_points": near / Q},
+    }
+    for st, rr in res.items():
+        out[f"{st}_stored"] = {"value": Q / (rr["ms_per_step"] * 1e-3), "ms_per_step": rr["ms_per_step"],
+                               "kernel_ms": rr["kernel_ms"], "build_ms": rr["build_ms"],
+                               "tree_nodes": rr["tree"]["n_nodes"], "tree_bytes": rr["tree"]["bytes"]}
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(np, p, n, A, attrs, x, df, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

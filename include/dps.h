@@ -1,0 +1,183 @@
+/*
+ * dps.h -- Barnes-Hut regularized dipole sums on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libdps.so.  The method is that of Chen, Miller, Gkioulekas,
+ * "3D Reconstruction with Fast Dipole Sums" (ACM TOG 43(6), 2024):
+ *
+ *   D_c(x) = sum_m A_m P_eps(x, p_m) mu_{m,c},                 (Sec. 4.2, eq. dipole_sum)
+ *   P_eps(x, y) = rho(|y-x|/eps) n(y).(y-x) / (4 pi |y-x|^3),  (Sec. 4.1, eq. regularized_poisson)
+ *   rho(t) = erf(t) - (2t/sqrt(pi)) exp(-t^2),
+ *
+ * one sum per attribute channel c (Sec. 5.1, eq. appearance_features), all
+ * channels sharing one traversal (Sec. 6.3).  Sums are evaluated with the
+ * Barnes-Hut scheme of Sec. 6.1 / Algorithm 1 over an octree whose nodes carry
+ * the area, area-weighted centroid, radius (eq. farfield_dipole) and the
+ * vector moments (eq. farfield_dipole_features); adjoints follow Sec. 6.2 and
+ * App. C (node accumulation, then one push-down to the points).
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers on the tree's device, except where
+ *    marked "host".  Arrays are dense, row-major, float32 unless stated.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Work
+ *    is enqueued on it; inputs must stay valid until the stream reaches it.
+ *  - The caller owns every input and output buffer.  Outputs are overwritten,
+ *    never accumulated, except the tree's internal adjoint accumulators, which
+ *    add up across dps_adjoint_accumulate calls until dps_adjoint_finalize.
+ *  - Errors are status codes; nothing throws across the ABI.  On
+ *    DPS_ERR_INVALID nothing is launched and no output is touched.  A
+ *    human-readable message for the last failure of the calling thread is
+ *    returned by dps_last_error().
+ *  - Point order: "caller order" is the order of the arrays given to
+ *    dps_build.  Internally points are kept in Morton order.
+ */
+#ifndef DPS_H
+#define DPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dps_tree_s *dps_tree;
+
+typedef enum {
+    DPS_OK = 0,
+    DPS_ERR_INVALID = 1, /* bad argument or non-finite / non-positive input data */
+    DPS_ERR_OOM = 2,     /* device allocation failed */
+    DPS_ERR_DEVICE = 3,  /* HIP runtime error (launch, copy, synchronisation) */
+    DPS_ERR_STATE = 4    /* handle unknown, destroyed, or in a failed state */
+} dps_status;
+
+typedef enum {
+    DPS_STORE_FP32 = 0,  /* attributes and node moments stored as float32 */
+    DPS_STORE_BF16 = 1   /* attributes and node moments stored as bfloat16 (RNE),
+                            accumulated in float32 (float64 for the top levels
+                            of trees with >= 4,194,304 points) */
+} dps_storage;
+
+/* Maximum number of attribute channels per tree. */
+#define DPS_MAX_CHANNELS 32
+/* Maximum leaf size (points per bucket leaf). */
+#define DPS_MAX_LEAF 256
+/* Octree depth: 21 levels below the root (63-bit Morton codes). */
+#define DPS_LEVELS 21
+
+/*
+ * dps_build -- octree over an oriented point cloud with its far-field data.
+ * Sec. 6.1 (octree, eq. farfield_dipole, eq. farfield_dipole_features) and
+ * Sec. 6.3 (built once, since points and areas are fixed during optimisation).
+ *
+ *  p      [M][3] point positions p_m          n [M][3] normals n_m (used as given)
+ *  A      [M]    area weights A_m (> 0)       attrs [M][C] per-point attributes mu_{m,c}
+ *  M      number of points, 1 <= M <= 2^31-1
+ *  C      channels, 1 <= C <= DPS_MAX_CHANNELS
+ *  leaf_size  bucket size, 1 <= leaf_size <= DPS_MAX_LEAF; a node is a leaf iff
+ *         it holds <= leaf_size points or sits at level DPS_LEVELS
+ *  storage    DPS_STORE_FP32 or DPS_STORE_BF16
+ *  out    host pointer receiving the handle (set to NULL on failure)
+ *
+ * Layout (canonical, reproduced bit-exactly by dps_export_tree): the bounding
+ * cube is the componentwise FP32 min of the points with side = max extent
+ * (FP64; 1 if zero), quantised as q = min(floor((p - lo) * 2^21/side), 2^21-1)
+ * in FP64, Morton code with x at bit 3i+2, y at 3i+1, z at 3i; points stably
+ * sorted by code; nodes numbered breadth-first with children contiguous in
+ * ascending octant order; node centroid and squared radius are FP64 sums
+ * rounded once to FP32.
+ *
+ * Synchronises `stream` (node counts are needed on the host).  Returns
+ * DPS_ERR_INVALID for bad sizes / NULL pointers, or if any p, n, A, attrs
+ * value is non-finite or any A_m <= 0 (checked on the device).
+ */
+dps_status dps_build(const float *p, const float *n, const float *A, const float *attrs,
+                     int64_t M, int32_t C, int32_t leaf_size, dps_storage storage,
+                     void *stream, dps_tree *out);
+
+/*
+ * dps_set_attributes -- moment refit after the attributes changed (Sec. 6.3:
+ * node moments are refreshed each iteration; eq. farfield_dipole_features).
+ *  attrs [M][C] in caller order.  Asynchronous; values are not checked.
+ */
+dps_status dps_set_attributes(dps_tree t, const float *attrs, void *stream);
+
+/*
+ * dps_query -- Barnes-Hut primal query (Algorithm 1, PrimalQuery; Sec. 6.1,
+ * eq. farfield) at Q points, all channels in one traversal.
+ *  x     [Q][3] query points
+ *  beta  > 0, finite: a node is used as far field iff |x - p_t| > beta r_t,
+ *        evaluated in FP32 as ((x-cx)^2+(y-cy)^2)+(z-cz)^2 > (beta*beta)*r_t^2
+ *  eps   >= 0, finite: regularisation; 0 gives the unregularised dipole sum
+ *  f     [Q][C] output values D_c(x)
+ *  grad  [Q][C][3] output spatial gradients dD_c/dx, or NULL
+ * Q = 0 is a no-op.  Asynchronous.
+ */
+dps_status dps_query(dps_tree t, const float *x, int64_t Q, float beta, float eps,
+                     float *f, float *grad, void *stream);
+
+/*
+ * dps_query_counts -- traversal statistics of dps_query (same decisions):
+ *  counts [Q][4] int32: nodes visited (far tests evaluated), nodes used as
+ *  far field, leaves opened, points summed exactly.  Asynchronous.
+ */
+dps_status dps_query_counts(dps_tree t, const float *x, int64_t Q, float beta,
+                            int32_t *counts, void *stream);
+
+/*
+ * Adjoint (Sec. 6.2, App. C).  Stage 1 (dps_adjoint_accumulate, Algorithm 1
+ * AdjointQuery) adds, for every query, df . (dD/dmu_t) into the node
+ * accumulators of the far-field nodes it uses (eq. farfield_gradient) and the
+ * exact near-field terms into per-point accumulators, and writes dL/dx.
+ * Stage 2 (dps_adjoint_finalize) pushes node accumulators down to the points
+ * through all their ancestors (eq. farfield_features_gradient).
+ *
+ * dps_adjoint_zero       clears the accumulators.
+ * dps_adjoint_accumulate x [Q][3], df [Q][C] = dL/dD_c(x); dx [Q][3] output
+ *                        dL/dx (overwritten), or NULL.  Same beta/eps rules
+ *                        as dps_query.  Accumulates across calls.
+ * dps_adjoint_finalize   dattrs [M][C] output dL/dmu in caller point order.
+ * dps_adjoint            zero + accumulate + finalize.
+ * All asynchronous.  Calls that mutate the tree (set_attributes, adjoint_*)
+ * must be ordered by the caller against other calls on the same tree.
+ */
+dps_status dps_adjoint_zero(dps_tree t, void *stream);
+dps_status dps_adjoint_accumulate(dps_tree t, const float *x, int64_t Q, float beta, float eps,
+                                  const float *df, float *dx, void *stream);
+dps_status dps_adjoint_finalize(dps_tree t, float *dattrs, void *stream);
+dps_status dps_adjoint(dps_tree t, const float *x, int64_t Q, float beta, float eps,
+                       const float *df, float *dattrs, float *dx, void *stream);
+
+/*
+ * dps_export_tree -- canonical arrays for parity checks (any may be NULL):
+ *  codes   [M] uint64 sorted Morton codes
+ *  perm    [M] uint32 sorted position -> caller index
+ *  nodes   [N][6] int32 {level, parent (-1 root), first_child (-1 leaf),
+ *          n_children, pt_begin, pt_count} in breadth-first order
+ *  geom    [N][4] float {cx, cy, cz, r^2}
+ *  moments [N][C][3] float node dipoles D_t = sum_{m in t} A_m mu_m n_m
+ *          (decoded to float32 from the storage format)
+ * Synchronises `stream`.
+ */
+dps_status dps_export_tree(dps_tree t, uint64_t *codes, uint32_t *perm, int32_t *nodes,
+                           float *geom, float *moments, void *stream);
+
+/* dps_tree_info -- host outputs (any may be NULL): node count, depth (deepest
+ * level), device bytes held by the tree, point count, channel count. */
+dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *bytes,
+                         int64_t *n_points, int32_t *channels);
+
+/* dps_check -- synchronises `stream` and reports device-side failures recorded
+ * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A
+ * traversal that would walk more than N nodes stops and sets this flag. */
+dps_status dps_check(dps_tree t, void *stream);
+
+/* dps_destroy -- frees the tree (synchronises the device first).  NULL is a no-op. */
+void dps_destroy(dps_tree t);
+
+/* Static strings. */
+const char *dps_status_string(dps_status s);
+const char *dps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPS_H */

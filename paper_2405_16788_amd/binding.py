@@ -1,0 +1,257 @@
+"""Thin ctypes binding of libdps.so (argument marshalling only).
+
+Every function mirrors an entry point of ``include/dps.h`` under the same
+name.  Tensors are torch CUDA float32 (int32 / int64 where stated), contiguous,
+on the tree's device; work is enqueued on torch's current stream.  Nothing here
+computes: every step runs in the HIP kernels of the library, and a missing
+library raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdps.so")
+
+DPS_OK, DPS_ERR_INVALID, DPS_ERR_OOM, DPS_ERR_DEVICE, DPS_ERR_STATE = range(5)
+DPS_STORE_FP32, DPS_STORE_BF16 = 0, 1
+STORAGE = {"fp32": DPS_STORE_FP32, "bf16": DPS_STORE_BF16}
+
+EXPORTED = (
+    "dps_build", "dps_set_attributes", "dps_query", "dps_query_counts", "dps_adjoint_zero",
+    "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
+    "dps_tree_info", "dps_check", "dps_destroy", "dps_status_string", "dps_last_error",
+)
+
+_lib = None
+
+
+class DpsError(RuntimeError):
+    def __init__(self, status: int, fn: str, message: str):
+        super().__init__(f"{fn} failed ({status}): {message}")
+        self.status = status
+
+
+def load():
+    """Loads libdps.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2405_16788_amd.build`")
+    try:  # share the HIP runtime torch already loaded, if any
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ct.CDLL(LIB_PATH)
+    vp, i64, i32, f32 = ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_float
+    sig = {
+        "dps_build": [vp, vp, vp, vp, i64, i32, i32, ct.c_int, vp, ct.POINTER(vp)],
+        "dps_set_attributes": [vp, vp, vp],
+        "dps_query": [vp, vp, i64, f32, f32, vp, vp, vp],
+        "dps_query_counts": [vp, vp, i64, f32, vp, vp],
+        "dps_adjoint_zero": [vp, vp],
+        "dps_check": [vp, vp],
+        "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
+        "dps_adjoint_finalize": [vp, vp, vp],
+        "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
+        "dps_export_tree": [vp, vp, vp, vp, vp, vp, vp],
+        "dps_tree_info": [vp, ct.POINTER(i64), ct.POINTER(i32), ct.POINTER(i64), ct.POINTER(i64),
+                          ct.POINTER(i32)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ct.c_int
+    lib.dps_destroy.argtypes = [vp]
+    lib.dps_destroy.restype = None
+    lib.dps_status_string.argtypes = [ct.c_int]
+    lib.dps_status_string.restype = ct.c_char_p
+    lib.dps_last_error.argtypes = []
+    lib.dps_last_error.restype = ct.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status: int, fn: str):
+    if status != DPS_OK:
+        raise DpsError(status, fn, load().dps_last_error().decode(errors="replace"))
+
+
+def _stream(device=None):
+    import torch
+    return ct.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t, dtype=None, shape=None, device=None, name="tensor"):
+    """Validated device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the tree on {device}")
+    return ct.c_void_p(t.data_ptr())
+
+
+class Tree:
+    """Owning handle of a dps_tree (destroyed with the object)."""
+
+    def __init__(self, handle, device, M, C, storage):
+        self._h = handle
+        self.device = device
+        self.M = M
+        self.C = C
+        self.storage = storage
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("tree has been destroyed")
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.dps_destroy(self._h)
+            self._h = None
+
+
+def dps_build(p, n, A, attrs, leaf_size: int = 16, storage: str = "fp32") -> Tree:
+    import torch
+    lib = load()
+    M = p.shape[0]
+    C = attrs.shape[1] if attrs.dim() == 2 else 1
+    dev = p.device
+    f = torch.float32
+    args = (_ptr(p, f, (M, 3), name="p"), _ptr(n, f, (M, 3), dev, "n"), _ptr(A, f, (M,), dev, "A"),
+            _ptr(attrs, f, (M, C) if attrs.dim() == 2 else (M,), dev, "attrs"))
+    h = ct.c_void_p()
+    with torch.cuda.device(dev):
+        _check(lib.dps_build(*args, M, C, int(leaf_size), STORAGE[storage], _stream(dev), ct.byref(h)),
+               "dps_build")
+    return Tree(h, dev, M, C, storage)
+
+
+def dps_set_attributes(tree: Tree, attrs):
+    import torch
+    p = _ptr(attrs, torch.float32, (tree.M, tree.C) if attrs.dim() == 2 else (tree.M,), tree.device, "attrs")
+    _check(load().dps_set_attributes(tree.handle, p, _stream(tree.device)), "dps_set_attributes")
+
+
+def dps_query(tree: Tree, x, beta: float, eps: float, grad: bool = True, f_out=None, g_out=None):
+    """Returns (f[Q,C], grad[Q,C,3] or None)."""
+    import torch
+    Q = x.shape[0]
+    xp = _ptr(x, torch.float32, (Q, 3), tree.device, "x")
+    f = f_out if f_out is not None else torch.empty((Q, tree.C), device=tree.device, dtype=torch.float32)
+    g = g_out if g_out is not None else (
+        torch.empty((Q, tree.C, 3), device=tree.device, dtype=torch.float32) if grad else None)
+    _check(load().dps_query(tree.handle, xp, Q, float(beta), float(eps),
+                            _ptr(f, torch.float32, (Q, tree.C), tree.device, "f"),
+                            _ptr(g, torch.float32, (Q, tree.C, 3), tree.device, "grad"),
+                            _stream(tree.device)), "dps_query")
+    return f, g
+
+
+def dps_query_counts(tree: Tree, x, beta: float):
+    """Returns int32 [Q,4]: visited nodes, far-field nodes, leaves opened, near points."""
+    import torch
+    Q = x.shape[0]
+    counts = torch.empty((Q, 4), device=tree.device, dtype=torch.int32)
+    _check(load().dps_query_counts(tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q,
+                                   float(beta), _ptr(counts, torch.int32), _stream(tree.device)),
+           "dps_query_counts")
+    return counts
+
+
+def dps_adjoint_zero(tree: Tree):
+    _check(load().dps_adjoint_zero(tree.handle, _stream(tree.device)), "dps_adjoint_zero")
+
+
+def dps_adjoint_accumulate(tree: Tree, x, beta: float, eps: float, df, want_dx: bool = True, dx_out=None):
+    """Stage 1; returns dx[Q,3] (or None)."""
+    import torch
+    Q = x.shape[0]
+    dx = dx_out if dx_out is not None else (
+        torch.empty((Q, 3), device=tree.device, dtype=torch.float32) if want_dx else None)
+    _check(load().dps_adjoint_accumulate(
+        tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q, float(beta), float(eps),
+        _ptr(df, torch.float32, (Q, tree.C), tree.device, "df"),
+        _ptr(dx, torch.float32, (Q, 3), tree.device, "dx"), _stream(tree.device)), "dps_adjoint_accumulate")
+    return dx
+
+
+def dps_adjoint_finalize(tree: Tree, dattrs_out=None):
+    """Stage 2; returns dL/dattrs [M,C] in caller point order."""
+    import torch
+    d = dattrs_out if dattrs_out is not None else torch.empty((tree.M, tree.C), device=tree.device,
+                                                              dtype=torch.float32)
+    _check(load().dps_adjoint_finalize(tree.handle, _ptr(d, torch.float32, (tree.M, tree.C), tree.device,
+                                                         "dattrs"), _stream(tree.device)),
+           "dps_adjoint_finalize")
+    return d
+
+
+def dps_adjoint(tree: Tree, x, beta: float, eps: float, df, want_dx: bool = True):
+    """zero + accumulate + finalize; returns (dattrs[M,C], dx[Q,3] or None)."""
+    import torch
+    Q = x.shape[0]
+    d = torch.empty((tree.M, tree.C), device=tree.device, dtype=torch.float32)
+    dx = torch.empty((Q, 3), device=tree.device, dtype=torch.float32) if want_dx else None
+    _check(load().dps_adjoint(tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q,
+                              float(beta), float(eps), _ptr(df, torch.float32, (Q, tree.C), tree.device, "df"),
+                              _ptr(d, torch.float32), _ptr(dx, torch.float32), _stream(tree.device)),
+           "dps_adjoint")
+    return d, dx
+
+
+def dps_tree_info(tree: Tree) -> dict:
+    n, depth, b, m, c = ct.c_int64(), ct.c_int32(), ct.c_int64(), ct.c_int64(), ct.c_int32()
+    _check(load().dps_tree_info(tree.handle, ct.byref(n), ct.byref(depth), ct.byref(b), ct.byref(m),
+                                ct.byref(c)), "dps_tree_info")
+    return {"n_nodes": n.value, "depth": depth.value, "bytes": b.value, "n_points": m.value,
+            "channels": c.value}
+
+
+def dps_export_tree(tree: Tree) -> dict:
+    """Canonical arrays as CUDA tensors: codes (int64 view of uint64), perm
+    (int32 view of uint32), nodes[N,6], geom[N,4], moments[N,C,3]."""
+    import torch
+    info = dps_tree_info(tree)
+    N, M, C = info["n_nodes"], tree.M, tree.C
+    dev = tree.device
+    codes = torch.empty(M, device=dev, dtype=torch.int64)
+    perm = torch.empty(M, device=dev, dtype=torch.int32)
+    nodes = torch.empty((N, 6), device=dev, dtype=torch.int32)
+    geom = torch.empty((N, 4), device=dev, dtype=torch.float32)
+    mom = torch.empty((N, C, 3), device=dev, dtype=torch.float32)
+    _check(load().dps_export_tree(tree.handle, _ptr(codes), _ptr(perm), _ptr(nodes), _ptr(geom), _ptr(mom),
+                                  _stream(dev)), "dps_export_tree")
+    return {"codes": codes, "perm": perm, "nodes": nodes, "geom": geom, "moments": mom}
+
+
+def dps_check(tree: Tree):
+    """Synchronises and raises if a device-side failure was recorded."""
+    _check(load().dps_check(tree.handle, _stream(tree.device)), "dps_check")
+
+
+def dps_destroy(tree: Tree):
+    if tree._h is not None:
+        load().dps_destroy(tree._h)
+        tree._h = None
+
+
+def dps_status_string(status: int) -> str:
+    return load().dps_status_string(int(status)).decode()
+
+
+def dps_last_error() -> str:
+    return load().dps_last_error().decode(errors="replace")

@@ -1,0 +1,293 @@
+// dps_api.hip -- the C ABI of libdps (declared in include/dps.h): argument
+// validation before any device work, handle bookkeeping, error reporting.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <mutex>
+#include <new>
+#include <unordered_set>
+
+#include "dps_tree.h"
+
+namespace dps {
+
+namespace {
+thread_local char g_last_error[512] = "";
+std::mutex g_mu;
+std::unordered_set<dps_tree_s *> g_live;
+
+bool live(dps_tree_s *t) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return t && g_live.count(t) && t->magic == kMagic;
+}
+}  // namespace
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+}
+
+dps_status hip_status(hipError_t e, const char *what) {
+    if (e == hipSuccess) return DPS_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? DPS_ERR_OOM : DPS_ERR_DEVICE;
+}
+
+static void free_tree(dps_tree_s *t) {
+    for (void *p : t->allocs) (void)hipFree(p);
+    t->allocs.clear();
+    t->magic = 0;
+    delete t;
+}
+
+static dps_status invalid(const char *msg) {
+    set_error("%s", msg);
+    return DPS_ERR_INVALID;
+}
+
+// Makes the tree's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace dps
+
+using namespace dps;
+
+extern "C" {
+
+const char *dps_status_string(dps_status s) {
+    switch (s) {
+        case DPS_OK: return "ok";
+        case DPS_ERR_INVALID: return "invalid argument";
+        case DPS_ERR_OOM: return "out of device memory";
+        case DPS_ERR_DEVICE: return "device error";
+        case DPS_ERR_STATE: return "invalid tree handle";
+    }
+    return "unknown status";
+}
+
+const char *dps_last_error(void) { return g_last_error; }
+
+dps_status dps_build(const float *p, const float *n, const float *A, const float *attrs, int64_t M,
+                     int32_t C, int32_t leaf_size, dps_storage storage, void *stream, dps_tree *out) {
+    if (!out) return invalid("dps_build: out is NULL");
+    *out = nullptr;
+    if (M < 1 || M > 0x7fffffffLL) return invalid("dps_build: M must be in [1, 2^31-1]");
+    if (C < 1 || C > DPS_MAX_CHANNELS) return invalid("dps_build: C must be in [1, 32]");
+    if (leaf_size < 1 || leaf_size > DPS_MAX_LEAF) return invalid("dps_build: leaf_size must be in [1, 256]");
+    if (storage != DPS_STORE_FP32 && storage != DPS_STORE_BF16) return invalid("dps_build: unknown storage mode");
+    if (!p || !n || !A || !attrs) return invalid("dps_build: NULL input array");
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0;
+    dps_status st = hip_status(hipGetDevice(&dev), "hipGetDevice");
+    if (st != DPS_OK) return st;
+
+    bool ok = false;
+    st = check_inputs(p, n, A, attrs, M, C, s, &ok);
+    if (st != DPS_OK) return st;
+    if (!ok) return invalid("dps_build: non-finite point, normal, area or attribute, or an area <= 0");
+
+    dps_tree_s *t = new (std::nothrow) dps_tree_s();
+    if (!t) { set_error("dps_build: host allocation failed"); return DPS_ERR_OOM; }
+    t->magic = kMagic;
+    t->device = dev;
+    t->M = M;
+    t->C = C;
+    t->leaf_size = leaf_size;
+    t->storage = storage;
+    t->wide_top = M >= kWideTopPoints;
+    const bool bf = storage == DPS_STORE_BF16;
+    t->mom_stride = bf ? ((3 * C + 1) & ~1) : 3 * C;
+    t->attr_stride = bf ? ((C + 1) & ~1) : C;
+
+    st = build_tree(t, p, n, A, s);
+    if (st == DPS_OK) {
+        const size_t esz = bf ? 2 : 4;
+        uint8_t *mom = nullptr, *attr = nullptr;
+        st = tree_alloc(t, &mom, (size_t)t->N * t->mom_stride * esz);
+        if (st == DPS_OK) st = tree_alloc(t, &attr, (size_t)M * t->attr_stride * esz);
+        t->mom = mom;
+        t->attr = attr;
+        if (st == DPS_OK) st = tree_alloc(t, &t->momw, (size_t)t->N * 3 * C);
+        if (st == DPS_OK && t->wide_top) st = tree_alloc(t, &t->momw64, (size_t)t->n_top * 3 * C);
+        if (st == DPS_OK) st = tree_alloc(t, &t->G, (size_t)t->N * 3 * C);
+        if (st == DPS_OK) st = tree_alloc(t, &t->S, (size_t)t->N * 3 * C);
+        if (st == DPS_OK) st = tree_alloc(t, &t->P, (size_t)M * C);
+        if (st == DPS_OK) st = tree_alloc(t, &t->err, 1);
+        if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->err, 0, sizeof(uint32_t), s), "zero err");
+        if (st == DPS_OK) st = refit_moments(t, attrs, s);
+        if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->G, 0, (size_t)t->N * 3 * C * sizeof(double), s), "zero G");
+        if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->P, 0, (size_t)M * C * sizeof(double), s), "zero P");
+        if (st == DPS_OK) st = hip_status(hipStreamSynchronize(s), "sync build");
+    }
+    if (st != DPS_OK) {
+        (void)hipStreamSynchronize(s);
+        free_tree(t);
+        return st;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.insert(t);
+    }
+    *out = t;
+    return DPS_OK;
+}
+
+static dps_status check_tree(dps_tree t, const char *fn) {
+    if (!live(t)) {
+        set_error("%s: unknown or destroyed tree handle", fn);
+        return DPS_ERR_STATE;
+    }
+    return DPS_OK;
+}
+
+static dps_status check_beta_eps(float beta, float eps, const char *fn) {
+    if (!(beta > 0.0f) || !isfinite(beta)) {
+        set_error("%s: beta must be finite and > 0", fn);
+        return DPS_ERR_INVALID;
+    }
+    if (!(eps >= 0.0f) || !isfinite(eps)) {
+        set_error("%s: eps must be finite and >= 0", fn);
+        return DPS_ERR_INVALID;
+    }
+    return DPS_OK;
+}
+
+dps_status dps_set_attributes(dps_tree t, const float *attrs, void *stream) {
+    dps_status st = check_tree(t, "dps_set_attributes");
+    if (st != DPS_OK) return st;
+    if (!attrs) return invalid("dps_set_attributes: attrs is NULL");
+    DeviceGuard dg(t->device);
+    return refit_moments(t, attrs, (hipStream_t)stream);
+}
+
+dps_status dps_query(dps_tree t, const float *x, int64_t Q, float beta, float eps, float *f,
+                     float *grad, void *stream) {
+    dps_status st = check_tree(t, "dps_query");
+    if (st != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_query")) != DPS_OK) return st;
+    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_query: Q out of range");
+    if (Q == 0) return DPS_OK;
+    if (!x || !f) return invalid("dps_query: NULL x or f");
+    DeviceGuard dg(t->device);
+    return launch_query(t, x, Q, beta, eps, f, grad, (hipStream_t)stream);
+}
+
+dps_status dps_query_counts(dps_tree t, const float *x, int64_t Q, float beta, int32_t *counts,
+                            void *stream) {
+    dps_status st = check_tree(t, "dps_query_counts");
+    if (st != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, 0.0f, "dps_query_counts")) != DPS_OK) return st;
+    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_query_counts: Q out of range");
+    if (Q == 0) return DPS_OK;
+    if (!x || !counts) return invalid("dps_query_counts: NULL x or counts");
+    DeviceGuard dg(t->device);
+    return launch_counts(t, x, Q, beta, counts, (hipStream_t)stream);
+}
+
+dps_status dps_adjoint_zero(dps_tree t, void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint_zero");
+    if (st != DPS_OK) return st;
+    DeviceGuard dg(t->device);
+    hipStream_t s = (hipStream_t)stream;
+    st = hip_status(hipMemsetAsync(t->G, 0, (size_t)t->N * 3 * t->C * sizeof(double), s), "zero G");
+    if (st != DPS_OK) return st;
+    return hip_status(hipMemsetAsync(t->P, 0, (size_t)t->M * t->C * sizeof(double), s), "zero P");
+}
+
+dps_status dps_adjoint_accumulate(dps_tree t, const float *x, int64_t Q, float beta, float eps,
+                                  const float *df, float *dx, void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint_accumulate");
+    if (st != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate")) != DPS_OK) return st;
+    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint_accumulate: Q out of range");
+    if (Q == 0) return DPS_OK;
+    if (!x || !df) return invalid("dps_adjoint_accumulate: NULL x or df");
+    DeviceGuard dg(t->device);
+    return launch_adjoint(t, x, Q, beta, eps, df, dx, (hipStream_t)stream);
+}
+
+dps_status dps_adjoint_finalize(dps_tree t, float *dattrs, void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint_finalize");
+    if (st != DPS_OK) return st;
+    if (!dattrs) return invalid("dps_adjoint_finalize: dattrs is NULL");
+    DeviceGuard dg(t->device);
+    return launch_finalize(t, dattrs, (hipStream_t)stream);
+}
+
+dps_status dps_adjoint(dps_tree t, const float *x, int64_t Q, float beta, float eps, const float *df,
+                       float *dattrs, float *dx, void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint");
+    if (st != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_adjoint")) != DPS_OK) return st;
+    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint: Q out of range");
+    if (!dattrs) return invalid("dps_adjoint: dattrs is NULL");
+    if (Q > 0 && (!x || !df)) return invalid("dps_adjoint: NULL x or df");
+    if ((st = dps_adjoint_zero(t, stream)) != DPS_OK) return st;
+    if (Q > 0 && (st = dps_adjoint_accumulate(t, x, Q, beta, eps, df, dx, stream)) != DPS_OK) return st;
+    return dps_adjoint_finalize(t, dattrs, stream);
+}
+
+dps_status dps_export_tree(dps_tree t, uint64_t *codes, uint32_t *perm, int32_t *nodes, float *geom,
+                           float *moments, void *stream) {
+    dps_status st = check_tree(t, "dps_export_tree");
+    if (st != DPS_OK) return st;
+    DeviceGuard dg(t->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (codes && (st = hip_status(hipMemcpyAsync(codes, t->codes, t->M * sizeof(uint64_t), hipMemcpyDeviceToDevice, s), "export codes")) != DPS_OK) return st;
+    if (perm && (st = hip_status(hipMemcpyAsync(perm, t->perm, t->M * sizeof(uint32_t), hipMemcpyDeviceToDevice, s), "export perm")) != DPS_OK) return st;
+    if ((st = launch_export(t, nodes, geom, moments, s)) != DPS_OK) return st;
+    return hip_status(hipStreamSynchronize(s), "sync export");
+}
+
+dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *bytes,
+                         int64_t *n_points, int32_t *channels) {
+    dps_status st = check_tree(t, "dps_tree_info");
+    if (st != DPS_OK) return st;
+    if (n_nodes) *n_nodes = t->N;
+    if (depth) *depth = t->depth;
+    if (bytes) *bytes = t->bytes;
+    if (n_points) *n_points = t->M;
+    if (channels) *channels = t->C;
+    return DPS_OK;
+}
+
+dps_status dps_check(dps_tree t, void *stream) {
+    dps_status st = check_tree(t, "dps_check");
+    if (st != DPS_OK) return st;
+    DeviceGuard dg(t->device);
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t h = 0;
+    if ((st = hip_status(hipMemcpyAsync(&h, t->err, sizeof h, hipMemcpyDeviceToHost, s), "read error word")) != DPS_OK) return st;
+    if ((st = hip_status(hipStreamSynchronize(s), "dps_check sync")) != DPS_OK) return st;
+    if (h) {
+        set_error("dps_check: a traversal exceeded the node count (internal error, code %u)", h);
+        return DPS_ERR_DEVICE;
+    }
+    return DPS_OK;
+}
+
+void dps_destroy(dps_tree t) {
+    if (!t) return;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_live.count(t)) return;
+        g_live.erase(t);
+    }
+    DeviceGuard dg(t->device);
+    (void)hipDeviceSynchronize();
+    free_tree(t);
+}
+
+}  // extern "C"

@@ -1,0 +1,184 @@
+// dps_internal.h -- device data layout and helpers shared by the libdps kernels.
+//
+// Layout in HBM (all arrays owned by the tree, Morton order):
+//   NodeRec  [N]      32 B: centroid, squared radius, link fields (one 8-dword scalar load)
+//   PointRec [M]      32 B: position, A*n, A (one 8-dword scalar load)
+//   moments  [N][ms]  node dipoles D_t = sum A_m mu_m n_m, channel-major 3-vectors,
+//                     FP32 (ms = 3C) or BF16 (ms = 3C rounded up to even)
+//   attrs    [M][as]  point attributes, FP32 (as = C) or BF16 (as = C rounded up to even)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dps.h"
+
+namespace dps {
+
+constexpr uint32_t kEnd = 0xffffffffu;   // escape pointer past the last subtree
+constexpr uint32_t kLeafFlag = 0x100u;   // NodeRec::meta bit: node is a leaf
+constexpr int kLevels = DPS_LEVELS;      // 21 levels below the root
+constexpr int kTopLevels = 3;            // "top-level" nodes: depth <= 3
+constexpr int64_t kWideTopPoints = 4194304;  // FP64 top-level moment sums from this size on
+
+struct alignas(32) NodeRec {
+    float cx, cy, cz, r2;  // FP32 centroid and squared radius
+    uint32_t first;        // first child (internal) or first point (leaf)
+    uint32_t count;        // number of children (internal) or points (leaf)
+    uint32_t escape;       // next node in depth-first order after this subtree
+    uint32_t meta;         // level | kLeafFlag
+};
+
+struct alignas(32) PointRec {
+    float x, y, z;         // position as given
+    float anx, any, anz;   // A_m * n_m (FP32 product)
+    float a;               // A_m
+    float pad;
+};
+
+// 1/(4 pi), 2/sqrt(pi), 4/sqrt(pi)
+constexpr float kInv4Pi = 0.0795774715459476679f;
+constexpr float k2SqrtPi = 1.12837916709551257f;
+constexpr float k4SqrtPi = 2.25675833419102515f;
+
+// Radial-factor branch points, in t^2 = (r/eps)^2: Taylor series below 0.5^2,
+// erf/exp in between, rho = 1 and psi = 3 above 4.5^2 (rho(4.5) = 1 - 8e-9).
+constexpr float kSeriesT2 = 0.25f;
+constexpr float kFarT2 = 20.25f;
+
+// ---------------------------------------------------------------------------
+// bf16 storage (round to nearest even; inputs are finite)
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint16_t f32_to_bf16(float v) {
+    uint32_t u;
+    __builtin_memcpy(&u, &v, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// ---------------------------------------------------------------------------
+// decision-critical FP32 arithmetic: fixed order, no contraction
+// ---------------------------------------------------------------------------
+__host__ __device__ inline float dist2_rn(float ax, float ay, float az, float bx, float by, float bz) {
+#pragma clang fp contract(off)
+    float dx = ax - bx;
+    float dy = ay - by;
+    float dz = az - bz;
+    float sxy = dx * dx + dy * dy;
+    return sxy + dz * dz;
+}
+
+__host__ __device__ inline float mul_rn(float a, float b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+// ---------------------------------------------------------------------------
+// radial factors kappa = rho(t)/(4 pi r^3), lambda = psi(t)/(4 pi r^5), t = r/eps,
+// psi = 3 rho - t rho'.  Series (derived from those of erf and exp):
+//   rho(t)/t^3 = (4/sqrt pi) sum_{n>=1} (-1)^{n+1} t^{2n-2} / ((n-1)! (2n+1))
+//   psi(t)/t^5 = (8/sqrt pi) sum_{n>=2} (-1)^n     t^{2n-4} / ((n-2)! (2n+1))
+// ---------------------------------------------------------------------------
+struct KernelParams {
+    float eps;       // 0: unregularised
+    float ieps2;     // 1/eps^2
+    float k3;        // 1/(4 pi eps^3)
+    float k5;        // 1/(4 pi eps^5)
+};
+
+__host__ inline KernelParams make_kernel_params(float eps) {
+    KernelParams kp;
+    kp.eps = eps;
+    if (eps > 0.0f) {
+        double e = eps;
+        kp.ieps2 = (float)(1.0 / (e * e));
+        kp.k3 = (float)(0.0795774715459476679 / (e * e * e));
+        kp.k5 = (float)(0.0795774715459476679 / (e * e * e * e * e));
+    } else {
+        kp.ieps2 = 0.0f;
+        kp.k3 = 0.0f;
+        kp.k5 = 0.0f;
+    }
+    return kp;
+}
+
+__device__ __forceinline__ float series_rho_t3(float u) {  // u = t^2
+    constexpr float c = 2.25675833419102515f;
+    return c * (1.0f / 3.0f + u * (-1.0f / 5.0f + u * (1.0f / 14.0f + u * (-1.0f / 54.0f +
+           u * (1.0f / 264.0f + u * (-1.0f / 1560.0f + u * (1.0f / 10800.0f + u * (-1.0f / 85680.0f))))))));
+}
+
+__device__ __forceinline__ float series_psi_t5(float u) {  // u = t^2
+    constexpr float c = 4.51351666838205030f;
+    return c * (1.0f / 5.0f + u * (-1.0f / 7.0f + u * (1.0f / 18.0f + u * (-1.0f / 66.0f +
+           u * (1.0f / 312.0f + u * (-1.0f / 1800.0f + u * (1.0f / 12240.0f + u * (-1.0f / 95760.0f))))))));
+}
+
+// r2 = |d|^2.  Returns false when the term is excluded (r = 0 with eps = 0).
+// With eps > 0 and r = 0 the finite series limits are used.
+__device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &kappa, float &lambda) {
+    if (kp.eps > 0.0f) {
+        float u = r2 * kp.ieps2;
+        if (u < kSeriesT2) {
+            kappa = kp.k3 * series_rho_t3(u);
+            lambda = kp.k5 * series_psi_t5(u);
+            return true;
+        }
+        if (u < kFarT2) {
+            float ir = rsqrtf(r2);
+            float ir2 = ir * ir;
+            float t = sqrtf(u);
+            float e = expf(-u);
+            float rho = erff(t) - k2SqrtPi * t * e;
+            float psi = 3.0f * rho - k4SqrtPi * t * u * e;
+            float k = kInv4Pi * ir * ir2;
+            kappa = k * rho;
+            lambda = k * ir2 * psi;
+            return true;
+        }
+    } else if (!(r2 > 0.0f)) {
+        return false;
+    }
+    float ir = rsqrtf(r2);
+    float ir2 = ir * ir;
+    kappa = kInv4Pi * ir * ir2;
+    lambda = 3.0f * kappa * ir2;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// wavefront (64-lane) reductions with DPP; every lane must be active
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Sum over the 64 lanes; the result is returned uniformly (from lane 63).
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp_f<0xb1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_f<0x4e>(v);          // quad_perm [2,3,0,1]
+    v += dpp_f<0x141>(v);         // row_half_mirror
+    v += dpp_f<0x140>(v);         // row_mirror: every lane holds its row sum
+    v += dpp_f<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Max over the 64 lanes of non-negative values.
+__device__ __forceinline__ float wave_max_nonneg(float v) {
+    v = fmaxf(v, dpp_f<0xb1>(v));
+    v = fmaxf(v, dpp_f<0x4e>(v));
+    v = fmaxf(v, dpp_f<0x141>(v));
+    v = fmaxf(v, dpp_f<0x140>(v));
+    v = fmaxf(v, dpp_f<0x142, 0xa>(v));
+    v = fmaxf(v, dpp_f<0x143, 0xc>(v));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+}  // namespace dps

@@ -1,0 +1,541 @@
+// dps_traverse.hip -- Barnes-Hut primal and adjoint dipole-sum queries.
+//
+// Algorithm 1 of the paper (PrimalQuery / AdjointQuery) visits, for one query
+// x, every node whose ancestors were all opened; a node is used as far field
+// iff |x - p_t| > beta r_t (tested before the leaf test), a leaf that is not
+// far contributes the exact terms of its points, and an internal node that is
+// not far recurses into its children.
+//
+// GPU mapping: a wavefront owns 64 queries and walks the union of their
+// traversals once, in depth-first order, without a stack:
+//   - `t` (the current node) is wave-uniform, so node records, moments and leaf
+//     points are fetched with scalar loads and broadcast to all lanes;
+//   - each lane keeps one bit per level: bit l set means the lane opened every
+//     ancestor of the current level-l node, i.e. Algorithm 1 would visit it;
+//   - after a node, the wave descends to its first child if any lane opened it
+//     (setting bit l+1 to "opened"), otherwise follows the node's escape
+//     pointer (next sibling, or the parent's escape).
+// Every lane therefore makes exactly the decisions of the recursive algorithm,
+// in the same depth-first order; lanes not visiting a node are masked off.
+//
+// The adjoint reduces each far-field increment (eq. farfield_gradient) and each
+// near-field point increment over the wavefront with DPP before one lane-
+// parallel FP64 atomic per value; dL/dx is private to the lane.
+#include <algorithm>
+
+#include "dps_tree.h"
+
+namespace dps {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <int CB, bool BF16>
+__device__ __forceinline__ void load_moments(const void *__restrict__ mom, int ms, uint32_t t, int c0,
+                                             float (&D)[3 * CB]) {
+    if constexpr (!BF16) {
+        const float *b = (const float *)mom + (size_t)t * ms + 3 * c0;
+#pragma unroll
+        for (int i = 0; i < 3 * CB; ++i) D[i] = b[i];
+    } else {
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)t * ms + 3 * c0);
+        constexpr int W = (3 * CB + 1) / 2;
+        uint32_t w[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) w[i] = b[i];
+#pragma unroll
+        for (int i = 0; i < 3 * CB; ++i) D[i] = (i & 1) ? bf16_hi(w[i >> 1]) : bf16_lo(w[i >> 1]);
+    }
+}
+
+template <int CB, bool BF16>
+__device__ __forceinline__ void load_attrs(const void *__restrict__ attr, int as, uint32_t j, int c0,
+                                           float (&mu)[CB]) {
+    if constexpr (!BF16) {
+        const float *b = (const float *)attr + (size_t)j * as + c0;
+#pragma unroll
+        for (int i = 0; i < CB; ++i) mu[i] = b[i];
+    } else {
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)attr + (size_t)j * as + c0);
+        constexpr int W = (CB + 1) / 2;
+        uint32_t w[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) w[i] = b[i];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) mu[i] = (i & 1) ? bf16_hi(w[i >> 1]) : bf16_lo(w[i >> 1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// primal query: f[q][c0..c0+CB) and optionally grad[q][c0..c0+CB)[3]
+// ---------------------------------------------------------------------------
+template <int CB, bool BF16, bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_query(
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
+    const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
+    float b2, KernelParams kp, int c0, float *__restrict__ fout, float *__restrict__ gout,
+    uint32_t limit, uint32_t *__restrict__ err) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = q < Q;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    if (valid) {
+        px = x[3 * q];
+        py = x[3 * q + 1];
+        pz = x[3 * q + 2];
+    }
+    float f[CB], g[CB][3];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        f[c] = 0.0f;
+        g[c][0] = g[c][1] = g[c][2] = 0.0f;
+    }
+    uint32_t bits = valid ? 1u : 0u;
+    uint32_t t = 0;
+    uint32_t steps = 0;
+    while (t != kEnd) {
+        if (++steps > limit) {  // a well-formed tree is walked in at most N steps
+            if (threadIdx.x % 64 == 0) atomicOr(err, 1u);
+            break;
+        }
+        const NodeRec nd = nodes[t];
+        const uint32_t lvl = nd.meta & 0xffu;
+        const bool in = (bits >> lvl) & 1u;
+        const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
+        const bool far = in && (s > mul_rn(b2, nd.r2));
+        if (__ballot(far)) {
+            float D[3 * CB];
+            load_moments<CB, BF16>(mom, ms, t, c0, D);
+            if (far) {
+                float kap, lam;
+                radial(s, kp, kap, lam);
+                const float dx = nd.cx - px, dy = nd.cy - py, dz = nd.cz - pz;
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
+                    f[c] += kap * sd;
+                    if (GRAD) {
+                        const float ls = lam * sd;
+                        g[c][0] += ls * dx - kap * D[3 * c];
+                        g[c][1] += ls * dy - kap * D[3 * c + 1];
+                        g[c][2] += ls * dz - kap * D[3 * c + 2];
+                    }
+                }
+            }
+        }
+        const bool open = in && !far;
+        if (__ballot(open)) {
+            if (!(nd.meta & kLeafFlag)) {
+                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
+                t = nd.first;
+                continue;
+            }
+            const uint32_t je = nd.first + nd.count;
+            for (uint32_t j = nd.first; j < je; ++j) {
+                const PointRec pr = pts[j];
+                float mu[CB];
+                load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                if (open) {
+                    const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    float kap, lam;
+                    if (radial(r2, kp, kap, lam)) {
+                        const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                        const float ks = kap * sa;
+                        const float ls = lam * sa;
+                        const float G0 = ls * dx - kap * pr.anx;
+                        const float G1 = ls * dy - kap * pr.any;
+                        const float G2 = ls * dz - kap * pr.anz;
+#pragma unroll
+                        for (int c = 0; c < CB; ++c) {
+                            f[c] += mu[c] * ks;
+                            if (GRAD) {
+                                g[c][0] += mu[c] * G0;
+                                g[c][1] += mu[c] * G1;
+                                g[c][2] += mu[c] * G2;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        t = nd.escape;
+    }
+    if (valid) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            fout[q * C + c0 + c] = f[c];
+            if (GRAD) {
+                gout[(q * C + c0 + c) * 3] = g[c][0];
+                gout[(q * C + c0 + c) * 3 + 1] = g[c][1];
+                gout[(q * C + c0 + c) * 3 + 2] = g[c][2];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// traversal statistics with the same decisions
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__ nodes,
+                                                     const float *__restrict__ x, int64_t Q, float b2,
+                                                     int32_t *__restrict__ counts, uint32_t limit,
+                                                     uint32_t *__restrict__ err) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = q < Q;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    if (valid) {
+        px = x[3 * q];
+        py = x[3 * q + 1];
+        pz = x[3 * q + 2];
+    }
+    int32_t visits = 0, nfar = 0, leaves = 0, near = 0;
+    uint32_t bits = valid ? 1u : 0u;
+    uint32_t t = 0;
+    uint32_t steps = 0;
+    while (t != kEnd) {
+        if (++steps > limit) {  // a well-formed tree is walked in at most N steps
+            if (threadIdx.x % 64 == 0) atomicOr(err, 1u);
+            break;
+        }
+        const NodeRec nd = nodes[t];
+        const uint32_t lvl = nd.meta & 0xffu;
+        const bool in = (bits >> lvl) & 1u;
+        const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
+        const bool far = in && (s > mul_rn(b2, nd.r2));
+        const bool open = in && !far;
+        visits += in;
+        nfar += far;
+        if (__ballot(open)) {
+            if (!(nd.meta & kLeafFlag)) {
+                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
+                t = nd.first;
+                continue;
+            }
+            leaves += open;
+            near += open ? (int32_t)nd.count : 0;
+        }
+        t = nd.escape;
+    }
+    if (valid) {
+        counts[4 * q] = visits;
+        counts[4 * q + 1] = nfar;
+        counts[4 * q + 2] = leaves;
+        counts[4 * q + 3] = near;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint stage 1: node accumulators G[N][C][3], point accumulators P[M][C], dx
+// ---------------------------------------------------------------------------
+template <int N_>
+__device__ __forceinline__ float pick_lane(const float (&v)[N_], int lane) {
+    float r = v[0];
+#pragma unroll
+    for (int i = 1; i < N_; ++i) r = lane == i ? v[i] : r;
+    return r;
+}
+
+template <int CB, bool BF16>
+__global__ __launch_bounds__(kThreads) void k_adjoint(
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
+    const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
+    float b2, KernelParams kp, int c0, const float *__restrict__ df, double *__restrict__ G,
+    double *__restrict__ P, float *__restrict__ dxout, int dx_mode, uint32_t limit,
+    uint32_t *__restrict__ err) {
+    const int lane = lane_id();
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = q < Q;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    float w[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) w[c] = 0.0f;
+    if (valid) {
+        px = x[3 * q];
+        py = x[3 * q + 1];
+        pz = x[3 * q + 2];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) w[c] = df[q * C + c0 + c];
+    }
+    float ax = 0.0f, ay = 0.0f, az = 0.0f;
+    uint32_t bits = valid ? 1u : 0u;
+    uint32_t t = 0;
+    uint32_t steps = 0;
+    while (t != kEnd) {
+        if (++steps > limit) {  // a well-formed tree is walked in at most N steps
+            if (threadIdx.x % 64 == 0) atomicOr(err, 1u);
+            break;
+        }
+        const NodeRec nd = nodes[t];
+        const uint32_t lvl = nd.meta & 0xffu;
+        const bool in = (bits >> lvl) & 1u;
+        const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
+        const bool far = in && (s > mul_rn(b2, nd.r2));
+        if (__ballot(far)) {
+            float D[3 * CB];
+            load_moments<CB, BF16>(mom, ms, t, c0, D);
+            float kap = 0.0f, dx = 0.0f, dy = 0.0f, dz = 0.0f;
+            if (far) {
+                float lam;
+                radial(s, kp, kap, lam);
+                dx = nd.cx - px;
+                dy = nd.cy - py;
+                dz = nd.cz - pz;
+                float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < CB; ++c) {
+                    E0 += w[c] * D[3 * c];
+                    E1 += w[c] * D[3 * c + 1];
+                    E2 += w[c] * D[3 * c + 2];
+                }
+                const float les = lam * (E0 * dx + E1 * dy + E2 * dz);
+                ax += les * dx - kap * E0;
+                ay += les * dy - kap * E1;
+                az += les * dz - kap * E2;
+            }
+            // node increment df_c * kappa * (p_t - x), summed over the wavefront
+            float red[3 * CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const float wk = w[c] * kap;
+                red[3 * c] = wave_sum(wk * dx);
+                red[3 * c + 1] = wave_sum(wk * dy);
+                red[3 * c + 2] = wave_sum(wk * dz);
+            }
+            const float v = pick_lane(red, lane);
+            if (lane < 3 * CB)
+                atomicAdd(&G[((size_t)t * C + c0) * 3 + lane], (double)v);
+        }
+        const bool open = in && !far;
+        if (__ballot(open)) {
+            if (!(nd.meta & kLeafFlag)) {
+                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
+                t = nd.first;
+                continue;
+            }
+            const uint32_t je = nd.first + nd.count;
+            for (uint32_t j = nd.first; j < je; ++j) {
+                const PointRec pr = pts[j];
+                float mu[CB];
+                load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                float ks = 0.0f;
+                if (open) {
+                    const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    float kap, lam;
+                    if (radial(r2, kp, kap, lam)) {
+                        const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                        ks = kap * sa;
+                        float wm = 0.0f;
+#pragma unroll
+                        for (int c = 0; c < CB; ++c) wm += w[c] * mu[c];
+                        const float les = lam * sa * wm;
+                        const float kw = kap * wm;
+                        ax += les * dx - kw * pr.anx;
+                        ay += les * dy - kw * pr.any;
+                        az += les * dz - kw * pr.anz;
+                    }
+                }
+                float red[CB];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) red[c] = wave_sum(w[c] * ks);
+                const float v = pick_lane(red, lane);
+                if (lane < CB) atomicAdd(&P[(size_t)j * C + c0 + lane], (double)v);
+            }
+        }
+        t = nd.escape;
+    }
+    if (valid && dx_mode != 0) {
+        if (dx_mode == 1) {
+            dxout[3 * q] = ax;
+            dxout[3 * q + 1] = ay;
+            dxout[3 * q + 2] = az;
+        } else {
+            dxout[3 * q] += ax;
+            dxout[3 * q + 1] += ay;
+            dxout[3 * q + 2] += az;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint stage 2 (eq. farfield_features_gradient): running sum of the node
+// accumulators from the root to each leaf, then each point adds
+// A_m n_m . (sum over its ancestors) to its own near-field accumulator.
+// ---------------------------------------------------------------------------
+__global__ void k_leaf_sums(int64_t N, int C, const NodeRec *__restrict__ nodes,
+                            const int32_t *__restrict__ parent, const double *__restrict__ G,
+                            double *__restrict__ S) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w3 = 3 * (int64_t)C;
+    if (i >= N * w3) return;
+    const int64_t t = i / w3;
+    const int64_t k = i - t * w3;
+    if (!(nodes[t].meta & kLeafFlag)) return;
+    double sum = 0.0;
+    for (int64_t a = t; a >= 0; a = parent[a]) sum += G[a * w3 + k];
+    S[t * w3 + k] = sum;
+}
+
+__global__ void k_points_out(int64_t M, int C, const int32_t *__restrict__ leaf_of,
+                             const uint32_t *__restrict__ perm, const PointRec *__restrict__ pts,
+                             const double *__restrict__ P, const double *__restrict__ S,
+                             float *__restrict__ dattrs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M * C) return;
+    const int64_t j = i / C;
+    const int c = (int)(i - j * C);
+    const int64_t l = leaf_of[j];
+    const double *Sl = S + (l * C + c) * 3;
+    const double v = P[j * C + c] + (double)pts[j].anx * Sl[0] + (double)pts[j].any * Sl[1] +
+                     (double)pts[j].anz * Sl[2];
+    dattrs[(int64_t)perm[j] * C + c] = (float)v;
+}
+
+// ---------------------------------------------------------------------------
+// canonical export
+// ---------------------------------------------------------------------------
+__global__ void k_export_nodes(int64_t N, const int32_t *__restrict__ lvl, const int32_t *__restrict__ parent,
+                               const int32_t *__restrict__ first_child, const int32_t *__restrict__ nchild,
+                               const int32_t *__restrict__ ptb, const int32_t *__restrict__ ptc,
+                               const NodeRec *__restrict__ nodes, int32_t *__restrict__ out_nodes,
+                               float *__restrict__ out_geom) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    if (out_nodes) {
+        int32_t *o = out_nodes + 6 * t;
+        o[0] = lvl[t];
+        o[1] = parent[t];
+        o[2] = first_child[t];
+        o[3] = nchild[t];
+        o[4] = ptb[t];
+        o[5] = ptc[t];
+    }
+    if (out_geom) {
+        out_geom[4 * t] = nodes[t].cx;
+        out_geom[4 * t + 1] = nodes[t].cy;
+        out_geom[4 * t + 2] = nodes[t].cz;
+        out_geom[4 * t + 3] = nodes[t].r2;
+    }
+}
+
+template <bool BF16>
+__global__ void k_export_moments(int64_t N, int C, int ms, const void *__restrict__ mom,
+                                 float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w3 = 3 * (int64_t)C;
+    if (i >= N * w3) return;
+    const int64_t t = i / w3;
+    const int64_t k = i - t * w3;
+    if (BF16) out[i] = __uint_as_float((uint32_t)((const uint16_t *)mom)[t * ms + k] << 16);
+    else out[i] = ((const float *)mom)[t * ms + k];
+}
+
+inline unsigned grid(int64_t n) { return (unsigned)std::max<int64_t>(1, cdiv(n, kThreads)); }
+
+// channel blocks: 8s, then a 4, then the remainder; block starts stay multiples of 4
+inline int next_block(int rem) { return rem >= 8 ? 8 : (rem >= 4 ? 4 : rem); }
+
+template <int CB>
+dps_status query_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+                       float *f, float *g, hipStream_t s) {
+    const unsigned gr = grid(Q);
+    const bool bf = t->storage == DPS_STORE_BF16;
+    if (bf && g)
+        k_query<CB, true, true><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N, t->err);
+    else if (bf)
+        k_query<CB, true, false><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N, t->err);
+    else if (g)
+        k_query<CB, false, true><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N, t->err);
+    else
+        k_query<CB, false, false><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N, t->err);
+    return hip_status(hipGetLastError(), "query launch");
+}
+
+template <int CB>
+dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+                         const float *df, float *dx, int dx_mode, hipStream_t s) {
+    const unsigned gr = grid(Q);
+    if (t->storage == DPS_STORE_BF16)
+        k_adjoint<CB, true><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, df, t->G, t->P, dx, dx_mode, (uint32_t)t->N, t->err);
+    else
+        k_adjoint<CB, false><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, df, t->G, t->P, dx, dx_mode, (uint32_t)t->N, t->err);
+    return hip_status(hipGetLastError(), "adjoint launch");
+}
+
+}  // namespace
+
+dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, float *f,
+                        float *g, hipStream_t s) {
+    const float b2 = mul_rn(beta, beta);
+    const KernelParams kp = make_kernel_params(eps);
+    for (int c0 = 0; c0 < t->C;) {
+        const int cb = next_block(t->C - c0);
+        dps_status st;
+        switch (cb) {
+            case 8: st = query_block<8>(t, x, Q, b2, kp, c0, f, g, s); break;
+            case 4: st = query_block<4>(t, x, Q, b2, kp, c0, f, g, s); break;
+            case 3: st = query_block<3>(t, x, Q, b2, kp, c0, f, g, s); break;
+            case 2: st = query_block<2>(t, x, Q, b2, kp, c0, f, g, s); break;
+            default: st = query_block<1>(t, x, Q, b2, kp, c0, f, g, s); break;
+        }
+        if (st != DPS_OK) return st;
+        c0 += cb;
+    }
+    return DPS_OK;
+}
+
+dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta, int32_t *counts,
+                         hipStream_t s) {
+    k_counts<<<grid(Q), kThreads, 0, s>>>(t->nodes, x, Q, mul_rn(beta, beta), counts, (uint32_t)t->N, t->err);
+    return hip_status(hipGetLastError(), "counts launch");
+}
+
+dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps,
+                          const float *df, float *dx, hipStream_t s) {
+    const float b2 = mul_rn(beta, beta);
+    const KernelParams kp = make_kernel_params(eps);
+    for (int c0 = 0; c0 < t->C;) {
+        const int cb = next_block(t->C - c0);
+        const int dx_mode = dx ? (c0 == 0 ? 1 : 2) : 0;
+        dps_status st;
+        switch (cb) {
+            case 8: st = adjoint_block<8>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
+            case 4: st = adjoint_block<4>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
+            case 3: st = adjoint_block<3>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
+            case 2: st = adjoint_block<2>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
+            default: st = adjoint_block<1>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
+        }
+        if (st != DPS_OK) return st;
+        c0 += cb;
+    }
+    return DPS_OK;
+}
+
+dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s) {
+    k_leaf_sums<<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->nodes, t->parent, t->G, t->S);
+    dps_status st = hip_status(hipGetLastError(), "leaf sums");
+    if (st != DPS_OK) return st;
+    k_points_out<<<grid(t->M * t->C), kThreads, 0, s>>>(t->M, t->C, t->leaf_of, t->perm, t->pts, t->P, t->S, dattrs);
+    return hip_status(hipGetLastError(), "point gradients");
+}
+
+dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *moments, hipStream_t s) {
+    if (nodes || geom) {
+        k_export_nodes<<<grid(t->N), kThreads, 0, s>>>(t->N, t->level, t->parent, t->first_child, t->nchild,
+                                                       t->ptb, t->ptc, t->nodes, nodes, geom);
+        dps_status st = hip_status(hipGetLastError(), "export nodes");
+        if (st != DPS_OK) return st;
+    }
+    if (moments) {
+        if (t->storage == DPS_STORE_BF16)
+            k_export_moments<true><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->mom_stride, t->mom, moments);
+        else
+            k_export_moments<false><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->mom_stride, t->mom, moments);
+        dps_status st = hip_status(hipGetLastError(), "export moments");
+        if (st != DPS_OK) return st;
+    }
+    return DPS_OK;
+}
+
+}  // namespace dps

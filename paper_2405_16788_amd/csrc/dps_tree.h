@@ -1,0 +1,87 @@
+// dps_tree.h -- host-side tree object and the internal entry points of libdps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "dps.h"
+#include "dps_internal.h"
+
+struct dps_tree_s {
+    uint64_t magic;
+    int device;
+    int64_t M, N;
+    int C, leaf_size, depth;
+    dps_storage storage;
+    int mom_stride;   // elements per node row of `mom`
+    int attr_stride;  // elements per point row of `attr`
+    int64_t level_start[dps::kLevels + 2];  // nodes of level l: [level_start[l], level_start[l+1])
+    int64_t n_top;    // nodes with level <= kTopLevels
+    bool wide_top;    // FP64 accumulation of top-level moments
+
+    uint64_t *codes;          // [M] sorted Morton codes
+    uint32_t *perm;           // [M] sorted position -> caller index
+    dps::PointRec *pts;       // [M]
+    dps::NodeRec *nodes;      // [N]
+    int32_t *level, *parent, *first_child, *nchild, *ptb, *ptc;  // [N] topology
+    int32_t *leaf_of;         // [M] leaf holding each sorted point
+    void *mom;                // [N][mom_stride] FP32 or BF16
+    void *attr;               // [M][attr_stride] FP32 or BF16
+    float *momw;              // [N][3C] FP32 working sums of the refit
+    double *momw64;           // [n_top][3C] FP64 working sums (wide_top only)
+    double *G;                // [N][C][3] node adjoint accumulators
+    double *P;                // [M][C] point adjoint accumulators
+    double *S;                // [N][C][3] push-down running sums
+    uint32_t *err;            // sticky device error word (traversal guard)
+
+    int64_t bytes;
+    std::vector<void *> allocs;
+};
+
+namespace dps {
+
+constexpr uint64_t kMagic = 0x6470732d74726565ull;
+
+void set_error(const char *fmt, ...);
+dps_status hip_status(hipError_t e, const char *what);
+
+// Allocates `count` elements on the current device and records the block in the tree.
+template <class T>
+dps_status tree_alloc(dps_tree_s *t, T **ptr, size_t count) {
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) return hip_status(e, "hipMalloc");
+    t->allocs.push_back(p);
+    t->bytes += (int64_t)(count * sizeof(T));
+    *ptr = (T *)p;
+    return DPS_OK;
+}
+
+dps_status build_tree(dps_tree_s *t, const float *p, const float *n, const float *A,
+                      hipStream_t s);
+dps_status refit_moments(dps_tree_s *t, const float *attrs, hipStream_t s);
+dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps,
+                        float *f, float *g, hipStream_t s);
+dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta,
+                         int32_t *counts, hipStream_t s);
+dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps,
+                          const float *df, float *dx, hipStream_t s);
+dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s);
+dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *moments,
+                         hipStream_t s);
+dps_status check_inputs(const float *p, const float *n, const float *A, const float *attrs,
+                        int64_t M, int C, hipStream_t s, bool *ok);
+
+// Device-wide scans of uint32 (in place allowed): out[i] = sum of in[0..i] (inclusive)
+// or in[0..i) (exclusive).  `tmp` must hold scan_tmp_words(n) words.
+size_t scan_tmp_words(int64_t n);
+dps_status device_scan(const uint32_t *in, uint32_t *out, int64_t n, bool inclusive,
+                       uint32_t *tmp, hipStream_t s);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace dps

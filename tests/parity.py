@@ -1,0 +1,42 @@
+"""Helpers for GPU-vs-oracle comparisons (test infrastructure)."""
+from __future__ import annotations
+
+import numpy as np
+
+# FP32-stored tolerance on errors normalised by the per-query absolute sums;
+# BF16-stored tolerance: each stored value carries <= 2^-9 relative error and
+# |dD.d| <= 2^-9 |D||d| (Cauchy-Schwarz), so the normalised error is < 2e-3.
+TOL_FP32 = 1e-5
+TOL_BF16 = 2e-3
+
+
+def norm_err(got, ref, scale):
+    """max |got - ref| / scale (scale broadcast over trailing axes)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.asarray(scale, dtype=np.float64)
+    while scale.ndim < ref.ndim:
+        scale = scale[..., None]
+    scale = np.maximum(scale, 1e-300)
+    if got.size == 0:
+        return 0.0
+    return float(np.max(np.abs(got - ref) / scale))
+
+
+def to_dev(*arrays):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]
+
+
+def to_host(t):
+    return t.detach().cpu().numpy()
+
+
+def node_abs_sums(perm, nodes, A, mu):
+    """Per node and channel: sum over its points of A_m |mu_m,c| (|n_m| = 1):
+    the absolute scale of the node dipole D_t,c."""
+    w = (A.astype(np.float64)[perm][:, None] * np.abs(mu.astype(np.float64)[perm]))
+    cs = np.concatenate([np.zeros((1, w.shape[1])), np.cumsum(w, axis=0)])
+    b = nodes[:, 4].astype(np.int64)
+    e = b + nodes[:, 5].astype(np.int64)
+    return cs[e] - cs[b]

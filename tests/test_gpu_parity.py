@@ -1,0 +1,188 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bit-exact: Morton codes, sort permutation, node topology, FP32 node geometry,
+traversal decisions (per-query visit counts).  Values, gradients and adjoints:
+within 1e-5 (FP32 storage) / 2e-3 (BF16 storage) of the oracle's Barnes-Hut
+result, normalised by the per-query (per-point) absolute sums.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from parity import TOL_BF16, TOL_FP32, node_abs_sums, norm_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dps():
+    import torch
+    import paper_2405_16788_amd as P
+    P.load()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return P
+
+
+def _random_cloud(M, seed, C=4):
+    rng = np.random.default_rng(seed)
+    p = rng.uniform(-1, 1, size=(M, 3))
+    n = rng.standard_normal((M, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    A = rng.uniform(0.5, 1.5, size=M) * (4.0 / max(M, 1))
+    mu = rng.standard_normal((M, C))
+    return p.astype(np.float32), n.astype(np.float32), A.astype(np.float32), mu.astype(np.float32)
+
+
+CLOUDS = {
+    "sphere-8k": lambda: workloads.sphere_cloud(8192, 1),
+    "random-1": lambda: _random_cloud(1, 5),
+    "random-17": lambda: _random_cloud(17, 6),
+    "random-3001": lambda: _random_cloud(3001, 7),
+    "random-3001-c5": lambda: _random_cloud(3001, 8, C=5),
+    "random-2000-c1": lambda: _random_cloud(2000, 9, C=1),
+}
+
+
+def _check_build(dps, orc, p, n, A, mu, leaf, storage="fp32"):
+    import torch  # noqa: F401
+    tree = dps.dps_build(*to_dev(p, n, A, mu), leaf_size=leaf, storage=storage)
+    ex = {k: to_host(v) for k, v in dps.dps_export_tree(tree).items()}
+    T = orc.Tree(p, n, A, mu, leaf)
+    oe = T.export()
+    assert np.array_equal(ex["codes"].view(np.uint64), oe["codes"]), "Morton codes differ"
+    assert np.array_equal(ex["perm"].view(np.uint32), oe["perm"]), "sort permutation differs"
+    assert ex["nodes"].shape == oe["nodes"].shape, (ex["nodes"].shape, oe["nodes"].shape)
+    assert np.array_equal(ex["nodes"], oe["nodes"]), "topology differs"
+    assert np.array_equal(ex["geom"].view(np.int32), oe["geom"].view(np.int32)), "node geometry differs"
+    scale = node_abs_sums(oe["perm"], oe["nodes"], A, mu)
+    if storage == "bf16":
+        # round-to-nearest-even to 8 significant bits: |err| <= 2^-8 |D| per
+        # element, on top of the FP32 accumulation error
+        err = np.abs(ex["moments"].astype(np.float64) - oe["D"])
+        assert np.all(err <= 2.0 ** -8 * np.abs(oe["D"]) + TOL_FP32 * scale[..., None])
+    else:
+        assert norm_err(ex["moments"], oe["D"], scale) <= TOL_FP32
+    return tree, T
+
+
+@pytest.mark.parametrize("name", sorted(CLOUDS))
+@pytest.mark.parametrize("leaf", [1, 16])
+def test_build_bit_exact(dps, orc, name, leaf):
+    p, n, A, mu = CLOUDS[name]()
+    _check_build(dps, orc, p, n, A, mu, leaf)
+
+
+@pytest.mark.parametrize("name", ["sphere-8k", "random-3001", "random-3001-c5", "random-2000-c1", "random-17",
+                                  "random-1"])
+@pytest.mark.parametrize("eps", [0.05, 0.0])
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_query_parity(dps, orc, name, eps, storage):
+    p, n, A, mu = CLOUDS[name]()
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16, storage)
+    x = workloads.sphere_queries(4099, 2)
+    if name == "sphere-8k":
+        on, ins, out = workloads.sphere_probes(256, 3)
+        x = np.concatenate([x, on, ins, out, p[:64]])  # includes queries exactly at points
+    (xd,) = to_dev(x)
+    f, g = dps.dps_query(tree, xd, 2.0, eps)
+    ref = T.query(x, 2.0, eps)
+    tol = TOL_BF16 if storage == "bf16" else TOL_FP32
+    ef = norm_err(to_host(f), ref["f"], ref["sf"])
+    eg = norm_err(to_host(g), ref["g"], ref["sg"])
+    assert ef <= tol and eg <= tol, (ef, eg)
+    counts = to_host(dps.dps_query_counts(tree, xd, 2.0))
+    assert np.array_equal(counts, ref["counts"]), "traversal decisions differ"
+
+
+@pytest.mark.parametrize("beta", [1.0, 1.5, 4.0])
+def test_query_parity_beta(dps, orc, beta):
+    p, n, A, mu = workloads.sphere_cloud(8192, 1)
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16)
+    x = workloads.sphere_queries(3000, 4)
+    (xd,) = to_dev(x)
+    f, g = dps.dps_query(tree, xd, beta, 0.05)
+    ref = T.query(x, beta, 0.05)
+    assert norm_err(to_host(f), ref["f"], ref["sf"]) <= TOL_FP32
+    assert norm_err(to_host(g), ref["g"], ref["sg"]) <= TOL_FP32
+    assert np.array_equal(to_host(dps.dps_query_counts(tree, xd, beta)), ref["counts"])
+
+
+@pytest.mark.parametrize("name", ["sphere-8k", "random-3001", "random-3001-c5", "random-2000-c1"])
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_adjoint_parity(dps, orc, name, storage):
+    p, n, A, mu = CLOUDS[name]()
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16, storage)
+    x = workloads.sphere_queries(3001, 12)
+    C = mu.shape[1]
+    df = workloads.cotangents(x.shape[0], C, 17)
+    xd, dfd = to_dev(x, df)
+    dattrs, dx = dps.dps_adjoint(tree, xd, 2.0, 0.05, dfd)
+    ref = T.adjoint(x, 2.0, 0.05, df)
+    tol = TOL_BF16 if storage == "bf16" else TOL_FP32
+    e1 = norm_err(to_host(dattrs), ref["dmu"], ref["sdmu"])
+    e2 = norm_err(to_host(dx), ref["dx"], ref["sdx"])
+    assert e1 <= TOL_FP32 and e2 <= tol, (e1, e2)
+
+
+def test_adjoint_accumulates_across_calls(dps, orc):
+    p, n, A, mu = workloads.sphere_cloud(8192, 1)
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16)
+    x = workloads.sphere_queries(4000, 12)
+    df = workloads.cotangents(4000, 4, 17)
+    xd, dfd = to_dev(x, df)
+    dps.dps_adjoint_zero(tree)
+    dps.dps_adjoint_accumulate(tree, xd[:1500].contiguous(), 2.0, 0.05, dfd[:1500].contiguous())
+    dps.dps_adjoint_accumulate(tree, xd[1500:].contiguous(), 2.0, 0.05, dfd[1500:].contiguous())
+    d = to_host(dps.dps_adjoint_finalize(tree))
+    ref = T.adjoint(x, 2.0, 0.05, df)
+    assert norm_err(d, ref["dmu"], ref["sdmu"]) <= TOL_FP32
+
+
+def test_set_attributes_refit(dps, orc):
+    p, n, A, mu = workloads.sphere_cloud(8192, 1)
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16)
+    mu2 = np.random.default_rng(3).standard_normal(mu.shape).astype(np.float32)
+    (mu2d,) = to_dev(mu2)
+    dps.dps_set_attributes(tree, mu2d)
+    T.set_attrs(mu2)
+    x = workloads.sphere_queries(2000, 2)
+    (xd,) = to_dev(x)
+    f, g = dps.dps_query(tree, xd, 2.0, 0.05)
+    ref = T.query(x, 2.0, 0.05)
+    assert norm_err(to_host(f), ref["f"], ref["sf"]) <= TOL_FP32
+    ex = dps.dps_export_tree(tree)
+    oe = T.export()
+    assert norm_err(to_host(ex["moments"]), oe["D"], node_abs_sums(oe["perm"], oe["nodes"], A, mu2)) <= TOL_FP32
+
+
+def test_empty_query_is_noop(dps):
+    import torch
+    p, n, A, mu = workloads.sphere_cloud(256, 1)
+    tree = dps.dps_build(*to_dev(p, n, A, mu))
+    x = torch.empty((0, 3), device="cuda")
+    f, g = dps.dps_query(tree, x, 2.0, 0.05)
+    assert f.shape == (0, 4)
+    d, dx = dps.dps_adjoint(tree, x, 2.0, 0.05, torch.empty((0, 4), device="cuda"))
+    assert float(d.abs().max()) == 0.0
+
+
+def test_invalid_data_rejected(dps):
+    import torch
+    p, n, A, mu = workloads.sphere_cloud(256, 1)
+    A = A.copy()
+    A[7] = 0.0
+    with pytest.raises(dps.DpsError) as e:
+        dps.dps_build(*to_dev(p, n, A, mu))
+    assert e.value.status == 1
+    p = p.copy()
+    p[3, 1] = np.nan
+    with pytest.raises(dps.DpsError):
+        dps.dps_build(*to_dev(p, n, workloads.sphere_cloud(256, 1)[2], mu))
+    tree = dps.dps_build(*to_dev(*workloads.sphere_cloud(256, 1)))
+    x = torch.zeros((4, 3), device="cuda")
+    for beta, eps in [(0.0, 0.1), (-1.0, 0.1), (float("nan"), 0.1), (2.0, -0.1), (2.0, float("inf"))]:
+        with pytest.raises(dps.DpsError) as e:
+            dps.dps_query(tree, x, beta, eps)
+        assert e.value.status == 1

@@ -1,0 +1,99 @@
+"""GPU parity at the benchmark's full size (sfm-1m: 1,000,000 points,
+512x512 rays x 128 samples = 33,554,432 queries), in the launch
+configuration the benchmark times: the whole query set in one call, outputs
+compared on a seeded sample that the oracle evaluates one by one, plus
+properties that hold at any size."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from parity import TOL_BF16, TOL_FP32, norm_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+EPS = math.sqrt(2.0) * 0.01
+BETA = 2.0
+
+
+@pytest.fixture(scope="module")
+def scene(orc):
+    import torch
+    import paper_2405_16788_amd as P
+    P.load()
+    assert torch.cuda.is_available()
+    p, n, A, mu = workloads.sfm_cloud(workloads.SFM_1M_SURFACE, workloads.SFM_1M_OUTLIERS, 10)
+    x = workloads.ray_samples(workloads.sfm_camera(11), 512, 512, 128, 12, order="tile")
+    T = orc.Tree(p, n, A, mu, 16)
+    dev = dict(zip("p n A mu x".split(), to_dev(p, n, A, mu, x)))
+    return P, T, (p, n, A, mu, x), dev
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_sfm_1m_full_query(scene, storage):
+    import torch
+    P, T, (p, n, A, mu, x), d = scene
+    print(f"[scale] build M={p.shape[0]} storage={storage}", flush=True)
+    tree = P.dps_build(d["p"], d["n"], d["A"], d["mu"], leaf_size=16, storage=storage)
+    ex = P.dps_export_tree(tree)
+    oe = T.export()
+    assert np.array_equal(to_host(ex["codes"]).view(np.uint64), oe["codes"])
+    assert np.array_equal(to_host(ex["perm"]).view(np.uint32), oe["perm"])
+    assert np.array_equal(to_host(ex["nodes"]), oe["nodes"])
+    assert np.array_equal(to_host(ex["geom"]).view(np.int32), oe["geom"].view(np.int32))
+    print(f"[scale] query Q={x.shape[0]}", flush=True)
+    f, g = P.dps_query(tree, d["x"], BETA, EPS)
+    counts = P.dps_query_counts(tree, d["x"], BETA)
+    P.dps_check(tree)
+    idx = np.sort(np.random.default_rng(18).choice(x.shape[0], 6000, replace=False))
+    ref = T.query(x[idx], BETA, EPS)
+    it = torch.from_numpy(idx).cuda()
+    tol = TOL_BF16 if storage == "bf16" else TOL_FP32
+    ef = norm_err(to_host(f[it]), ref["f"], ref["sf"])
+    eg = norm_err(to_host(g[it]), ref["g"], ref["sg"])
+    print(f"[scale] {storage}: max normalised error f {ef:.3g} grad {eg:.3g}", flush=True)
+    assert ef <= tol and eg <= tol
+    assert np.array_equal(to_host(counts[it]), ref["counts"])
+    assert torch.isfinite(f).all() and torch.isfinite(g).all()
+    P.dps_destroy(tree)
+
+
+def test_sfm_1m_adjoint(scene):
+    import torch
+    P, T, (p, n, A, mu, x), d = scene
+    tree = P.dps_build(d["p"], d["n"], d["A"], d["mu"], leaf_size=16)
+    Q = x.shape[0]
+    df = workloads.cotangents(Q, mu.shape[1], 17)
+    (dfd,) = to_dev(df)
+    # full-size adjoint, checked through a property that holds at any size:
+    # L = sum df . f is linear in the attributes, so sum df . f = sum dattrs . mu
+    f, _ = P.dps_query(tree, d["x"], BETA, EPS, grad=False)
+    dattrs, dx = P.dps_adjoint(tree, d["x"], BETA, EPS, dfd)
+    P.dps_check(tree)
+    lhs = torch.sum(dfd.double() * f.double(), dim=0)
+    rhs = torch.sum(dattrs.double() * d["mu"].double(), dim=0)
+    scale = torch.sum((dfd.double() * f.double()).abs(), dim=0)
+    rel = ((lhs - rhs).abs() / scale).max().item()
+    print(f"[scale] dot-product identity, relative to sum |df f|: {rel:.3g}", flush=True)
+    assert rel < 1e-4
+    # dL/dx of the full launch on sampled queries
+    idx = np.sort(np.random.default_rng(19).choice(Q, 3000, replace=False))
+    g = T.query(x[idx], BETA, EPS)["g"]
+    want = np.einsum("qc,qck->qk", df[idx].astype(np.float64), g)
+    sdx = np.sum(np.abs(df[idx]).astype(np.float64) * T.query(x[idx], BETA, EPS)["sg"], axis=1)
+    e = norm_err(to_host(dx[torch.from_numpy(idx).cuda()]), want, sdx)
+    print(f"[scale] dx sampled error {e:.3g}", flush=True)
+    assert e <= TOL_FP32
+    # dL/dattrs against the oracle adjoint on a tile-aligned sub-batch (the
+    # oracle cannot run all 33.5M queries in a test)
+    sub = slice(64 * 128 * 2000, 64 * 128 * 2000 + 64 * 128 * 6)
+    xs, dfs = x[sub], df[sub]
+    xsd, dfsd = to_dev(xs, dfs)
+    da, dxs = P.dps_adjoint(tree, xsd, BETA, EPS, dfsd)
+    ref = T.adjoint(xs, BETA, EPS, dfs)
+    e1 = norm_err(to_host(da), ref["dmu"], ref["sdmu"])
+    e2 = norm_err(to_host(dxs), ref["dx"], ref["sdx"])
+    print(f"[scale] sub-batch adjoint errors dattrs {e1:.3g} dx {e2:.3g}", flush=True)
+    assert e1 <= TOL_FP32 and e2 <= TOL_FP32
+    P.dps_destroy(tree)

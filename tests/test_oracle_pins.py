@@ -490,3 +490,44 @@ def test_far_test_worked_example(orc):
     d0 = -x[0].astype(np.float64)
     assert r["f"][0, 0] == pytest.approx(D @ d0 / (4 * math.pi * np.linalg.norm(d0) ** 3), rel=1e-12)
     assert r["f"][1, 0] == pytest.approx(orc.direct(p, n, A, mu, x[1:2], 0.0)["f"][0, 0], rel=1e-12)
+
+
+def test_bh_adjoint_through_render_loss_matches_fd(orc):
+    # the oracle adjoint, driven by dL/df of the render proxy, against central
+    # differences of the same loss: attributes perturbed through linearity,
+    # sample positions perturbed and re-queried
+    import torch
+    from render_proxy import fd_linear, fd_position, loss_numpy, loss_torch
+    p, n, A, mu = workloads.sfm_cloud(20000, 1000, 10)
+    R, S, eps, h = 16, 64, 0.03, 1e-4
+    pix, x = workloads.pixel_ray_samples(workloads.sfm_camera(11), 64, 64, S, 12, R, 14)
+    target = np.random.default_rng(13).uniform(size=(R, 3))
+    T = orc.Tree(p, n, A, mu, 16)
+    base = T.query(x, 2.0, eps)
+    f0 = base["f"]
+    ft = torch.tensor(f0, requires_grad=True)
+    loss_torch(ft, R, S, torch.tensor(target)).backward()
+    df = ft.grad.numpy()
+    adj = T.adjoint(x, 2.0, eps, df.astype(np.float32))
+    loss = lambda ff: loss_numpy(ff, R, S, target)
+    worst = 0.0
+    for m in np.random.default_rng(15).choice(p.shape[0], 24, replace=False):
+        e = np.zeros_like(mu)
+        e[m] = 1.0
+        T.set_attrs(e)
+        fe = T.query(x, 2.0, eps, want_grad=False)["f"]
+        for c in range(4):
+            fd = fd_linear(f0, fe[:, c], c, loss, h)
+            worst = max(worst, abs(adj["dmu"][m, c] - fd) / (adj["sdmu"][m, c] + 1e-300))
+    assert worst < 1e-5
+    T.set_attrs(mu)
+    worst, used = 0.0, 0
+    for q in np.random.default_rng(16).choice(x.shape[0], 24, replace=False):
+        for k in range(3):
+            fd = fd_position(T, x, f0, base["counts"], q, k, S, target, h, 2.0, eps)
+            if fd is None:
+                continue
+            scale = np.sum(np.abs(df[q]) * base["sg"][q])
+            worst = max(worst, abs(adj["dx"][q, k] - fd) / scale)
+            used += 1
+    assert used >= 36 and worst < 1e-4

@@ -308,3 +308,18 @@ def fibonacci_sphere(M: int, radius: float = 1.0):
     n = np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
     A = np.full(M, 4.0 * math.pi * radius * radius / M)
     return (radius * n).astype(np.float32), n.astype(np.float32), A.astype(np.float32)
+
+
+def pixel_ray_samples(eye, H: int, W: int, S: int, seed: int, n_rays: int, pix_seed: int,
+                      fov_deg: float = 50.0):
+    """Stratified samples on ``n_rays`` pixels drawn (seed ``pix_seed``) from
+    an H x W pinhole image.  Returns (pixels[n_rays], x[n_rays*S, 3]) with the
+    samples of each ray contiguous."""
+    o, d, t0, t1 = camera_rays(eye, H, W, fov_deg)
+    pix = np.sort(np.random.default_rng(pix_seed).choice(H * W, size=n_rays, replace=False))
+    u = np.random.default_rng(seed).uniform(size=(n_rays, S))
+    o, d = o.reshape(-1, 3)[pix], d.reshape(-1, 3)[pix]
+    t0, t1 = t0.reshape(-1)[pix], t1.reshape(-1)[pix]
+    t = t0[:, None] + (np.arange(S)[None, :] + u) * ((t1 - t0) / S)[:, None]
+    x = o[:, None, :] + t[..., None] * d[:, None, :]
+    return pix, x.reshape(-1, 3).astype(np.float32)
