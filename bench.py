@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--res", type=int, default=RES, help="image side (rays = res^2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--packet", type=str, default="auto",
+                    help="queries per lane 'query,adjoint' (e.g. 1,2) or 'auto' (autotuned)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a 1 GiB device fill + copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -87,7 +89,7 @@ def make_inputs(res):
     return p, n, A, attrs, x, df, np
 
 
-def time_storage(P, dev_in, storage, steps, warmup):
+def time_storage(P, dev_in, storage, steps, warmup, packet):
     import torch
     p, n, A, attrs, x, df = dev_in
     Q, C = x.shape[0], attrs.shape[1]
@@ -96,6 +98,13 @@ def time_storage(P, dev_in, storage, steps, warmup):
     tree = P.dps_build(p, n, A, attrs, leaf_size=LEAF, storage=storage)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
+    if packet == "auto":
+        from paper_2405_16788_amd import autotune
+        tuned = autotune.tune(tree, x, df, BETA, EPS, cache="", verbose=True)
+    else:
+        kq, ka = (int(v) for v in packet.split(","))
+        P.dps_set_packet(tree, kq, ka)
+        tuned = {"query": kq, "adjoint": ka}
     f = torch.empty((Q, C), device="cuda")
     g = torch.empty((Q, C, 3), device="cuda")
     dx = torch.empty((Q, 3), device="cuda")
@@ -136,7 +145,7 @@ def time_storage(P, dev_in, storage, steps, warmup):
     info = P.dps_tree_info(tree)
     P.dps_destroy(tree)
     return {"ms_per_step": total_ms / steps, "build_ms": build_ms, "kernel_ms": per,
-            "counts_total": csum, "tree": info}
+            "counts_total": csum, "tree": info, "packet": {"query": tuned["query"], "adjoint": tuned["adjoint"]}}
 
 
 def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
@@ -158,9 +167,13 @@ def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
         T.adjoint(xs, BETA, EPS, dfs, nthreads=cores)
         return time.perf_counter() - t0
 
-    probe = 4096
-    dt = run(probe)
-    k = int(min(x.shape[0], max(probe, probe * seconds / max(dt, 1e-3))))
+    # the oracle adjoint has a fixed cost (thread-private accumulators over all
+    # nodes and points), so calibrate time = a + b k on two sample sizes
+    k1, k2 = 8192, 32768
+    t1, t2 = run(k1), run(k2)
+    b = max((t2 - t1) / (k2 - k1), 1e-9)
+    a = max(t1 - b * k1, 0.0)
+    k = int(min(x.shape[0], max(k2, (seconds - a) / b)))
     dt = run(k)
     return {"value": k / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
             "sample": f"{k} queries drawn (seed 18) from the {x.shape[0]}-query set; FP64 Barnes-Hut "
@@ -195,7 +208,7 @@ def main():
     res = {}
     for st in storages:
         log(f"[bench] timing storage={st}")
-        res[st] = time_storage(P, dev_in, st, args.steps, args.warmup)
+        res[st] = time_storage(P, dev_in, st, args.steps, args.warmup, args.packet)
         log(f"[bench] {st}: {res[st]['ms_per_step']:.2f} ms/step, kernels {res[st]['kernel_ms']}")
     main_st = "fp32" if "fp32" in res else storages[0]
     r = res[main_st]
@@ -232,7 +245,8 @@ def main():
     for st, rr in res.items():
         out[f"{st}_stored"] = {"value": Q / (rr["ms_per_step"] * 1e-3), "ms_per_step": rr["ms_per_step"],
                                "kernel_ms": rr["kernel_ms"], "build_ms": rr["build_ms"],
-                               "tree_nodes": rr["tree"]["n_nodes"], "tree_bytes": rr["tree"]["bytes"]}
+                               "tree_nodes": rr["tree"]["n_nodes"], "tree_bytes": rr["tree"]["bytes"],
+                               "packet": rr["packet"]}
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(np, p, n, A, attrs, x, df, args.cpu_seconds)

@@ -165,6 +165,17 @@ dps_status dps_export_tree(dps_tree t, uint64_t *codes, uint32_t *perm, int32_t 
 dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *bytes,
                          int64_t *n_points, int32_t *channels);
 
+/*
+ * dps_set_packet -- launch shape of the traversal kernels: each 64-lane
+ * wavefront walks the tree once for 64*k consecutive queries, lane l carrying
+ * queries base + 64 i + l (i < k), so node fetches and, in the adjoint, the
+ * wavefront sums and atomics are shared by 64*k queries (the packet queries
+ * suggested in Sec. 6.3).  Results do not depend on k beyond FP rounding order.
+ *  query_k, adjoint_k  1, 2 or 4; 0 keeps the current value.  Large channel
+ *  blocks cap k so accumulators stay in registers.  Host-only, immediate.
+ */
+dps_status dps_set_packet(dps_tree t, int32_t query_k, int32_t adjoint_k);
+
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A
  * traversal that would walk more than N nodes stops and sets this flag. */

@@ -1,0 +1,83 @@
+"""Autotuner for the traversal launch shape (queries per lane, 1 / 2 / 4).
+
+Times dps_query and dps_adjoint_accumulate for each packet size on a slice of
+the caller's own queries (HIP events on the current stream), keeps the
+fastest, and applies it with dps_set_packet.  Results are cached in a JSON file
+keyed by the workload shape, so later runs skip the sweep.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+from . import binding as B
+
+PACKETS = (1, 2, 4)
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dps_autotune.json")
+
+
+def _key(tree, Q, beta, eps):
+    return f"M{tree.M}_C{tree.C}_{tree.storage}_Q{Q}_b{beta:g}_e{eps:g}"
+
+
+def _time(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=False):
+    """Picks and applies the fastest packet sizes; returns
+    {"query": k, "adjoint": k, "ms": {...}}."""
+    import torch
+    cache = cache if cache is not None else os.environ.get("DPS_AUTOTUNE_CACHE", DEFAULT_CACHE)
+    key = _key(tree, x.shape[0], beta, eps)
+    table = {}
+    if cache and os.path.exists(cache):
+        try:
+            table = json.load(open(cache))
+        except (OSError, ValueError):
+            table = {}
+    if key in table:
+        best = table[key]
+        B.dps_set_packet(tree, best["query"], best["adjoint"])
+        return best
+    n = min(x.shape[0], sample)
+    # a contiguous slice keeps the spatial coherence of the caller's layout
+    start = (x.shape[0] - n) // 2 // 256 * 256
+    xs = x[start:start + n].contiguous()
+    dfs = df[start:start + n].contiguous()
+    f = torch.empty((n, tree.C), device=x.device)
+    g = torch.empty((n, tree.C, 3), device=x.device)
+    dx = torch.empty((n, 3), device=x.device)
+    ms = {"query": {}, "adjoint": {}}
+    for k in PACKETS:
+        B.dps_set_packet(tree, k, k)
+        ms["query"][k] = _time(lambda: B.dps_query(tree, xs, beta, eps, f_out=f, g_out=g), reps)
+        B.dps_adjoint_zero(tree)
+        ms["adjoint"][k] = _time(lambda: B.dps_adjoint_accumulate(tree, xs, beta, eps, dfs, dx_out=dx), reps)
+        if verbose:
+            print(f"[autotune] k={k}: query {ms['query'][k]:.3f} ms, adjoint {ms['adjoint'][k]:.3f} ms",
+                  flush=True)
+    B.dps_adjoint_zero(tree)
+    best = {"query": min(ms["query"], key=ms["query"].get),
+            "adjoint": min(ms["adjoint"], key=ms["adjoint"].get),
+            "ms": {p: {str(k): v for k, v in d.items()} for p, d in ms.items()}}
+    B.dps_set_packet(tree, best["query"], best["adjoint"])
+    if cache:
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            table[key] = best
+            tmp = cache + ".tmp"
+            json.dump(table, open(tmp, "w"), indent=1)
+            os.replace(tmp, cache)
+        except OSError:
+            pass
+    return best

@@ -21,7 +21,7 @@ STORAGE = {"fp32": DPS_STORE_FP32, "bf16": DPS_STORE_BF16}
 EXPORTED = (
     "dps_build", "dps_set_attributes", "dps_query", "dps_query_counts", "dps_adjoint_zero",
     "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
-    "dps_tree_info", "dps_check", "dps_destroy", "dps_status_string", "dps_last_error",
+    "dps_tree_info", "dps_set_packet", "dps_check", "dps_destroy", "dps_status_string", "dps_last_error",
 )
 
 _lib = None
@@ -53,6 +53,7 @@ def load():
         "dps_query_counts": [vp, vp, i64, f32, vp, vp],
         "dps_adjoint_zero": [vp, vp],
         "dps_check": [vp, vp],
+        "dps_set_packet": [vp, i32, i32],
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
         "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
@@ -236,6 +237,11 @@ def dps_export_tree(tree: Tree) -> dict:
     _check(load().dps_export_tree(tree.handle, _ptr(codes), _ptr(perm), _ptr(nodes), _ptr(geom), _ptr(mom),
                                   _stream(dev)), "dps_export_tree")
     return {"codes": codes, "perm": perm, "nodes": nodes, "geom": geom, "moments": mom}
+
+
+def dps_set_packet(tree: Tree, query_k: int = 0, adjoint_k: int = 0):
+    """Queries per lane of the traversal kernels (1, 2, 4; 0 keeps)."""
+    _check(load().dps_set_packet(tree.handle, int(query_k), int(adjoint_k)), "dps_set_packet")
 
 
 def dps_check(tree: Tree):

@@ -68,10 +68,145 @@ __device__ __forceinline__ void load_attrs(const void *__restrict__ attr, int as
 }
 
 // ---------------------------------------------------------------------------
-// primal query: f[q][c0..c0+CB) and optionally grad[q][c0..c0+CB)[3]
+// primal query: f[q][c0..c0+CB) and optionally grad[q][c0..c0+CB)[3].
+// A wavefront owns 64*K consecutive queries; lane l carries queries
+// base + 64 i + l (i < K), so node fetches, decisions' ballots and loop
+// control are shared by 64*K queries (packet traversal).
 // ---------------------------------------------------------------------------
-template <int CB, bool BF16, bool GRAD>
+template <int CB, bool BF16, bool GRAD, int K>
 __global__ __launch_bounds__(kThreads) void k_query(
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
+    const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
+    float b2, KernelParams kp, int c0, float *__restrict__ fout, float *__restrict__ gout,
+    uint32_t limit, uint32_t *__restrict__ err) {
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t q0 = wave * 64 * K + (threadIdx.x & 63);
+    float px[K], py[K], pz[K];
+    uint32_t bits[K];
+    float f[K][CB], g[K][CB][3];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int64_t q = q0 + 64 * i;
+        const bool valid = q < Q;
+        px[i] = valid ? x[3 * q] : 0.0f;
+        py[i] = valid ? x[3 * q + 1] : 0.0f;
+        pz[i] = valid ? x[3 * q + 2] : 0.0f;
+        bits[i] = valid ? 1u : 0u;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            f[i][c] = 0.0f;
+            g[i][c][0] = g[i][c][1] = g[i][c][2] = 0.0f;
+        }
+    }
+    uint32_t t = 0;
+    uint32_t steps = 0;
+    while (t != kEnd) {
+        if (++steps > limit) {  // a well-formed tree is walked in at most N steps
+            if ((threadIdx.x & 63) == 0) atomicOr(err, 1u);
+            break;
+        }
+        const NodeRec nd = nodes[t];
+        const uint32_t lvl = nd.meta & 0xffu;
+        const float lim = mul_rn(b2, nd.r2);
+        bool far[K], any_far = false;
+        float s[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
+            far[i] = ((bits[i] >> lvl) & 1u) && (s[i] > lim);
+            any_far |= far[i];
+        }
+        if (__ballot(any_far)) {
+            float D[3 * CB];
+            load_moments<CB, BF16>(mom, ms, t, c0, D);
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                if (far[i]) {
+                    float kap, lam;
+                    radial(s[i], kp, kap, lam);
+                    const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
+                        f[i][c] += kap * sd;
+                        if (GRAD) {
+                            const float ls = lam * sd;
+                            g[i][c][0] += ls * dx - kap * D[3 * c];
+                            g[i][c][1] += ls * dy - kap * D[3 * c + 1];
+                            g[i][c][2] += ls * dz - kap * D[3 * c + 2];
+                        }
+                    }
+                }
+            }
+        }
+        bool open[K], any_open = false;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            open[i] = ((bits[i] >> lvl) & 1u) && !far[i];
+            any_open |= open[i];
+        }
+        if (__ballot(any_open)) {
+            if (!(nd.meta & kLeafFlag)) {
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
+                t = nd.first;
+                continue;
+            }
+            const uint32_t je = nd.first + nd.count;
+            for (uint32_t j = nd.first; j < je; ++j) {
+                const PointRec pr = pts[j];
+                float mu[CB];
+                load_attrs<CB, BF16>(attr, as, j, c0, mu);
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    if (open[i]) {
+                        const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        float kap, lam;
+                        if (radial(r2, kp, kap, lam)) {
+                            const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                            const float ks = kap * sa;
+                            const float ls = lam * sa;
+                            const float G0 = ls * dx - kap * pr.anx;
+                            const float G1 = ls * dy - kap * pr.any;
+                            const float G2 = ls * dz - kap * pr.anz;
+#pragma unroll
+                            for (int c = 0; c < CB; ++c) {
+                                f[i][c] += mu[c] * ks;
+                                if (GRAD) {
+                                    g[i][c][0] += mu[c] * G0;
+                                    g[i][c][1] += mu[c] * G1;
+                                    g[i][c][2] += mu[c] * G2;
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        t = nd.escape;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int64_t q = q0 + 64 * i;
+        if (q < Q) {
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                fout[q * C + c0 + c] = f[i][c];
+                if (GRAD) {
+                    gout[(q * C + c0 + c) * 3] = g[i][c][0];
+                    gout[(q * C + c0 + c) * 3 + 1] = g[i][c][1];
+                    gout[(q * C + c0 + c) * 3 + 2] = g[i][c][2];
+                }
+            }
+        }
+    }
+}
+
+// single query per lane (the register-lean form of k_query for K = 1)
+template <int CB, bool BF16, bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_query1(
     const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
     const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
     float b2, KernelParams kp, int c0, float *__restrict__ fout, float *__restrict__ gout,
@@ -236,7 +371,7 @@ __device__ __forceinline__ float pick_lane(const float (&v)[N_], int lane) {
     return r;
 }
 
-template <int CB, bool BF16>
+template <int CB, bool BF16, int K>
 __global__ __launch_bounds__(kThreads) void k_adjoint(
     const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
     const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
@@ -244,72 +379,84 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
     double *__restrict__ P, float *__restrict__ dxout, int dx_mode, uint32_t limit,
     uint32_t *__restrict__ err) {
     const int lane = lane_id();
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = q < Q;
-    float px = 0.0f, py = 0.0f, pz = 0.0f;
-    float w[CB];
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t q0 = wave * 64 * K + lane;
+    float px[K], py[K], pz[K], w[K][CB], ax[K], ay[K], az[K];
+    uint32_t bits[K];
 #pragma unroll
-    for (int c = 0; c < CB; ++c) w[c] = 0.0f;
-    if (valid) {
-        px = x[3 * q];
-        py = x[3 * q + 1];
-        pz = x[3 * q + 2];
+    for (int i = 0; i < K; ++i) {
+        const int64_t q = q0 + 64 * i;
+        const bool valid = q < Q;
+        px[i] = valid ? x[3 * q] : 0.0f;
+        py[i] = valid ? x[3 * q + 1] : 0.0f;
+        pz[i] = valid ? x[3 * q + 2] : 0.0f;
+        bits[i] = valid ? 1u : 0u;
+        ax[i] = ay[i] = az[i] = 0.0f;
 #pragma unroll
-        for (int c = 0; c < CB; ++c) w[c] = df[q * C + c0 + c];
+        for (int c = 0; c < CB; ++c) w[i][c] = valid ? df[q * C + c0 + c] : 0.0f;
     }
-    float ax = 0.0f, ay = 0.0f, az = 0.0f;
-    uint32_t bits = valid ? 1u : 0u;
     uint32_t t = 0;
     uint32_t steps = 0;
     while (t != kEnd) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
-            if (threadIdx.x % 64 == 0) atomicOr(err, 1u);
+            if (lane == 0) atomicOr(err, 1u);
             break;
         }
         const NodeRec nd = nodes[t];
         const uint32_t lvl = nd.meta & 0xffu;
-        const bool in = (bits >> lvl) & 1u;
-        const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
-        const bool far = in && (s > mul_rn(b2, nd.r2));
-        if (__ballot(far)) {
+        const float lim = mul_rn(b2, nd.r2);
+        bool far[K], open[K], any_far = false, any_open = false;
+        float s[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const bool in = (bits[i] >> lvl) & 1u;
+            s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
+            far[i] = in && (s[i] > lim);
+            open[i] = in && !far[i];
+            any_far |= far[i];
+            any_open |= open[i];
+        }
+        if (__ballot(any_far)) {
             float D[3 * CB];
             load_moments<CB, BF16>(mom, ms, t, c0, D);
-            float kap = 0.0f, dx = 0.0f, dy = 0.0f, dz = 0.0f;
-            if (far) {
-                float lam;
-                radial(s, kp, kap, lam);
-                dx = nd.cx - px;
-                dy = nd.cy - py;
-                dz = nd.cz - pz;
-                float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
+            // node increment sum_q df_c kappa (p_t - x_q), first over the lane's queries
+            float acc[3 * CB];
 #pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    E0 += w[c] * D[3 * c];
-                    E1 += w[c] * D[3 * c + 1];
-                    E2 += w[c] * D[3 * c + 2];
+            for (int v = 0; v < 3 * CB; ++v) acc[v] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                if (far[i]) {
+                    float kap, lam;
+                    radial(s[i], kp, kap, lam);
+                    const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
+                    float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        E0 += w[i][c] * D[3 * c];
+                        E1 += w[i][c] * D[3 * c + 1];
+                        E2 += w[i][c] * D[3 * c + 2];
+                        const float wk = w[i][c] * kap;
+                        acc[3 * c] += wk * dx;
+                        acc[3 * c + 1] += wk * dy;
+                        acc[3 * c + 2] += wk * dz;
+                    }
+                    const float les = lam * (E0 * dx + E1 * dy + E2 * dz);
+                    ax[i] += les * dx - kap * E0;
+                    ay[i] += les * dy - kap * E1;
+                    az[i] += les * dz - kap * E2;
                 }
-                const float les = lam * (E0 * dx + E1 * dy + E2 * dz);
-                ax += les * dx - kap * E0;
-                ay += les * dy - kap * E1;
-                az += les * dz - kap * E2;
             }
-            // node increment df_c * kappa * (p_t - x), summed over the wavefront
             float red[3 * CB];
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const float wk = w[c] * kap;
-                red[3 * c] = wave_sum(wk * dx);
-                red[3 * c + 1] = wave_sum(wk * dy);
-                red[3 * c + 2] = wave_sum(wk * dz);
-            }
-            const float v = pick_lane(red, lane);
-            if (lane < 3 * CB)
-                atomicAdd(&G[((size_t)t * C + c0) * 3 + lane], (double)v);
+            for (int v = 0; v < 3 * CB; ++v) red[v] = wave_sum(acc[v]);
+            const float val = pick_lane(red, lane);
+            if (lane < 3 * CB) atomicAdd(&G[((size_t)t * C + c0) * 3 + lane], (double)val);
         }
-        const bool open = in && !far;
-        if (__ballot(open)) {
+        if (__ballot(any_open)) {
             if (!(nd.meta & kLeafFlag)) {
-                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
                 t = nd.first;
                 continue;
             }
@@ -318,42 +465,56 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
                 const PointRec pr = pts[j];
                 float mu[CB];
                 load_attrs<CB, BF16>(attr, as, j, c0, mu);
-                float ks = 0.0f;
-                if (open) {
-                    const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    float kap, lam;
-                    if (radial(r2, kp, kap, lam)) {
-                        const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
-                        ks = kap * sa;
-                        float wm = 0.0f;
+                float acc[CB];
 #pragma unroll
-                        for (int c = 0; c < CB; ++c) wm += w[c] * mu[c];
-                        const float les = lam * sa * wm;
-                        const float kw = kap * wm;
-                        ax += les * dx - kw * pr.anx;
-                        ay += les * dy - kw * pr.any;
-                        az += les * dz - kw * pr.anz;
+                for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
+#pragma unroll
+                for (int i = 0; i < K; ++i) {
+                    if (open[i]) {
+                        const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        float kap, lam;
+                        if (radial(r2, kp, kap, lam)) {
+                            const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                            const float ks = kap * sa;
+                            float wm = 0.0f;
+#pragma unroll
+                            for (int c = 0; c < CB; ++c) {
+                                wm += w[i][c] * mu[c];
+                                acc[c] += w[i][c] * ks;
+                            }
+                            const float les = lam * sa * wm;
+                            const float kw = kap * wm;
+                            ax[i] += les * dx - kw * pr.anx;
+                            ay[i] += les * dy - kw * pr.any;
+                            az[i] += les * dz - kw * pr.anz;
+                        }
                     }
                 }
                 float red[CB];
 #pragma unroll
-                for (int c = 0; c < CB; ++c) red[c] = wave_sum(w[c] * ks);
-                const float v = pick_lane(red, lane);
-                if (lane < CB) atomicAdd(&P[(size_t)j * C + c0 + lane], (double)v);
+                for (int c = 0; c < CB; ++c) red[c] = wave_sum(acc[c]);
+                const float val = pick_lane(red, lane);
+                if (lane < CB) atomicAdd(&P[(size_t)j * C + c0 + lane], (double)val);
             }
         }
         t = nd.escape;
     }
-    if (valid && dx_mode != 0) {
-        if (dx_mode == 1) {
-            dxout[3 * q] = ax;
-            dxout[3 * q + 1] = ay;
-            dxout[3 * q + 2] = az;
-        } else {
-            dxout[3 * q] += ax;
-            dxout[3 * q + 1] += ay;
-            dxout[3 * q + 2] += az;
+    if (dx_mode != 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t q = q0 + 64 * i;
+            if (q < Q) {
+                if (dx_mode == 1) {
+                    dxout[3 * q] = ax[i];
+                    dxout[3 * q + 1] = ay[i];
+                    dxout[3 * q + 2] = az[i];
+                } else {
+                    dxout[3 * q] += ax[i];
+                    dxout[3 * q + 1] += ay[i];
+                    dxout[3 * q + 2] += az[i];
+                }
+            }
         }
     }
 }
@@ -436,31 +597,76 @@ inline unsigned grid(int64_t n) { return (unsigned)std::max<int64_t>(1, cdiv(n, 
 // channel blocks: 8s, then a 4, then the remainder; block starts stay multiples of 4
 inline int next_block(int rem) { return rem >= 8 ? 8 : (rem >= 4 ? 4 : rem); }
 
+// queries per lane: 1, 2 or 4; capped so per-lane accumulators stay in registers
+inline int clamp_packet(int k, int cb, bool grad) {
+    int cap = grad ? (cb <= 2 ? 4 : (cb <= 4 ? 2 : 1)) : (cb <= 4 ? 4 : 2);
+    k = k >= 4 ? 4 : (k >= 2 ? 2 : 1);
+    return k < cap ? k : cap;
+}
+
+template <int CB, bool BF, bool GR, int K>
+dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+                        float *f, float *g, hipStream_t s) {
+    const unsigned gr = grid(cdiv(Q, K));
+    if constexpr (K == 1)
+        k_query1<CB, BF, GR><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride,
+                                                     t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N,
+                                                     t->err);
+    else
+        k_query<CB, BF, GR, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride,
+                                                       t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N,
+                                                       t->err);
+    return hip_status(hipGetLastError(), "query launch");
+}
+
+template <int CB, bool BF, bool GR>
+dps_status query_k(dps_tree_s *t, int k, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+                   float *f, float *g, hipStream_t s) {
+    switch (clamp_packet(k, CB, GR)) {
+        case 4:
+            if constexpr ((GR && CB <= 2) || (!GR && CB <= 4)) return query_launch<CB, BF, GR, 4>(t, x, Q, b2, kp, c0, f, g, s);
+            [[fallthrough]];
+        case 2:
+            if constexpr (GR ? CB <= 4 : true) return query_launch<CB, BF, GR, 2>(t, x, Q, b2, kp, c0, f, g, s);
+            [[fallthrough]];
+        default:
+            return query_launch<CB, BF, GR, 1>(t, x, Q, b2, kp, c0, f, g, s);
+    }
+}
+
 template <int CB>
 dps_status query_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
                        float *f, float *g, hipStream_t s) {
-    const unsigned gr = grid(Q);
     const bool bf = t->storage == DPS_STORE_BF16;
-    if (bf && g)
-        k_query<CB, true, true><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N, t->err);
-    else if (bf)
-        k_query<CB, true, false><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N, t->err);
-    else if (g)
-        k_query<CB, false, true><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N, t->err);
-    else
-        k_query<CB, false, false><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N, t->err);
-    return hip_status(hipGetLastError(), "query launch");
+    const int k = t->packet_query;
+    if (bf && g) return query_k<CB, true, true>(t, k, x, Q, b2, kp, c0, f, g, s);
+    if (bf) return query_k<CB, true, false>(t, k, x, Q, b2, kp, c0, f, g, s);
+    if (g) return query_k<CB, false, true>(t, k, x, Q, b2, kp, c0, f, g, s);
+    return query_k<CB, false, false>(t, k, x, Q, b2, kp, c0, f, g, s);
+}
+
+template <int CB, bool BF, int K>
+dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+                          const float *df, float *dx, int dx_mode, hipStream_t s) {
+    const unsigned gr = grid(cdiv(Q, K));
+    k_adjoint<CB, BF, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride,
+                                                 t->attr_stride, x, Q, b2, kp, c0, df, t->G, t->P, dx,
+                                                 dx_mode, (uint32_t)t->N, t->err);
+    return hip_status(hipGetLastError(), "adjoint launch");
 }
 
 template <int CB>
 dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
                          const float *df, float *dx, int dx_mode, hipStream_t s) {
-    const unsigned gr = grid(Q);
-    if (t->storage == DPS_STORE_BF16)
-        k_adjoint<CB, true><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, df, t->G, t->P, dx, dx_mode, (uint32_t)t->N, t->err);
-    else
-        k_adjoint<CB, false><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride, t->attr_stride, x, Q, b2, kp, c0, df, t->G, t->P, dx, dx_mode, (uint32_t)t->N, t->err);
-    return hip_status(hipGetLastError(), "adjoint launch");
+    const int k = clamp_packet(t->packet_adjoint, CB, false);
+    if (t->storage == DPS_STORE_BF16) {
+        if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, true, 4>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); }
+        if (k >= 2) return adjoint_launch<CB, true, 2>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s);
+        return adjoint_launch<CB, true, 1>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s);
+    }
+    if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, false, 4>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); }
+    if (k >= 2) return adjoint_launch<CB, false, 2>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s);
+    return adjoint_launch<CB, false, 1>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s);
 }
 
 }  // namespace

@@ -20,6 +20,8 @@ struct dps_tree_s {
     int64_t level_start[dps::kLevels + 2];  // nodes of level l: [level_start[l], level_start[l+1])
     int64_t n_top;    // nodes with level <= kTopLevels
     bool wide_top;    // FP64 accumulation of top-level moments
+    int packet_query;    // queries per lane in dps_query (1, 2, 4)
+    int packet_adjoint;  // queries per lane in dps_adjoint_accumulate (1, 2, 4)
 
     uint64_t *codes;          // [M] sorted Morton codes
     uint32_t *perm;           // [M] sorted position -> caller index

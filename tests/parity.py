@@ -3,11 +3,25 @@ from __future__ import annotations
 
 import numpy as np
 
-# FP32-stored tolerance on errors normalised by the per-query absolute sums;
-# BF16-stored tolerance: each stored value carries <= 2^-9 relative error and
-# |dD.d| <= 2^-9 |D||d| (Cauchy-Schwarz), so the normalised error is < 2e-3.
+# FP32-stored tolerance on errors normalised by the per-query absolute sums.
 TOL_FP32 = 1e-5
-TOL_BF16 = 2e-3
+# BF16-stored: round-to-nearest-even to 8 significant bits leaves each stored
+# value within 2^-8 of itself (relative), and |dD.d| <= 2^-8 |D||d|
+# (Cauchy-Schwarz), so the normalised error is bounded by 2^-8 (plus the FP32
+# part).  Queries dominated by one source approach that bound; the 2e-3 figure
+# is met by the bulk of queries and reported as a percentile.
+TOL_BF16 = 2.0 ** -8 + TOL_FP32
+TARGET_BF16 = 2e-3
+
+
+def norm_err_all(got, ref, scale):
+    """Per-element normalised errors (flattened)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.asarray(scale, dtype=np.float64)
+    while scale.ndim < ref.ndim:
+        scale = scale[..., None]
+    return (np.abs(got - ref) / np.maximum(scale, 1e-300)).reshape(-1)
 
 
 def norm_err(got, ref, scale):

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads
-from parity import TOL_BF16, TOL_FP32, node_abs_sums, norm_err, to_dev, to_host
+from parity import TOL_BF16, TOL_FP32, node_abs_sums, norm_err, norm_err_all, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +92,11 @@ def test_query_parity(dps, orc, name, eps, storage):
     ef = norm_err(to_host(f), ref["f"], ref["sf"])
     eg = norm_err(to_host(g), ref["g"], ref["sg"])
     assert ef <= tol and eg <= tol, (ef, eg)
+    if storage == "bf16":
+        # few-source clouds cannot average the per-source rounding; the 2e-3
+        # percentile target is checked on the 1M-point workload
+        pf = np.percentile(norm_err_all(to_host(f), ref["f"], ref["sf"]), 99.9)
+        print(f"[bf16] {name} eps={eps}: max {ef:.3g} / {eg:.3g}, 99.9th percentile f {pf:.3g}", flush=True)
     counts = to_host(dps.dps_query_counts(tree, xd, 2.0))
     assert np.array_equal(counts, ref["counts"]), "traversal decisions differ"
 
@@ -186,3 +191,35 @@ def test_invalid_data_rejected(dps):
         with pytest.raises(dps.DpsError) as e:
             dps.dps_query(tree, x, beta, eps)
         assert e.value.status == 1
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+@pytest.mark.parametrize("name,Q", [("sphere-8k", 4099), ("random-3001-c5", 1000), ("random-2000-c1", 257)])
+def test_packet_sizes_parity(dps, orc, k, name, Q):
+    # every launch shape makes the same per-query decisions; ragged tails
+    p, n, A, mu = CLOUDS[name]()
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16)
+    dps.dps_set_packet(tree, k, k)
+    x = workloads.sphere_queries(Q, 31)
+    df = workloads.cotangents(Q, mu.shape[1], 17)
+    xd, dfd = to_dev(x, df)
+    f, g = dps.dps_query(tree, xd, 2.0, 0.05)
+    ref = T.query(x, 2.0, 0.05)
+    assert norm_err(to_host(f), ref["f"], ref["sf"]) <= TOL_FP32
+    assert norm_err(to_host(g), ref["g"], ref["sg"]) <= TOL_FP32
+    f2, _ = dps.dps_query(tree, xd, 2.0, 0.05, grad=False)
+    assert norm_err(to_host(f2), ref["f"], ref["sf"]) <= TOL_FP32
+    dattrs, dx = dps.dps_adjoint(tree, xd, 2.0, 0.05, dfd)
+    adj = T.adjoint(x, 2.0, 0.05, df)
+    assert norm_err(to_host(dattrs), adj["dmu"], adj["sdmu"]) <= TOL_FP32
+    assert norm_err(to_host(dx), adj["dx"], adj["sdx"]) <= TOL_FP32
+    dps.dps_check(tree)
+
+
+def test_set_packet_rejects_bad_sizes(dps):
+    p, n, A, mu = workloads.sphere_cloud(256, 1)
+    tree = dps.dps_build(*to_dev(p, n, A, mu))
+    for k in (3, 5, -1, 8):
+        with pytest.raises(dps.DpsError):
+            dps.dps_set_packet(tree, k, 1)
+    dps.dps_set_packet(tree, 0, 4)
