@@ -170,11 +170,18 @@ dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *
  * wavefront walks the tree once for 64*k consecutive queries, lane l carrying
  * queries base + 64 i + l (i < k), so node fetches and, in the adjoint, the
  * wavefront sums and atomics are shared by 64*k queries (the packet queries
- * suggested in Sec. 6.3).  Results do not depend on k beyond FP rounding order.
+ * suggested in Sec. 6.3).  Results do not depend on the launch shape beyond
+ * FP rounding order.
  *  query_k, adjoint_k  1, 2 or 4; 0 keeps the current value.  Large channel
- *  blocks cap k so accumulators stay in registers.  Host-only, immediate.
+ *                      blocks cap k so accumulators stay in registers.
+ *  xcd_order           bit 0 (dps_query) / bit 1 (dps_adjoint_accumulate): the
+ *                      workgroups that run on one of the 8 XCDs take a
+ *                      contiguous eighth of the queries, so each XCD's L2
+ *                      serves one region of a coherently ordered query set;
+ *                      bit clear: plain order.  -1 keeps the current value.
+ * Host-only, takes effect for later launches.
  */
-dps_status dps_set_packet(dps_tree t, int32_t query_k, int32_t adjoint_k);
+dps_status dps_set_packet(dps_tree t, int32_t query_k, int32_t adjoint_k, int32_t xcd_order);
 
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A

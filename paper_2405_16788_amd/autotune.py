@@ -1,8 +1,9 @@
-"""Autotuner for the traversal launch shape (queries per lane, 1 / 2 / 4).
+"""Autotuner for the traversal launch shape: queries per lane (1 / 2 / 4) and
+the XCD-contiguous workgroup order (off / on).
 
-Times dps_query and dps_adjoint_accumulate for each packet size on a slice of
-the caller's own queries (HIP events on the current stream), keeps the
-fastest, and applies it with dps_set_packet.  Results are cached in a JSON file
+Times dps_query and dps_adjoint_accumulate for each shape on a slice of the
+caller's own queries (HIP events on the current stream), keeps the fastest,
+and applies it with dps_set_packet.  Results are cached in a JSON file
 keyed by the workload shape, so later runs skip the sweep.
 """
 from __future__ import annotations
@@ -48,6 +49,7 @@ def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=Fal
     if key in table:
         best = table[key]
         B.dps_set_packet(tree, best["query"], best["adjoint"])
+        B.dps_set_packet(tree, 0, 0, best.get("xcd_query", 0) | (best.get("xcd_adjoint", 0) << 1))
         return best
     n = min(x.shape[0], sample)
     # a contiguous slice keeps the spatial coherence of the caller's layout
@@ -58,19 +60,22 @@ def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=Fal
     g = torch.empty((n, tree.C, 3), device=x.device)
     dx = torch.empty((n, 3), device=x.device)
     ms = {"query": {}, "adjoint": {}}
-    for k in PACKETS:
-        B.dps_set_packet(tree, k, k)
-        ms["query"][k] = _time(lambda: B.dps_query(tree, xs, beta, eps, f_out=f, g_out=g), reps)
-        B.dps_adjoint_zero(tree)
-        ms["adjoint"][k] = _time(lambda: B.dps_adjoint_accumulate(tree, xs, beta, eps, dfs, dx_out=dx), reps)
-        if verbose:
-            print(f"[autotune] k={k}: query {ms['query'][k]:.3f} ms, adjoint {ms['adjoint'][k]:.3f} ms",
-                  flush=True)
+    for xo in (0, 1):
+        for k in PACKETS:
+            B.dps_set_packet(tree, k, k, 3 * xo)
+            ms["query"][(k, xo)] = _time(lambda: B.dps_query(tree, xs, beta, eps, f_out=f, g_out=g), reps)
+            B.dps_adjoint_zero(tree)
+            ms["adjoint"][(k, xo)] = _time(
+                lambda: B.dps_adjoint_accumulate(tree, xs, beta, eps, dfs, dx_out=dx), reps)
+            if verbose:
+                print(f"[autotune] k={k} xcd_order={xo}: query {ms['query'][(k, xo)]:.3f} ms, "
+                      f"adjoint {ms['adjoint'][(k, xo)]:.3f} ms", flush=True)
     B.dps_adjoint_zero(tree)
-    best = {"query": min(ms["query"], key=ms["query"].get),
-            "adjoint": min(ms["adjoint"], key=ms["adjoint"].get),
-            "ms": {p: {str(k): v for k, v in d.items()} for p, d in ms.items()}}
-    B.dps_set_packet(tree, best["query"], best["adjoint"])
+    bq = min(ms["query"], key=ms["query"].get)
+    ba = min(ms["adjoint"], key=ms["adjoint"].get)
+    best = {"query": bq[0], "adjoint": ba[0], "xcd_query": bq[1], "xcd_adjoint": ba[1],
+            "ms": {p: {f"k{k}_x{x}": v for (k, x), v in d.items()} for p, d in ms.items()}}
+    B.dps_set_packet(tree, best["query"], best["adjoint"], best["xcd_query"] | (best["xcd_adjoint"] << 1))
     if cache:
         try:
             os.makedirs(os.path.dirname(cache), exist_ok=True)

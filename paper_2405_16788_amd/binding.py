@@ -53,7 +53,7 @@ def load():
         "dps_query_counts": [vp, vp, i64, f32, vp, vp],
         "dps_adjoint_zero": [vp, vp],
         "dps_check": [vp, vp],
-        "dps_set_packet": [vp, i32, i32],
+        "dps_set_packet": [vp, i32, i32, i32],
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
         "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
@@ -239,9 +239,10 @@ def dps_export_tree(tree: Tree) -> dict:
     return {"codes": codes, "perm": perm, "nodes": nodes, "geom": geom, "moments": mom}
 
 
-def dps_set_packet(tree: Tree, query_k: int = 0, adjoint_k: int = 0):
-    """Queries per lane of the traversal kernels (1, 2, 4; 0 keeps)."""
-    _check(load().dps_set_packet(tree.handle, int(query_k), int(adjoint_k)), "dps_set_packet")
+def dps_set_packet(tree: Tree, query_k: int = 0, adjoint_k: int = 0, xcd_order: int = -1):
+    """Queries per lane of the traversal kernels (1, 2, 4; 0 keeps) and the
+    XCD-contiguous workgroup order (bit 0 query, bit 1 adjoint; -1 keeps)."""
+    _check(load().dps_set_packet(tree.handle, int(query_k), int(adjoint_k), int(xcd_order)), "dps_set_packet")
 
 
 def dps_check(tree: Tree):

@@ -109,6 +109,7 @@ dps_status dps_build(const float *p, const float *n, const float *A, const float
     t->wide_top = M >= kWideTopPoints;
     t->packet_query = kDefaultPacketQuery;
     t->packet_adjoint = kDefaultPacketAdjoint;
+    t->xcd_remap = kDefaultXcdRemap;
     const bool bf = storage == DPS_STORE_BF16;
     t->mom_stride = bf ? ((3 * C + 1) & ~1) : 3 * C;
     t->attr_stride = bf ? ((C + 1) & ~1) : C;
@@ -265,13 +266,15 @@ dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *
     return DPS_OK;
 }
 
-dps_status dps_set_packet(dps_tree t, int32_t query_k, int32_t adjoint_k) {
+dps_status dps_set_packet(dps_tree t, int32_t query_k, int32_t adjoint_k, int32_t xcd_order) {
     dps_status st = check_tree(t, "dps_set_packet");
     if (st != DPS_OK) return st;
     auto ok = [](int32_t k) { return k == 0 || k == 1 || k == 2 || k == 4; };
     if (!ok(query_k) || !ok(adjoint_k)) return invalid("dps_set_packet: packet sizes must be 0 (keep), 1, 2 or 4");
+    if (xcd_order < -1 || xcd_order > 3) return invalid("dps_set_packet: xcd_order must be -1 (keep) or a 2-bit mask");
     if (query_k) t->packet_query = query_k;
     if (adjoint_k) t->packet_adjoint = adjoint_k;
+    if (xcd_order >= 0) t->xcd_remap = xcd_order;
     return DPS_OK;
 }
 

@@ -21,7 +21,8 @@ constexpr int kLevels = DPS_LEVELS;      // 21 levels below the root
 constexpr int kTopLevels = 3;            // "top-level" nodes: depth <= 3
 constexpr int64_t kWideTopPoints = 4194304;  // FP64 top-level moment sums from this size on
 constexpr int kDefaultPacketQuery = 1;     // queries per lane (tuned: dps_set_packet)
-constexpr int kDefaultPacketAdjoint = 2;
+constexpr int kDefaultPacketAdjoint = 4;
+constexpr int kDefaultXcdRemap = 0;
 
 struct alignas(32) NodeRec {
     float cx, cy, cz, r2;  // FP32 centroid and squared radius

@@ -67,6 +67,19 @@ __device__ __forceinline__ void load_attrs(const void *__restrict__ attr, int as
     }
 }
 
+// Workgroups are handed to the 8 XCDs round-robin.  With remapping, the
+// workgroups on one XCD take a contiguous eighth of the work, so each XCD's L2
+// serves one spatial region of the (tile-ordered) queries.  Returns the
+// logical block index, or -1 for padding blocks.
+__device__ __forceinline__ int64_t remap_block(int remap) {
+    const int64_t b = blockIdx.x;
+    if (!remap) return b;
+    const int64_t nb = remap;  // number of logical blocks
+    const int64_t per = (nb + 7) / 8;
+    const int64_t l = (b % 8) * per + b / 8;
+    return l < nb ? l : -1;
+}
+
 // ---------------------------------------------------------------------------
 // primal query: f[q][c0..c0+CB) and optionally grad[q][c0..c0+CB)[3].
 // A wavefront owns 64*K consecutive queries; lane l carries queries
@@ -78,8 +91,10 @@ __global__ __launch_bounds__(kThreads) void k_query(
     const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
     const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
     float b2, KernelParams kp, int c0, float *__restrict__ fout, float *__restrict__ gout,
-    uint32_t limit, uint32_t *__restrict__ err) {
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    uint32_t limit, uint32_t *__restrict__ err, int xcd_remap) {
+    const int64_t blk = remap_block(xcd_remap);
+    if (blk < 0) return;
+    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
     const int64_t q0 = wave * 64 * K + (threadIdx.x & 63);
     float px[K], py[K], pz[K];
     uint32_t bits[K];
@@ -99,26 +114,37 @@ __global__ __launch_bounds__(kThreads) void k_query(
         }
     }
     uint32_t t = 0;
+    NodeRec nd = nodes[0];
+    float D[3 * CB];
+    load_moments<CB, BF16>(mom, ms, 0, c0, D);
     uint32_t steps = 0;
-    while (t != kEnd) {
+    for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
             if ((threadIdx.x & 63) == 0) atomicOr(err, 1u);
             break;
         }
-        const NodeRec nd = nodes[t];
         const uint32_t lvl = nd.meta & 0xffu;
+        const bool leaf = (nd.meta & kLeafFlag) != 0;
         const float lim = mul_rn(b2, nd.r2);
-        bool far[K], any_far = false;
+        bool far[K], open[K], lane_far = false, lane_open = false;
         float s[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) {
+            const bool in = (bits[i] >> lvl) & 1u;
             s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
-            far[i] = ((bits[i] >> lvl) & 1u) && (s[i] > lim);
-            any_far |= far[i];
+            far[i] = in && (s[i] > lim);
+            open[i] = in && !far[i];
+            lane_far |= far[i];
+            lane_open |= open[i];
         }
-        if (__ballot(any_far)) {
-            float D[3 * CB];
-            load_moments<CB, BF16>(mom, ms, t, c0, D);
+        const bool any_far = __ballot(lane_far) != 0;
+        const bool any_open = __ballot(lane_open) != 0;
+        const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
+        const uint32_t pf = next == kEnd ? t : next;
+        const NodeRec nn = nodes[pf];
+        float Dn[3 * CB];
+        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+        if (any_far) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 if (far[i]) {
@@ -139,45 +165,38 @@ __global__ __launch_bounds__(kThreads) void k_query(
                 }
             }
         }
-        bool open[K], any_open = false;
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            open[i] = ((bits[i] >> lvl) & 1u) && !far[i];
-            any_open |= open[i];
-        }
-        if (__ballot(any_open)) {
-            if (!(nd.meta & kLeafFlag)) {
+        if (any_open) {
+            if (!leaf) {
 #pragma unroll
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
-                t = nd.first;
-                continue;
-            }
-            const uint32_t je = nd.first + nd.count;
-            for (uint32_t j = nd.first; j < je; ++j) {
-                const PointRec pr = pts[j];
-                float mu[CB];
-                load_attrs<CB, BF16>(attr, as, j, c0, mu);
+            } else {
+                const uint32_t je = nd.first + nd.count;
+                for (uint32_t j = nd.first; j < je; ++j) {
+                    const PointRec pr = pts[j];
+                    float mu[CB];
+                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
 #pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    if (open[i]) {
-                        const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        float kap, lam;
-                        if (radial(r2, kp, kap, lam)) {
-                            const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
-                            const float ks = kap * sa;
-                            const float ls = lam * sa;
-                            const float G0 = ls * dx - kap * pr.anx;
-                            const float G1 = ls * dy - kap * pr.any;
-                            const float G2 = ls * dz - kap * pr.anz;
+                    for (int i = 0; i < K; ++i) {
+                        if (open[i]) {
+                            const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
+                            const float r2 = dx * dx + dy * dy + dz * dz;
+                            float kap, lam;
+                            if (radial(r2, kp, kap, lam)) {
+                                const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                                const float ks = kap * sa;
+                                const float ls = lam * sa;
+                                const float G0 = ls * dx - kap * pr.anx;
+                                const float G1 = ls * dy - kap * pr.any;
+                                const float G2 = ls * dz - kap * pr.anz;
 #pragma unroll
-                            for (int c = 0; c < CB; ++c) {
-                                f[i][c] += mu[c] * ks;
-                                if (GRAD) {
-                                    g[i][c][0] += mu[c] * G0;
-                                    g[i][c][1] += mu[c] * G1;
-                                    g[i][c][2] += mu[c] * G2;
+                                for (int c = 0; c < CB; ++c) {
+                                    f[i][c] += mu[c] * ks;
+                                    if (GRAD) {
+                                        g[i][c][0] += mu[c] * G0;
+                                        g[i][c][1] += mu[c] * G1;
+                                        g[i][c][2] += mu[c] * G2;
+                                    }
                                 }
                             }
                         }
@@ -185,7 +204,11 @@ __global__ __launch_bounds__(kThreads) void k_query(
                 }
             }
         }
-        t = nd.escape;
+        if (next == kEnd) break;
+        t = next;
+        nd = nn;
+#pragma unroll
+        for (int v = 0; v < 3 * CB; ++v) D[v] = Dn[v];
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -204,14 +227,19 @@ __global__ __launch_bounds__(kThreads) void k_query(
     }
 }
 
-// single query per lane (the register-lean form of k_query for K = 1)
+// single query per lane (the register-lean form of k_query for K = 1).
+// Software-pipelined: the next node is known right after the ballots, so its
+// record and moments are fetched before the far-field / leaf work of the
+// current node, hiding the scalar-load latency behind that work.
 template <int CB, bool BF16, bool GRAD>
 __global__ __launch_bounds__(kThreads) void k_query1(
     const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
     const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
     float b2, KernelParams kp, int c0, float *__restrict__ fout, float *__restrict__ gout,
-    uint32_t limit, uint32_t *__restrict__ err) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t limit, uint32_t *__restrict__ err, int xcd_remap) {
+    const int64_t blk = remap_block(xcd_remap);
+    if (blk < 0) return;
+    const int64_t q = blk * blockDim.x + threadIdx.x;
     const bool valid = q < Q;
     float px = 0.0f, py = 0.0f, pz = 0.0f;
     if (valid) {
@@ -227,74 +255,83 @@ __global__ __launch_bounds__(kThreads) void k_query1(
     }
     uint32_t bits = valid ? 1u : 0u;
     uint32_t t = 0;
+    NodeRec nd = nodes[0];
+    float D[3 * CB];
+    load_moments<CB, BF16>(mom, ms, 0, c0, D);
     uint32_t steps = 0;
-    while (t != kEnd) {
+    for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
-            if (threadIdx.x % 64 == 0) atomicOr(err, 1u);
+            if ((threadIdx.x & 63) == 0) atomicOr(err, 1u);
             break;
         }
-        const NodeRec nd = nodes[t];
         const uint32_t lvl = nd.meta & 0xffu;
+        const bool leaf = (nd.meta & kLeafFlag) != 0;
         const bool in = (bits >> lvl) & 1u;
         const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
         const bool far = in && (s > mul_rn(b2, nd.r2));
-        if (__ballot(far)) {
-            float D[3 * CB];
-            load_moments<CB, BF16>(mom, ms, t, c0, D);
-            if (far) {
-                float kap, lam;
-                radial(s, kp, kap, lam);
-                const float dx = nd.cx - px, dy = nd.cy - py, dz = nd.cz - pz;
+        const bool open = in && !far;
+        const bool any_far = __ballot(far) != 0;
+        const bool any_open = __ballot(open) != 0;
+        const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
+        const uint32_t pf = next == kEnd ? t : next;
+        const NodeRec nn = nodes[pf];
+        float Dn[3 * CB];
+        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+        if (any_far && far) {
+            float kap, lam;
+            radial(s, kp, kap, lam);
+            const float dx = nd.cx - px, dy = nd.cy - py, dz = nd.cz - pz;
 #pragma unroll
-                for (int c = 0; c < CB; ++c) {
-                    const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
-                    f[c] += kap * sd;
-                    if (GRAD) {
-                        const float ls = lam * sd;
-                        g[c][0] += ls * dx - kap * D[3 * c];
-                        g[c][1] += ls * dy - kap * D[3 * c + 1];
-                        g[c][2] += ls * dz - kap * D[3 * c + 2];
-                    }
+            for (int c = 0; c < CB; ++c) {
+                const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
+                f[c] += kap * sd;
+                if (GRAD) {
+                    const float ls = lam * sd;
+                    g[c][0] += ls * dx - kap * D[3 * c];
+                    g[c][1] += ls * dy - kap * D[3 * c + 1];
+                    g[c][2] += ls * dz - kap * D[3 * c + 2];
                 }
             }
         }
-        const bool open = in && !far;
-        if (__ballot(open)) {
-            if (!(nd.meta & kLeafFlag)) {
+        if (any_open) {
+            if (!leaf) {
                 bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
-                t = nd.first;
-                continue;
-            }
-            const uint32_t je = nd.first + nd.count;
-            for (uint32_t j = nd.first; j < je; ++j) {
-                const PointRec pr = pts[j];
-                float mu[CB];
-                load_attrs<CB, BF16>(attr, as, j, c0, mu);
-                if (open) {
-                    const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    float kap, lam;
-                    if (radial(r2, kp, kap, lam)) {
-                        const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
-                        const float ks = kap * sa;
-                        const float ls = lam * sa;
-                        const float G0 = ls * dx - kap * pr.anx;
-                        const float G1 = ls * dy - kap * pr.any;
-                        const float G2 = ls * dz - kap * pr.anz;
+            } else {
+                const uint32_t je = nd.first + nd.count;
+                for (uint32_t j = nd.first; j < je; ++j) {
+                    const PointRec pr = pts[j];
+                    float mu[CB];
+                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                    if (open) {
+                        const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        float kap, lam;
+                        if (radial(r2, kp, kap, lam)) {
+                            const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                            const float ks = kap * sa;
+                            const float ls = lam * sa;
+                            const float G0 = ls * dx - kap * pr.anx;
+                            const float G1 = ls * dy - kap * pr.any;
+                            const float G2 = ls * dz - kap * pr.anz;
 #pragma unroll
-                        for (int c = 0; c < CB; ++c) {
-                            f[c] += mu[c] * ks;
-                            if (GRAD) {
-                                g[c][0] += mu[c] * G0;
-                                g[c][1] += mu[c] * G1;
-                                g[c][2] += mu[c] * G2;
+                            for (int c = 0; c < CB; ++c) {
+                                f[c] += mu[c] * ks;
+                                if (GRAD) {
+                                    g[c][0] += mu[c] * G0;
+                                    g[c][1] += mu[c] * G1;
+                                    g[c][2] += mu[c] * G2;
+                                }
                             }
                         }
                     }
                 }
             }
         }
-        t = nd.escape;
+        if (next == kEnd) break;
+        t = next;
+        nd = nn;
+#pragma unroll
+        for (int v = 0; v < 3 * CB; ++v) D[v] = Dn[v];
     }
     if (valid) {
 #pragma unroll
@@ -377,9 +414,11 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
     const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
     float b2, KernelParams kp, int c0, const float *__restrict__ df, double *__restrict__ G,
     double *__restrict__ P, float *__restrict__ dxout, int dx_mode, uint32_t limit,
-    uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ err, int xcd_remap) {
     const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t blk = remap_block(xcd_remap);
+    if (blk < 0) return;
+    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
     const int64_t q0 = wave * 64 * K + lane;
     float px[K], py[K], pz[K], w[K][CB], ax[K], ay[K], az[K];
     uint32_t bits[K];
@@ -396,16 +435,19 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
         for (int c = 0; c < CB; ++c) w[i][c] = valid ? df[q * C + c0 + c] : 0.0f;
     }
     uint32_t t = 0;
+    NodeRec nd = nodes[0];
+    float D[3 * CB];
+    load_moments<CB, BF16>(mom, ms, 0, c0, D);
     uint32_t steps = 0;
-    while (t != kEnd) {
+    for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
             if (lane == 0) atomicOr(err, 1u);
             break;
         }
-        const NodeRec nd = nodes[t];
         const uint32_t lvl = nd.meta & 0xffu;
+        const bool leaf = (nd.meta & kLeafFlag) != 0;
         const float lim = mul_rn(b2, nd.r2);
-        bool far[K], open[K], any_far = false, any_open = false;
+        bool far[K], open[K], lane_far = false, lane_open = false;
         float s[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) {
@@ -413,12 +455,17 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
             s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
             far[i] = in && (s[i] > lim);
             open[i] = in && !far[i];
-            any_far |= far[i];
-            any_open |= open[i];
+            lane_far |= far[i];
+            lane_open |= open[i];
         }
-        if (__ballot(any_far)) {
-            float D[3 * CB];
-            load_moments<CB, BF16>(mom, ms, t, c0, D);
+        const bool any_far = __ballot(lane_far) != 0;
+        const bool any_open = __ballot(lane_open) != 0;
+        const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
+        const uint32_t pf = next == kEnd ? t : next;
+        const NodeRec nn = nodes[pf];
+        float Dn[3 * CB];
+        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+        if (any_far) {
             // node increment sum_q df_c kappa (p_t - x_q), first over the lane's queries
             float acc[3 * CB];
 #pragma unroll
@@ -452,53 +499,56 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
             const float val = pick_lane(red, lane);
             if (lane < 3 * CB) atomicAdd(&G[((size_t)t * C + c0) * 3 + lane], (double)val);
         }
-        if (__ballot(any_open)) {
-            if (!(nd.meta & kLeafFlag)) {
+        if (any_open) {
+            if (!leaf) {
 #pragma unroll
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
-                t = nd.first;
-                continue;
-            }
-            const uint32_t je = nd.first + nd.count;
-            for (uint32_t j = nd.first; j < je; ++j) {
-                const PointRec pr = pts[j];
-                float mu[CB];
-                load_attrs<CB, BF16>(attr, as, j, c0, mu);
-                float acc[CB];
+            } else {
+                const uint32_t je = nd.first + nd.count;
+                for (uint32_t j = nd.first; j < je; ++j) {
+                    const PointRec pr = pts[j];
+                    float mu[CB];
+                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                    float acc[CB];
 #pragma unroll
-                for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
+                    for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
 #pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    if (open[i]) {
-                        const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        float kap, lam;
-                        if (radial(r2, kp, kap, lam)) {
-                            const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
-                            const float ks = kap * sa;
-                            float wm = 0.0f;
+                    for (int i = 0; i < K; ++i) {
+                        if (open[i]) {
+                            const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
+                            const float r2 = dx * dx + dy * dy + dz * dz;
+                            float kap, lam;
+                            if (radial(r2, kp, kap, lam)) {
+                                const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                                const float ks = kap * sa;
+                                float wm = 0.0f;
 #pragma unroll
-                            for (int c = 0; c < CB; ++c) {
-                                wm += w[i][c] * mu[c];
-                                acc[c] += w[i][c] * ks;
+                                for (int c = 0; c < CB; ++c) {
+                                    wm += w[i][c] * mu[c];
+                                    acc[c] += w[i][c] * ks;
+                                }
+                                const float les = lam * sa * wm;
+                                const float kw = kap * wm;
+                                ax[i] += les * dx - kw * pr.anx;
+                                ay[i] += les * dy - kw * pr.any;
+                                az[i] += les * dz - kw * pr.anz;
                             }
-                            const float les = lam * sa * wm;
-                            const float kw = kap * wm;
-                            ax[i] += les * dx - kw * pr.anx;
-                            ay[i] += les * dy - kw * pr.any;
-                            az[i] += les * dz - kw * pr.anz;
                         }
                     }
-                }
-                float red[CB];
+                    float red[CB];
 #pragma unroll
-                for (int c = 0; c < CB; ++c) red[c] = wave_sum(acc[c]);
-                const float val = pick_lane(red, lane);
-                if (lane < CB) atomicAdd(&P[(size_t)j * C + c0 + lane], (double)val);
+                    for (int c = 0; c < CB; ++c) red[c] = wave_sum(acc[c]);
+                    const float val = pick_lane(red, lane);
+                    if (lane < CB) atomicAdd(&P[(size_t)j * C + c0 + lane], (double)val);
+                }
             }
         }
-        t = nd.escape;
+        if (next == kEnd) break;
+        t = next;
+        nd = nn;
+#pragma unroll
+        for (int v = 0; v < 3 * CB; ++v) D[v] = Dn[v];
     }
     if (dx_mode != 0) {
 #pragma unroll
@@ -607,15 +657,18 @@ inline int clamp_packet(int k, int cb, bool grad) {
 template <int CB, bool BF, bool GR, int K>
 dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
                         float *f, float *g, hipStream_t s) {
-    const unsigned gr = grid(cdiv(Q, K));
+    const unsigned nb = grid(cdiv(Q, K));
+    const bool remap = (t->xcd_remap & 1) != 0;
+    const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
+    const int rm = remap ? (int)nb : 0;
     if constexpr (K == 1)
         k_query1<CB, BF, GR><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride,
                                                      t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N,
-                                                     t->err);
+                                                     t->err, rm);
     else
         k_query<CB, BF, GR, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride,
                                                        t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N,
-                                                       t->err);
+                                                       t->err, rm);
     return hip_status(hipGetLastError(), "query launch");
 }
 
@@ -648,10 +701,13 @@ dps_status query_block(dps_tree_s *t, const float *x, int64_t Q, float b2, Kerne
 template <int CB, bool BF, int K>
 dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
                           const float *df, float *dx, int dx_mode, hipStream_t s) {
-    const unsigned gr = grid(cdiv(Q, K));
+    const unsigned nb = grid(cdiv(Q, K));
+    const bool remap = (t->xcd_remap & 2) != 0;
+    const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
+    const int rm = remap ? (int)nb : 0;
     k_adjoint<CB, BF, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride,
                                                  t->attr_stride, x, Q, b2, kp, c0, df, t->G, t->P, dx,
-                                                 dx_mode, (uint32_t)t->N, t->err);
+                                                 dx_mode, (uint32_t)t->N, t->err, rm);
     return hip_status(hipGetLastError(), "adjoint launch");
 }
 

@@ -22,6 +22,7 @@ struct dps_tree_s {
     bool wide_top;    // FP64 accumulation of top-level moments
     int packet_query;    // queries per lane in dps_query (1, 2, 4)
     int packet_adjoint;  // queries per lane in dps_adjoint_accumulate (1, 2, 4)
+    int xcd_remap;       // bit 0 query, bit 1 adjoint: workgroups of one XCD take a contiguous share
 
     uint64_t *codes;          // [M] sorted Morton codes
     uint32_t *perm;           // [M] sorted position -> caller index

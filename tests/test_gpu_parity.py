@@ -193,13 +193,15 @@ def test_invalid_data_rejected(dps):
         assert e.value.status == 1
 
 
+@pytest.mark.parametrize("xcd", [0, 3])
 @pytest.mark.parametrize("k", [1, 2, 4])
-@pytest.mark.parametrize("name,Q", [("sphere-8k", 4099), ("random-3001-c5", 1000), ("random-2000-c1", 257)])
-def test_packet_sizes_parity(dps, orc, k, name, Q):
+@pytest.mark.parametrize("name,Q", [("sphere-8k", 4099), ("random-3001-c5", 1000), ("random-2000-c1", 257),
+                                    ("sphere-8k", 70000)])
+def test_packet_sizes_parity(dps, orc, k, xcd, name, Q):
     # every launch shape makes the same per-query decisions; ragged tails
     p, n, A, mu = CLOUDS[name]()
     tree, T = _check_build(dps, orc, p, n, A, mu, 16)
-    dps.dps_set_packet(tree, k, k)
+    dps.dps_set_packet(tree, k, k, xcd)
     x = workloads.sphere_queries(Q, 31)
     df = workloads.cotangents(Q, mu.shape[1], 17)
     xd, dfd = to_dev(x, df)
@@ -222,4 +224,8 @@ def test_set_packet_rejects_bad_sizes(dps):
     for k in (3, 5, -1, 8):
         with pytest.raises(dps.DpsError):
             dps.dps_set_packet(tree, k, 1)
+    for xo in (-2, 4):
+        with pytest.raises(dps.DpsError):
+            dps.dps_set_packet(tree, 1, 1, xo)
     dps.dps_set_packet(tree, 0, 4)
+    dps.dps_set_packet(tree, 2, 0, 3)
