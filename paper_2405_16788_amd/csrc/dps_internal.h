@@ -87,6 +87,7 @@ __host__ __device__ inline float mul_rn(float a, float b) {
 // ---------------------------------------------------------------------------
 struct KernelParams {
     float eps;       // 0: unregularised
+    float ieps;      // 1/eps
     float ieps2;     // 1/eps^2
     float k3;        // 1/(4 pi eps^3)
     float k5;        // 1/(4 pi eps^5)
@@ -97,10 +98,12 @@ __host__ inline KernelParams make_kernel_params(float eps) {
     kp.eps = eps;
     if (eps > 0.0f) {
         double e = eps;
+        kp.ieps = (float)(1.0 / e);
         kp.ieps2 = (float)(1.0 / (e * e));
         kp.k3 = (float)(0.0795774715459476679 / (e * e * e));
         kp.k5 = (float)(0.0795774715459476679 / (e * e * e * e * e));
     } else {
+        kp.ieps = 0.0f;
         kp.ieps2 = 0.0f;
         kp.k3 = 0.0f;
         kp.k5 = 0.0f;
@@ -121,34 +124,32 @@ __device__ __forceinline__ float series_psi_t5(float u) {  // u = t^2
 }
 
 // r2 = |d|^2.  Returns false when the term is excluded (r = 0 with eps = 0).
-// With eps > 0 and r = 0 the finite series limits are used.
+// Common case first, without branches: rho = 1, psi = 3 (t >= 4.5 or eps = 0),
+// with the hardware reciprocal square root (1 ulp).  Inside the regularised
+// zone t < 4.5 (a minority of interactions) the factors are recomputed:
+// series below t = 0.5 (finite at r = 0), erf / exp above.
 __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &kappa, float &lambda) {
-    if (kp.eps > 0.0f) {
-        float u = r2 * kp.ieps2;
-        if (u < kSeriesT2) {
-            kappa = kp.k3 * series_rho_t3(u);
-            lambda = kp.k5 * series_psi_t5(u);
-            return true;
-        }
-        if (u < kFarT2) {
-            float ir = rsqrtf(r2);
-            float ir2 = ir * ir;
-            float t = sqrtf(u);
-            float e = expf(-u);
-            float rho = erff(t) - k2SqrtPi * t * e;
-            float psi = 3.0f * rho - k4SqrtPi * t * u * e;
-            float k = kInv4Pi * ir * ir2;
-            kappa = k * rho;
-            lambda = k * ir2 * psi;
-            return true;
-        }
-    } else if (!(r2 > 0.0f)) {
-        return false;
-    }
-    float ir = rsqrtf(r2);
-    float ir2 = ir * ir;
+    if (kp.eps == 0.0f && !(r2 > 0.0f)) return false;
+    const float ir = __builtin_amdgcn_rsqf(r2);
+    const float ir2 = ir * ir;
     kappa = kInv4Pi * ir * ir2;
     lambda = 3.0f * kappa * ir2;
+    if (kp.eps > 0.0f) {
+        const float u = r2 * kp.ieps2;
+        if (u < kFarT2) {
+            if (u < kSeriesT2) {
+                kappa = kp.k3 * series_rho_t3(u);
+                lambda = kp.k5 * series_psi_t5(u);
+            } else {
+                const float t = r2 * ir * kp.ieps;
+                const float e = expf(-u);
+                const float rho = erff(t) - k2SqrtPi * t * e;
+                const float psi = 3.0f * rho - k4SqrtPi * t * u * e;
+                kappa = kappa * rho;
+                lambda = kInv4Pi * ir * ir2 * ir2 * psi;
+            }
+        }
+    }
     return true;
 }
 

@@ -154,12 +154,12 @@ __global__ __launch_bounds__(kThreads) void k_query(
 #pragma unroll
                     for (int c = 0; c < CB; ++c) {
                         const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
-                        f[i][c] += kap * sd;
+                        f[i][c] = fmaf(kap, sd, f[i][c]);
                         if (GRAD) {
                             const float ls = lam * sd;
-                            g[i][c][0] += ls * dx - kap * D[3 * c];
-                            g[i][c][1] += ls * dy - kap * D[3 * c + 1];
-                            g[i][c][2] += ls * dz - kap * D[3 * c + 2];
+                            g[i][c][0] = fmaf(-kap, D[3 * c], fmaf(ls, dx, g[i][c][0]));
+                            g[i][c][1] = fmaf(-kap, D[3 * c + 1], fmaf(ls, dy, g[i][c][1]));
+                            g[i][c][2] = fmaf(-kap, D[3 * c + 2], fmaf(ls, dz, g[i][c][2]));
                         }
                     }
                 }
@@ -186,16 +186,16 @@ __global__ __launch_bounds__(kThreads) void k_query(
                                 const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
                                 const float ks = kap * sa;
                                 const float ls = lam * sa;
-                                const float G0 = ls * dx - kap * pr.anx;
-                                const float G1 = ls * dy - kap * pr.any;
-                                const float G2 = ls * dz - kap * pr.anz;
+                                const float G0 = fmaf(ls, dx, -kap * pr.anx);
+                                const float G1 = fmaf(ls, dy, -kap * pr.any);
+                                const float G2 = fmaf(ls, dz, -kap * pr.anz);
 #pragma unroll
                                 for (int c = 0; c < CB; ++c) {
-                                    f[i][c] += mu[c] * ks;
+                                    f[i][c] = fmaf(mu[c], ks, f[i][c]);
                                     if (GRAD) {
-                                        g[i][c][0] += mu[c] * G0;
-                                        g[i][c][1] += mu[c] * G1;
-                                        g[i][c][2] += mu[c] * G2;
+                                        g[i][c][0] = fmaf(mu[c], G0, g[i][c][0]);
+                                        g[i][c][1] = fmaf(mu[c], G1, g[i][c][1]);
+                                        g[i][c][2] = fmaf(mu[c], G2, g[i][c][2]);
                                     }
                                 }
                             }
@@ -284,12 +284,12 @@ __global__ __launch_bounds__(kThreads) void k_query1(
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
-                f[c] += kap * sd;
+                f[c] = fmaf(kap, sd, f[c]);
                 if (GRAD) {
                     const float ls = lam * sd;
-                    g[c][0] += ls * dx - kap * D[3 * c];
-                    g[c][1] += ls * dy - kap * D[3 * c + 1];
-                    g[c][2] += ls * dz - kap * D[3 * c + 2];
+                    g[c][0] = fmaf(-kap, D[3 * c], fmaf(ls, dx, g[c][0]));
+                    g[c][1] = fmaf(-kap, D[3 * c + 1], fmaf(ls, dy, g[c][1]));
+                    g[c][2] = fmaf(-kap, D[3 * c + 2], fmaf(ls, dz, g[c][2]));
                 }
             }
         }
@@ -310,16 +310,16 @@ __global__ __launch_bounds__(kThreads) void k_query1(
                             const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
                             const float ks = kap * sa;
                             const float ls = lam * sa;
-                            const float G0 = ls * dx - kap * pr.anx;
-                            const float G1 = ls * dy - kap * pr.any;
-                            const float G2 = ls * dz - kap * pr.anz;
+                            const float G0 = fmaf(ls, dx, -kap * pr.anx);
+                            const float G1 = fmaf(ls, dy, -kap * pr.any);
+                            const float G2 = fmaf(ls, dz, -kap * pr.anz);
 #pragma unroll
                             for (int c = 0; c < CB; ++c) {
-                                f[c] += mu[c] * ks;
+                                f[c] = fmaf(mu[c], ks, f[c]);
                                 if (GRAD) {
-                                    g[c][0] += mu[c] * G0;
-                                    g[c][1] += mu[c] * G1;
-                                    g[c][2] += mu[c] * G2;
+                                    g[c][0] = fmaf(mu[c], G0, g[c][0]);
+                                    g[c][1] = fmaf(mu[c], G1, g[c][1]);
+                                    g[c][2] = fmaf(mu[c], G2, g[c][2]);
                                 }
                             }
                         }
@@ -488,9 +488,9 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
                         acc[3 * c + 2] += wk * dz;
                     }
                     const float les = lam * (E0 * dx + E1 * dy + E2 * dz);
-                    ax[i] += les * dx - kap * E0;
-                    ay[i] += les * dy - kap * E1;
-                    az[i] += les * dz - kap * E2;
+                    ax[i] = fmaf(-kap, E0, fmaf(les, dx, ax[i]));
+                    ay[i] = fmaf(-kap, E1, fmaf(les, dy, ay[i]));
+                    az[i] = fmaf(-kap, E2, fmaf(les, dz, az[i]));
                 }
             }
             float red[3 * CB];
@@ -530,9 +530,9 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
                                 }
                                 const float les = lam * sa * wm;
                                 const float kw = kap * wm;
-                                ax[i] += les * dx - kw * pr.anx;
-                                ay[i] += les * dy - kw * pr.any;
-                                az[i] += les * dz - kw * pr.anz;
+                                ax[i] = fmaf(-kw, pr.anx, fmaf(les, dx, ax[i]));
+                                ay[i] = fmaf(-kw, pr.any, fmaf(les, dy, ay[i]));
+                                az[i] = fmaf(-kw, pr.anz, fmaf(les, dz, az[i]));
                             }
                         }
                     }
