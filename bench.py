@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--packet", type=str, default="auto",
-                    help="queries per lane 'query,adjoint' (e.g. 1,2) or 'auto' (autotuned)")
+                    help="launch shape 'query_k,adjoint_k[,flags]' (e.g. 2,4,3) or 'auto' (autotuned)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a 1 GiB device fill + copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -102,9 +102,11 @@ def time_storage(P, dev_in, storage, steps, warmup, packet):
         from paper_2405_16788_amd import autotune
         tuned = autotune.tune(tree, x, df, BETA, EPS, cache="", verbose=True)
     else:
-        kq, ka = (int(v) for v in packet.split(","))
-        P.dps_set_packet(tree, kq, ka)
-        tuned = {"query": kq, "adjoint": ka}
+        vals = [int(v) for v in packet.split(",")]
+        kq, ka = vals[0], vals[1]
+        flags = vals[2] if len(vals) > 2 else -1
+        P.dps_set_launch(tree, kq, ka, flags)
+        tuned = {"query": kq, "adjoint": ka, "flags": P.dps_get_launch(tree)["flags"]}
     f = torch.empty((Q, C), device="cuda")
     g = torch.empty((Q, C, 3), device="cuda")
     dx = torch.empty((Q, 3), device="cuda")
@@ -145,7 +147,7 @@ def time_storage(P, dev_in, storage, steps, warmup, packet):
     info = P.dps_tree_info(tree)
     P.dps_destroy(tree)
     return {"ms_per_step": total_ms / steps, "build_ms": build_ms, "kernel_ms": per,
-            "counts_total": csum, "tree": info, "packet": {"query": tuned["query"], "adjoint": tuned["adjoint"]}}
+            "counts_total": csum, "tree": info, "packet": {"query": tuned["query"], "adjoint": tuned["adjoint"], "flags": tuned["flags"]}}
 
 
 def cpu_baseline(np, p, n, A, attrs, x, df, seconds):

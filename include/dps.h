@@ -136,8 +136,10 @@ dps_status dps_query_counts(dps_tree t, const float *x, int64_t Q, float beta,
  *                        as dps_query.  Accumulates across calls.
  * dps_adjoint_finalize   dattrs [M][C] output dL/dmu in caller point order.
  * dps_adjoint            zero + accumulate + finalize.
- * All asynchronous.  Calls that mutate the tree (set_attributes, adjoint_*)
- * must be ordered by the caller against other calls on the same tree.
+ * All asynchronous and free of host synchronisation and memory set / copy
+ * nodes, so a training step (set_attributes, query, adjoint) can be captured
+ * in a hipGraph and replayed.  Calls that mutate the tree (set_attributes,
+ * adjoint_*) must be ordered by the caller against other calls on the same tree.
  */
 dps_status dps_adjoint_zero(dps_tree t, void *stream);
 dps_status dps_adjoint_accumulate(dps_tree t, const float *x, int64_t Q, float beta, float eps,
@@ -166,22 +168,37 @@ dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *
                          int64_t *n_points, int32_t *channels);
 
 /*
- * dps_set_packet -- launch shape of the traversal kernels: each 64-lane
- * wavefront walks the tree once for 64*k consecutive queries, lane l carrying
- * queries base + 64 i + l (i < k), so node fetches and, in the adjoint, the
- * wavefront sums and atomics are shared by 64*k queries (the packet queries
- * suggested in Sec. 6.3).  Results do not depend on the launch shape beyond
- * FP rounding order.
- *  query_k, adjoint_k  1, 2 or 4; 0 keeps the current value.  Large channel
- *                      blocks cap k so accumulators stay in registers.
- *  xcd_order           bit 0 (dps_query) / bit 1 (dps_adjoint_accumulate): the
- *                      workgroups that run on one of the 8 XCDs take a
- *                      contiguous eighth of the queries, so each XCD's L2
- *                      serves one region of a coherently ordered query set;
- *                      bit clear: plain order.  -1 keeps the current value.
- * Host-only, takes effect for later launches.
+ * dps_set_launch -- launch shape of the traversal kernels (results do not
+ * depend on it beyond floating-point summation order).
+ *  query_k, adjoint_k  queries per lane, 1, 2 or 4 (0 keeps): a 64-lane
+ *      wavefront walks the tree once for 64*k consecutive queries, lane l
+ *      carrying queries base + 64 i + l, so node fetches and, in the adjoint,
+ *      the wavefront sums and atomics are shared by 64*k queries (the packet
+ *      queries suggested in Sec. 6.3).  Large channel blocks cap k so the
+ *      accumulators stay in registers.
+ *  flags  (-1 keeps) bit 0 / bit 1: for dps_query / the adjoint, the
+ *      workgroups that run on one of the 8 XCDs take a contiguous eighth of
+ *      the queries, so each XCD's L2 serves one region of a coherently ordered
+ *      query set; bit 2 / bit 3: persistent launch -- a grid of resident
+ *      workgroups pulls 64*k-query tiles from per-XCD counters (own eighth
+ *      first, then the others), balancing uneven batches inside one launch.
+ * Host-only; applies to later launches.  The defaults are k = 2 / 4 with the
+ * XCD-contiguous order.
  */
-dps_status dps_set_packet(dps_tree t, int32_t query_k, int32_t adjoint_k, int32_t xcd_order);
+dps_status dps_set_launch(dps_tree t, int32_t query_k, int32_t adjoint_k, int32_t flags);
+dps_status dps_get_launch(dps_tree t, int32_t *query_k, int32_t *adjoint_k, int32_t *flags);
+
+/*
+ * dps_query_channels / dps_adjoint_accumulate_channels -- as dps_query /
+ * dps_adjoint_accumulate for the channel range [c_begin, c_begin+n_channels)
+ * only (e.g. the geometry channel alone for shadow rays).  f, grad and df rows
+ * hold n_channels entries.  With BF16 storage c_begin must be even.
+ */
+dps_status dps_query_channels(dps_tree t, const float *x, int64_t Q, float beta, float eps, int32_t c_begin,
+                              int32_t n_channels, float *f, float *grad, void *stream);
+dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q, float beta, float eps,
+                                           int32_t c_begin, int32_t n_channels, const float *df, float *dx,
+                                           void *stream);
 
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A

@@ -1,9 +1,9 @@
 """Autotuner for the traversal launch shape: queries per lane (1 / 2 / 4) and
-the XCD-contiguous workgroup order (off / on).
+the schedule (plain grid, XCD-contiguous grid, persistent tile queue).
 
 Times dps_query and dps_adjoint_accumulate for each shape on a slice of the
-caller's own queries (HIP events on the current stream), keeps the fastest,
-and applies it with dps_set_packet.  Results are cached in a JSON file
+caller's own queries (HIP events on the current stream), keeps the fastest
+per kernel, and applies it with dps_set_launch.  Results are cached in a JSON file
 keyed by the workload shape, so later runs skip the sweep.
 """
 from __future__ import annotations
@@ -14,6 +14,9 @@ import os
 from . import binding as B
 
 PACKETS = (1, 2, 4)
+# schedule name -> (flag bits for dps_query, flag bits for the adjoint)
+SCHEDULES = {"grid": (0, 0), "xcd": (B.LAUNCH_XCD_QUERY, B.LAUNCH_XCD_ADJOINT),
+             "persistent": (B.LAUNCH_PERSISTENT_QUERY, B.LAUNCH_PERSISTENT_ADJOINT)}
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dps_autotune.json")
 
 
@@ -48,8 +51,7 @@ def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=Fal
             table = {}
     if key in table:
         best = table[key]
-        B.dps_set_packet(tree, best["query"], best["adjoint"])
-        B.dps_set_packet(tree, 0, 0, best.get("xcd_query", 0) | (best.get("xcd_adjoint", 0) << 1))
+        B.dps_set_launch(tree, best["query"], best["adjoint"], best["flags"])
         return best
     n = min(x.shape[0], sample)
     # a contiguous slice keeps the spatial coherence of the caller's layout
@@ -60,22 +62,23 @@ def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=Fal
     g = torch.empty((n, tree.C, 3), device=x.device)
     dx = torch.empty((n, 3), device=x.device)
     ms = {"query": {}, "adjoint": {}}
-    for xo in (0, 1):
+    for mode, (qbit, abit) in SCHEDULES.items():
         for k in PACKETS:
-            B.dps_set_packet(tree, k, k, 3 * xo)
-            ms["query"][(k, xo)] = _time(lambda: B.dps_query(tree, xs, beta, eps, f_out=f, g_out=g), reps)
+            B.dps_set_launch(tree, k, k, qbit | abit)
+            ms["query"][(k, mode)] = _time(lambda: B.dps_query(tree, xs, beta, eps, f_out=f, g_out=g), reps)
             B.dps_adjoint_zero(tree)
-            ms["adjoint"][(k, xo)] = _time(
+            ms["adjoint"][(k, mode)] = _time(
                 lambda: B.dps_adjoint_accumulate(tree, xs, beta, eps, dfs, dx_out=dx), reps)
             if verbose:
-                print(f"[autotune] k={k} xcd_order={xo}: query {ms['query'][(k, xo)]:.3f} ms, "
-                      f"adjoint {ms['adjoint'][(k, xo)]:.3f} ms", flush=True)
+                print(f"[autotune] k={k} {mode}: query {ms['query'][(k, mode)]:.3f} ms, "
+                      f"adjoint {ms['adjoint'][(k, mode)]:.3f} ms", flush=True)
     B.dps_adjoint_zero(tree)
     bq = min(ms["query"], key=ms["query"].get)
     ba = min(ms["adjoint"], key=ms["adjoint"].get)
-    best = {"query": bq[0], "adjoint": ba[0], "xcd_query": bq[1], "xcd_adjoint": ba[1],
-            "ms": {p: {f"k{k}_x{x}": v for (k, x), v in d.items()} for p, d in ms.items()}}
-    B.dps_set_packet(tree, best["query"], best["adjoint"], best["xcd_query"] | (best["xcd_adjoint"] << 1))
+    flags = SCHEDULES[bq[1]][0] | SCHEDULES[ba[1]][1]
+    best = {"query": bq[0], "adjoint": ba[0], "query_schedule": bq[1], "adjoint_schedule": ba[1], "flags": flags,
+            "ms": {p: {f"k{k}_{m}": v for (k, m), v in d.items()} for p, d in ms.items()}}
+    B.dps_set_launch(tree, best["query"], best["adjoint"], flags)
     if cache:
         try:
             os.makedirs(os.path.dirname(cache), exist_ok=True)

@@ -21,7 +21,8 @@ STORAGE = {"fp32": DPS_STORE_FP32, "bf16": DPS_STORE_BF16}
 EXPORTED = (
     "dps_build", "dps_set_attributes", "dps_query", "dps_query_counts", "dps_adjoint_zero",
     "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
-    "dps_tree_info", "dps_set_packet", "dps_check", "dps_destroy", "dps_status_string", "dps_last_error",
+    "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_query_channels",
+    "dps_adjoint_accumulate_channels", "dps_check", "dps_destroy", "dps_status_string", "dps_last_error",
 )
 
 _lib = None
@@ -53,7 +54,10 @@ def load():
         "dps_query_counts": [vp, vp, i64, f32, vp, vp],
         "dps_adjoint_zero": [vp, vp],
         "dps_check": [vp, vp],
-        "dps_set_packet": [vp, i32, i32, i32],
+        "dps_set_launch": [vp, i32, i32, i32],
+        "dps_get_launch": [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)],
+        "dps_query_channels": [vp, vp, i64, f32, f32, i32, i32, vp, vp, vp],
+        "dps_adjoint_accumulate_channels": [vp, vp, i64, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
         "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
@@ -239,10 +243,49 @@ def dps_export_tree(tree: Tree) -> dict:
     return {"codes": codes, "perm": perm, "nodes": nodes, "geom": geom, "moments": mom}
 
 
-def dps_set_packet(tree: Tree, query_k: int = 0, adjoint_k: int = 0, xcd_order: int = -1):
+LAUNCH_XCD_QUERY, LAUNCH_XCD_ADJOINT, LAUNCH_PERSISTENT_QUERY, LAUNCH_PERSISTENT_ADJOINT = 1, 2, 4, 8
+
+
+def dps_set_launch(tree: Tree, query_k: int = 0, adjoint_k: int = 0, flags: int = -1):
     """Queries per lane of the traversal kernels (1, 2, 4; 0 keeps) and the
-    XCD-contiguous workgroup order (bit 0 query, bit 1 adjoint; -1 keeps)."""
-    _check(load().dps_set_packet(tree.handle, int(query_k), int(adjoint_k), int(xcd_order)), "dps_set_packet")
+    launch flags (LAUNCH_* bits; -1 keeps)."""
+    _check(load().dps_set_launch(tree.handle, int(query_k), int(adjoint_k), int(flags)), "dps_set_launch")
+
+
+def dps_get_launch(tree: Tree):
+    a, b, c = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    _check(load().dps_get_launch(tree.handle, ct.byref(a), ct.byref(b), ct.byref(c)), "dps_get_launch")
+    return {"query": a.value, "adjoint": b.value, "flags": c.value}
+
+
+def dps_query_channels(tree: Tree, x, beta: float, eps: float, c_begin: int, n_channels: int,
+                       grad: bool = True, f_out=None, g_out=None):
+    """Channels [c_begin, c_begin+n_channels) only; returns (f[Q,n], grad[Q,n,3] or None)."""
+    import torch
+    Q = x.shape[0]
+    f = f_out if f_out is not None else torch.empty((Q, n_channels), device=tree.device, dtype=torch.float32)
+    g = g_out if g_out is not None else (
+        torch.empty((Q, n_channels, 3), device=tree.device, dtype=torch.float32) if grad else None)
+    _check(load().dps_query_channels(tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q,
+                                     float(beta), float(eps), int(c_begin), int(n_channels),
+                                     _ptr(f, torch.float32, (Q, n_channels), tree.device, "f"),
+                                     _ptr(g, torch.float32, (Q, n_channels, 3), tree.device, "grad"),
+                                     _stream(tree.device)), "dps_query_channels")
+    return f, g
+
+
+def dps_adjoint_accumulate_channels(tree: Tree, x, beta: float, eps: float, c_begin: int, n_channels: int,
+                                    df, want_dx: bool = True, dx_out=None):
+    """Stage 1 for a channel range; df rows hold n_channels entries."""
+    import torch
+    Q = x.shape[0]
+    dx = dx_out if dx_out is not None else (
+        torch.empty((Q, 3), device=tree.device, dtype=torch.float32) if want_dx else None)
+    _check(load().dps_adjoint_accumulate_channels(
+        tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q, float(beta), float(eps), int(c_begin),
+        int(n_channels), _ptr(df, torch.float32, (Q, n_channels), tree.device, "df"),
+        _ptr(dx, torch.float32, (Q, 3), tree.device, "dx"), _stream(tree.device)), "dps_adjoint_accumulate_channels")
+    return dx
 
 
 def dps_check(tree: Tree):

@@ -109,7 +109,7 @@ dps_status dps_build(const float *p, const float *n, const float *A, const float
     t->wide_top = M >= kWideTopPoints;
     t->packet_query = kDefaultPacketQuery;
     t->packet_adjoint = kDefaultPacketAdjoint;
-    t->xcd_remap = kDefaultXcdRemap;
+    t->launch_flags = kDefaultLaunchFlags;
     const bool bf = storage == DPS_STORE_BF16;
     t->mom_stride = bf ? ((3 * C + 1) & ~1) : 3 * C;
     t->attr_stride = bf ? ((C + 1) & ~1) : C;
@@ -128,6 +128,7 @@ dps_status dps_build(const float *p, const float *n, const float *A, const float
         if (st == DPS_OK) st = tree_alloc(t, &t->S, (size_t)t->N * 3 * C);
         if (st == DPS_OK) st = tree_alloc(t, &t->P, (size_t)M * C);
         if (st == DPS_OK) st = tree_alloc(t, &t->err, 1);
+        if (st == DPS_OK) st = tree_alloc(t, &t->ctr, 16);
         if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->err, 0, sizeof(uint32_t), s), "zero err");
         if (st == DPS_OK) st = refit_moments(t, attrs, s);
         if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->G, 0, (size_t)t->N * 3 * C * sizeof(double), s), "zero G");
@@ -184,7 +185,32 @@ dps_status dps_query(dps_tree t, const float *x, int64_t Q, float beta, float ep
     if (Q == 0) return DPS_OK;
     if (!x || !f) return invalid("dps_query: NULL x or f");
     DeviceGuard dg(t->device);
-    return launch_query(t, x, Q, beta, eps, f, grad, (hipStream_t)stream);
+    return launch_query(t, x, Q, beta, eps, 0, t->C, f, grad, (hipStream_t)stream);
+}
+
+static dps_status check_channels(dps_tree t, int32_t c_begin, int32_t n_channels, const char *fn) {
+    if (c_begin < 0 || n_channels < 1 || (int64_t)c_begin + n_channels > t->C) {
+        set_error("%s: channel range [%d, %d) outside [0, %d)", fn, c_begin, c_begin + n_channels, t->C);
+        return DPS_ERR_INVALID;
+    }
+    if (t->storage == DPS_STORE_BF16 && (c_begin & 1)) {
+        set_error("%s: with BF16 storage the first channel must be even", fn);
+        return DPS_ERR_INVALID;
+    }
+    return DPS_OK;
+}
+
+dps_status dps_query_channels(dps_tree t, const float *x, int64_t Q, float beta, float eps, int32_t c_begin,
+                              int32_t n_channels, float *f, float *grad, void *stream) {
+    dps_status st = check_tree(t, "dps_query_channels");
+    if (st != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_query_channels")) != DPS_OK) return st;
+    if ((st = check_channels(t, c_begin, n_channels, "dps_query_channels")) != DPS_OK) return st;
+    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_query_channels: Q out of range");
+    if (Q == 0) return DPS_OK;
+    if (!x || !f) return invalid("dps_query_channels: NULL x or f");
+    DeviceGuard dg(t->device);
+    return launch_query(t, x, Q, beta, eps, c_begin, n_channels, f, grad, (hipStream_t)stream);
 }
 
 dps_status dps_query_counts(dps_tree t, const float *x, int64_t Q, float beta, int32_t *counts,
@@ -203,10 +229,7 @@ dps_status dps_adjoint_zero(dps_tree t, void *stream) {
     dps_status st = check_tree(t, "dps_adjoint_zero");
     if (st != DPS_OK) return st;
     DeviceGuard dg(t->device);
-    hipStream_t s = (hipStream_t)stream;
-    st = hip_status(hipMemsetAsync(t->G, 0, (size_t)t->N * 3 * t->C * sizeof(double), s), "zero G");
-    if (st != DPS_OK) return st;
-    return hip_status(hipMemsetAsync(t->P, 0, (size_t)t->M * t->C * sizeof(double), s), "zero P");
+    return launch_zero(t, (hipStream_t)stream);  // fill kernels: safe inside captured graphs
 }
 
 dps_status dps_adjoint_accumulate(dps_tree t, const float *x, int64_t Q, float beta, float eps,
@@ -218,7 +241,21 @@ dps_status dps_adjoint_accumulate(dps_tree t, const float *x, int64_t Q, float b
     if (Q == 0) return DPS_OK;
     if (!x || !df) return invalid("dps_adjoint_accumulate: NULL x or df");
     DeviceGuard dg(t->device);
-    return launch_adjoint(t, x, Q, beta, eps, df, dx, (hipStream_t)stream);
+    return launch_adjoint(t, x, Q, beta, eps, 0, t->C, df, dx, (hipStream_t)stream);
+}
+
+dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q, float beta, float eps,
+                                           int32_t c_begin, int32_t n_channels, const float *df, float *dx,
+                                           void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint_accumulate_channels");
+    if (st != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate_channels")) != DPS_OK) return st;
+    if ((st = check_channels(t, c_begin, n_channels, "dps_adjoint_accumulate_channels")) != DPS_OK) return st;
+    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint_accumulate_channels: Q out of range");
+    if (Q == 0) return DPS_OK;
+    if (!x || !df) return invalid("dps_adjoint_accumulate_channels: NULL x or df");
+    DeviceGuard dg(t->device);
+    return launch_adjoint(t, x, Q, beta, eps, c_begin, n_channels, df, dx, (hipStream_t)stream);
 }
 
 dps_status dps_adjoint_finalize(dps_tree t, float *dattrs, void *stream) {
@@ -266,15 +303,24 @@ dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *
     return DPS_OK;
 }
 
-dps_status dps_set_packet(dps_tree t, int32_t query_k, int32_t adjoint_k, int32_t xcd_order) {
-    dps_status st = check_tree(t, "dps_set_packet");
+dps_status dps_set_launch(dps_tree t, int32_t query_k, int32_t adjoint_k, int32_t flags) {
+    dps_status st = check_tree(t, "dps_set_launch");
     if (st != DPS_OK) return st;
     auto ok = [](int32_t k) { return k == 0 || k == 1 || k == 2 || k == 4; };
-    if (!ok(query_k) || !ok(adjoint_k)) return invalid("dps_set_packet: packet sizes must be 0 (keep), 1, 2 or 4");
-    if (xcd_order < -1 || xcd_order > 3) return invalid("dps_set_packet: xcd_order must be -1 (keep) or a 2-bit mask");
+    if (!ok(query_k) || !ok(adjoint_k)) return invalid("dps_set_launch: packet sizes must be 0 (keep), 1, 2 or 4");
+    if (flags < -1 || flags > 15) return invalid("dps_set_launch: flags must be -1 (keep) or a 4-bit mask");
     if (query_k) t->packet_query = query_k;
     if (adjoint_k) t->packet_adjoint = adjoint_k;
-    if (xcd_order >= 0) t->xcd_remap = xcd_order;
+    if (flags >= 0) t->launch_flags = flags;
+    return DPS_OK;
+}
+
+dps_status dps_get_launch(dps_tree t, int32_t *query_k, int32_t *adjoint_k, int32_t *flags) {
+    dps_status st = check_tree(t, "dps_get_launch");
+    if (st != DPS_OK) return st;
+    if (query_k) *query_k = t->packet_query;
+    if (adjoint_k) *adjoint_k = t->packet_adjoint;
+    if (flags) *flags = t->launch_flags;
     return DPS_OK;
 }
 

@@ -20,9 +20,13 @@ constexpr uint32_t kLeafFlag = 0x100u;   // NodeRec::meta bit: node is a leaf
 constexpr int kLevels = DPS_LEVELS;      // 21 levels below the root
 constexpr int kTopLevels = 3;            // "top-level" nodes: depth <= 3
 constexpr int64_t kWideTopPoints = 4194304;  // FP64 top-level moment sums from this size on
-constexpr int kDefaultPacketQuery = 1;     // queries per lane (tuned: dps_set_packet)
+constexpr int kDefaultPacketQuery = 2;     // queries per lane (tuned: dps_set_launch)
 constexpr int kDefaultPacketAdjoint = 4;
-constexpr int kDefaultXcdRemap = 0;
+constexpr int kFlagXcdQuery = 1;          // launch flags (dps_set_launch)
+constexpr int kFlagXcdAdjoint = 2;
+constexpr int kFlagPersistentQuery = 4;
+constexpr int kFlagPersistentAdjoint = 8;
+constexpr int kDefaultLaunchFlags = kFlagXcdQuery | kFlagXcdAdjoint;
 
 struct alignas(32) NodeRec {
     float cx, cy, cz, r2;  // FP32 centroid and squared radius

@@ -67,10 +67,21 @@ __device__ __forceinline__ void load_attrs(const void *__restrict__ attr, int as
     }
 }
 
-// Workgroups are handed to the 8 XCDs round-robin.  With remapping, the
-// workgroups on one XCD take a contiguous eighth of the work, so each XCD's L2
-// serves one spatial region of the (tile-ordered) queries.  Returns the
-// logical block index, or -1 for padding blocks.
+// ---------------------------------------------------------------------------
+// launch shapes
+//
+// Grid launch: one workgroup per 4 wavefronts of work.  Workgroups are handed
+// to the 8 XCDs round-robin; with `remap` the workgroups on one XCD take a
+// contiguous eighth of the work, so each XCD's L2 serves one spatial region of
+// a coherently ordered query set.
+//
+// Persistent launch: a grid sized to the resident wavefronts; each wavefront
+// pulls 64*K-query tiles from 8 counters, one per contiguous eighth of the
+// tiles, starting with the partition of its own XCD and then taking tiles from
+// the others, so uneven batches (views of different sizes, shadow rays)
+// balance inside one launch.  Every wavefront leaves once all partitions are
+// exhausted.
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t remap_block(int remap) {
     const int64_t b = blockIdx.x;
     if (!remap) return b;
@@ -80,22 +91,158 @@ __device__ __forceinline__ int64_t remap_block(int remap) {
     return l < nb ? l : -1;
 }
 
+__device__ __forceinline__ int xcc_id() {
+    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u);  // HW_REG_XCC_ID[3:0]
+}
+
+__device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t ntiles, int &part) {
+    const int64_t per = (ntiles + 7) / 8;
+    for (int a = 0; a < 8; ++a) {
+        const int pi = (part + a) & 7;
+        uint32_t got = 0;
+        if ((threadIdx.x & 63) == 0) got = atomicAdd(&ctr[pi], 1u);
+        got = __builtin_amdgcn_readfirstlane(got);
+        const int64_t tile = (int64_t)pi * per + got;
+        if ((int64_t)got < per && tile < ntiles) {
+            part = pi;
+            return tile;
+        }
+    }
+    return -1;
+}
+
+// Shared parameters of the traversal bodies.  f / grad / df rows have `ldo`
+// channels and tree channel c0 sits in column co of them (channel subsets).
+#define DPS_TRAV_PARAMS                                                                             \
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts,                           \
+        const void *__restrict__ mom, const void *__restrict__ attr, int ms, int as,               \
+        const float *__restrict__ x, int64_t Q, float b2, KernelParams kp, int c0, int ldo, int co, \
+        uint32_t limit, uint32_t *__restrict__ err
+#define DPS_TRAV_ARGS nodes, pts, mom, attr, ms, as, x, Q, b2, kp, c0, ldo, co, limit, err
+
 // ---------------------------------------------------------------------------
-// primal query: f[q][c0..c0+CB) and optionally grad[q][c0..c0+CB)[3].
-// A wavefront owns 64*K consecutive queries; lane l carries queries
-// base + 64 i + l (i < K), so node fetches, decisions' ballots and loop
-// control are shared by 64*K queries (packet traversal).
+// primal query, one query per lane (register-lean).  Software-pipelined: the
+// next node is known right after the ballots, so its record and moments are
+// fetched before the far-field / leaf work of the current node.
+// ---------------------------------------------------------------------------
+template <int CB, bool BF16, bool GRAD>
+__device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *__restrict__ fout,
+                                            float *__restrict__ gout) {
+    const bool valid = q < Q;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    if (valid) {
+        px = x[3 * q];
+        py = x[3 * q + 1];
+        pz = x[3 * q + 2];
+    }
+    float f[CB], g[CB][3];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        f[c] = 0.0f;
+        g[c][0] = g[c][1] = g[c][2] = 0.0f;
+    }
+    uint32_t bits = valid ? 1u : 0u;
+    uint32_t t = 0;
+    NodeRec nd = nodes[0];
+    float D[3 * CB];
+    load_moments<CB, BF16>(mom, ms, 0, c0, D);
+    uint32_t steps = 0;
+    for (;;) {
+        if (++steps > limit) {  // a well-formed tree is walked in at most N steps
+            if ((threadIdx.x & 63) == 0) atomicOr(err, 1u);
+            break;
+        }
+        const uint32_t lvl = nd.meta & 0xffu;
+        const bool leaf = (nd.meta & kLeafFlag) != 0;
+        const bool in = (bits >> lvl) & 1u;
+        const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
+        const bool far = in && (s > mul_rn(b2, nd.r2));
+        const bool open = in && !far;
+        const bool any_far = __ballot(far) != 0;
+        const bool any_open = __ballot(open) != 0;
+        const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
+        const uint32_t pf = next == kEnd ? t : next;
+        const NodeRec nn = nodes[pf];
+        float Dn[3 * CB];
+        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+        if (any_far && far) {
+            float kap, lam;
+            radial(s, kp, kap, lam);
+            const float dx = nd.cx - px, dy = nd.cy - py, dz = nd.cz - pz;
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
+                f[c] = fmaf(kap, sd, f[c]);
+                if (GRAD) {
+                    const float ls = lam * sd;
+                    g[c][0] = fmaf(-kap, D[3 * c], fmaf(ls, dx, g[c][0]));
+                    g[c][1] = fmaf(-kap, D[3 * c + 1], fmaf(ls, dy, g[c][1]));
+                    g[c][2] = fmaf(-kap, D[3 * c + 2], fmaf(ls, dz, g[c][2]));
+                }
+            }
+        }
+        if (any_open) {
+            if (!leaf) {
+                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
+            } else {
+                const uint32_t je = nd.first + nd.count;
+                for (uint32_t j = nd.first; j < je; ++j) {
+                    const PointRec pr = pts[j];
+                    float mu[CB];
+                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                    if (open) {
+                        const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        float kap, lam;
+                        if (radial(r2, kp, kap, lam)) {
+                            const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                            const float ks = kap * sa;
+                            const float ls = lam * sa;
+                            const float G0 = fmaf(ls, dx, -kap * pr.anx);
+                            const float G1 = fmaf(ls, dy, -kap * pr.any);
+                            const float G2 = fmaf(ls, dz, -kap * pr.anz);
+#pragma unroll
+                            for (int c = 0; c < CB; ++c) {
+                                f[c] = fmaf(mu[c], ks, f[c]);
+                                if (GRAD) {
+                                    g[c][0] = fmaf(mu[c], G0, g[c][0]);
+                                    g[c][1] = fmaf(mu[c], G1, g[c][1]);
+                                    g[c][2] = fmaf(mu[c], G2, g[c][2]);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (next == kEnd) break;
+        t = next;
+        nd = nn;
+#pragma unroll
+        for (int v = 0; v < 3 * CB; ++v) D[v] = Dn[v];
+    }
+    if (valid) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int64_t o = q * ldo + co + c;
+            fout[o] = f[c];
+            if (GRAD) {
+                gout[3 * o] = g[c][0];
+                gout[3 * o + 1] = g[c][1];
+                gout[3 * o + 2] = g[c][2];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// primal query, K queries per lane: the wavefront owns 64*K consecutive
+// queries, lane l carrying queries q0 + 64 i (i < K), so node fetches, ballots
+// and loop control are shared by 64*K queries (packet traversal).
 // ---------------------------------------------------------------------------
 template <int CB, bool BF16, bool GRAD, int K>
-__global__ __launch_bounds__(kThreads) void k_query(
-    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
-    const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
-    float b2, KernelParams kp, int c0, float *__restrict__ fout, float *__restrict__ gout,
-    uint32_t limit, uint32_t *__restrict__ err, int xcd_remap) {
-    const int64_t blk = remap_block(xcd_remap);
-    if (blk < 0) return;
-    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
-    const int64_t q0 = wave * 64 * K + (threadIdx.x & 63);
+__device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *__restrict__ fout,
+                                            float *__restrict__ gout) {
     float px[K], py[K], pz[K];
     uint32_t bits[K];
     float f[K][CB], g[K][CB][3];
@@ -216,133 +363,44 @@ __global__ __launch_bounds__(kThreads) void k_query(
         if (q < Q) {
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
-                fout[q * C + c0 + c] = f[i][c];
+                const int64_t o = q * ldo + co + c;
+                fout[o] = f[i][c];
                 if (GRAD) {
-                    gout[(q * C + c0 + c) * 3] = g[i][c][0];
-                    gout[(q * C + c0 + c) * 3 + 1] = g[i][c][1];
-                    gout[(q * C + c0 + c) * 3 + 2] = g[i][c][2];
+                    gout[3 * o] = g[i][c][0];
+                    gout[3 * o + 1] = g[i][c][1];
+                    gout[3 * o + 2] = g[i][c][2];
                 }
             }
         }
     }
 }
 
-// single query per lane (the register-lean form of k_query for K = 1).
-// Software-pipelined: the next node is known right after the ballots, so its
-// record and moments are fetched before the far-field / leaf work of the
-// current node, hiding the scalar-load latency behind that work.
-template <int CB, bool BF16, bool GRAD>
-__global__ __launch_bounds__(kThreads) void k_query1(
-    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
-    const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
-    float b2, KernelParams kp, int c0, float *__restrict__ fout, float *__restrict__ gout,
-    uint32_t limit, uint32_t *__restrict__ err, int xcd_remap) {
+template <int CB, bool BF16, bool GRAD, int K>
+__device__ __forceinline__ void query_body(int64_t q0, DPS_TRAV_PARAMS, float *__restrict__ fout,
+                                           float *__restrict__ gout) {
+    if constexpr (K == 1) query1_body<CB, BF16, GRAD>(q0, DPS_TRAV_ARGS, fout, gout);
+    else queryk_body<CB, BF16, GRAD, K>(q0, DPS_TRAV_ARGS, fout, gout);
+}
+
+template <int CB, bool BF16, bool GRAD, int K>
+__global__ __launch_bounds__(kThreads) void k_query(DPS_TRAV_PARAMS, float *__restrict__ fout,
+                                                    float *__restrict__ gout, int xcd_remap) {
     const int64_t blk = remap_block(xcd_remap);
     if (blk < 0) return;
-    const int64_t q = blk * blockDim.x + threadIdx.x;
-    const bool valid = q < Q;
-    float px = 0.0f, py = 0.0f, pz = 0.0f;
-    if (valid) {
-        px = x[3 * q];
-        py = x[3 * q + 1];
-        pz = x[3 * q + 2];
-    }
-    float f[CB], g[CB][3];
-#pragma unroll
-    for (int c = 0; c < CB; ++c) {
-        f[c] = 0.0f;
-        g[c][0] = g[c][1] = g[c][2] = 0.0f;
-    }
-    uint32_t bits = valid ? 1u : 0u;
-    uint32_t t = 0;
-    NodeRec nd = nodes[0];
-    float D[3 * CB];
-    load_moments<CB, BF16>(mom, ms, 0, c0, D);
-    uint32_t steps = 0;
+    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
+    query_body<CB, BF16, GRAD, K>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, fout, gout);
+}
+
+template <int CB, bool BF16, bool GRAD, int K>
+__global__ __launch_bounds__(kThreads) void k_query_persistent(DPS_TRAV_PARAMS, float *__restrict__ fout,
+                                                               float *__restrict__ gout,
+                                                               uint32_t *__restrict__ ctr) {
+    const int64_t ntiles = (Q + 64 * K - 1) / (64 * K);
+    int part = xcc_id();
     for (;;) {
-        if (++steps > limit) {  // a well-formed tree is walked in at most N steps
-            if ((threadIdx.x & 63) == 0) atomicOr(err, 1u);
-            break;
-        }
-        const uint32_t lvl = nd.meta & 0xffu;
-        const bool leaf = (nd.meta & kLeafFlag) != 0;
-        const bool in = (bits >> lvl) & 1u;
-        const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
-        const bool far = in && (s > mul_rn(b2, nd.r2));
-        const bool open = in && !far;
-        const bool any_far = __ballot(far) != 0;
-        const bool any_open = __ballot(open) != 0;
-        const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
-        const uint32_t pf = next == kEnd ? t : next;
-        const NodeRec nn = nodes[pf];
-        float Dn[3 * CB];
-        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
-        if (any_far && far) {
-            float kap, lam;
-            radial(s, kp, kap, lam);
-            const float dx = nd.cx - px, dy = nd.cy - py, dz = nd.cz - pz;
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
-                f[c] = fmaf(kap, sd, f[c]);
-                if (GRAD) {
-                    const float ls = lam * sd;
-                    g[c][0] = fmaf(-kap, D[3 * c], fmaf(ls, dx, g[c][0]));
-                    g[c][1] = fmaf(-kap, D[3 * c + 1], fmaf(ls, dy, g[c][1]));
-                    g[c][2] = fmaf(-kap, D[3 * c + 2], fmaf(ls, dz, g[c][2]));
-                }
-            }
-        }
-        if (any_open) {
-            if (!leaf) {
-                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
-            } else {
-                const uint32_t je = nd.first + nd.count;
-                for (uint32_t j = nd.first; j < je; ++j) {
-                    const PointRec pr = pts[j];
-                    float mu[CB];
-                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
-                    if (open) {
-                        const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
-                        const float r2 = dx * dx + dy * dy + dz * dz;
-                        float kap, lam;
-                        if (radial(r2, kp, kap, lam)) {
-                            const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
-                            const float ks = kap * sa;
-                            const float ls = lam * sa;
-                            const float G0 = fmaf(ls, dx, -kap * pr.anx);
-                            const float G1 = fmaf(ls, dy, -kap * pr.any);
-                            const float G2 = fmaf(ls, dz, -kap * pr.anz);
-#pragma unroll
-                            for (int c = 0; c < CB; ++c) {
-                                f[c] = fmaf(mu[c], ks, f[c]);
-                                if (GRAD) {
-                                    g[c][0] = fmaf(mu[c], G0, g[c][0]);
-                                    g[c][1] = fmaf(mu[c], G1, g[c][1]);
-                                    g[c][2] = fmaf(mu[c], G2, g[c][2]);
-                                }
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        if (next == kEnd) break;
-        t = next;
-        nd = nn;
-#pragma unroll
-        for (int v = 0; v < 3 * CB; ++v) D[v] = Dn[v];
-    }
-    if (valid) {
-#pragma unroll
-        for (int c = 0; c < CB; ++c) {
-            fout[q * C + c0 + c] = f[c];
-            if (GRAD) {
-                gout[(q * C + c0 + c) * 3] = g[c][0];
-                gout[(q * C + c0 + c) * 3 + 1] = g[c][1];
-                gout[(q * C + c0 + c) * 3 + 2] = g[c][2];
-            }
-        }
+        const int64_t tile = next_tile(ctr, ntiles, part);
+        if (tile < 0) break;
+        query_body<CB, BF16, GRAD, K>(tile * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, fout, gout);
     }
 }
 
@@ -397,9 +455,6 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
     }
 }
 
-// ---------------------------------------------------------------------------
-// adjoint stage 1: node accumulators G[N][C][3], point accumulators P[M][C], dx
-// ---------------------------------------------------------------------------
 template <int N_>
 __device__ __forceinline__ float pick_lane(const float (&v)[N_], int lane) {
     float r = v[0];
@@ -408,18 +463,15 @@ __device__ __forceinline__ float pick_lane(const float (&v)[N_], int lane) {
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// adjoint stage 1 (Algorithm 1, AdjointQuery): node accumulators G[N][C][3]
+// (eq. farfield_gradient), point accumulators P[M][C], dL/dx per query
+// ---------------------------------------------------------------------------
 template <int CB, bool BF16, int K>
-__global__ __launch_bounds__(kThreads) void k_adjoint(
-    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
-    const void *__restrict__ attr, int C, int ms, int as, const float *__restrict__ x, int64_t Q,
-    float b2, KernelParams kp, int c0, const float *__restrict__ df, double *__restrict__ G,
-    double *__restrict__ P, float *__restrict__ dxout, int dx_mode, uint32_t limit,
-    uint32_t *__restrict__ err, int xcd_remap) {
+__device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C, const float *__restrict__ df,
+                                             double *__restrict__ G, double *__restrict__ P,
+                                             float *__restrict__ dxout, int dx_mode) {
     const int lane = lane_id();
-    const int64_t blk = remap_block(xcd_remap);
-    if (blk < 0) return;
-    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
-    const int64_t q0 = wave * 64 * K + lane;
     float px[K], py[K], pz[K], w[K][CB], ax[K], ay[K], az[K];
     uint32_t bits[K];
 #pragma unroll
@@ -432,7 +484,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
         bits[i] = valid ? 1u : 0u;
         ax[i] = ay[i] = az[i] = 0.0f;
 #pragma unroll
-        for (int c = 0; c < CB; ++c) w[i][c] = valid ? df[q * C + c0 + c] : 0.0f;
+        for (int c = 0; c < CB; ++c) w[i][c] = valid ? df[q * ldo + co + c] : 0.0f;
     }
     uint32_t t = 0;
     NodeRec nd = nodes[0];
@@ -569,6 +621,41 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(
     }
 }
 
+template <int CB, bool BF16, int K>
+__global__ __launch_bounds__(kThreads) void k_adjoint(DPS_TRAV_PARAMS, int C, const float *__restrict__ df,
+                                                      double *__restrict__ G, double *__restrict__ P,
+                                                      float *__restrict__ dxout, int dx_mode, int xcd_remap) {
+    const int64_t blk = remap_block(xcd_remap);
+    if (blk < 0) return;
+    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
+    adjoint_body<CB, BF16, K>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout, dx_mode);
+}
+
+template <int CB, bool BF16, int K>
+__global__ __launch_bounds__(kThreads) void k_adjoint_persistent(DPS_TRAV_PARAMS, int C,
+                                                                 const float *__restrict__ df,
+                                                                 double *__restrict__ G, double *__restrict__ P,
+                                                                 float *__restrict__ dxout, int dx_mode,
+                                                                 uint32_t *__restrict__ ctr) {
+    const int64_t ntiles = (Q + 64 * K - 1) / (64 * K);
+    int part = xcc_id();
+    for (;;) {
+        const int64_t tile = next_tile(ctr, ntiles, part);
+        if (tile < 0) break;
+        adjoint_body<CB, BF16, K>(tile * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout, dx_mode);
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+__global__ void k_fill_f64(double *__restrict__ a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // adjoint stage 2 (eq. farfield_features_gradient): running sum of the node
 // accumulators from the root to each leaf, then each point adds
@@ -644,7 +731,7 @@ __global__ void k_export_moments(int64_t N, int C, int ms, const void *__restric
 
 inline unsigned grid(int64_t n) { return (unsigned)std::max<int64_t>(1, cdiv(n, kThreads)); }
 
-// channel blocks: 8s, then a 4, then the remainder; block starts stay multiples of 4
+// channel blocks: 8s, then a 4, then the remainder
 inline int next_block(int rem) { return rem >= 8 ? 8 : (rem >= 4 ? 4 : rem); }
 
 // queries per lane: 1, 2 or 4; capped so per-lane accumulators stay in registers
@@ -654,92 +741,120 @@ inline int clamp_packet(int k, int cb, bool grad) {
     return k < cap ? k : cap;
 }
 
+// resident workgroups of a kernel on the current device (persistent grid size)
+inline unsigned persistent_grid(const void *fn) {
+    int dev = 0, ncu = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, 0) != hipSuccess || per < 1) per = 1;
+    return (unsigned)(ncu * per);
+}
+
+struct Sub {       // one channel block of a (possibly partial) channel range
+    int c0;        // first tree channel of the block
+    int ldo;       // channels per row of f / grad / df
+    int co;        // column of c0 in those rows
+};
+
 template <int CB, bool BF, bool GR, int K>
-dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
                         float *f, float *g, hipStream_t s) {
-    const unsigned nb = grid(cdiv(Q, K));
-    const bool remap = (t->xcd_remap & 1) != 0;
-    const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
-    const int rm = remap ? (int)nb : 0;
-    if constexpr (K == 1)
-        k_query1<CB, BF, GR><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride,
-                                                     t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N,
-                                                     t->err, rm);
-    else
-        k_query<CB, BF, GR, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride,
-                                                       t->attr_stride, x, Q, b2, kp, c0, f, g, (uint32_t)t->N,
-                                                       t->err, rm);
+    const uint32_t lim = (uint32_t)t->N;
+    if (t->launch_flags & kFlagPersistentQuery) {
+        k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
+        const void *fn = reinterpret_cast<const void *>(&k_query_persistent<CB, BF, GR, K>);
+        k_query_persistent<CB, BF, GR, K><<<persistent_grid(fn), kThreads, 0, s>>>(
+            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, b2, kp, sb.c0, sb.ldo, sb.co,
+            lim, t->err, f, g, t->ctr);
+    } else {
+        const unsigned nb = grid(cdiv(Q, K));
+        const bool remap = (t->launch_flags & kFlagXcdQuery) != 0;
+        const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
+        k_query<CB, BF, GR, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+                                                       t->attr_stride, x, Q, b2, kp, sb.c0, sb.ldo, sb.co, lim,
+                                                       t->err, f, g, remap ? (int)nb : 0);
+    }
     return hip_status(hipGetLastError(), "query launch");
 }
 
 template <int CB, bool BF, bool GR>
-dps_status query_k(dps_tree_s *t, int k, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+dps_status query_k(dps_tree_s *t, int k, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
                    float *f, float *g, hipStream_t s) {
     switch (clamp_packet(k, CB, GR)) {
         case 4:
-            if constexpr ((GR && CB <= 2) || (!GR && CB <= 4)) return query_launch<CB, BF, GR, 4>(t, x, Q, b2, kp, c0, f, g, s);
+            if constexpr ((GR && CB <= 2) || (!GR && CB <= 4)) return query_launch<CB, BF, GR, 4>(t, x, Q, b2, kp, sb, f, g, s);
             [[fallthrough]];
         case 2:
-            if constexpr (GR ? CB <= 4 : true) return query_launch<CB, BF, GR, 2>(t, x, Q, b2, kp, c0, f, g, s);
+            if constexpr (GR ? CB <= 4 : true) return query_launch<CB, BF, GR, 2>(t, x, Q, b2, kp, sb, f, g, s);
             [[fallthrough]];
         default:
-            return query_launch<CB, BF, GR, 1>(t, x, Q, b2, kp, c0, f, g, s);
+            return query_launch<CB, BF, GR, 1>(t, x, Q, b2, kp, sb, f, g, s);
     }
 }
 
 template <int CB>
-dps_status query_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+dps_status query_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
                        float *f, float *g, hipStream_t s) {
     const bool bf = t->storage == DPS_STORE_BF16;
     const int k = t->packet_query;
-    if (bf && g) return query_k<CB, true, true>(t, k, x, Q, b2, kp, c0, f, g, s);
-    if (bf) return query_k<CB, true, false>(t, k, x, Q, b2, kp, c0, f, g, s);
-    if (g) return query_k<CB, false, true>(t, k, x, Q, b2, kp, c0, f, g, s);
-    return query_k<CB, false, false>(t, k, x, Q, b2, kp, c0, f, g, s);
+    if (bf && g) return query_k<CB, true, true>(t, k, x, Q, b2, kp, sb, f, g, s);
+    if (bf) return query_k<CB, true, false>(t, k, x, Q, b2, kp, sb, f, g, s);
+    if (g) return query_k<CB, false, true>(t, k, x, Q, b2, kp, sb, f, g, s);
+    return query_k<CB, false, false>(t, k, x, Q, b2, kp, sb, f, g, s);
 }
 
 template <int CB, bool BF, int K>
-dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
                           const float *df, float *dx, int dx_mode, hipStream_t s) {
-    const unsigned nb = grid(cdiv(Q, K));
-    const bool remap = (t->xcd_remap & 2) != 0;
-    const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
-    const int rm = remap ? (int)nb : 0;
-    k_adjoint<CB, BF, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->C, t->mom_stride,
-                                                 t->attr_stride, x, Q, b2, kp, c0, df, t->G, t->P, dx,
-                                                 dx_mode, (uint32_t)t->N, t->err, rm);
+    const uint32_t lim = (uint32_t)t->N;
+    if (t->launch_flags & kFlagPersistentAdjoint) {
+        k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
+        const void *fn = reinterpret_cast<const void *>(&k_adjoint_persistent<CB, BF, K>);
+        k_adjoint_persistent<CB, BF, K><<<persistent_grid(fn), kThreads, 0, s>>>(
+            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, b2, kp, sb.c0, sb.ldo, sb.co,
+            lim, t->err, t->C, df, t->G, t->P, dx, dx_mode, t->ctr + 8);
+    } else {
+        const unsigned nb = grid(cdiv(Q, K));
+        const bool remap = (t->launch_flags & kFlagXcdAdjoint) != 0;
+        const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
+        k_adjoint<CB, BF, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+                                                     t->attr_stride, x, Q, b2, kp, sb.c0, sb.ldo, sb.co, lim,
+                                                     t->err, t->C, df, t->G, t->P, dx, dx_mode,
+                                                     remap ? (int)nb : 0);
+    }
     return hip_status(hipGetLastError(), "adjoint launch");
 }
 
 template <int CB>
-dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, int c0,
+dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
                          const float *df, float *dx, int dx_mode, hipStream_t s) {
     const int k = clamp_packet(t->packet_adjoint, CB, false);
     if (t->storage == DPS_STORE_BF16) {
-        if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, true, 4>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); }
-        if (k >= 2) return adjoint_launch<CB, true, 2>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s);
-        return adjoint_launch<CB, true, 1>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s);
+        if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, true, 4>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); }
+        if (k >= 2) return adjoint_launch<CB, true, 2>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s);
+        return adjoint_launch<CB, true, 1>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s);
     }
-    if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, false, 4>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); }
-    if (k >= 2) return adjoint_launch<CB, false, 2>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s);
-    return adjoint_launch<CB, false, 1>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s);
+    if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, false, 4>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); }
+    if (k >= 2) return adjoint_launch<CB, false, 2>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s);
+    return adjoint_launch<CB, false, 1>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s);
 }
 
 }  // namespace
 
-dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, float *f,
-                        float *g, hipStream_t s) {
+dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, int cbegin, int nc,
+                        float *f, float *g, hipStream_t s) {
     const float b2 = mul_rn(beta, beta);
     const KernelParams kp = make_kernel_params(eps);
-    for (int c0 = 0; c0 < t->C;) {
-        const int cb = next_block(t->C - c0);
+    for (int c0 = cbegin; c0 < cbegin + nc;) {
+        const int cb = next_block(cbegin + nc - c0);
+        const Sub sb{c0, nc, c0 - cbegin};
         dps_status st;
         switch (cb) {
-            case 8: st = query_block<8>(t, x, Q, b2, kp, c0, f, g, s); break;
-            case 4: st = query_block<4>(t, x, Q, b2, kp, c0, f, g, s); break;
-            case 3: st = query_block<3>(t, x, Q, b2, kp, c0, f, g, s); break;
-            case 2: st = query_block<2>(t, x, Q, b2, kp, c0, f, g, s); break;
-            default: st = query_block<1>(t, x, Q, b2, kp, c0, f, g, s); break;
+            case 8: st = query_block<8>(t, x, Q, b2, kp, sb, f, g, s); break;
+            case 4: st = query_block<4>(t, x, Q, b2, kp, sb, f, g, s); break;
+            case 3: st = query_block<3>(t, x, Q, b2, kp, sb, f, g, s); break;
+            case 2: st = query_block<2>(t, x, Q, b2, kp, sb, f, g, s); break;
+            default: st = query_block<1>(t, x, Q, b2, kp, sb, f, g, s); break;
         }
         if (st != DPS_OK) return st;
         c0 += cb;
@@ -753,25 +868,35 @@ dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta, i
     return hip_status(hipGetLastError(), "counts launch");
 }
 
-dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps,
+dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, int cbegin, int nc,
                           const float *df, float *dx, hipStream_t s) {
     const float b2 = mul_rn(beta, beta);
     const KernelParams kp = make_kernel_params(eps);
-    for (int c0 = 0; c0 < t->C;) {
-        const int cb = next_block(t->C - c0);
-        const int dx_mode = dx ? (c0 == 0 ? 1 : 2) : 0;
+    for (int c0 = cbegin; c0 < cbegin + nc;) {
+        const int cb = next_block(cbegin + nc - c0);
+        const int dx_mode = dx ? (c0 == cbegin ? 1 : 2) : 0;
+        const Sub sb{c0, nc, c0 - cbegin};
         dps_status st;
         switch (cb) {
-            case 8: st = adjoint_block<8>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
-            case 4: st = adjoint_block<4>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
-            case 3: st = adjoint_block<3>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
-            case 2: st = adjoint_block<2>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
-            default: st = adjoint_block<1>(t, x, Q, b2, kp, c0, df, dx, dx_mode, s); break;
+            case 8: st = adjoint_block<8>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
+            case 4: st = adjoint_block<4>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
+            case 3: st = adjoint_block<3>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
+            case 2: st = adjoint_block<2>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
+            default: st = adjoint_block<1>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
         }
         if (st != DPS_OK) return st;
         c0 += cb;
     }
     return DPS_OK;
+}
+
+dps_status launch_zero(dps_tree_s *t, hipStream_t s) {
+    const int64_t ng = t->N * 3 * t->C, np = t->M * t->C;
+    k_fill_f64<<<(unsigned)std::min<int64_t>(cdiv(ng, kThreads), 4096), kThreads, 0, s>>>(t->G, ng);
+    dps_status st = hip_status(hipGetLastError(), "zero node accumulators");
+    if (st != DPS_OK) return st;
+    k_fill_f64<<<(unsigned)std::min<int64_t>(cdiv(np, kThreads), 4096), kThreads, 0, s>>>(t->P, np);
+    return hip_status(hipGetLastError(), "zero point accumulators");
 }
 
 dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s) {

@@ -22,7 +22,8 @@ struct dps_tree_s {
     bool wide_top;    // FP64 accumulation of top-level moments
     int packet_query;    // queries per lane in dps_query (1, 2, 4)
     int packet_adjoint;  // queries per lane in dps_adjoint_accumulate (1, 2, 4)
-    int xcd_remap;       // bit 0 query, bit 1 adjoint: workgroups of one XCD take a contiguous share
+    int launch_flags;    // kFlag* bits: XCD-contiguous order / persistent launch per kernel
+    uint32_t *ctr;       // [16] tile counters of the persistent launches (query, adjoint)
 
     uint64_t *codes;          // [M] sorted Morton codes
     uint32_t *perm;           // [M] sorted position -> caller index
@@ -67,12 +68,13 @@ dps_status tree_alloc(dps_tree_s *t, T **ptr, size_t count) {
 dps_status build_tree(dps_tree_s *t, const float *p, const float *n, const float *A,
                       hipStream_t s);
 dps_status refit_moments(dps_tree_s *t, const float *attrs, hipStream_t s);
-dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps,
+dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, int cbegin, int nc,
                         float *f, float *g, hipStream_t s);
 dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta,
                          int32_t *counts, hipStream_t s);
-dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps,
+dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, int cbegin, int nc,
                           const float *df, float *dx, hipStream_t s);
+dps_status launch_zero(dps_tree_s *t, hipStream_t s);
 dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s);
 dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *moments,
                          hipStream_t s);

@@ -193,15 +193,16 @@ def test_invalid_data_rejected(dps):
         assert e.value.status == 1
 
 
-@pytest.mark.parametrize("xcd", [0, 3])
+@pytest.mark.parametrize("flags", [0, 3, 12])
 @pytest.mark.parametrize("k", [1, 2, 4])
 @pytest.mark.parametrize("name,Q", [("sphere-8k", 4099), ("random-3001-c5", 1000), ("random-2000-c1", 257),
                                     ("sphere-8k", 70000)])
-def test_packet_sizes_parity(dps, orc, k, xcd, name, Q):
-    # every launch shape makes the same per-query decisions; ragged tails
+def test_launch_shapes_parity(dps, orc, k, flags, name, Q):
+    # every launch shape (packet size, XCD order, persistent queue) makes the
+    # same per-query decisions; ragged tails
     p, n, A, mu = CLOUDS[name]()
     tree, T = _check_build(dps, orc, p, n, A, mu, 16)
-    dps.dps_set_packet(tree, k, k, xcd)
+    dps.dps_set_launch(tree, k, k, flags)
     x = workloads.sphere_queries(Q, 31)
     df = workloads.cotangents(Q, mu.shape[1], 17)
     xd, dfd = to_dev(x, df)
@@ -218,14 +219,48 @@ def test_packet_sizes_parity(dps, orc, k, xcd, name, Q):
     dps.dps_check(tree)
 
 
-def test_set_packet_rejects_bad_sizes(dps):
+def test_set_launch_rejects_bad_shapes(dps):
     p, n, A, mu = workloads.sphere_cloud(256, 1)
     tree = dps.dps_build(*to_dev(p, n, A, mu))
     for k in (3, 5, -1, 8):
         with pytest.raises(dps.DpsError):
-            dps.dps_set_packet(tree, k, 1)
-    for xo in (-2, 4):
+            dps.dps_set_launch(tree, k, 1)
+    for fl in (-2, 16):
         with pytest.raises(dps.DpsError):
-            dps.dps_set_packet(tree, 1, 1, xo)
-    dps.dps_set_packet(tree, 0, 4)
-    dps.dps_set_packet(tree, 2, 0, 3)
+            dps.dps_set_launch(tree, 1, 1, fl)
+    dps.dps_set_launch(tree, 0, 4)
+    dps.dps_set_launch(tree, 2, 0, 15)
+    assert dps.dps_get_launch(tree) == {"query": 2, "adjoint": 4, "flags": 15}
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+@pytest.mark.parametrize("c_begin,nc", [(0, 1), (2, 2), (0, 5), (4, 1), (1, 3)])
+def test_channel_subsets(dps, orc, storage, c_begin, nc):
+    p, n, A, mu = CLOUDS["random-3001-c5"]()
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16, storage)
+    x = workloads.sphere_queries(2000, 41)
+    (xd,) = to_dev(x)
+    if storage == "bf16" and c_begin % 2:
+        with pytest.raises(dps.DpsError):
+            dps.dps_query_channels(tree, xd, 2.0, 0.05, c_begin, nc)
+        return
+    f, g = dps.dps_query_channels(tree, xd, 2.0, 0.05, c_begin, nc)
+    ref = T.query(x, 2.0, 0.05)
+    sl = slice(c_begin, c_begin + nc)
+    tol = TOL_BF16 if storage == "bf16" else TOL_FP32
+    assert norm_err(to_host(f), ref["f"][:, sl], ref["sf"][:, sl]) <= tol
+    assert norm_err(to_host(g), ref["g"][:, sl], ref["sg"][:, sl]) <= tol
+    # adjoint of the subset = full adjoint with zero cotangents elsewhere
+    dfs = workloads.cotangents(2000, nc, 43)
+    dffull = np.zeros((2000, mu.shape[1]), np.float32)
+    dffull[:, sl] = dfs
+    (dfsd,) = to_dev(dfs)
+    dps.dps_adjoint_zero(tree)
+    dx = dps.dps_adjoint_accumulate_channels(tree, xd, 2.0, 0.05, c_begin, nc, dfsd)
+    da = dps.dps_adjoint_finalize(tree)
+    adj = T.adjoint(x, 2.0, 0.05, dffull)
+    assert norm_err(to_host(da), adj["dmu"], adj["sdmu"] + 1e-30) <= TOL_FP32
+    assert norm_err(to_host(dx), adj["dx"], adj["sdx"]) <= tol
+    for cb, k in ((-1, 1), (0, 0), (4, 2), (5, 1)):
+        with pytest.raises(dps.DpsError):
+            dps.dps_query_channels(tree, xd, 2.0, 0.05, cb, k)
