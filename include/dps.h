@@ -193,12 +193,19 @@ dps_status dps_get_launch(dps_tree t, int32_t *query_k, int32_t *adjoint_k, int3
  * dps_adjoint_accumulate for the channel range [c_begin, c_begin+n_channels)
  * only (e.g. the geometry channel alone for shadow rays).  f, grad and df rows
  * hold n_channels entries.  With BF16 storage c_begin must be even.
+ *  Q        rows of x / f / grad / df / dx (capacity)
+ *  q_count  device pointer or NULL: when given, only the first
+ *           min(Q, max(*q_count, 0)) rows are processed, the count being read
+ *           on the device when the kernels run (batch sizes decided on the GPU,
+ *           e.g. the number of shadow rays, inside a captured graph); the other
+ *           rows are left untouched.
  */
-dps_status dps_query_channels(dps_tree t, const float *x, int64_t Q, float beta, float eps, int32_t c_begin,
-                              int32_t n_channels, float *f, float *grad, void *stream);
-dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q, float beta, float eps,
-                                           int32_t c_begin, int32_t n_channels, const float *df, float *dx,
-                                           void *stream);
+dps_status dps_query_channels(dps_tree t, const float *x, int64_t Q, const int64_t *q_count, float beta,
+                              float eps, int32_t c_begin, int32_t n_channels, float *f, float *grad,
+                              void *stream);
+dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q, const int64_t *q_count,
+                                           float beta, float eps, int32_t c_begin, int32_t n_channels,
+                                           const float *df, float *dx, void *stream);
 
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A

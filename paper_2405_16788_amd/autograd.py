@@ -1,14 +1,19 @@
 """Differentiation pattern: the dipole-sum query as a torch.autograd.Function.
 
-Forward evaluates the Barnes-Hut sums (values and spatial gradients) with
-``dps_query``; backward runs the two-stage adjoint of Sec. 6.2 / App. C
-(``dps_adjoint``: node accumulation with a recomputed traversal, then the
-push-down to the points).  Nothing about the traversal is stored between the
-two passes: the adjoint walks the tree again for each query.
+Forward evaluates the Barnes-Hut sums (values and, optionally, spatial
+gradients) with ``dps_query`` / ``dps_query_channels``; backward runs the
+two-stage adjoint of Sec. 6.2 / App. C (node accumulation with a recomputed
+traversal, then the push-down to the points).  Nothing about the traversal is
+stored between the two passes: the adjoint walks the tree again for each query.
 
 The value D(x) is linear in the attributes, and the traversal depends only on
 x and the fixed geometry, so dL/dattrs is the exact transpose of the forward
 map; dL/dx is sum_c dL/dD_c * grad_x D_c with the same accepted sources.
+
+Both passes are free of host synchronisation, so a forward + backward built
+from these calls can be captured in a graph and replayed; ``refit=True`` puts
+the moment refit inside the captured work (attributes updated in place between
+replays are then picked up).
 """
 from __future__ import annotations
 
@@ -24,39 +29,83 @@ def _refit_if_changed(tree: B.Tree, attrs: torch.Tensor):
         tree._attr_key = key
 
 
-class DipoleSum(torch.autograd.Function):
-    """f, grad = DipoleSum.apply(attrs[M,C], x[Q,3], tree, beta, eps).
+def _refit(tree: B.Tree, attrs: torch.Tensor, mode):
+    if mode is True:
+        B.dps_set_attributes(tree, attrs)
+        tree._attr_key = (attrs.data_ptr(), attrs._version)
+    elif mode == "auto":
+        _refit_if_changed(tree, attrs)
 
-    ``f`` [Q,C] is differentiable w.r.t. attrs and x; ``grad`` [Q,C,3] is
-    returned as a non-differentiable output."""
+
+class DipoleSum(torch.autograd.Function):
+    """f, grad = DipoleSum.apply(attrs[M,C], x[Q,3], tree, beta, eps, opts).
+
+    ``opts`` = (c_begin, n_channels, q_count, want_grad, refit) with
+    n_channels None meaning all channels.  ``f`` [Q,n] is differentiable
+    w.r.t. attrs and x; ``grad`` [Q,n,3] (or None) is non-differentiable.
+    With a device row count ``q_count`` (int64 CUDA tensor [1]) only the first
+    min(Q, q_count) rows are evaluated; the other rows of f / grad and of the
+    position gradient are zero."""
 
     @staticmethod
-    def forward(ctx, attrs, x, tree, beta, eps):
+    def forward(ctx, attrs, x, tree, beta, eps, opts):
+        c_begin, n_ch, q_count, want_grad, refit = opts
+        ctx.set_materialize_grads(False)
         attrs_c = attrs.detach().contiguous()
         x_c = x.detach().contiguous()
-        _refit_if_changed(tree, attrs_c)
-        f, g = B.dps_query(tree, x_c, beta, eps, grad=True)
+        _refit(tree, attrs_c, refit)
+        full = n_ch is None and q_count is None
+        if full:
+            f, g = B.dps_query(tree, x_c, beta, eps, grad=want_grad)
+        else:
+            n = tree.C - c_begin if n_ch is None else n_ch
+            Q = x_c.shape[0]
+            # rows past the device count are never written by the kernels
+            f = torch.zeros((Q, n), device=x_c.device, dtype=torch.float32)
+            g = torch.zeros((Q, n, 3), device=x_c.device, dtype=torch.float32) if want_grad else None
+            B.dps_query_channels(tree, x_c, beta, eps, c_begin, n, f_out=f, g_out=g, q_count=q_count)
         ctx.save_for_backward(x_c, attrs_c)
-        ctx.tree, ctx.beta, ctx.eps = tree, float(beta), float(eps)
-        ctx.mark_non_differentiable(g)
+        ctx.tree, ctx.beta, ctx.eps, ctx.opts, ctx.full = tree, float(beta), float(eps), opts, full
+        if g is not None:
+            ctx.mark_non_differentiable(g)
         return f, g
 
     @staticmethod
     def backward(ctx, df, dg):
-        if dg is not None and bool(torch.any(dg != 0)):
-            raise NotImplementedError("cotangents of the spatial gradient output are not supported")
+        # dg is never a real cotangent: the gradient output is marked
+        # non-differentiable (cotangents of it would need the Hessian kernel)
         x, attrs = ctx.saved_tensors
         tree = ctx.tree
-        _refit_if_changed(tree, attrs)
+        c_begin, n_ch, q_count, _, refit = ctx.opts
+        if refit == "auto":
+            _refit_if_changed(tree, attrs)
         need_attr, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if df is None or not (need_attr or need_x):
-            return None, None, None, None, None
-        dattrs, dx = B.dps_adjoint(tree, x, ctx.beta, ctx.eps, df.contiguous().to(torch.float32),
-                                   want_dx=need_x)
+            return None, None, None, None, None, None
+        df = df.contiguous().to(torch.float32)
+        if ctx.full:
+            dattrs, dx = B.dps_adjoint(tree, x, ctx.beta, ctx.eps, df, want_dx=need_x)
+        else:
+            n = df.shape[1]
+            dx = torch.zeros((x.shape[0], 3), device=x.device, dtype=torch.float32) if need_x else None
+            B.dps_adjoint_zero(tree)
+            B.dps_adjoint_accumulate_channels(tree, x, ctx.beta, ctx.eps, c_begin, n, df, want_dx=need_x,
+                                              dx_out=dx, q_count=q_count)
+            dattrs = B.dps_adjoint_finalize(tree)
         dattrs = dattrs.reshape(attrs.shape) if need_attr else None
-        return dattrs, (dx if need_x else None), None, None, None
+        return dattrs, (dx if need_x else None), None, None, None, None
 
 
-def dipole_sum(attrs, x, tree, beta: float, eps: float):
-    """Functional form of ``DipoleSum``: returns (f, grad)."""
-    return DipoleSum.apply(attrs, x, tree, beta, eps)
+def dipole_sum(attrs, x, tree, beta: float, eps: float, *, channels=None, q_count=None, grad: bool = True,
+               refit="auto"):
+    """Functional form of ``DipoleSum``: returns (f, grad or None).
+
+    channels: None (all) or (c_begin, n_channels); q_count: optional int64
+    CUDA tensor [1] with the number of rows to evaluate; grad: also return the
+    spatial gradients; refit: "auto" (refit when attrs changed since the last
+    refit, judged from its storage and version), True (always, e.g. inside a
+    captured graph) or False (never)."""
+    c_begin, n_ch = (0, None) if channels is None else (int(channels[0]), int(channels[1]))
+    if channels is not None and c_begin == 0 and n_ch == tree.C:
+        n_ch = None
+    return DipoleSum.apply(attrs, x, tree, beta, eps, (c_begin, n_ch, q_count, bool(grad), refit))

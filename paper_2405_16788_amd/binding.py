@@ -56,8 +56,8 @@ def load():
         "dps_check": [vp, vp],
         "dps_set_launch": [vp, i32, i32, i32],
         "dps_get_launch": [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)],
-        "dps_query_channels": [vp, vp, i64, f32, f32, i32, i32, vp, vp, vp],
-        "dps_adjoint_accumulate_channels": [vp, vp, i64, f32, f32, i32, i32, vp, vp, vp],
+        "dps_query_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
+        "dps_adjoint_accumulate_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
         "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
@@ -259,14 +259,16 @@ def dps_get_launch(tree: Tree):
 
 
 def dps_query_channels(tree: Tree, x, beta: float, eps: float, c_begin: int, n_channels: int,
-                       grad: bool = True, f_out=None, g_out=None):
-    """Channels [c_begin, c_begin+n_channels) only; returns (f[Q,n], grad[Q,n,3] or None)."""
+                       grad: bool = True, f_out=None, g_out=None, q_count=None):
+    """Channels [c_begin, c_begin+n_channels) only; returns (f[Q,n], grad[Q,n,3] or None).
+    q_count: optional int64 CUDA tensor [1]; only its first rows are processed."""
     import torch
     Q = x.shape[0]
     f = f_out if f_out is not None else torch.empty((Q, n_channels), device=tree.device, dtype=torch.float32)
     g = g_out if g_out is not None else (
         torch.empty((Q, n_channels, 3), device=tree.device, dtype=torch.float32) if grad else None)
     _check(load().dps_query_channels(tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q,
+                                     _ptr(q_count, torch.int64, (1,), tree.device, "q_count"),
                                      float(beta), float(eps), int(c_begin), int(n_channels),
                                      _ptr(f, torch.float32, (Q, n_channels), tree.device, "f"),
                                      _ptr(g, torch.float32, (Q, n_channels, 3), tree.device, "grad"),
@@ -275,14 +277,15 @@ def dps_query_channels(tree: Tree, x, beta: float, eps: float, c_begin: int, n_c
 
 
 def dps_adjoint_accumulate_channels(tree: Tree, x, beta: float, eps: float, c_begin: int, n_channels: int,
-                                    df, want_dx: bool = True, dx_out=None):
+                                    df, want_dx: bool = True, dx_out=None, q_count=None):
     """Stage 1 for a channel range; df rows hold n_channels entries."""
     import torch
     Q = x.shape[0]
     dx = dx_out if dx_out is not None else (
         torch.empty((Q, 3), device=tree.device, dtype=torch.float32) if want_dx else None)
     _check(load().dps_adjoint_accumulate_channels(
-        tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q, float(beta), float(eps), int(c_begin),
+        tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q,
+        _ptr(q_count, torch.int64, (1,), tree.device, "q_count"), float(beta), float(eps), int(c_begin),
         int(n_channels), _ptr(df, torch.float32, (Q, n_channels), tree.device, "df"),
         _ptr(dx, torch.float32, (Q, 3), tree.device, "dx"), _stream(tree.device)), "dps_adjoint_accumulate_channels")
     return dx

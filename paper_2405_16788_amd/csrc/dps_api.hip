@@ -185,7 +185,7 @@ dps_status dps_query(dps_tree t, const float *x, int64_t Q, float beta, float ep
     if (Q == 0) return DPS_OK;
     if (!x || !f) return invalid("dps_query: NULL x or f");
     DeviceGuard dg(t->device);
-    return launch_query(t, x, Q, beta, eps, 0, t->C, f, grad, (hipStream_t)stream);
+    return launch_query(t, x, Q, nullptr, beta, eps, 0, t->C, f, grad, (hipStream_t)stream);
 }
 
 static dps_status check_channels(dps_tree t, int32_t c_begin, int32_t n_channels, const char *fn) {
@@ -200,8 +200,8 @@ static dps_status check_channels(dps_tree t, int32_t c_begin, int32_t n_channels
     return DPS_OK;
 }
 
-dps_status dps_query_channels(dps_tree t, const float *x, int64_t Q, float beta, float eps, int32_t c_begin,
-                              int32_t n_channels, float *f, float *grad, void *stream) {
+dps_status dps_query_channels(dps_tree t, const float *x, int64_t Q, const int64_t *q_count, float beta, float eps,
+                              int32_t c_begin, int32_t n_channels, float *f, float *grad, void *stream) {
     dps_status st = check_tree(t, "dps_query_channels");
     if (st != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_query_channels")) != DPS_OK) return st;
@@ -210,7 +210,7 @@ dps_status dps_query_channels(dps_tree t, const float *x, int64_t Q, float beta,
     if (Q == 0) return DPS_OK;
     if (!x || !f) return invalid("dps_query_channels: NULL x or f");
     DeviceGuard dg(t->device);
-    return launch_query(t, x, Q, beta, eps, c_begin, n_channels, f, grad, (hipStream_t)stream);
+    return launch_query(t, x, Q, q_count, beta, eps, c_begin, n_channels, f, grad, (hipStream_t)stream);
 }
 
 dps_status dps_query_counts(dps_tree t, const float *x, int64_t Q, float beta, int32_t *counts,
@@ -241,12 +241,12 @@ dps_status dps_adjoint_accumulate(dps_tree t, const float *x, int64_t Q, float b
     if (Q == 0) return DPS_OK;
     if (!x || !df) return invalid("dps_adjoint_accumulate: NULL x or df");
     DeviceGuard dg(t->device);
-    return launch_adjoint(t, x, Q, beta, eps, 0, t->C, df, dx, (hipStream_t)stream);
+    return launch_adjoint(t, x, Q, nullptr, beta, eps, 0, t->C, df, dx, (hipStream_t)stream);
 }
 
-dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q, float beta, float eps,
-                                           int32_t c_begin, int32_t n_channels, const float *df, float *dx,
-                                           void *stream) {
+dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q, const int64_t *q_count,
+                                           float beta, float eps, int32_t c_begin, int32_t n_channels,
+                                           const float *df, float *dx, void *stream) {
     dps_status st = check_tree(t, "dps_adjoint_accumulate_channels");
     if (st != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate_channels")) != DPS_OK) return st;
@@ -255,7 +255,7 @@ dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q
     if (Q == 0) return DPS_OK;
     if (!x || !df) return invalid("dps_adjoint_accumulate_channels: NULL x or df");
     DeviceGuard dg(t->device);
-    return launch_adjoint(t, x, Q, beta, eps, c_begin, n_channels, df, dx, (hipStream_t)stream);
+    return launch_adjoint(t, x, Q, q_count, beta, eps, c_begin, n_channels, df, dx, (hipStream_t)stream);
 }
 
 dps_status dps_adjoint_finalize(dps_tree t, float *dattrs, void *stream) {

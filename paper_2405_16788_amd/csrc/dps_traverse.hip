@@ -119,6 +119,14 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t
         const float *__restrict__ x, int64_t Q, float b2, KernelParams kp, int c0, int ldo, int co, \
         uint32_t limit, uint32_t *__restrict__ err
 #define DPS_TRAV_ARGS nodes, pts, mom, attr, ms, as, x, Q, b2, kp, c0, ldo, co, limit, err
+// Kernel entry: Qcap rows, of which the first min(Qcap, *qdev) are processed
+// when qdev is given (batch sizes decided on the device, e.g. inside a graph).
+#define DPS_KERN_PARAMS                                                                            \
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts,                           \
+        const void *__restrict__ mom, const void *__restrict__ attr, int ms, int as,               \
+        const float *__restrict__ x, int64_t Qcap, const int64_t *__restrict__ qdev, float b2,     \
+        KernelParams kp, int c0, int ldo, int co, uint32_t limit, uint32_t *__restrict__ err
+#define DPS_ROWS const int64_t Q = qdev ? (qdev[0] < Qcap ? (qdev[0] > 0 ? qdev[0] : 0) : Qcap) : Qcap
 
 // ---------------------------------------------------------------------------
 // primal query, one query per lane (register-lean).  Software-pipelined: the
@@ -383,18 +391,20 @@ __device__ __forceinline__ void query_body(int64_t q0, DPS_TRAV_PARAMS, float *_
 }
 
 template <int CB, bool BF16, bool GRAD, int K>
-__global__ __launch_bounds__(kThreads) void k_query(DPS_TRAV_PARAMS, float *__restrict__ fout,
+__global__ __launch_bounds__(kThreads) void k_query(DPS_KERN_PARAMS, float *__restrict__ fout,
                                                     float *__restrict__ gout, int xcd_remap) {
+    DPS_ROWS;
     const int64_t blk = remap_block(xcd_remap);
-    if (blk < 0) return;
+    if (blk < 0 || blk * (int64_t)blockDim.x * K >= Q) return;  // whole block past the rows
     const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
     query_body<CB, BF16, GRAD, K>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, fout, gout);
 }
 
 template <int CB, bool BF16, bool GRAD, int K>
-__global__ __launch_bounds__(kThreads) void k_query_persistent(DPS_TRAV_PARAMS, float *__restrict__ fout,
+__global__ __launch_bounds__(kThreads) void k_query_persistent(DPS_KERN_PARAMS, float *__restrict__ fout,
                                                                float *__restrict__ gout,
                                                                uint32_t *__restrict__ ctr) {
+    DPS_ROWS;
     const int64_t ntiles = (Q + 64 * K - 1) / (64 * K);
     int part = xcc_id();
     for (;;) {
@@ -622,21 +632,23 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
 }
 
 template <int CB, bool BF16, int K>
-__global__ __launch_bounds__(kThreads) void k_adjoint(DPS_TRAV_PARAMS, int C, const float *__restrict__ df,
+__global__ __launch_bounds__(kThreads) void k_adjoint(DPS_KERN_PARAMS, int C, const float *__restrict__ df,
                                                       double *__restrict__ G, double *__restrict__ P,
                                                       float *__restrict__ dxout, int dx_mode, int xcd_remap) {
+    DPS_ROWS;
     const int64_t blk = remap_block(xcd_remap);
-    if (blk < 0) return;
+    if (blk < 0 || blk * (int64_t)blockDim.x * K >= Q) return;  // whole block past the rows
     const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
     adjoint_body<CB, BF16, K>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout, dx_mode);
 }
 
 template <int CB, bool BF16, int K>
-__global__ __launch_bounds__(kThreads) void k_adjoint_persistent(DPS_TRAV_PARAMS, int C,
+__global__ __launch_bounds__(kThreads) void k_adjoint_persistent(DPS_KERN_PARAMS, int C,
                                                                  const float *__restrict__ df,
                                                                  double *__restrict__ G, double *__restrict__ P,
                                                                  float *__restrict__ dxout, int dx_mode,
                                                                  uint32_t *__restrict__ ctr) {
+    DPS_ROWS;
     const int64_t ntiles = (Q + 64 * K - 1) / (64 * K);
     int part = xcc_id();
     for (;;) {
@@ -757,68 +769,68 @@ struct Sub {       // one channel block of a (possibly partial) channel range
 };
 
 template <int CB, bool BF, bool GR, int K>
-dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
+dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
                         float *f, float *g, hipStream_t s) {
     const uint32_t lim = (uint32_t)t->N;
     if (t->launch_flags & kFlagPersistentQuery) {
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_query_persistent<CB, BF, GR, K>);
         k_query_persistent<CB, BF, GR, K><<<persistent_grid(fn), kThreads, 0, s>>>(
-            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, b2, kp, sb.c0, sb.ldo, sb.co,
+            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
             lim, t->err, f, g, t->ctr);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdQuery) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
         k_query<CB, BF, GR, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
-                                                       t->attr_stride, x, Q, b2, kp, sb.c0, sb.ldo, sb.co, lim,
+                                                       t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co, lim,
                                                        t->err, f, g, remap ? (int)nb : 0);
     }
     return hip_status(hipGetLastError(), "query launch");
 }
 
 template <int CB, bool BF, bool GR>
-dps_status query_k(dps_tree_s *t, int k, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
+dps_status query_k(dps_tree_s *t, int k, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
                    float *f, float *g, hipStream_t s) {
     switch (clamp_packet(k, CB, GR)) {
         case 4:
-            if constexpr ((GR && CB <= 2) || (!GR && CB <= 4)) return query_launch<CB, BF, GR, 4>(t, x, Q, b2, kp, sb, f, g, s);
+            if constexpr ((GR && CB <= 2) || (!GR && CB <= 4)) return query_launch<CB, BF, GR, 4>(t, x, Q, qdev, b2, kp, sb, f, g, s);
             [[fallthrough]];
         case 2:
-            if constexpr (GR ? CB <= 4 : true) return query_launch<CB, BF, GR, 2>(t, x, Q, b2, kp, sb, f, g, s);
+            if constexpr (GR ? CB <= 4 : true) return query_launch<CB, BF, GR, 2>(t, x, Q, qdev, b2, kp, sb, f, g, s);
             [[fallthrough]];
         default:
-            return query_launch<CB, BF, GR, 1>(t, x, Q, b2, kp, sb, f, g, s);
+            return query_launch<CB, BF, GR, 1>(t, x, Q, qdev, b2, kp, sb, f, g, s);
     }
 }
 
 template <int CB>
-dps_status query_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
+dps_status query_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
                        float *f, float *g, hipStream_t s) {
     const bool bf = t->storage == DPS_STORE_BF16;
     const int k = t->packet_query;
-    if (bf && g) return query_k<CB, true, true>(t, k, x, Q, b2, kp, sb, f, g, s);
-    if (bf) return query_k<CB, true, false>(t, k, x, Q, b2, kp, sb, f, g, s);
-    if (g) return query_k<CB, false, true>(t, k, x, Q, b2, kp, sb, f, g, s);
-    return query_k<CB, false, false>(t, k, x, Q, b2, kp, sb, f, g, s);
+    if (bf && g) return query_k<CB, true, true>(t, k, x, Q, qdev, b2, kp, sb, f, g, s);
+    if (bf) return query_k<CB, true, false>(t, k, x, Q, qdev, b2, kp, sb, f, g, s);
+    if (g) return query_k<CB, false, true>(t, k, x, Q, qdev, b2, kp, sb, f, g, s);
+    return query_k<CB, false, false>(t, k, x, Q, qdev, b2, kp, sb, f, g, s);
 }
 
 template <int CB, bool BF, int K>
-dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
+dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
                           const float *df, float *dx, int dx_mode, hipStream_t s) {
     const uint32_t lim = (uint32_t)t->N;
     if (t->launch_flags & kFlagPersistentAdjoint) {
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_adjoint_persistent<CB, BF, K>);
         k_adjoint_persistent<CB, BF, K><<<persistent_grid(fn), kThreads, 0, s>>>(
-            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, b2, kp, sb.c0, sb.ldo, sb.co,
+            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
             lim, t->err, t->C, df, t->G, t->P, dx, dx_mode, t->ctr + 8);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdAdjoint) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
         k_adjoint<CB, BF, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
-                                                     t->attr_stride, x, Q, b2, kp, sb.c0, sb.ldo, sb.co, lim,
+                                                     t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co, lim,
                                                      t->err, t->C, df, t->G, t->P, dx, dx_mode,
                                                      remap ? (int)nb : 0);
     }
@@ -826,23 +838,23 @@ dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, float b2, Ke
 }
 
 template <int CB>
-dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, float b2, KernelParams kp, Sub sb,
+dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
                          const float *df, float *dx, int dx_mode, hipStream_t s) {
     const int k = clamp_packet(t->packet_adjoint, CB, false);
     if (t->storage == DPS_STORE_BF16) {
-        if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, true, 4>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); }
-        if (k >= 2) return adjoint_launch<CB, true, 2>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s);
-        return adjoint_launch<CB, true, 1>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s);
+        if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, true, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); }
+        if (k >= 2) return adjoint_launch<CB, true, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
+        return adjoint_launch<CB, true, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
     }
-    if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, false, 4>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); }
-    if (k >= 2) return adjoint_launch<CB, false, 2>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s);
-    return adjoint_launch<CB, false, 1>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s);
+    if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, false, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); }
+    if (k >= 2) return adjoint_launch<CB, false, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
+    return adjoint_launch<CB, false, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
 }
 
 }  // namespace
 
-dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, int cbegin, int nc,
-                        float *f, float *g, hipStream_t s) {
+dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
+                        int cbegin, int nc, float *f, float *g, hipStream_t s) {
     const float b2 = mul_rn(beta, beta);
     const KernelParams kp = make_kernel_params(eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
@@ -850,11 +862,11 @@ dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, float beta, fl
         const Sub sb{c0, nc, c0 - cbegin};
         dps_status st;
         switch (cb) {
-            case 8: st = query_block<8>(t, x, Q, b2, kp, sb, f, g, s); break;
-            case 4: st = query_block<4>(t, x, Q, b2, kp, sb, f, g, s); break;
-            case 3: st = query_block<3>(t, x, Q, b2, kp, sb, f, g, s); break;
-            case 2: st = query_block<2>(t, x, Q, b2, kp, sb, f, g, s); break;
-            default: st = query_block<1>(t, x, Q, b2, kp, sb, f, g, s); break;
+            case 8: st = query_block<8>(t, x, Q, qdev, b2, kp, sb, f, g, s); break;
+            case 4: st = query_block<4>(t, x, Q, qdev, b2, kp, sb, f, g, s); break;
+            case 3: st = query_block<3>(t, x, Q, qdev, b2, kp, sb, f, g, s); break;
+            case 2: st = query_block<2>(t, x, Q, qdev, b2, kp, sb, f, g, s); break;
+            default: st = query_block<1>(t, x, Q, qdev, b2, kp, sb, f, g, s); break;
         }
         if (st != DPS_OK) return st;
         c0 += cb;
@@ -868,8 +880,8 @@ dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta, i
     return hip_status(hipGetLastError(), "counts launch");
 }
 
-dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, int cbegin, int nc,
-                          const float *df, float *dx, hipStream_t s) {
+dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
+                          int cbegin, int nc, const float *df, float *dx, hipStream_t s) {
     const float b2 = mul_rn(beta, beta);
     const KernelParams kp = make_kernel_params(eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
@@ -878,11 +890,11 @@ dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, float beta, 
         const Sub sb{c0, nc, c0 - cbegin};
         dps_status st;
         switch (cb) {
-            case 8: st = adjoint_block<8>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
-            case 4: st = adjoint_block<4>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
-            case 3: st = adjoint_block<3>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
-            case 2: st = adjoint_block<2>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
-            default: st = adjoint_block<1>(t, x, Q, b2, kp, sb, df, dx, dx_mode, s); break;
+            case 8: st = adjoint_block<8>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
+            case 4: st = adjoint_block<4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
+            case 3: st = adjoint_block<3>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
+            case 2: st = adjoint_block<2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
+            default: st = adjoint_block<1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
         }
         if (st != DPS_OK) return st;
         c0 += cb;

@@ -68,12 +68,12 @@ dps_status tree_alloc(dps_tree_s *t, T **ptr, size_t count) {
 dps_status build_tree(dps_tree_s *t, const float *p, const float *n, const float *A,
                       hipStream_t s);
 dps_status refit_moments(dps_tree_s *t, const float *attrs, hipStream_t s);
-dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, int cbegin, int nc,
-                        float *f, float *g, hipStream_t s);
+dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
+                        int cbegin, int nc, float *f, float *g, hipStream_t s);
 dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta,
                          int32_t *counts, hipStream_t s);
-dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, float beta, float eps, int cbegin, int nc,
-                          const float *df, float *dx, hipStream_t s);
+dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
+                          int cbegin, int nc, const float *df, float *dx, hipStream_t s);
 dps_status launch_zero(dps_tree_s *t, hipStream_t s);
 dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s);
 dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *moments,

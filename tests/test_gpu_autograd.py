@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads
-from render_proxy import fd_linear, fd_position, loss_numpy, loss_torch
+from workloads.render import fd_linear, fd_position, loss_numpy, loss_torch
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +34,7 @@ def test_sfm_1m_autograd_matches_fd(orc):
     tree = P.dps_build(dev(p), dev(n), dev(A), dev(mu), leaf_size=16)
     attrs_t = dev(mu).requires_grad_(True)
     x_t = dev(x).requires_grad_(True)
-    f, g = P.DipoleSum.apply(attrs_t, x_t, tree, BETA, EPS)
+    f, g = P.dipole_sum(attrs_t, x_t, tree, BETA, EPS)
     L = loss_torch(f.double(), R, S, dev(target))
     L.backward()
     ga = attrs_t.grad.cpu().numpy().astype(np.float64)

@@ -497,7 +497,7 @@ def test_bh_adjoint_through_render_loss_matches_fd(orc):
     # differences of the same loss: attributes perturbed through linearity,
     # sample positions perturbed and re-queried
     import torch
-    from render_proxy import fd_linear, fd_position, loss_numpy, loss_torch
+    from workloads.render import fd_linear, fd_position, loss_numpy, loss_torch
     p, n, A, mu = workloads.sfm_cloud(20000, 1000, 10)
     R, S, eps, h = 16, 64, 0.03, 1e-4
     pix, x = workloads.pixel_ray_samples(workloads.sfm_camera(11), 64, 64, S, 12, R, 14)
