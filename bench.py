@@ -11,16 +11,25 @@ One step = one training iteration of the hot path: moment refit from the
 attributes (dps_set_attributes), primal query with gradients (dps_query), and
 the two-stage adjoint (dps_adjoint_zero / _accumulate / _finalize) with
 dL/df ~ N(0,1).  The tree itself is built once (points are fixed) and its
-build time is reported separately.  value = Q / (time per step).
+build time is reported separately.  value = Q / (time per step), FP32-stored
+attributes and moments, eager launches.  The same step is also timed with
+BF16 storage, eager and captured in one graph.
 
-    python bench.py [--steps K] [--warmup W] [--storage fp32|bf16|both]
+Batched workload (sfm-8m, reported under "batched"): 8,388,608 points, 8 views
+of 256^2 .. 1024^2 rays x 128 samples (438,829,056 primary samples), one shadow
+ray of 64 samples per primary hit, BF16 storage, persistent autotuned
+launches, the whole forward + backward of the render proxy in one graph.
+
+    python bench.py [--steps K] [--warmup W] [--storage fp32|bf16|both] [--no-batched]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -54,7 +63,56 @@ def flops_adj(C):
 
 
 MI355X_FP32_VECTOR_TFLOPS = 157.3   # published peak (packed FP32)
+MI355X_FP32_VECTOR_NONPACKED_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 MI355X_HBM_TBS = 8.0
+
+# sources that determine the traversal kernels; the HBM byte counters committed
+# under profiles/ are used only while these are unchanged
+KERNEL_SOURCES = ("paper_2405_16788_amd/csrc/dps_traverse.hip", "paper_2405_16788_amd/csrc/dps_internal.h",
+                  "paper_2405_16788_amd/csrc/dps_tree.h")
+COUNTER_SUMMARY = "profiles/sfm1m_fp32_hbm_counters.md"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(kernel, packet, storage):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or (None, reason)."""
+    path = os.path.join(ROOT, COUNTER_SUMMARY)
+    try:
+        text = open(path).read()
+    except OSError:
+        return None, "no committed counter summary"
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None, "counter summary has no data block"
+    d = json.loads(m.group(1))
+    if d.get("source_sha256") != kernel_source_hash():
+        return None, "kernel sources changed since the counters were taken"
+    if d.get("storage") != storage or d.get("packet") != packet:
+        return None, f"counters taken at {d.get('storage')} {d.get('packet')}, timed run used {storage} {packet}"
+    k = d.get("kernels", {}).get(kernel)
+    if not k:
+        return None, f"no counters for {kernel}"
+    return k["read_bytes"] + k["write_bytes"], COUNTER_SUMMARY
+
+
+# algorithmic bytes per query (fp32 storage s = 4): 32 B node record per
+# visit, 12 C s per far-field moment, (32 + C s) per near point, plus I/O;
+# the adjoint adds the scatter read-modify-write of 2 x 4 x 3C per far node
+# and 2 x 4 x C per near point (before any aggregation)
+def bytes_fwd(C, s=4):
+    return {"visit": 32, "far": 12 * C * s, "near": 32 + C * s, "io": 12 + 16 * C}
+
+
+def bytes_adj(C, s=4):
+    return {"visit": 32, "far": 12 * C * s + 24 * C, "near": 32 + C * s + 8 * C, "io": 12 + 4 * C + 12}
 
 
 def parse():
@@ -70,6 +128,10 @@ def parse():
                     help="launch shape 'query_k,adjoint_k[,flags]' (e.g. 2,4,3) or 'auto' (autotuned)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a 1 GiB device fill + copy (calibrates HBM byte counters)")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-captured BF16 variant")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 8M-point workload")
+    ap.add_argument("--batched-only", action="store_true", help="only run the batched workload")
+    ap.add_argument("--batched-steps", type=int, default=3)
     return ap.parse_args()
 
 
@@ -89,7 +151,7 @@ def make_inputs(res):
     return p, n, A, attrs, x, df, np
 
 
-def time_storage(P, dev_in, storage, steps, warmup, packet):
+def time_storage(P, dev_in, storage, steps, warmup, packet, graph=False):
     import torch
     p, n, A, attrs, x, df = dev_in
     Q, C = x.shape[0], attrs.shape[1]
@@ -142,12 +204,116 @@ def time_storage(P, dev_in, storage, steps, warmup, packet):
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(end)
     per = {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in ev.items()}
+    graph_ms = None
+    if graph:
+        # the same step captured once and replayed
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step(False)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        cg = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(cg):
+            step(False)
+        for _ in range(max(warmup, 1)):
+            cg.replay()
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(steps):
+            cg.replay()
+        end.record()
+        torch.cuda.synchronize()
+        graph_ms = start.elapsed_time(end) / steps
+        del cg
     counts = P.dps_query_counts(tree, x, BETA)
     csum = counts.to(torch.int64).sum(0).tolist()
     info = P.dps_tree_info(tree)
     P.dps_destroy(tree)
-    return {"ms_per_step": total_ms / steps, "build_ms": build_ms, "kernel_ms": per,
+    return {"ms_per_step": total_ms / steps, "graph_ms_per_step": graph_ms, "build_ms": build_ms, "kernel_ms": per,
             "counts_total": csum, "tree": info, "packet": {"query": tuned["query"], "adjoint": tuned["adjoint"], "flags": tuned["flags"]}}
+
+
+def time_batched(P, steps, warmup):
+    """The batched multi-view + shadow-ray step (see the module docstring),
+    eager once and then as replays of one captured graph."""
+    import torch
+    import workloads
+    from workloads import render as R
+    from paper_2405_16788_amd import autotune
+    t0 = time.time()
+    p, n, A, attrs = workloads.sfm_8m_cloud()
+    batch = workloads.make_ray_batch()
+    dev = [torch.from_numpy(a).cuda() for a in (p, n, A, attrs)]
+    M, C = p.shape[0], attrs.shape[1]
+    del p, n, A, attrs
+    log(f"[bench] batched inputs generated in {time.time() - t0:.1f}s: M={M} primaries={batch.Q} "
+        f"rays={batch.n_rays}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tree = P.dps_build(*dev, leaf_size=LEAF, storage="bf16")
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    attrs_d = dev[3]
+    del dev
+    n_tune = min(batch.Q, 1 << 25)  # a contiguous slice (the first views) of the primaries
+    df = torch.ones((n_tune, C), device="cuda")
+    tuned = autotune.tune(tree, batch.x[:n_tune], df, BETA, EPS, sample=n_tune, cache="", verbose=True)
+    del df
+
+    def step():
+        a = attrs_d.detach().requires_grad_(True)
+        xl = batch.x.detach().requires_grad_(True)
+        loss, aux = R.batched_forward(P.dipole_sum, a, xl, tree, batch, BETA, EPS)
+        da, dx = torch.autograd.grad(loss, [a, xl])
+        return loss.detach(), aux, da, dx
+
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        out = step()  # warm-up (allocator, kernels)
+        del out
+        torch.cuda.synchronize()
+        start.record(side)
+        out = step()
+        end.record(side)
+        torch.cuda.synchronize()
+        eager_ms = start.elapsed_time(end)
+        n_hits, q_count = int(out[1]["n_hits"]), int(out[1]["q_count"][0])
+        del out
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        g_out = step()
+    for _ in range(max(warmup, 1)):
+        graph.replay()
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        graph.replay()
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    if int(g_out[1]["n_hits"]) != n_hits:
+        raise RuntimeError("graph replay found a different number of hits than the eager step")
+    P.dps_check(tree)
+    info = P.dps_tree_info(tree)
+    del graph, g_out
+    P.dps_destroy(tree)
+    K = batch.S_shadow
+    queries = batch.Q + n_hits * K
+    return {"value": queries / (ms * 1e-3), "unit": "queries/s", "ms_per_step": ms, "eager_ms_per_step": eager_ms,
+            "steps": steps, "queries_per_step": queries, "primary_queries": batch.Q,
+            "shadow_rays": n_hits, "shadow_queries": n_hits * K, "shadow_rows_evaluated": q_count,
+            "build_ms": build_ms, "tree_nodes": info["n_nodes"], "tree_depth": info["depth"],
+            "storage": "bf16", "packet": {"query": tuned["query"], "adjoint": tuned["adjoint"], "flags": tuned["flags"]},
+            "workload": f"sfm-8m: {M} points, views {'/'.join(str(r) for r in batch.res)} squared x "
+                        f"{batch.S} samples = {batch.Q} primary samples + {K} per shadow ray, C={C}, "
+                        f"beta={BETA}, eps={EPS:.5f}, leaf {LEAF}",
+            "step": "refit + primary query (values, gradients) + hit search + shadow query (channel 0, device "
+                    "row count) + render proxy + backward (both adjoints, autograd of the proxy), one graph"}
 
 
 def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
@@ -203,6 +369,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.batched_only:
+        b = time_batched(P, args.batched_steps, args.warmup)
+        print(json.dumps({"metric": "batched dipole-sum queries/sec fwd+adjoint, 8M pts, 8 views + shadow rays, "
+                                    "BF16-stored, one graph", "value": b["value"], "unit": "queries/s", "n_gpus": 1,
+                          "steps": args.batched_steps, "warmup": args.warmup, "ms_per_step": b["ms_per_step"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                          "data": "synthetic", "config": {"workload": b["workload"]}, "batched": b}), flush=True)
+        return
     p, n, A, attrs, x, df, np = make_inputs(args.res)
     dev_in = [torch.from_numpy(a).cuda() for a in (p, n, A, attrs, x, df)]
     Q, C = x.shape[0], attrs.shape[1]
@@ -210,17 +384,27 @@ def main():
     res = {}
     for st in storages:
         log(f"[bench] timing storage={st}")
-        res[st] = time_storage(P, dev_in, st, args.steps, args.warmup, args.packet)
-        log(f"[bench] {st}: {res[st]['ms_per_step']:.2f} ms/step, kernels {res[st]['kernel_ms']}")
+        res[st] = time_storage(P, dev_in, st, args.steps, args.warmup, args.packet,
+                               graph=(st == "bf16" and not args.no_graph))
+        log(f"[bench] {st}: {res[st]['ms_per_step']:.2f} ms/step (graph {res[st]['graph_ms_per_step']}), "
+            f"kernels {res[st]['kernel_ms']}")
+    del dev_in
     main_st = "fp32" if "fp32" in res else storages[0]
     r = res[main_st]
     visits, nfar, leaves, near = r["counts_total"]
     ffw, fad = flops_fwd(C), flops_adj(C)
     fl_q = ffw["test"] * visits + ffw["far"] * nfar + ffw["near"] * near
     fl_a = fad["test"] * visits + fad["far"] * nfar + fad["near"] * near
+    bfw, bad = bytes_fwd(C), bytes_adj(C)
+    by_q = bfw["visit"] * visits + bfw["far"] * nfar + bfw["near"] * near + bfw["io"] * Q
+    by_a = bad["visit"] * visits + bad["far"] * nfar + bad["near"] * near + bad["io"] * Q
     kq, ka = r["kernel_ms"]["query"], r["kernel_ms"]["adjoint_accumulate"]
-    dom, fl, ms = ("adjoint_accumulate", fl_a, ka) if ka >= kq else ("query", fl_q, kq)
+    dom, fl, by, ms = ("adjoint_accumulate", fl_a, by_a, ka) if ka >= kq else ("query", fl_q, by_q, kq)
     achieved = fl / (ms * 1e-3) / 1e12
+    pk = r["packet"]
+    kname = ("k_adjoint" if dom == "adjoint_accumulate" else "k_query") + (
+        "_persistent" if pk["flags"] & (8 if dom == "adjoint_accumulate" else 4) else "")
+    traffic, traffic_src = committed_traffic(kname, [pk["query"], pk["adjoint"], pk["flags"]], main_st)
     out = {
         "metric": METRIC,
         "value": Q / (r["ms_per_step"] * 1e-3),
@@ -239,8 +423,16 @@ def main():
                    "storage": main_st, "step": "refit + query(values, gradients) + adjoint(zero, "
                                                "accumulate, finalize)"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": MI355X_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_VECTOR_TFLOPS, "traffic": None,
-                     "flops_per_launch": fl, "avg_launch_ms": ms},
+                     "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_VECTOR_TFLOPS, "traffic": traffic,
+                     "traffic_source": traffic_src, "flops_per_launch": fl, "avg_launch_ms": ms,
+                     "peak_nonpacked": MI355X_FP32_VECTOR_NONPACKED_TFLOPS,
+                     "frac_nonpacked": achieved / MI355X_FP32_VECTOR_NONPACKED_TFLOPS,
+                     "hbm_achieved_GBps": (traffic / (ms * 1e-3) / 1e9) if traffic else None},
+        "roofline_hbm_algorithmic": {
+            "kernel": dom, "bytes_per_launch": by, "achieved": by / (ms * 1e-3) / 1e9, "peak": MI355X_HBM_TBS * 1e3,
+            "unit": "GB/s", "frac": by / (ms * 1e-3) / 1e9 / (MI355X_HBM_TBS * 1e3),
+            "note": "bytes the method touches if nothing were shared; coherent wavefronts share node and moment "
+                    "loads through the caches, so this exceeds HBM peak"},
         "per_query": {"nodes_visited": visits / Q, "far_nodes": nfar / Q, "leaves_opened": leaves / Q,
                       "near_points": near / Q},
     }
@@ -249,9 +441,22 @@ def main():
                                "kernel_ms": rr["kernel_ms"], "build_ms": rr["build_ms"],
                                "tree_nodes": rr["tree"]["n_nodes"], "tree_bytes": rr["tree"]["bytes"],
                                "packet": rr["packet"]}
+        if rr["graph_ms_per_step"]:
+            out[f"{st}_stored_graph"] = {"value": Q / (rr["graph_ms_per_step"] * 1e-3),
+                                         "ms_per_step": rr["graph_ms_per_step"],
+                                         "step": "the same step captured in one graph and replayed"}
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(np, p, n, A, attrs, x, df, args.cpu_seconds)
+    del p, n, A, attrs, x, df
+    if not args.no_batched:
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        log("[bench] batched workload")
+        out["batched"] = time_batched(P, args.batched_steps, args.warmup)
+        log(f"[bench] batched: {out['batched']['ms_per_step']:.1f} ms/step, "
+            f"{out['batched']['value'] / 1e6:.1f} M queries/s")
     print(json.dumps(out), flush=True)
 
 

@@ -53,6 +53,8 @@ def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=Fal
         best = table[key]
         B.dps_set_launch(tree, best["query"], best["adjoint"], best["flags"])
         return best
+    if df.shape[0] != x.shape[0] or df.shape[1] != tree.C:
+        raise ValueError("df must hold one row of tree.C cotangents per query of x")
     n = min(x.shape[0], sample)
     # a contiguous slice keeps the spatial coherence of the caller's layout
     start = (x.shape[0] - n) // 2 // 256 * 256
