@@ -160,6 +160,8 @@ __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &
 // ---------------------------------------------------------------------------
 // wavefront (64-lane) reductions with DPP; every lane must be active
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ float dpp_f(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
@@ -176,6 +178,103 @@ __device__ __forceinline__ float wave_sum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// ---------------------------------------------------------------------------
+// Reduce-scatter of N <= 16 per-lane values over the 64 lanes.
+//
+// Pairs of lanes exchange half of their partial sums at each of the four
+// in-row DPP steps (partners lane^1, lane^2, lane^7, lane^15 inside a row of
+// 16), so the number of values a lane carries halves at each step instead of
+// every value being reduced separately; the four rows are then summed with
+// the gfx950 row-swap permutes.  Every lane ends with the total of one value
+// index, wave_slot<N>(lane); lanes 0 .. P-1 (P the power of two >= N) hold
+// distinct indices.  The "upper half" bit of step s is the parity of the lane
+// bits in a_s = {0,2}, {1,2}, {2,3}, {3}: partners differ in it, and agree in
+// the bits of the earlier steps, so they always hold the same index set.
+// ---------------------------------------------------------------------------
+template <int N_>
+constexpr int scatter_width() { return N_ <= 1 ? 1 : N_ <= 2 ? 2 : N_ <= 4 ? 4 : N_ <= 8 ? 8 : 16; }
+
+__device__ __forceinline__ void scatter_bits(int lane, bool &h0, bool &h1, bool &h2, bool &h3) {
+    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+    h0 = (b0 ^ b2) != 0;
+    h1 = (b1 ^ b2) != 0;
+    h2 = (b2 ^ b3) != 0;
+    h3 = b3 != 0;
+}
+
+template <int N_>
+__device__ __forceinline__ int wave_slot(int lane) {
+    constexpr int P = scatter_width<N_>();
+    bool h0, h1, h2, h3;
+    scatter_bits(lane, h0, h1, h2, h3);
+    if (P == 16) return 8 * h0 + 4 * h1 + 2 * h2 + h3;
+    if (P == 8) return 4 * h0 + 2 * h1 + h2;
+    if (P == 4) return 2 * h0 + h1;
+    if (P == 2) return h0;
+    return 0;
+}
+
+// one halving step: W values -> W/2, partner through the DPP control CTRL
+template <int CTRL, int W>
+__device__ __forceinline__ void scatter_step(const float *in, float *out, bool hi) {
+#pragma unroll
+    for (int k = 0; k < W / 2; ++k) {
+        const float keep = hi ? in[k + W / 2] : in[k];
+        const float send = hi ? in[k] : in[k + W / 2];
+        out[k] = keep + dpp_f<CTRL>(send);
+    }
+}
+
+template <int N_>
+__device__ __forceinline__ float wave_sum_scatter(const float (&v)[N_]) {
+    static_assert(N_ >= 1 && N_ <= 16, "at most 16 values per call");
+    constexpr int P = scatter_width<N_>();
+    bool h0, h1, h2, h3;
+    scatter_bits(lane_id(), h0, h1, h2, h3);
+    float a[16], b[8];
+#pragma unroll
+    for (int k = 0; k < P; ++k) a[k] = k < N_ ? v[k] : 0.0f;
+    float r;
+    if constexpr (P == 16) {
+        scatter_step<0xb1, 16>(a, b, h0);
+        scatter_step<0x4e, 8>(b, a, h1);
+        scatter_step<0x141, 4>(a, b, h2);
+        scatter_step<0x140, 2>(b, a, h3);
+        r = a[0];
+    } else if constexpr (P == 8) {
+        scatter_step<0xb1, 8>(a, b, h0);
+        scatter_step<0x4e, 4>(b, a, h1);
+        scatter_step<0x141, 2>(a, b, h2);
+        r = b[0];
+        r += dpp_f<0x140>(r);
+    } else if constexpr (P == 4) {
+        scatter_step<0xb1, 4>(a, b, h0);
+        scatter_step<0x4e, 2>(b, a, h1);
+        r = a[0];
+        r += dpp_f<0x141>(r);
+        r += dpp_f<0x140>(r);
+    } else if constexpr (P == 2) {
+        scatter_step<0xb1, 2>(a, b, h0);
+        r = b[0];
+        r += dpp_f<0x4e>(r);
+        r += dpp_f<0x141>(r);
+        r += dpp_f<0x140>(r);
+    } else {
+        r = a[0];
+        r += dpp_f<0xb1>(r);
+        r += dpp_f<0x4e>(r);
+        r += dpp_f<0x141>(r);
+        r += dpp_f<0x140>(r);
+    }
+    // rows of 16 -> the whole wavefront: swap odd / even rows, then halves
+    const unsigned u = __float_as_uint(r);
+    const auto s16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    const float r2 = __uint_as_float(s16[0]) + __uint_as_float(s16[1]);
+    const unsigned u2 = __float_as_uint(r2);
+    const auto s32 = __builtin_amdgcn_permlane32_swap(u2, u2, false, false);
+    return __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
+}
+
 // Max over the 64 lanes of non-negative values.
 __device__ __forceinline__ float wave_max_nonneg(float v) {
     v = fmaxf(v, dpp_f<0xb1>(v));
@@ -187,6 +286,5 @@ __device__ __forceinline__ float wave_max_nonneg(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 
 }  // namespace dps

@@ -465,12 +465,19 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
     }
 }
 
-template <int N_>
-__device__ __forceinline__ float pick_lane(const float (&v)[N_], int lane) {
-    float r = v[0];
+// Adds the wavefront totals of v[0..N) to dst[0..N) with one FP64 atomic per
+// value: reduce-scatter in chunks of at most 16 values; in each chunk lanes
+// 0 .. P-1 hold distinct values and issue the atomics.
+template <int N_, int B = 0>
+__device__ __forceinline__ void scatter_add_node(const float (&v)[N_], int lane, double *dst) {
+    constexpr int W = (N_ - B) < 16 ? (N_ - B) : 16;
+    float part[W];
 #pragma unroll
-    for (int i = 1; i < N_; ++i) r = lane == i ? v[i] : r;
-    return r;
+    for (int k = 0; k < W; ++k) part[k] = v[B + k];
+    const float tot = wave_sum_scatter<W>(part);
+    const int slot = wave_slot<W>(lane);
+    if (lane < scatter_width<W>() && slot < W) atomicAdd(&dst[B + slot], (double)tot);
+    if constexpr (B + 16 < N_) scatter_add_node<N_, B + 16>(v, lane, dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -555,11 +562,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                     az[i] = fmaf(-kap, E2, fmaf(les, dz, az[i]));
                 }
             }
-            float red[3 * CB];
-#pragma unroll
-            for (int v = 0; v < 3 * CB; ++v) red[v] = wave_sum(acc[v]);
-            const float val = pick_lane(red, lane);
-            if (lane < 3 * CB) atomicAdd(&G[((size_t)t * C + c0) * 3 + lane], (double)val);
+            scatter_add_node(acc, lane, &G[((size_t)t * C + c0) * 3]);
         }
         if (any_open) {
             if (!leaf) {
@@ -598,11 +601,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                             }
                         }
                     }
-                    float red[CB];
-#pragma unroll
-                    for (int c = 0; c < CB; ++c) red[c] = wave_sum(acc[c]);
-                    const float val = pick_lane(red, lane);
-                    if (lane < CB) atomicAdd(&P[(size_t)j * C + c0 + lane], (double)val);
+                    scatter_add_node(acc, lane, &P[(size_t)j * C + c0]);
                 }
             }
         }
@@ -643,7 +642,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(DPS_KERN_PARAMS, int C, co
 }
 
 template <int CB, bool BF16, int K>
-__global__ __launch_bounds__(kThreads) void k_adjoint_persistent(DPS_KERN_PARAMS, int C,
+__global__ __launch_bounds__(kThreads, (CB == 4 && K == 4) ? 5 : 1) void k_adjoint_persistent(DPS_KERN_PARAMS, int C,
                                                                  const float *__restrict__ df,
                                                                  double *__restrict__ G, double *__restrict__ P,
                                                                  float *__restrict__ dxout, int dx_mode,
