@@ -81,9 +81,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def committed_traffic(kernel, packet, storage):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or (None, reason)."""
+def committed_traffic(kernel, k, persistent, storage):
+    """HBM bytes per launch of ``kernel`` (queries per lane k, persistent or
+    not) from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
+    copy-calibrated), or (None, reason)."""
     path = os.path.join(ROOT, COUNTER_SUMMARY)
     try:
         text = open(path).read()
@@ -95,12 +96,13 @@ def committed_traffic(kernel, packet, storage):
     d = json.loads(m.group(1))
     if d.get("source_sha256") != kernel_source_hash():
         return None, "kernel sources changed since the counters were taken"
-    if d.get("storage") != storage or d.get("packet") != packet:
-        return None, f"counters taken at {d.get('storage')} {d.get('packet')}, timed run used {storage} {packet}"
-    k = d.get("kernels", {}).get(kernel)
-    if not k:
+    e = d.get("kernels", {}).get(kernel)
+    if not e:
         return None, f"no counters for {kernel}"
-    return k["read_bytes"] + k["write_bytes"], COUNTER_SUMMARY
+    if d.get("storage") != storage or e.get("k") != k or e.get("persistent") != persistent:
+        return None, (f"counters taken at {d.get('storage')} k={e.get('k')} persistent={e.get('persistent')}, "
+                      f"timed run used {storage} k={k} persistent={persistent}")
+    return e["read_bytes"] + e["write_bytes"], COUNTER_SUMMARY
 
 
 # algorithmic bytes per query (fp32 storage s = 4): 32 B node record per
@@ -402,9 +404,13 @@ def main():
     dom, fl, by, ms = ("adjoint_accumulate", fl_a, by_a, ka) if ka >= kq else ("query", fl_q, by_q, kq)
     achieved = fl / (ms * 1e-3) / 1e12
     pk = r["packet"]
-    kname = ("k_adjoint" if dom == "adjoint_accumulate" else "k_query") + (
-        "_persistent" if pk["flags"] & (8 if dom == "adjoint_accumulate" else 4) else "")
-    traffic, traffic_src = committed_traffic(kname, [pk["query"], pk["adjoint"], pk["flags"]], main_st)
+    adj = dom == "adjoint_accumulate"
+    persistent = bool(pk["flags"] & (8 if adj else 4))
+    kname = ("k_adjoint" if adj else "k_query") + ("_persistent" if persistent else "")
+    # queries per lane the kernel ran with: the query with gradients over 4
+    # channels runs packets of 4 as 2
+    k_run = pk["adjoint"] if adj else min(pk["query"], 2)
+    traffic, traffic_src = committed_traffic(kname, k_run, persistent, main_st)
     out = {
         "metric": METRIC,
         "value": Q / (r["ms_per_step"] * 1e-3),

@@ -641,8 +641,14 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(DPS_KERN_PARAMS, int C, co
     adjoint_body<CB, BF16, K>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout, dx_mode);
 }
 
+// resident waves per SIMD requested for the 4-query, 4-channel persistent
+// adjoint (a register budget of 96; measured faster than the unbounded 4)
+#ifndef DPS_ADJOINT_WAVES
+#define DPS_ADJOINT_WAVES 5
+#endif
+
 template <int CB, bool BF16, int K>
-__global__ __launch_bounds__(kThreads, (CB == 4 && K == 4) ? 5 : 1) void k_adjoint_persistent(DPS_KERN_PARAMS, int C,
+__global__ __launch_bounds__(kThreads, (CB == 4 && K == 4) ? DPS_ADJOINT_WAVES : 1) void k_adjoint_persistent(DPS_KERN_PARAMS, int C,
                                                                  const float *__restrict__ df,
                                                                  double *__restrict__ G, double *__restrict__ P,
                                                                  float *__restrict__ dxout, int dx_mode,
