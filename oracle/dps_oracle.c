@@ -40,6 +40,17 @@
  *              eq. (farfield_gradient); the second stage applies eq.
  *              (farfield_features_gradient) to every point through all its
  *              ancestors (evaluated as a top-down running sum).
+ *  gradient    cotangents h of the spatial gradient g (needed when a loss uses
+ *  cotangent   grad D, as the surface density of Sec. 3.1, eq.
+ *              (surface_density) does): g is linear in each source dipole D
+ *              with d g / d D = lambda d d^T - kappa I, and its x-derivative
+ *              is the Hessian of the term,
+ *                nu s d d^T - lambda (d D^T + D d^T) - lambda s I,
+ *              s = D.d, nu = -lambda'(r)/r = chi(t)/(4 pi r^7),
+ *              chi(t) = 5 psi(t) - t psi'(t)
+ *                     = 15 rho(t) - (4/sqrt(pi)) (5 t^3 + 2 t^5) exp(-t^2).
+ *              The paper does not write these; they are the derivatives of
+ *              its terms, taken through the same accepted sources.
  *
  * Precision: everything is FP64 except two things that the GPU must decide
  * bit-identically: the far test, evaluated in FP32 as
@@ -89,6 +100,20 @@ static double psi_over_t5_series(double t2)
     return 8.0 / ORC_SQRT_PI * sum;
 }
 
+/* chi(t)/t^7 from the same series (the n = 1, 2 terms of 5 psi - t psi'
+ * vanish):  chi(t)/t^7 = (16/sqrt(pi)) sum_{n>=3} (-1)^{n+1} t^{2n-6}
+ * / ((n-3)! (2n+1)). */
+static double chi_over_t7_series(double t2)
+{
+    double sum = 0.0, pw = 1.0, fact = 1.0;
+    for (int n = 3; n <= 18; ++n) {
+        if (n > 3) { fact *= (double)(n - 3); pw *= t2; }
+        double c = pw / (fact * (double)(2 * n + 1));
+        sum += (n & 1) ? c : -c;
+    }
+    return 16.0 / ORC_SQRT_PI * sum;
+}
+
 double orc_rho(double t)
 {
     if (t < 0.5) return rho_over_t3_series(t * t) * t * t * t;
@@ -101,6 +126,15 @@ double orc_psi(double t)
     double rho = erf(t) - 2.0 * t / ORC_SQRT_PI * exp(-t * t);
     return 3.0 * rho - 4.0 / ORC_SQRT_PI * t * t * t * exp(-t * t);
 }
+
+double orc_chi(double t)
+{
+    if (t < 0.5) return chi_over_t7_series(t * t) * pow(t, 7.0);
+    double ex = exp(-t * t);
+    double rho = erf(t) - 2.0 * t / ORC_SQRT_PI * ex;
+    return 15.0 * rho - 4.0 / ORC_SQRT_PI * (5.0 * t * t * t + 2.0 * pow(t, 5.0)) * ex;
+}
+double orc_chi_series(double t) { return chi_over_t7_series(t * t) * pow(t, 7.0); }
 
 /* Exposed for the pins: the series branch and the closed-form branch. */
 double orc_rho_series(double t) { return rho_over_t3_series(t * t) * t * t * t; }
@@ -136,6 +170,39 @@ static void radial(double r, double eps, double *kappa, double *lambda)
 void orc_radial(double r, double eps, double *kappa, double *lambda)
 {
     radial(r, eps, kappa, lambda);
+}
+
+/* nu = chi(r/eps)/(4 pi r^7) (eps = 0: chi = 15); finite at r = 0 for eps > 0. */
+static double radial_nu(double r, double eps)
+{
+    if (eps == 0.0) return 15.0 / (4.0 * ORC_PI * pow(r, 7.0));
+    double t = r / eps;
+    if (t < 0.5) return chi_over_t7_series(t * t) / (4.0 * ORC_PI * pow(eps, 7.0));
+    return orc_chi(t) / (4.0 * ORC_PI * pow(r, 7.0));
+}
+
+double orc_radial_nu(double r, double eps) { return radial_nu(r, eps); }
+
+/* Cotangent h of the gradient of one source term with dipole D at offset
+ * d = c - x (radial factors kap, lam, nu):
+ *   dD += lambda (d.h) d - kappa h          (the term's derivative in D)
+ *   dx += nu s (d.h) d - lambda (d (D.h) + D (d.h)) - lambda s h
+ * and the matching absolute scales. */
+static void grad_cotangent(const double d[3], double r, double kap, double lam, double nu,
+                           const double D[3], const double h[3], double dD[3], double dx[3],
+                           double *sdD, double *sdx)
+{
+    double s = D[0] * d[0] + D[1] * d[1] + D[2] * d[2];
+    double dh = d[0] * h[0] + d[1] * h[1] + d[2] * h[2];
+    double Dh = D[0] * h[0] + D[1] * h[1] + D[2] * h[2];
+    for (int k = 0; k < 3; ++k) {
+        if (dD) dD[k] += lam * dh * d[k] - kap * h[k];
+        if (dx) dx[k] += nu * s * dh * d[k] - lam * (d[k] * Dh + D[k] * dh) - lam * s * h[k];
+    }
+    double nh = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
+    double nD = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    if (sdD) *sdD += nh * (fabs(lam) * r * r + kap);
+    if (sdx) *sdx += nh * nD * (fabs(nu) * r * r * r + 3.0 * fabs(lam) * r);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -213,14 +280,18 @@ int orc_direct(const float *p, const float *n, const float *A, const float *mu,
     return 0;
 }
 
-/* Exact transpose of orc_direct: given df[Q][C],
- *   dmu[m][c] = sum_q df[q][c] A_m kappa_qm (n_m . d_qm),
- *   dx[q]     = sum_m sum_c df[q][c] (-kappa D_mc + lambda (D_mc . d) d). */
+/* Exact transpose of orc_direct: given df[Q][C] and (optionally, may be
+ * NULL) the gradient cotangents dg[Q][C][3],
+ *   dmu[m][c] = sum_q df[q][c] A_m kappa_qm (n_m . d_qm)
+ *             + sum_q A_m n_m . (lambda (d.h) d - kappa h),   h = dg[q][c],
+ *   dx[q]     = sum_m sum_c df[q][c] (-kappa D_mc + lambda (D_mc . d) d)
+ *             + sum_m sum_c (Hessian of the term) h.
+ * df may be NULL when dg is given (value cotangents zero). */
 int orc_direct_adjoint(const float *p, const float *n, const float *A, const float *mu,
                        int64_t M, int C, const float *x, int64_t Q, double eps,
-                       const float *df, double *dmu, double *dx, int nthreads)
+                       const float *df, const float *dg, double *dmu, double *dx, int nthreads)
 {
-    if (M < 0 || Q < 0 || C < 1 || C > 64 || eps < 0) return 1;
+    if (M < 0 || Q < 0 || C < 1 || C > 64 || eps < 0 || (!df && !dg)) return 1;
     int nt = nthreads_or_default(nthreads);
     if (dx) {
 #pragma omp parallel for schedule(static) num_threads(nt)
@@ -232,12 +303,26 @@ int orc_direct_adjoint(const float *p, const float *n, const float *A, const flo
                 double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
                 if (r2 == 0.0 && eps == 0.0) continue;
                 double kap, lam;
-                radial(sqrt(r2), eps, &kap, &lam);
-                double w = 0;
-                for (int ch = 0; ch < C; ++ch) w += (double)df[q * C + ch] * (double)mu[m * C + ch];
-                for (int k = 0; k < 3; ++k) E[k] = w * (double)A[m] * (double)n[3 * m + k];
-                double s = E[0] * d[0] + E[1] * d[1] + E[2] * d[2];
-                for (int k = 0; k < 3; ++k) acc[k] += -kap * E[k] + lam * s * d[k];
+                double r = sqrt(r2);
+                radial(r, eps, &kap, &lam);
+                if (df) {
+                    double w = 0;
+                    for (int ch = 0; ch < C; ++ch) w += (double)df[q * C + ch] * (double)mu[m * C + ch];
+                    for (int k = 0; k < 3; ++k) E[k] = w * (double)A[m] * (double)n[3 * m + k];
+                    double s = E[0] * d[0] + E[1] * d[1] + E[2] * d[2];
+                    for (int k = 0; k < 3; ++k) acc[k] += -kap * E[k] + lam * s * d[k];
+                }
+                if (dg) {
+                    double nu = radial_nu(r, eps);
+                    for (int ch = 0; ch < C; ++ch) {
+                        double D[3], h[3];
+                        for (int k = 0; k < 3; ++k) {
+                            D[k] = (double)A[m] * (double)mu[m * C + ch] * (double)n[3 * m + k];
+                            h[k] = (double)dg[(q * C + ch) * 3 + k];
+                        }
+                        grad_cotangent(d, r, kap, lam, nu, D, h, NULL, acc, NULL, NULL);
+                    }
+                }
             }
             for (int k = 0; k < 3; ++k) dx[3 * q + k] = acc[k];
         }
@@ -254,9 +339,18 @@ int orc_direct_adjoint(const float *p, const float *n, const float *A, const flo
                 if (r2 == 0.0 && eps == 0.0) continue;
                 double kap, lam;
                 radial(sqrt(r2), eps, &kap, &lam);
-                double s = (double)A[m] * ((double)n[3 * m] * d[0] + (double)n[3 * m + 1] * d[1] +
-                                           (double)n[3 * m + 2] * d[2]);
-                for (int ch = 0; ch < C; ++ch) acc[ch] += (double)df[q * C + ch] * kap * s;
+                double An[3] = {(double)A[m] * (double)n[3 * m], (double)A[m] * (double)n[3 * m + 1],
+                                (double)A[m] * (double)n[3 * m + 2]};
+                double s = An[0] * d[0] + An[1] * d[1] + An[2] * d[2];
+                for (int ch = 0; ch < C; ++ch) {
+                    if (df) acc[ch] += (double)df[q * C + ch] * kap * s;
+                    if (dg) {
+                        const float *h = dg + (q * C + ch) * 3;
+                        double dh = d[0] * h[0] + d[1] * h[1] + d[2] * h[2];
+                        double Anh = An[0] * h[0] + An[1] * h[1] + An[2] * h[2];
+                        acc[ch] += lam * dh * s - kap * Anh;
+                    }
+                }
             }
             for (int ch = 0; ch < C; ++ch) dmu[m * C + ch] = acc[ch];
         }
@@ -603,7 +697,8 @@ typedef struct {
     double eps;
     const float *xf;
     double x[3];
-    const double *df;   /* [C] */
+    const double *df;   /* [C] or NULL */
+    const double *dg;   /* [C][3] or NULL */
     double dx[3], sdx;
     double *G;          /* [N][C][3] node gradient accumulators */
     double *H;          /* [N][C] absolute scale of G */
@@ -623,20 +718,28 @@ static void adjoint(astate *st, int64_t i)
         double r = sqrt(r2), kap, lam;
         radial(r, st->eps, &kap, &lam);
         const double *Dt = t->D + i * C * 3;
-        double E[3] = {0, 0, 0};
-        for (int ch = 0; ch < C; ++ch) {
-            double w = st->df[ch] * kap;
-            for (int k = 0; k < 3; ++k) {
-                st->G[(i * C + ch) * 3 + k] += w * d[k];
-                E[k] += st->df[ch] * Dt[3 * ch + k];
+        if (st->df) {
+            double E[3] = {0, 0, 0};
+            for (int ch = 0; ch < C; ++ch) {
+                double w = st->df[ch] * kap;
+                for (int k = 0; k < 3; ++k) {
+                    st->G[(i * C + ch) * 3 + k] += w * d[k];
+                    E[k] += st->df[ch] * Dt[3 * ch + k];
+                }
+                st->H[i * C + ch] += fabs(st->df[ch]) * kap * r;
+                double nD = sqrt(Dt[3 * ch] * Dt[3 * ch] + Dt[3 * ch + 1] * Dt[3 * ch + 1] +
+                                 Dt[3 * ch + 2] * Dt[3 * ch + 2]);
+                st->sdx += fabs(st->df[ch]) * nD * (kap + fabs(lam) * r2);
             }
-            st->H[i * C + ch] += fabs(st->df[ch]) * kap * r;
-            double nD = sqrt(Dt[3 * ch] * Dt[3 * ch] + Dt[3 * ch + 1] * Dt[3 * ch + 1] +
-                             Dt[3 * ch + 2] * Dt[3 * ch + 2]);
-            st->sdx += fabs(st->df[ch]) * nD * (kap + fabs(lam) * r2);
+            double s = E[0] * d[0] + E[1] * d[1] + E[2] * d[2];
+            for (int k = 0; k < 3; ++k) st->dx[k] += -kap * E[k] + lam * s * d[k];
         }
-        double s = E[0] * d[0] + E[1] * d[1] + E[2] * d[2];
-        for (int k = 0; k < 3; ++k) st->dx[k] += -kap * E[k] + lam * s * d[k];
+        if (st->dg) {
+            double nu = radial_nu(r, st->eps);
+            for (int ch = 0; ch < C; ++ch)
+                grad_cotangent(d, r, kap, lam, nu, Dt + 3 * ch, st->dg + 3 * ch, st->G + (i * C + ch) * 3,
+                               st->dx, st->H + i * C + ch, &st->sdx);
+        }
         return;
     }
     if (nd[3] == 0) {
@@ -650,32 +753,47 @@ static void adjoint(astate *st, int64_t i)
             double An[3] = {t->Am[j] * t->nm[3 * j], t->Am[j] * t->nm[3 * j + 1], t->Am[j] * t->nm[3 * j + 2]};
             double s = An[0] * d[0] + An[1] * d[1] + An[2] * d[2];
             double nAn = sqrt(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]);
-            double w = 0;
-            for (int ch = 0; ch < C; ++ch) {
-                double mu = t->mu[j * C + ch];
-                st->P[j * C + ch] += st->df[ch] * kap * s;
-                st->HP[j * C + ch] += fabs(st->df[ch]) * kap * nAn * r;
-                w += st->df[ch] * mu;
-                st->sdx += fabs(st->df[ch]) * fabs(mu) * nAn * (kap + fabs(lam) * r2);
+            if (st->df) {
+                double w = 0;
+                for (int ch = 0; ch < C; ++ch) {
+                    double mu = t->mu[j * C + ch];
+                    st->P[j * C + ch] += st->df[ch] * kap * s;
+                    st->HP[j * C + ch] += fabs(st->df[ch]) * kap * nAn * r;
+                    w += st->df[ch] * mu;
+                    st->sdx += fabs(st->df[ch]) * fabs(mu) * nAn * (kap + fabs(lam) * r2);
+                }
+                double Es = w * s;
+                for (int k = 0; k < 3; ++k) st->dx[k] += -kap * w * An[k] + lam * Es * d[k];
             }
-            double Es = w * s;
-            for (int k = 0; k < 3; ++k) st->dx[k] += -kap * w * An[k] + lam * Es * d[k];
+            if (st->dg) {
+                double nu = radial_nu(r, st->eps);
+                for (int ch = 0; ch < C; ++ch) {
+                    double mu = t->mu[j * C + ch];
+                    double D[3] = {mu * An[0], mu * An[1], mu * An[2]};
+                    double dAn[3] = {0, 0, 0}, sc = 0;
+                    /* derivative in the point's dipole, then through D = mu A n */
+                    grad_cotangent(d, r, kap, lam, nu, D, st->dg + 3 * ch, dAn, st->dx, &sc, &st->sdx);
+                    st->P[j * C + ch] += An[0] * dAn[0] + An[1] * dAn[1] + An[2] * dAn[2];
+                    st->HP[j * C + ch] += sc * nAn;
+                }
+            }
         }
         return;
     }
     for (int64_t c = nd[2]; c < (int64_t)nd[2] + nd[3]; ++c) adjoint(st, c);
 }
 
-/* x: [Q][3] FP32, df: [Q][C] FP32.  Outputs FP64 (any may be NULL):
+/* x: [Q][3] FP32, df: [Q][C] FP32 and/or dg: [Q][C][3] FP32 (either may be
+ * NULL, not both).  Outputs FP64 (any may be NULL):
  * dmu[M][C] in caller point order, dx[Q][3], and the absolute scales
  * sdmu[M][C], sdx[Q] used to normalise errors.  Thread-private accumulators
  * are reduced in a fixed order, so the result is deterministic for a given
  * thread count. */
 int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, double eps,
-                   const float *df, double *dmu, double *dx, double *sdmu, double *sdx,
-                   int nthreads)
+                   const float *df, const float *dg, double *dmu, double *dx, double *sdmu,
+                   double *sdx, int nthreads)
 {
-    if (!t || !t->D || Q < 0 || !(beta > 0) || eps < 0) return 1;
+    if (!t || !t->D || Q < 0 || !(beta > 0) || eps < 0 || (!df && !dg)) return 1;
     int C = t->C;
     int64_t N = t->N, M = t->M;
     int nt = nthreads_or_default(nthreads);
@@ -693,11 +811,14 @@ int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, dou
 #endif
 #pragma omp for schedule(static)
         for (int64_t q = 0; q < Q; ++q) {
-            double dfl[64];
-            for (int ch = 0; ch < C; ++ch) dfl[ch] = (double)df[q * C + ch];
+            double dfl[64], dgl[192];
+            if (df) for (int ch = 0; ch < C; ++ch) dfl[ch] = (double)df[q * C + ch];
+            if (dg) for (int v = 0; v < 3 * C; ++v) dgl[v] = (double)dg[q * C * 3 + v];
             astate st;
             memset(&st, 0, sizeof st);
-            st.t = t; st.b2 = b2; st.eps = eps; st.xf = x + 3 * q; st.df = dfl;
+            st.t = t; st.b2 = b2; st.eps = eps; st.xf = x + 3 * q;
+            st.df = df ? dfl : NULL;
+            st.dg = dg ? dgl : NULL;
             for (int k = 0; k < 3; ++k) st.x[k] = (double)x[3 * q + k];
             st.G = G + (size_t)tid * N * C * 3; st.H = H + (size_t)tid * N * C;
             st.P = P + (size_t)tid * M * C; st.HP = HP + (size_t)tid * M * C;

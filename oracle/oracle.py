@@ -42,9 +42,11 @@ def load():
     lib.orc_rho.argtypes = [ct.c_double]
     lib.orc_psi.restype = ct.c_double
     lib.orc_psi.argtypes = [ct.c_double]
-    for nm in ("orc_rho_series", "orc_psi_series", "orc_rho_closed"):
+    for nm in ("orc_rho_series", "orc_psi_series", "orc_rho_closed", "orc_chi", "orc_chi_series"):
         getattr(lib, nm).restype = ct.c_double
         getattr(lib, nm).argtypes = [ct.c_double]
+    lib.orc_radial_nu.restype = ct.c_double
+    lib.orc_radial_nu.argtypes = [ct.c_double, ct.c_double]
     lib.orc_radial.restype = None
     lib.orc_radial.argtypes = [ct.c_double, ct.c_double, _f64p, _f64p]
     lib.orc_direct.restype = ct.c_int
@@ -52,7 +54,7 @@ def load():
                                vp, vp, vp, vp, ct.c_int]
     lib.orc_direct_adjoint.restype = ct.c_int
     lib.orc_direct_adjoint.argtypes = [vp, vp, vp, vp, ct.c_int64, ct.c_int, vp, ct.c_int64,
-                                       ct.c_double, vp, vp, vp, ct.c_int]
+                                       ct.c_double, vp, vp, vp, vp, ct.c_int]
     lib.orc_tree_build.restype = vp
     lib.orc_tree_build.argtypes = [vp, vp, vp, ct.c_int64, ct.c_int]
     lib.orc_tree_free.restype = None
@@ -70,7 +72,7 @@ def load():
                                  ct.c_int]
     lib.orc_bh_adjoint.restype = ct.c_int
     lib.orc_bh_adjoint.argtypes = [vp, vp, ct.c_int64, ct.c_float, ct.c_double, vp, vp, vp, vp,
-                                   vp, ct.c_int]
+                                   vp, vp, ct.c_int]
     _lib = lib
     return lib
 
@@ -91,6 +93,13 @@ def psi(t): return load().orc_psi(float(t))
 def rho_series(t): return load().orc_rho_series(float(t))
 def psi_series(t): return load().orc_psi_series(float(t))
 def rho_closed(t): return load().orc_rho_closed(float(t))
+def chi(t): return load().orc_chi(float(t))
+def chi_series(t): return load().orc_chi_series(float(t))
+
+
+def radial_nu(r, eps):
+    """nu = chi(r/eps)/(4 pi r^7), the Hessian's radial factor."""
+    return load().orc_radial_nu(float(r), float(eps))
 
 
 def radial(r, eps):
@@ -118,8 +127,9 @@ def direct(p, n, A, mu, x, eps, want_grad=True, nthreads=0):
     return {"f": f, "g": g, "sf": sf, "sg": sg}
 
 
-def direct_adjoint(p, n, A, mu, x, eps, df, nthreads=0):
-    """Exact transpose of ``direct``: returns (dmu[M,C], dx[Q,3])."""
+def direct_adjoint(p, n, A, mu, x, eps, df, nthreads=0, dg=None):
+    """Exact transpose of ``direct`` (values and, with dg[Q,C,3], gradients):
+    returns (dmu[M,C], dx[Q,3]).  df may be None when dg is given."""
     lib = load()
     p, n, x = _c32(p, 3), _c32(n, 3), _c32(x, 3)
     A = _c32(A).reshape(-1)
@@ -127,10 +137,11 @@ def direct_adjoint(p, n, A, mu, x, eps, df, nthreads=0):
     if mu.ndim == 1:
         mu = mu[:, None]
     M, C, Q = p.shape[0], mu.shape[1], x.shape[0]
-    df = _c32(df).reshape(Q, C)
+    df = None if df is None else _c32(df).reshape(Q, C)
+    dg = None if dg is None else _c32(dg).reshape(Q, C, 3)
     dmu = np.zeros((M, C)); dx = np.zeros((Q, 3))
     rc = lib.orc_direct_adjoint(_ptr(p), _ptr(n), _ptr(A), _ptr(mu), M, C, _ptr(x), Q, float(eps),
-                                _ptr(df), _ptr(dmu), _ptr(dx), int(nthreads))
+                                _ptr(df), _ptr(dg), _ptr(dmu), _ptr(dx), int(nthreads))
     if rc:
         raise ValueError("orc_direct_adjoint rejected its arguments")
     return dmu, dx
@@ -199,15 +210,18 @@ class Tree:
             raise ValueError("orc_bh_query rejected its arguments")
         return {"f": f, "g": g, "sf": sf, "sg": sg, "counts": counts}
 
-    def adjoint(self, x, beta, eps, df, nthreads=0):
-        """Barnes-Hut adjoint.  Returns dict dmu[M,C] (caller order), dx[Q,3],
-        sdmu[M,C], sdx[Q] (absolute scales for error normalisation)."""
+    def adjoint(self, x, beta, eps, df, nthreads=0, dg=None):
+        """Barnes-Hut adjoint for value cotangents df[Q,C] and/or gradient
+        cotangents dg[Q,C,3] (df may be None when dg is given).  Returns dict
+        dmu[M,C] (caller order), dx[Q,3], sdmu[M,C], sdx[Q] (absolute scales
+        for error normalisation)."""
         x = _c32(x, 3)
         Q, C, M = x.shape[0], self.C, self.M
-        df = _c32(df).reshape(Q, C)
+        df = None if df is None else _c32(df).reshape(Q, C)
+        dg = None if dg is None else _c32(dg).reshape(Q, C, 3)
         dmu = np.zeros((M, C)); dx = np.zeros((Q, 3))
         sdmu = np.zeros((M, C)); sdx = np.zeros(Q)
-        rc = load().orc_bh_adjoint(self._h, _ptr(x), Q, float(beta), float(eps), _ptr(df),
+        rc = load().orc_bh_adjoint(self._h, _ptr(x), Q, float(beta), float(eps), _ptr(df), _ptr(dg),
                                    _ptr(dmu), _ptr(dx), _ptr(sdmu), _ptr(sdx), int(nthreads))
         if rc:
             raise ValueError("orc_bh_adjoint rejected its arguments")

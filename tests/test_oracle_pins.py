@@ -531,3 +531,141 @@ def test_bh_adjoint_through_render_loss_matches_fd(orc):
             worst = max(worst, abs(adj["dx"][q, k] - fd) / scale)
             used += 1
     assert used >= 36 and worst < 1e-4
+
+
+# --------------------------------------------------------------------------
+# gradient cotangents: the Hessian factor nu and the adjoint of grad D
+# --------------------------------------------------------------------------
+def test_chi_series_equals_closed_form(orc):
+    # chi(t) = 5 psi(t) - t psi'(t): series branch vs erf / exp branch
+    for t in (0.05, 0.2, 0.35, 0.5, 0.65, 0.8):
+        ref = orc.chi(t) if t >= 0.5 else orc.chi_series(t)
+        closed = 15 * orc.rho_closed(t) - 4 / math.sqrt(math.pi) * (5 * t ** 3 + 2 * t ** 5) * math.exp(-t * t)
+        assert abs(orc.chi_series(t) - closed) <= 1e-12 * max(1e-3, abs(closed)) + 1e-15
+        assert abs(ref - closed) <= 1e-12 * max(1e-3, abs(closed)) + 1e-15
+
+
+def test_chi_definition(orc):
+    # chi(t) = 5 psi(t) - t psi'(t), psi' by central differences of the oracle
+    for t in (0.1, 0.4, 0.6, 1.0, 2.0, 3.0):
+        h = 1e-5
+        d = (orc.psi(t + h) - orc.psi(t - h)) / (2 * h)
+        assert abs(orc.chi(t) - (5 * orc.psi(t) - t * d)) < 1e-8
+
+
+def test_nu_is_minus_lambda_prime_over_r(orc):
+    # the Hessian factor is nu = -lambda'(r)/r; lambda' by central differences
+    for eps in (0.05, 0.0):
+        for r in (0.01, 0.04, 0.07, 0.2, 1.0):
+            h = r * 1e-5
+            lp = (orc.radial(r + h, eps)[1] - orc.radial(r - h, eps)[1]) / (2 * h)
+            nu = orc.radial_nu(r, eps)
+            assert abs(nu + lp / r) <= 1e-6 * abs(nu)
+    # coincident limit of the regularized kernel, and the unregularized r^-7 law
+    assert abs(orc.radial_nu(0.0, 0.05) * 4 * math.pi * 0.05 ** 7 - 16 / (7 * math.sqrt(math.pi))) < 1e-13
+    assert abs(orc.radial_nu(2.0, 0.0) - 15 / (4 * math.pi * 2.0 ** 7)) < 1e-15
+
+
+def _axis_cotangents(Q, C, k, seed):
+    """dg[q,c,:] = a_qc e_k with a ~ N(0,1)."""
+    a = np.random.default_rng(seed).standard_normal((Q, C))
+    dg = np.zeros((Q, C, 3), np.float32)
+    dg[:, :, k] = a
+    return dg
+
+
+def test_direct_grad_cotangent_dx_is_hessian(orc):
+    # with dg = a e_k, dL/dx = sum_c a_c d(grad f_c)/dx_k: central differences
+    # of the (pinned) gradient along axis k
+    p, n, A, mu = workloads.sfm_cloud(2000, 100, 10)
+    x = workloads.sphere_queries(40, 5, half=1.0).astype(np.float64)
+    h = 2.0 ** -14
+    for eps in (0.05, 0.0):
+        for k in range(3):
+            dg = _axis_cotangents(40, mu.shape[1], k, 30 + k)
+            _, dx = orc.direct_adjoint(p, n, A, mu, x.astype(np.float32), eps, None, dg=dg)
+            xp, xm = x.copy(), x.copy()
+            xp[:, k] += h
+            xm[:, k] -= h
+            xp32, xm32 = xp.astype(np.float32), xm.astype(np.float32)
+            gp = orc.direct(p, n, A, mu, xp32, eps)["g"]
+            gm = orc.direct(p, n, A, mu, xm32, eps)["g"]
+            dxk = xp32[:, k].astype(np.float64) - xm32[:, k].astype(np.float64)
+            fd = np.einsum("qc,qcj->qj", dg[:, :, k].astype(np.float64), gp - gm) / dxk[:, None]
+            scale = np.max(np.abs(fd), axis=1, keepdims=True) + 1e-9
+            assert np.max(np.abs(fd - dx) / scale) < 1e-4
+
+
+def test_direct_grad_cotangent_dmu_is_transpose(orc):
+    # grad f is linear in mu: <dg, g(mu)> = <dmu, mu>
+    p, n, A, mu = workloads.sfm_cloud(1500, 100, 10)
+    x = workloads.sphere_queries(300, 7, half=1.0)
+    rng = np.random.default_rng(31)
+    dg = rng.standard_normal((300, mu.shape[1], 3)).astype(np.float32)
+    for eps in (0.02, 0.0):
+        g = orc.direct(p, n, A, mu, x, eps)["g"]
+        dmu, _ = orc.direct_adjoint(p, n, A, mu, x, eps, None, dg=dg)
+        lhs = np.sum(dg.astype(np.float64) * g)
+        rhs = np.sum(dmu * mu.astype(np.float64))
+        assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(dg.astype(np.float64) * g)) + 1e-14
+    # value and gradient cotangents add
+    df = workloads.cotangents(300, mu.shape[1], 17)
+    a = orc.direct_adjoint(p, n, A, mu, x, 0.02, df)
+    b = orc.direct_adjoint(p, n, A, mu, x, 0.02, None, dg=dg)
+    c = orc.direct_adjoint(p, n, A, mu, x, 0.02, df, dg=dg)
+    assert np.allclose(c[0], a[0] + b[0], rtol=1e-12, atol=1e-15)
+    assert np.allclose(c[1], a[1] + b[1], rtol=1e-12, atol=1e-15)
+
+
+def test_bh_grad_cotangent_is_transpose(orc):
+    p, n, A, mu = workloads.sfm_cloud(4000, 200, 10)
+    x = workloads.sphere_queries(500, 11, half=1.0)
+    rng = np.random.default_rng(32)
+    dg = rng.standard_normal((500, mu.shape[1], 3)).astype(np.float32)
+    T = orc.Tree(p, n, A, mu, 16)
+    for beta in (1.0, 2.0):
+        g = T.query(x, beta, 0.02)["g"]
+        a = T.adjoint(x, beta, 0.02, None, dg=dg)
+        lhs = np.sum(dg.astype(np.float64) * g)
+        rhs = np.sum(a["dmu"] * mu.astype(np.float64))
+        assert abs(lhs - rhs) <= 1e-12 * np.sum(np.abs(dg * g))
+        assert np.all(a["sdmu"] >= np.abs(a["dmu"]) * (1 - 1e-12))
+        assert np.all(a["sdx"] >= np.linalg.norm(a["dx"], axis=1) * (1 - 1e-12))
+
+
+def test_bh_grad_cotangent_matches_direct_at_large_beta(orc):
+    p, n, A, mu = workloads.sfm_cloud(1500, 50, 10)
+    x = workloads.sphere_queries(200, 12, half=1.0)
+    rng = np.random.default_rng(33)
+    dg = rng.standard_normal((200, mu.shape[1], 3)).astype(np.float32)
+    df = workloads.cotangents(200, mu.shape[1], 17)
+    T = orc.Tree(p, n, A, mu, 16)
+    a = T.adjoint(x, 1e4, 0.02, df, dg=dg)
+    dmu, dx = orc.direct_adjoint(p, n, A, mu, x, 0.02, df, dg=dg)
+    assert np.allclose(a["dmu"], dmu, rtol=1e-10, atol=1e-14)
+    assert np.allclose(a["dx"], dx, rtol=1e-10, atol=1e-14)
+
+
+def test_bh_grad_cotangent_dx_matches_finite_differences(orc):
+    # L = sum dg . grad f_BH; smooth in x away from decision boundaries
+    p, n, A, mu = workloads.sfm_cloud(3000, 100, 10)
+    T = orc.Tree(p, n, A, mu, 16)
+    x = workloads.sphere_queries(60, 13, half=1.0).astype(np.float64)
+    h = 2.0 ** -14
+    base = T.query(x.astype(np.float32), 2.0, 0.05)
+    checked = 0
+    for k in range(3):
+        dg = _axis_cotangents(60, mu.shape[1], k, 40 + k)
+        a = T.adjoint(x.astype(np.float32), 2.0, 0.05, None, dg=dg)
+        xp, xm = x.copy(), x.copy()
+        xp[:, k] += h
+        xm[:, k] -= h
+        rp = T.query(xp.astype(np.float32), 2.0, 0.05)
+        rm = T.query(xm.astype(np.float32), 2.0, 0.05)
+        same = np.all(rp["counts"] == base["counts"], axis=1) & np.all(rm["counts"] == base["counts"], axis=1)
+        dxk = (xp[:, k].astype(np.float32).astype(np.float64) - xm[:, k].astype(np.float32).astype(np.float64))
+        fd = np.einsum("qc,qcj->qj", dg[:, :, k].astype(np.float64), rp["g"] - rm["g"]) / dxk[:, None]
+        err = np.linalg.norm(fd - a["dx"], axis=1) / a["sdx"]
+        assert np.all(err[same] < 1e-3)
+        checked += int(same.sum())
+    assert checked > 100
