@@ -207,6 +207,31 @@ dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q
                                            float beta, float eps, int32_t c_begin, int32_t n_channels,
                                            const float *df, float *dx, void *stream);
 
+/*
+ * dps_adjoint_accumulate_grad -- stage 1 of the adjoint for cotangents of the
+ * spatial gradients (and optionally of the values), for losses that use
+ * grad D, as the surface density sigma = |w . grad v| / v of Sec. 3.1, eq.
+ * (surface_density), does.  Each source term's gradient
+ * -kappa D + lambda (D.d) d (d = source - x) is linear in its dipole D, so the
+ * cotangent h adds lambda (d.h) d - kappa h to the same node and point
+ * accumulators as the value cotangents (finalised by dps_adjoint_finalize);
+ * dL/dx adds the term's Hessian applied to h,
+ *   nu s (d.h) d - lambda (d (D.h) + D (d.h)) - lambda s h,  s = D.d,
+ * nu = chi(t)/(4 pi r^7), chi = 5 psi - t psi'.  Same traversal decisions
+ * (Algorithm 1) as the forward query.
+ *  x        device [Q][3]
+ *  q_count  device row count or NULL (as dps_query_channels)
+ *  c_begin, n_channels  channel range (BF16 storage: c_begin even)
+ *  df       device [Q][n_channels] value cotangents, or NULL (zero)
+ *  dg       device [Q][n_channels][3] gradient cotangents (required)
+ *  dx       device [Q][3] or NULL: overwritten with dL/dx of these rows
+ * Accumulators add across calls (mixing with dps_adjoint_accumulate*).
+ * Graph-safe; DPS_ERR_INVALID for a NULL x / dg or bad ranges.
+ */
+dps_status dps_adjoint_accumulate_grad(dps_tree t, const float *x, int64_t Q, const int64_t *q_count, float beta,
+                                       float eps, int32_t c_begin, int32_t n_channels, const float *df,
+                                       const float *dg, float *dx, void *stream);
+
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A
  * traversal that would walk more than N nodes stops and sets this flag. */

@@ -6,9 +6,11 @@ two-stage adjoint of Sec. 6.2 / App. C (node accumulation with a recomputed
 traversal, then the push-down to the points).  Nothing about the traversal is
 stored between the two passes: the adjoint walks the tree again for each query.
 
-The value D(x) is linear in the attributes, and the traversal depends only on
-x and the fixed geometry, so dL/dattrs is the exact transpose of the forward
-map; dL/dx is sum_c dL/dD_c * grad_x D_c with the same accepted sources.
+The value D(x) and its gradient are linear in the attributes, and the
+traversal depends only on x and the fixed geometry, so dL/dattrs is the exact
+transpose of the forward map; dL/dx is sum_c dL/dD_c * grad_x D_c plus, for
+cotangents of the gradient output, the Hessian of D_c applied to them, with
+the same accepted sources.
 
 Both passes are free of host synchronisation, so a forward + backward built
 from these calls can be captured in a graph and replayed; ``refit=True`` puts
@@ -41,8 +43,9 @@ class DipoleSum(torch.autograd.Function):
     """f, grad = DipoleSum.apply(attrs[M,C], x[Q,3], tree, beta, eps, opts).
 
     ``opts`` = (c_begin, n_channels, q_count, want_grad, refit) with
-    n_channels None meaning all channels.  ``f`` [Q,n] is differentiable
-    w.r.t. attrs and x; ``grad`` [Q,n,3] (or None) is non-differentiable.
+    n_channels None meaning all channels.  ``f`` [Q,n] and ``grad`` [Q,n,3]
+    (or None) are both differentiable w.r.t. attrs and x: cotangents of grad
+    go through the Hessian adjoint (``dps_adjoint_accumulate_grad``).
     With a device row count ``q_count`` (int64 CUDA tensor [1]) only the first
     min(Q, q_count) rows are evaluated; the other rows of f / grad and of the
     position gradient are zero."""
@@ -66,24 +69,29 @@ class DipoleSum(torch.autograd.Function):
             B.dps_query_channels(tree, x_c, beta, eps, c_begin, n, f_out=f, g_out=g, q_count=q_count)
         ctx.save_for_backward(x_c, attrs_c)
         ctx.tree, ctx.beta, ctx.eps, ctx.opts, ctx.full = tree, float(beta), float(eps), opts, full
-        if g is not None:
-            ctx.mark_non_differentiable(g)
+        ctx.n = f.shape[1]
         return f, g
 
     @staticmethod
     def backward(ctx, df, dg):
-        # dg is never a real cotangent: the gradient output is marked
-        # non-differentiable (cotangents of it would need the Hessian kernel)
         x, attrs = ctx.saved_tensors
         tree = ctx.tree
         c_begin, n_ch, q_count, _, refit = ctx.opts
         if refit == "auto":
             _refit_if_changed(tree, attrs)
         need_attr, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        if df is None or not (need_attr or need_x):
+        if (df is None and dg is None) or not (need_attr or need_x):
             return None, None, None, None, None, None
-        df = df.contiguous().to(torch.float32)
-        if ctx.full:
+        df = None if df is None else df.contiguous().to(torch.float32)
+        if dg is not None:
+            # gradient cotangents (with the value cotangents, if any)
+            dg = dg.contiguous().to(torch.float32)
+            dx = torch.zeros((x.shape[0], 3), device=x.device, dtype=torch.float32) if need_x else None
+            B.dps_adjoint_zero(tree)
+            B.dps_adjoint_accumulate_grad(tree, x, ctx.beta, ctx.eps, dg, df=df, c_begin=c_begin, n_channels=ctx.n,
+                                          want_dx=need_x, dx_out=dx, q_count=q_count)
+            dattrs = B.dps_adjoint_finalize(tree)
+        elif ctx.full:
             dattrs, dx = B.dps_adjoint(tree, x, ctx.beta, ctx.eps, df, want_dx=need_x)
         else:
             n = df.shape[1]

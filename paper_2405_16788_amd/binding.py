@@ -22,7 +22,8 @@ EXPORTED = (
     "dps_build", "dps_set_attributes", "dps_query", "dps_query_counts", "dps_adjoint_zero",
     "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
     "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_query_channels",
-    "dps_adjoint_accumulate_channels", "dps_check", "dps_destroy", "dps_status_string", "dps_last_error",
+    "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_check", "dps_destroy",
+    "dps_status_string", "dps_last_error",
 )
 
 _lib = None
@@ -58,6 +59,7 @@ def load():
         "dps_get_launch": [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)],
         "dps_query_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
+        "dps_adjoint_accumulate_grad": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp, vp],
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
         "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
@@ -288,6 +290,24 @@ def dps_adjoint_accumulate_channels(tree: Tree, x, beta: float, eps: float, c_be
         _ptr(q_count, torch.int64, (1,), tree.device, "q_count"), float(beta), float(eps), int(c_begin),
         int(n_channels), _ptr(df, torch.float32, (Q, n_channels), tree.device, "df"),
         _ptr(dx, torch.float32, (Q, 3), tree.device, "dx"), _stream(tree.device)), "dps_adjoint_accumulate_channels")
+    return dx
+
+
+def dps_adjoint_accumulate_grad(tree: Tree, x, beta: float, eps: float, dg, df=None, c_begin: int = 0,
+                                n_channels=None, want_dx: bool = True, dx_out=None, q_count=None):
+    """Stage 1 for gradient cotangents dg[Q,n,3] (and optional value cotangents
+    df[Q,n]) of channels [c_begin, c_begin+n); returns dx[Q,3] (or None)."""
+    import torch
+    Q = x.shape[0]
+    n = tree.C - c_begin if n_channels is None else n_channels
+    dx = dx_out if dx_out is not None else (
+        torch.empty((Q, 3), device=tree.device, dtype=torch.float32) if want_dx else None)
+    _check(load().dps_adjoint_accumulate_grad(
+        tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q,
+        _ptr(q_count, torch.int64, (1,), tree.device, "q_count"), float(beta), float(eps), int(c_begin), int(n),
+        _ptr(df, torch.float32, (Q, n), tree.device, "df"),
+        _ptr(dg, torch.float32, (Q, n, 3), tree.device, "dg"),
+        _ptr(dx, torch.float32, (Q, 3), tree.device, "dx"), _stream(tree.device)), "dps_adjoint_accumulate_grad")
     return dx
 
 

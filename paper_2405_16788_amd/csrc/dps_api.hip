@@ -258,6 +258,20 @@ dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q
     return launch_adjoint(t, x, Q, q_count, beta, eps, c_begin, n_channels, df, dx, (hipStream_t)stream);
 }
 
+dps_status dps_adjoint_accumulate_grad(dps_tree t, const float *x, int64_t Q, const int64_t *q_count, float beta,
+                                       float eps, int32_t c_begin, int32_t n_channels, const float *df,
+                                       const float *dg, float *dx, void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint_accumulate_grad");
+    if (st != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate_grad")) != DPS_OK) return st;
+    if ((st = check_channels(t, c_begin, n_channels, "dps_adjoint_accumulate_grad")) != DPS_OK) return st;
+    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint_accumulate_grad: Q out of range");
+    if (Q == 0) return DPS_OK;
+    if (!x || !dg) return invalid("dps_adjoint_accumulate_grad: NULL x or dg");
+    DeviceGuard guard(t->device);
+    return launch_adjoint_g(t, x, Q, q_count, beta, eps, c_begin, n_channels, df, dg, dx, (hipStream_t)stream);
+}
+
 dps_status dps_adjoint_finalize(dps_tree t, float *dattrs, void *stream) {
     dps_status st = check_tree(t, "dps_adjoint_finalize");
     if (st != DPS_OK) return st;

@@ -85,9 +85,12 @@ __host__ __device__ inline float mul_rn(float a, float b) {
 
 // ---------------------------------------------------------------------------
 // radial factors kappa = rho(t)/(4 pi r^3), lambda = psi(t)/(4 pi r^5), t = r/eps,
-// psi = 3 rho - t rho'.  Series (derived from those of erf and exp):
-//   rho(t)/t^3 = (4/sqrt pi) sum_{n>=1} (-1)^{n+1} t^{2n-2} / ((n-1)! (2n+1))
-//   psi(t)/t^5 = (8/sqrt pi) sum_{n>=2} (-1)^n     t^{2n-4} / ((n-2)! (2n+1))
+// psi = 3 rho - t rho', and for the Hessian nu = chi(t)/(4 pi r^7) = -lambda'(r)/r,
+// chi = 5 psi - t psi' = 15 rho - (4/sqrt pi)(5 t^3 + 2 t^5) exp(-t^2).
+// Series (derived from those of erf and exp):
+//   rho(t)/t^3 = (4/sqrt pi)  sum_{n>=1} (-1)^{n+1} t^{2n-2} / ((n-1)! (2n+1))
+//   psi(t)/t^5 = (8/sqrt pi)  sum_{n>=2} (-1)^n     t^{2n-4} / ((n-2)! (2n+1))
+//   chi(t)/t^7 = (16/sqrt pi) sum_{n>=3} (-1)^{n+1} t^{2n-6} / ((n-3)! (2n+1))
 // ---------------------------------------------------------------------------
 struct KernelParams {
     float eps;       // 0: unregularised
@@ -95,6 +98,7 @@ struct KernelParams {
     float ieps2;     // 1/eps^2
     float k3;        // 1/(4 pi eps^3)
     float k5;        // 1/(4 pi eps^5)
+    float k7;        // 1/(4 pi eps^7)
 };
 
 __host__ inline KernelParams make_kernel_params(float eps) {
@@ -106,11 +110,13 @@ __host__ inline KernelParams make_kernel_params(float eps) {
         kp.ieps2 = (float)(1.0 / (e * e));
         kp.k3 = (float)(0.0795774715459476679 / (e * e * e));
         kp.k5 = (float)(0.0795774715459476679 / (e * e * e * e * e));
+        kp.k7 = (float)(0.0795774715459476679 / (e * e * e * e * e * e * e));
     } else {
         kp.ieps = 0.0f;
         kp.ieps2 = 0.0f;
         kp.k3 = 0.0f;
         kp.k5 = 0.0f;
+        kp.k7 = 0.0f;
     }
     return kp;
 }
@@ -125,6 +131,12 @@ __device__ __forceinline__ float series_psi_t5(float u) {  // u = t^2
     constexpr float c = 4.51351666838205030f;
     return c * (1.0f / 5.0f + u * (-1.0f / 7.0f + u * (1.0f / 18.0f + u * (-1.0f / 66.0f +
            u * (1.0f / 312.0f + u * (-1.0f / 1800.0f + u * (1.0f / 12240.0f + u * (-1.0f / 95760.0f))))))));
+}
+
+__device__ __forceinline__ float series_chi_t7(float u) {  // u = t^2
+    constexpr float c = 9.02703333676410060f;
+    return c * (1.0f / 7.0f + u * (-1.0f / 9.0f + u * (1.0f / 22.0f + u * (-1.0f / 78.0f +
+           u * (1.0f / 360.0f + u * (-1.0f / 2040.0f + u * (1.0f / 13680.0f + u * (-1.0f / 105840.0f))))))));
 }
 
 // r2 = |d|^2.  Returns false when the term is excluded (r = 0 with eps = 0).
@@ -151,6 +163,39 @@ __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &
                 const float psi = 3.0f * rho - k4SqrtPi * t * u * e;
                 kappa = kappa * rho;
                 lambda = kInv4Pi * ir * ir2 * ir2 * psi;
+            }
+        }
+    }
+    return true;
+}
+
+// kappa, lambda and the Hessian factor nu = chi(t)/(4 pi r^7), same branches
+// as radial(); chi = 15 where rho = 1, psi = 3.
+__device__ __forceinline__ bool radial3(float r2, const KernelParams &kp, float &kappa, float &lambda,
+                                        float &nu) {
+    if (kp.eps == 0.0f && !(r2 > 0.0f)) return false;
+    const float ir = __builtin_amdgcn_rsqf(r2);
+    const float ir2 = ir * ir;
+    kappa = kInv4Pi * ir * ir2;
+    lambda = 3.0f * kappa * ir2;
+    nu = 5.0f * lambda * ir2;
+    if (kp.eps > 0.0f) {
+        const float u = r2 * kp.ieps2;
+        if (u < kFarT2) {
+            if (u < kSeriesT2) {
+                kappa = kp.k3 * series_rho_t3(u);
+                lambda = kp.k5 * series_psi_t5(u);
+                nu = kp.k7 * series_chi_t7(u);
+            } else {
+                const float t = r2 * ir * kp.ieps;
+                const float e = expf(-u);
+                const float rho = erff(t) - k2SqrtPi * t * e;
+                const float psi = 3.0f * rho - k4SqrtPi * t * u * e;
+                const float chi = 15.0f * rho - k4SqrtPi * t * u * (5.0f + 2.0f * u) * e;
+                const float ir5 = ir * ir2 * ir2;
+                kappa = kappa * rho;
+                lambda = kInv4Pi * ir5 * psi;
+                nu = kInv4Pi * ir5 * ir2 * chi;
             }
         }
     }

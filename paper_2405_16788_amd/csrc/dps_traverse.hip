@@ -663,6 +663,212 @@ __global__ __launch_bounds__(kThreads, (CB == 4 && K == 4) ? DPS_ADJOINT_WAVES :
     }
 }
 
+// ---------------------------------------------------------------------------
+// adjoint with cotangents h = dL/d(grad D) of the spatial gradient (and,
+// with DF, dL/dD of the values).  The gradient of a source term is linear in
+// its dipole with d g / d D = lambda d d^T - kappa I, so h feeds the same node
+// and point accumulators as df:  dD += (kappa w + lambda (d.h)) d - kappa h.
+// dL/dx adds the Hessian of the term applied to h,
+//   nu s (d.h) d - lambda (d (D.h) + D (d.h)) - lambda s h,  s = D.d,
+// with nu = chi(t)/(4 pi r^7).  Per source and query, with
+// beta_c = kappa w_c + lambda (d.h_c):
+//   dx += [sum_c lambda w_c s_c + nu s_c (d.h_c) - lambda (D_c.h_c)] d
+//         - sum_c beta_c D_c - lambda sum_c s_c h_c.
+// ---------------------------------------------------------------------------
+template <int CB, bool BF16, int K, bool DF>
+__device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int C, const float *__restrict__ df,
+                                               const float *__restrict__ dg, double *__restrict__ G,
+                                               double *__restrict__ P, float *__restrict__ dxout, int dx_mode) {
+    const int lane = lane_id();
+    float px[K], py[K], pz[K], w[K][CB], h[K][CB][3], ax[K], ay[K], az[K];
+    uint32_t bits[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int64_t q = q0 + 64 * i;
+        const bool valid = q < Q;
+        px[i] = valid ? x[3 * q] : 0.0f;
+        py[i] = valid ? x[3 * q + 1] : 0.0f;
+        pz[i] = valid ? x[3 * q + 2] : 0.0f;
+        bits[i] = valid ? 1u : 0u;
+        ax[i] = ay[i] = az[i] = 0.0f;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            w[i][c] = (DF && valid) ? df[q * ldo + co + c] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 3; ++j) h[i][c][j] = valid ? dg[(q * ldo + co + c) * 3 + j] : 0.0f;
+        }
+    }
+    uint32_t t = 0;
+    NodeRec nd = nodes[0];
+    float D[3 * CB];
+    load_moments<CB, BF16>(mom, ms, 0, c0, D);
+    uint32_t steps = 0;
+    for (;;) {
+        if (++steps > limit) {  // a well-formed tree is walked in at most N steps
+            if (lane == 0) atomicOr(err, 1u);
+            break;
+        }
+        const uint32_t lvl = nd.meta & 0xffu;
+        const bool leaf = (nd.meta & kLeafFlag) != 0;
+        const float lim = mul_rn(b2, nd.r2);
+        bool far[K], open[K], lane_far = false, lane_open = false;
+        float s2[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const bool in = (bits[i] >> lvl) & 1u;
+            s2[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
+            far[i] = in && (s2[i] > lim);
+            open[i] = in && !far[i];
+            lane_far |= far[i];
+            lane_open |= open[i];
+        }
+        const bool any_far = __ballot(lane_far) != 0;
+        const bool any_open = __ballot(lane_open) != 0;
+        const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
+        const uint32_t pf = next == kEnd ? t : next;
+        const NodeRec nn = nodes[pf];
+        float Dn[3 * CB];
+        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+        if (any_far) {
+            float acc[3 * CB];
+#pragma unroll
+            for (int v = 0; v < 3 * CB; ++v) acc[v] = 0.0f;
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                if (far[i]) {
+                    float kap, lam, nu;
+                    radial3(s2[i], kp, kap, lam, nu);
+                    const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
+                    float al = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        const float Dx = D[3 * c], Dy = D[3 * c + 1], Dz = D[3 * c + 2];
+                        const float hx = h[i][c][0], hy = h[i][c][1], hz = h[i][c][2];
+                        const float sc = Dx * dx + Dy * dy + Dz * dz;
+                        const float dh = dx * hx + dy * hy + dz * hz;
+                        const float Dh = Dx * hx + Dy * hy + Dz * hz;
+                        const float be = fmaf(kap, w[i][c], lam * dh);
+                        al = fmaf(sc, fmaf(lam, w[i][c], nu * dh), fmaf(-lam, Dh, al));
+                        const float ls = lam * sc;
+                        vx = fmaf(be, Dx, fmaf(ls, hx, vx));
+                        vy = fmaf(be, Dy, fmaf(ls, hy, vy));
+                        vz = fmaf(be, Dz, fmaf(ls, hz, vz));
+                        acc[3 * c] = fmaf(be, dx, fmaf(-kap, hx, acc[3 * c]));
+                        acc[3 * c + 1] = fmaf(be, dy, fmaf(-kap, hy, acc[3 * c + 1]));
+                        acc[3 * c + 2] = fmaf(be, dz, fmaf(-kap, hz, acc[3 * c + 2]));
+                    }
+                    ax[i] += fmaf(al, dx, -vx);
+                    ay[i] += fmaf(al, dy, -vy);
+                    az[i] += fmaf(al, dz, -vz);
+                }
+            }
+            scatter_add_node(acc, lane, &G[((size_t)t * C + c0) * 3]);
+        }
+        if (any_open) {
+            if (!leaf) {
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
+            } else {
+                const uint32_t je = nd.first + nd.count;
+                for (uint32_t j = nd.first; j < je; ++j) {
+                    const PointRec pr = pts[j];
+                    float mu[CB];
+                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                    float acc[CB];
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < K; ++i) {
+                        if (open[i]) {
+                            const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
+                            const float r2 = dx * dx + dy * dy + dz * dz;
+                            float kap, lam, nu;
+                            if (radial3(r2, kp, kap, lam, nu)) {
+                                const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                                float al = 0.0f, bsum = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
+#pragma unroll
+                                for (int c = 0; c < CB; ++c) {
+                                    const float hx = h[i][c][0], hy = h[i][c][1], hz = h[i][c][2];
+                                    const float dh = dx * hx + dy * hy + dz * hz;
+                                    const float Ah = pr.anx * hx + pr.any * hy + pr.anz * hz;
+                                    const float be = fmaf(kap, w[i][c], lam * dh);
+                                    // point accumulator: (d g_c / d mu_c) . h_c and the value part
+                                    acc[c] = fmaf(be, sa, fmaf(-kap, Ah, acc[c]));
+                                    const float sc = mu[c] * sa;
+                                    al = fmaf(sc, fmaf(lam, w[i][c], nu * dh), fmaf(-lam * mu[c], Ah, al));
+                                    bsum = fmaf(be, mu[c], bsum);
+                                    const float ls = lam * sc;
+                                    vx = fmaf(ls, hx, vx);
+                                    vy = fmaf(ls, hy, vy);
+                                    vz = fmaf(ls, hz, vz);
+                                }
+                                ax[i] += fmaf(al, dx, -fmaf(bsum, pr.anx, vx));
+                                ay[i] += fmaf(al, dy, -fmaf(bsum, pr.any, vy));
+                                az[i] += fmaf(al, dz, -fmaf(bsum, pr.anz, vz));
+                            }
+                        }
+                    }
+                    scatter_add_node(acc, lane, &P[(size_t)j * C + c0]);
+                }
+            }
+        }
+        if (next == kEnd) break;
+        t = next;
+        nd = nn;
+#pragma unroll
+        for (int v = 0; v < 3 * CB; ++v) D[v] = Dn[v];
+    }
+    if (dx_mode != 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            const int64_t q = q0 + 64 * i;
+            if (q < Q) {
+                if (dx_mode == 1) {
+                    dxout[3 * q] = ax[i];
+                    dxout[3 * q + 1] = ay[i];
+                    dxout[3 * q + 2] = az[i];
+                } else {
+                    dxout[3 * q] += ax[i];
+                    dxout[3 * q + 1] += ay[i];
+                    dxout[3 * q + 2] += az[i];
+                }
+            }
+        }
+    }
+}
+
+template <int CB, bool BF16, int K, bool DF>
+__global__ __launch_bounds__(kThreads) void k_adjoint_g(DPS_KERN_PARAMS, int C, const float *__restrict__ df,
+                                                        const float *__restrict__ dg, double *__restrict__ G,
+                                                        double *__restrict__ P, float *__restrict__ dxout,
+                                                        int dx_mode, int xcd_remap) {
+    DPS_ROWS;
+    const int64_t blk = remap_block(xcd_remap);
+    if (blk < 0 || blk * (int64_t)blockDim.x * K >= Q) return;  // whole block past the rows
+    const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
+    adjoint_g_body<CB, BF16, K, DF>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, dg, G, P, dxout,
+                                    dx_mode);
+}
+
+template <int CB, bool BF16, int K, bool DF>
+__global__ __launch_bounds__(kThreads) void k_adjoint_g_persistent(DPS_KERN_PARAMS, int C,
+                                                                   const float *__restrict__ df,
+                                                                   const float *__restrict__ dg,
+                                                                   double *__restrict__ G, double *__restrict__ P,
+                                                                   float *__restrict__ dxout, int dx_mode,
+                                                                   uint32_t *__restrict__ ctr) {
+    DPS_ROWS;
+    const int64_t ntiles = (Q + 64 * K - 1) / (64 * K);
+    int part = xcc_id();
+    for (;;) {
+        const int64_t tile = next_tile(ctr, ntiles, part);
+        if (tile < 0) break;
+        adjoint_g_body<CB, BF16, K, DF>(tile * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, dg, G, P, dxout,
+                                        dx_mode);
+    }
+}
+
 __global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         a[i] = v;
@@ -856,6 +1062,49 @@ dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t
     return adjoint_launch<CB, false, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
 }
 
+template <int CB, bool BF, int K, bool DF>
+dps_status adjoint_g_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp,
+                            Sub sb, const float *df, const float *dg, float *dx, int dx_mode, hipStream_t s) {
+    const uint32_t lim = (uint32_t)t->N;
+    if (t->launch_flags & kFlagPersistentAdjoint) {
+        k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
+        const void *fn = reinterpret_cast<const void *>(&k_adjoint_g_persistent<CB, BF, K, DF>);
+        k_adjoint_g_persistent<CB, BF, K, DF><<<persistent_grid(fn), kThreads, 0, s>>>(
+            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
+            lim, t->err, t->C, df, dg, t->G, t->P, dx, dx_mode, t->ctr + 8);
+    } else {
+        const unsigned nb = grid(cdiv(Q, K));
+        const bool remap = (t->launch_flags & kFlagXcdAdjoint) != 0;
+        const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
+        k_adjoint_g<CB, BF, K, DF><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+                                                           t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
+                                                           lim, t->err, t->C, df, dg, t->G, t->P, dx, dx_mode,
+                                                           remap ? (int)nb : 0);
+    }
+    return hip_status(hipGetLastError(), "adjoint launch");
+}
+
+// queries per lane of the gradient-cotangent adjoint: 2 up to 2 channels
+// per block, else 1 (each query carries 3 cotangents per channel)
+template <int CB, bool BF, bool DF>
+dps_status adjoint_g_k(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
+                       const float *df, const float *dg, float *dx, int dx_mode, hipStream_t s) {
+    if constexpr (CB <= 2) {
+        if (t->packet_adjoint >= 2) return adjoint_g_launch<CB, BF, 2, DF>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
+    }
+    return adjoint_g_launch<CB, BF, 1, DF>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
+}
+
+template <int CB>
+dps_status adjoint_g_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp,
+                           Sub sb, const float *df, const float *dg, float *dx, int dx_mode, hipStream_t s) {
+    const bool bf = t->storage == DPS_STORE_BF16;
+    if (bf && df) return adjoint_g_k<CB, true, true>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
+    if (bf) return adjoint_g_k<CB, true, false>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
+    if (df) return adjoint_g_k<CB, false, true>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
+    return adjoint_g_k<CB, false, false>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
+}
+
 }  // namespace
 
 dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
@@ -938,6 +1187,29 @@ dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *mome
             k_export_moments<false><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->mom_stride, t->mom, moments);
         dps_status st = hip_status(hipGetLastError(), "export moments");
         if (st != DPS_OK) return st;
+    }
+    return DPS_OK;
+}
+
+dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
+                            int cbegin, int nc, const float *df, const float *dg, float *dx, hipStream_t s) {
+    const float b2 = mul_rn(beta, beta);
+    const KernelParams kp = make_kernel_params(eps);
+    for (int c0 = cbegin; c0 < cbegin + nc;) {
+        // blocks of at most 4 channels: each carries 4 floats per channel and query
+        const int rem = cbegin + nc - c0;
+        const int cb = rem >= 4 ? 4 : rem;
+        const int dx_mode = dx ? (c0 == cbegin ? 1 : 2) : 0;
+        const Sub sb{c0, nc, c0 - cbegin};
+        dps_status st;
+        switch (cb) {
+            case 4: st = adjoint_g_block<4>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s); break;
+            case 3: st = adjoint_g_block<3>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s); break;
+            case 2: st = adjoint_g_block<2>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s); break;
+            default: st = adjoint_g_block<1>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s); break;
+        }
+        if (st != DPS_OK) return st;
+        c0 += cb;
     }
     return DPS_OK;
 }

@@ -74,6 +74,8 @@ dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta,
                          int32_t *counts, hipStream_t s);
 dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                           int cbegin, int nc, const float *df, float *dx, hipStream_t s);
+dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
+                            int cbegin, int nc, const float *df, const float *dg, float *dx, hipStream_t s);
 dps_status launch_zero(dps_tree_s *t, hipStream_t s);
 dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s);
 dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *moments,
