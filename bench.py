@@ -10,7 +10,9 @@ in HBM before timing starts.
 One step = one training iteration of the hot path: moment refit from the
 attributes (dps_set_attributes), primal query with gradients (dps_query), and
 the two-stage adjoint (dps_adjoint_zero / _accumulate / _finalize) with
-dL/df ~ N(0,1).  The tree itself is built once (points are fixed) and its
+dL/df ~ N(0,1).  The adjoint that also takes cotangents of the gradients
+(dps_adjoint_accumulate_grad, N(0,1)) is timed beside it and reported in
+kernel_ms.  The tree itself is built once (points are fixed) and its
 build time is reported separately.  value = Q / (time per step), FP32-stored
 attributes and moments, eager launches.  The same step is also timed with
 BF16 storage, eager and captured in one graph.
@@ -228,10 +230,29 @@ def time_storage(P, dev_in, storage, steps, warmup, packet, graph=False):
         torch.cuda.synchronize()
         graph_ms = start.elapsed_time(end) / steps
         del cg
+    # the adjoint with cotangents of the spatial gradients as well (losses
+    # built on grad D, like the paper's surface density): same traversal, the
+    # Hessian of each accepted source applied to the cotangents
+    gen = torch.Generator(device="cuda").manual_seed(19)
+    dg = torch.randn((Q, C, 3), device="cuda", generator=gen)
+    P.dps_adjoint_zero(tree)
+    P.dps_adjoint_accumulate_grad(tree, x, BETA, EPS, dg, df=df, dx_out=dx)
+    torch.cuda.synchronize()
+    gms = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        P.dps_adjoint_zero(tree)
+        a.record()
+        P.dps_adjoint_accumulate_grad(tree, x, BETA, EPS, dg, df=df, dx_out=dx)
+        b.record()
+        torch.cuda.synchronize()
+        gms.append(a.elapsed_time(b))
+    del dg
     counts = P.dps_query_counts(tree, x, BETA)
     csum = counts.to(torch.int64).sum(0).tolist()
     info = P.dps_tree_info(tree)
     P.dps_destroy(tree)
+    per["adjoint_accumulate_with_grad_cotangents"] = sorted(gms)[1]
     return {"ms_per_step": total_ms / steps, "graph_ms_per_step": graph_ms, "build_ms": build_ms, "kernel_ms": per,
             "counts_total": csum, "tree": info, "packet": {"query": tuned["query"], "adjoint": tuned["adjoint"], "flags": tuned["flags"]}}
 

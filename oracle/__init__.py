@@ -7,5 +7,5 @@ paper each part follows.
 """
 from .oracle import (  # noqa: F401
     build, load, direct, direct_adjoint, Tree, rho, psi, rho_series,
-    psi_series, rho_closed, radial, chi, chi_series, radial_nu,
+    psi_series, rho_closed, radial, chi, chi_series, radial_nu, radial_eps,
 )

@@ -51,6 +51,13 @@
  *                     = 15 rho(t) - (4/sqrt(pi)) (5 t^3 + 2 t^5) exp(-t^2).
  *              The paper does not write these; they are the derivatives of
  *              its terms, taken through the same accepted sources.
+ *  normals,    Sec. 5.2 optimises the point normals and the global eps as
+ *  eps         well.  A term depends on n_m through D = A_m mu_m n_m only (the
+ *              tree geometry does not involve normals), so dL/dn_m =
+ *              A_m sum_c mu_mc dL/dD_mc, the far-field part through the node
+ *              dipoles of all ancestors; and d kappa / d eps =
+ *              -exp(-t^2) / (pi^1.5 eps^4), d lambda / d eps =
+ *              -2 exp(-t^2) / (pi^1.5 eps^6) (both vanish as eps -> 0).
  *
  * Precision: everything is FP64 except two things that the GPU must decide
  * bit-identically: the far test, evaluated in FP32 as
@@ -183,6 +190,36 @@ static double radial_nu(double r, double eps)
 
 double orc_radial_nu(double r, double eps) { return radial_nu(r, eps); }
 
+/* d kappa / d eps and d lambda / d eps (0 for eps = 0) */
+static void radial_eps(double r, double eps, double *kap_e, double *lam_e)
+{
+    if (eps == 0.0) { *kap_e = 0.0; *lam_e = 0.0; return; }
+    double t = r / eps;
+    double e = exp(-t * t) / (ORC_PI * ORC_SQRT_PI);
+    double e2 = eps * eps;
+    *kap_e = -e / (e2 * e2);
+    *lam_e = -2.0 * e / (e2 * e2 * e2);
+}
+
+void orc_radial_eps(double r, double eps, double *kap_e, double *lam_e) { radial_eps(r, eps, kap_e, lam_e); }
+
+/* dL/deps of one term with dipole D, value cotangent w (or 0) and gradient
+ * cotangent h (or NULL), and its absolute scale */
+static double term_eps(const double d[3], double kap_e, double lam_e, const double D[3], double w,
+                       const double *h, double *scale)
+{
+    double s = D[0] * d[0] + D[1] * d[1] + D[2] * d[2];
+    double v = w * kap_e * s, a = fabs(w * kap_e * s);
+    if (h) {
+        double dh = d[0] * h[0] + d[1] * h[1] + d[2] * h[2];
+        double Dh = D[0] * h[0] + D[1] * h[1] + D[2] * h[2];
+        v += lam_e * s * dh - kap_e * Dh;
+        a += fabs(lam_e * s * dh) + fabs(kap_e * Dh);
+    }
+    if (scale) *scale += a;
+    return v;
+}
+
 /* Cotangent h of the gradient of one source term with dipole D at offset
  * d = c - x (radial factors kap, lam, nu):
  *   dD += lambda (d.h) d - kappa h          (the term's derivative in D)
@@ -289,7 +326,8 @@ int orc_direct(const float *p, const float *n, const float *A, const float *mu,
  * df may be NULL when dg is given (value cotangents zero). */
 int orc_direct_adjoint(const float *p, const float *n, const float *A, const float *mu,
                        int64_t M, int C, const float *x, int64_t Q, double eps,
-                       const float *df, const float *dg, double *dmu, double *dx, int nthreads)
+                       const float *df, const float *dg, double *dmu, double *dx, double *dn,
+                       double *deps, int nthreads)
 {
     if (M < 0 || Q < 0 || C < 1 || C > 64 || eps < 0 || (!df && !dg)) return 1;
     int nt = nthreads_or_default(nthreads);
@@ -354,6 +392,57 @@ int orc_direct_adjoint(const float *p, const float *n, const float *A, const flo
             }
             for (int ch = 0; ch < C; ++ch) dmu[m * C + ch] = acc[ch];
         }
+    }
+    if (dn) {
+        /* dL/dn_m = A_m sum_c mu_mc dL/dD_mc */
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t m = 0; m < M; ++m) {
+            double acc[3] = {0, 0, 0};
+            for (int64_t q = 0; q < Q; ++q) {
+                double d[3] = {p[3 * m] - (double)x[3 * q], p[3 * m + 1] - (double)x[3 * q + 1],
+                               p[3 * m + 2] - (double)x[3 * q + 2]};
+                double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (r2 == 0.0 && eps == 0.0) continue;
+                double kap, lam;
+                radial(sqrt(r2), eps, &kap, &lam);
+                for (int ch = 0; ch < C; ++ch) {
+                    double dD[3] = {0, 0, 0};
+                    double w = df ? (double)df[q * C + ch] : 0.0;
+                    for (int k = 0; k < 3; ++k) dD[k] = w * kap * d[k];
+                    if (dg) {
+                        const float *h = dg + (q * C + ch) * 3;
+                        double dh = d[0] * h[0] + d[1] * h[1] + d[2] * h[2];
+                        for (int k = 0; k < 3; ++k) dD[k] += lam * dh * d[k] - kap * h[k];
+                    }
+                    double am = (double)A[m] * (double)mu[m * C + ch];
+                    for (int k = 0; k < 3; ++k) acc[k] += am * dD[k];
+                }
+            }
+            for (int k = 0; k < 3; ++k) dn[3 * m + k] = acc[k];
+        }
+    }
+    if (deps) {
+        double tot = 0.0;
+#pragma omp parallel for schedule(static) num_threads(nt) reduction(+ : tot)
+        for (int64_t q = 0; q < Q; ++q) {
+            double xq[3] = {x[3 * q], x[3 * q + 1], x[3 * q + 2]};
+            for (int64_t m = 0; m < M; ++m) {
+                double d[3] = {p[3 * m] - xq[0], p[3 * m + 1] - xq[1], p[3 * m + 2] - xq[2]};
+                double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (r2 == 0.0 && eps == 0.0) continue;
+                double ke, le;
+                radial_eps(sqrt(r2), eps, &ke, &le);
+                for (int ch = 0; ch < C; ++ch) {
+                    double D[3], h[3];
+                    for (int k = 0; k < 3; ++k) {
+                        D[k] = (double)A[m] * (double)mu[m * C + ch] * (double)n[3 * m + k];
+                        if (dg) h[k] = (double)dg[(q * C + ch) * 3 + k];
+                    }
+                    tot += term_eps(d, ke, le, D, df ? (double)df[q * C + ch] : 0.0, dg ? h : NULL, NULL);
+                }
+            }
+        }
+        *deps = tot;
     }
     return 0;
 }
@@ -704,6 +793,10 @@ typedef struct {
     double *H;          /* [N][C] absolute scale of G */
     double *P;          /* [M][C] near-field point accumulators (sorted order) */
     double *HP;         /* [M][C] absolute scale of P */
+    double *PN;         /* [M][3] near-field dL/dn accumulators, or NULL */
+    double *HPN;        /* [M] absolute scale of PN */
+    int want_eps;
+    double deps, sdeps; /* dL/deps of this query and its absolute scale */
 } astate;
 
 static void adjoint(astate *st, int64_t i)
@@ -739,6 +832,13 @@ static void adjoint(astate *st, int64_t i)
             for (int ch = 0; ch < C; ++ch)
                 grad_cotangent(d, r, kap, lam, nu, Dt + 3 * ch, st->dg + 3 * ch, st->G + (i * C + ch) * 3,
                                st->dx, st->H + i * C + ch, &st->sdx);
+        }
+        if (st->want_eps) {
+            double ke, le;
+            radial_eps(r, st->eps, &ke, &le);
+            for (int ch = 0; ch < C; ++ch)
+                st->deps += term_eps(d, ke, le, Dt + 3 * ch, st->df ? st->df[ch] : 0.0,
+                                     st->dg ? st->dg + 3 * ch : NULL, &st->sdeps);
         }
         return;
     }
@@ -777,6 +877,36 @@ static void adjoint(astate *st, int64_t i)
                     st->HP[j * C + ch] += sc * nAn;
                 }
             }
+            if (st->PN) {
+                /* dL/dn_j = A_j sum_c mu_jc dL/dD_jc of this query's term */
+                double sc = 0;
+                for (int ch = 0; ch < C; ++ch) {
+                    double dD[3] = {0, 0, 0}, s1 = 0;
+                    double w = st->df ? st->df[ch] : 0.0;
+                    for (int k = 0; k < 3; ++k) dD[k] = w * kap * d[k];
+                    s1 += fabs(w) * kap * r;
+                    if (st->dg) {
+                        const double *h = st->dg + 3 * ch;
+                        double dh = d[0] * h[0] + d[1] * h[1] + d[2] * h[2];
+                        for (int k = 0; k < 3; ++k) dD[k] += lam * dh * d[k] - kap * h[k];
+                        s1 += sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]) * (fabs(lam) * r2 + kap);
+                    }
+                    double am = t->Am[j] * t->mu[j * C + ch];
+                    for (int k = 0; k < 3; ++k) st->PN[3 * j + k] += am * dD[k];
+                    sc += fabs(am) * s1;
+                }
+                st->HPN[j] += sc;
+            }
+            if (st->want_eps) {
+                double ke, le;
+                radial_eps(r, st->eps, &ke, &le);
+                for (int ch = 0; ch < C; ++ch) {
+                    double mu = t->mu[j * C + ch];
+                    double D[3] = {mu * An[0], mu * An[1], mu * An[2]};
+                    st->deps += term_eps(d, ke, le, D, st->df ? st->df[ch] : 0.0,
+                                         st->dg ? st->dg + 3 * ch : NULL, &st->sdeps);
+                }
+            }
         }
         return;
     }
@@ -790,8 +920,8 @@ static void adjoint(astate *st, int64_t i)
  * are reduced in a fixed order, so the result is deterministic for a given
  * thread count. */
 int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, double eps,
-                   const float *df, const float *dg, double *dmu, double *dx, double *sdmu,
-                   double *sdx, int nthreads)
+                   const float *df, const float *dg, double *dmu, double *dx, double *dn,
+                   double *deps, double *sdmu, double *sdx, double *sdn, double *sdeps, int nthreads)
 {
     if (!t || !t->D || Q < 0 || !(beta > 0) || eps < 0 || (!df && !dg)) return 1;
     int C = t->C;
@@ -802,7 +932,13 @@ int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, dou
     double *H = (double *)calloc((size_t)nt * N * C, sizeof(double));
     double *P = (double *)calloc((size_t)nt * M * C, sizeof(double));
     double *HP = (double *)calloc((size_t)nt * M * C, sizeof(double));
-    if (!G || !H || !P || !HP) { free(G); free(H); free(P); free(HP); return 2; }
+    double *PN = dn ? (double *)calloc((size_t)nt * M * 3, sizeof(double)) : NULL;
+    double *HPN = dn ? (double *)calloc((size_t)nt * M, sizeof(double)) : NULL;
+    double *E = (double *)calloc((size_t)nt * 2, sizeof(double));
+    if (!G || !H || !P || !HP || !E || (dn && (!PN || !HPN))) {
+        free(G); free(H); free(P); free(HP); free(PN); free(HPN); free(E);
+        return 2;
+    }
 #pragma omp parallel num_threads(nt)
     {
         int tid = 0;
@@ -822,9 +958,14 @@ int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, dou
             for (int k = 0; k < 3; ++k) st.x[k] = (double)x[3 * q + k];
             st.G = G + (size_t)tid * N * C * 3; st.H = H + (size_t)tid * N * C;
             st.P = P + (size_t)tid * M * C; st.HP = HP + (size_t)tid * M * C;
+            st.PN = dn ? PN + (size_t)tid * M * 3 : NULL;
+            st.HPN = dn ? HPN + (size_t)tid * M : NULL;
+            st.want_eps = deps != NULL;
             adjoint(&st, 0);
             if (dx) for (int k = 0; k < 3; ++k) dx[3 * q + k] = st.dx[k];
             if (sdx) sdx[q] = st.sdx;
+            E[2 * tid] += st.deps;
+            E[2 * tid + 1] += st.sdeps;
         }
     }
     /* fixed-order reduction of the thread-private accumulators */
@@ -835,7 +976,15 @@ int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, dou
             P[i] += P[(size_t)k * M * C + i];
             HP[i] += HP[(size_t)k * M * C + i];
         }
+        if (dn) {
+            for (int64_t i = 0; i < M * 3; ++i) PN[i] += PN[(size_t)k * M * 3 + i];
+            for (int64_t i = 0; i < M; ++i) HPN[i] += HPN[(size_t)k * M + i];
+        }
+        E[0] += E[2 * k];
+        E[1] += E[2 * k + 1];
     }
+    if (deps) *deps = E[0];
+    if (sdeps) *sdeps = E[1];
     /* second stage: running sums from the root down (parents precede
      * children in breadth-first order), then each point takes
      * A_m n_m . (sum over its ancestors) -- eq. (farfield_features_gradient) */
@@ -855,7 +1004,19 @@ int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, dou
             if (dmu) dmu[orig * C + c] = v;
             if (sdmu) sdmu[orig * C + c] = HP[j * C + c] + nAn * H[l * C + c];
         }
+        if (dn) {
+            /* far field: every ancestor's node dipole holds A_j mu_jc n_j */
+            double v[3] = {PN[3 * j], PN[3 * j + 1], PN[3 * j + 2]}, sc = HPN[j];
+            for (int c = 0; c < C; ++c) {
+                double am = t->Am[j] * t->mu[j * C + c];
+                const double *S = G + (l * C + c) * 3;
+                for (int k = 0; k < 3; ++k) v[k] += am * S[k];
+                sc += fabs(am) * H[l * C + c];
+            }
+            for (int k = 0; k < 3; ++k) dn[3 * orig + k] = v[k];
+            if (sdn) sdn[orig] = sc;
+        }
     }
-    free(G); free(H); free(P); free(HP);
+    free(G); free(H); free(P); free(HP); free(PN); free(HPN); free(E);
     return 0;
 }

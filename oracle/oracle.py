@@ -47,6 +47,8 @@ def load():
         getattr(lib, nm).argtypes = [ct.c_double]
     lib.orc_radial_nu.restype = ct.c_double
     lib.orc_radial_nu.argtypes = [ct.c_double, ct.c_double]
+    lib.orc_radial_eps.restype = None
+    lib.orc_radial_eps.argtypes = [ct.c_double, ct.c_double, _f64p, _f64p]
     lib.orc_radial.restype = None
     lib.orc_radial.argtypes = [ct.c_double, ct.c_double, _f64p, _f64p]
     lib.orc_direct.restype = ct.c_int
@@ -54,7 +56,7 @@ def load():
                                vp, vp, vp, vp, ct.c_int]
     lib.orc_direct_adjoint.restype = ct.c_int
     lib.orc_direct_adjoint.argtypes = [vp, vp, vp, vp, ct.c_int64, ct.c_int, vp, ct.c_int64,
-                                       ct.c_double, vp, vp, vp, vp, ct.c_int]
+                                       ct.c_double, vp, vp, vp, vp, vp, vp, ct.c_int]
     lib.orc_tree_build.restype = vp
     lib.orc_tree_build.argtypes = [vp, vp, vp, ct.c_int64, ct.c_int]
     lib.orc_tree_free.restype = None
@@ -72,7 +74,7 @@ def load():
                                  ct.c_int]
     lib.orc_bh_adjoint.restype = ct.c_int
     lib.orc_bh_adjoint.argtypes = [vp, vp, ct.c_int64, ct.c_float, ct.c_double, vp, vp, vp, vp,
-                                   vp, vp, ct.c_int]
+                                   vp, vp, vp, vp, vp, vp, ct.c_int]
     _lib = lib
     return lib
 
@@ -102,6 +104,13 @@ def radial_nu(r, eps):
     return load().orc_radial_nu(float(r), float(eps))
 
 
+def radial_eps(r, eps):
+    """(d kappa / d eps, d lambda / d eps)."""
+    k, l = ct.c_double(), ct.c_double()
+    load().orc_radial_eps(float(r), float(eps), ct.byref(k), ct.byref(l))
+    return k.value, l.value
+
+
 def radial(r, eps):
     """(kappa, lambda) = (rho(r/eps)/(4 pi r^3), psi(r/eps)/(4 pi r^5))."""
     k, l = ct.c_double(), ct.c_double()
@@ -127,9 +136,11 @@ def direct(p, n, A, mu, x, eps, want_grad=True, nthreads=0):
     return {"f": f, "g": g, "sf": sf, "sg": sg}
 
 
-def direct_adjoint(p, n, A, mu, x, eps, df, nthreads=0, dg=None):
+def direct_adjoint(p, n, A, mu, x, eps, df, nthreads=0, dg=None, extra=False):
     """Exact transpose of ``direct`` (values and, with dg[Q,C,3], gradients):
-    returns (dmu[M,C], dx[Q,3]).  df may be None when dg is given."""
+    returns (dmu[M,C], dx[Q,3]), or with extra=True (dmu, dx, dn[M,3], deps)
+    including the derivatives in the normals and in eps.  df may be None when
+    dg is given."""
     lib = load()
     p, n, x = _c32(p, 3), _c32(n, 3), _c32(x, 3)
     A = _c32(A).reshape(-1)
@@ -140,11 +151,13 @@ def direct_adjoint(p, n, A, mu, x, eps, df, nthreads=0, dg=None):
     df = None if df is None else _c32(df).reshape(Q, C)
     dg = None if dg is None else _c32(dg).reshape(Q, C, 3)
     dmu = np.zeros((M, C)); dx = np.zeros((Q, 3))
+    dn = np.zeros((M, 3)) if extra else None
+    deps = np.zeros(1) if extra else None
     rc = lib.orc_direct_adjoint(_ptr(p), _ptr(n), _ptr(A), _ptr(mu), M, C, _ptr(x), Q, float(eps),
-                                _ptr(df), _ptr(dg), _ptr(dmu), _ptr(dx), int(nthreads))
+                                _ptr(df), _ptr(dg), _ptr(dmu), _ptr(dx), _ptr(dn), _ptr(deps), int(nthreads))
     if rc:
         raise ValueError("orc_direct_adjoint rejected its arguments")
-    return dmu, dx
+    return (dmu, dx, dn, float(deps[0])) if extra else (dmu, dx)
 
 
 class Tree:
@@ -210,19 +223,28 @@ class Tree:
             raise ValueError("orc_bh_query rejected its arguments")
         return {"f": f, "g": g, "sf": sf, "sg": sg, "counts": counts}
 
-    def adjoint(self, x, beta, eps, df, nthreads=0, dg=None):
+    def adjoint(self, x, beta, eps, df, nthreads=0, dg=None, extra=False):
         """Barnes-Hut adjoint for value cotangents df[Q,C] and/or gradient
         cotangents dg[Q,C,3] (df may be None when dg is given).  Returns dict
         dmu[M,C] (caller order), dx[Q,3], sdmu[M,C], sdx[Q] (absolute scales
-        for error normalisation)."""
+        for error normalisation); with extra=True also dn[M,3] (normals,
+        caller order), sdn[M], deps and sdeps (the global eps)."""
         x = _c32(x, 3)
         Q, C, M = x.shape[0], self.C, self.M
         df = None if df is None else _c32(df).reshape(Q, C)
         dg = None if dg is None else _c32(dg).reshape(Q, C, 3)
         dmu = np.zeros((M, C)); dx = np.zeros((Q, 3))
         sdmu = np.zeros((M, C)); sdx = np.zeros(Q)
+        dn = np.zeros((M, 3)) if extra else None
+        sdn = np.zeros(M) if extra else None
+        deps = np.zeros(1) if extra else None
+        sdeps = np.zeros(1) if extra else None
         rc = load().orc_bh_adjoint(self._h, _ptr(x), Q, float(beta), float(eps), _ptr(df), _ptr(dg),
-                                   _ptr(dmu), _ptr(dx), _ptr(sdmu), _ptr(sdx), int(nthreads))
+                                   _ptr(dmu), _ptr(dx), _ptr(dn), _ptr(deps), _ptr(sdmu), _ptr(sdx), _ptr(sdn),
+                                   _ptr(sdeps), int(nthreads))
         if rc:
             raise ValueError("orc_bh_adjoint rejected its arguments")
-        return {"dmu": dmu, "dx": dx, "sdmu": sdmu, "sdx": sdx}
+        out = {"dmu": dmu, "dx": dx, "sdmu": sdmu, "sdx": sdx}
+        if extra:
+            out.update(dn=dn, sdn=sdn, deps=float(deps[0]), sdeps=float(sdeps[0]))
+        return out

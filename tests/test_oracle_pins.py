@@ -669,3 +669,87 @@ def test_bh_grad_cotangent_dx_matches_finite_differences(orc):
         assert np.all(err[same] < 1e-3)
         checked += int(same.sum())
     assert checked > 100
+
+
+# --------------------------------------------------------------------------
+# derivatives in the normals and in eps (both optimised in Sec. 5.2)
+# --------------------------------------------------------------------------
+def test_eps_derivatives_of_radial(orc):
+    # d kappa / d eps and d lambda / d eps against central differences in eps
+    for eps in (0.02, 0.05, 0.3):
+        for r in (0.0, 0.005, 0.02, 0.06, 0.2):
+            h = eps * 1e-5
+            kp, lp = orc.radial(r, eps + h)
+            km, lm = orc.radial(r, eps - h)
+            ke, le = orc.radial_eps(r, eps)
+            assert abs((kp - km) / (2 * h) - ke) <= 1e-6 * abs(ke) + 1e-9 * abs(kp)
+            assert abs((lp - lm) / (2 * h) - le) <= 1e-6 * abs(le) + 1e-9 * abs(lp)
+    assert orc.radial_eps(0.1, 0.0) == (0.0, 0.0)
+
+
+def _loss_direct(orc, p, n, A, mu, x, eps, df, dg):
+    r = orc.direct(p, n, A, mu, x, eps)
+    return float(np.sum(df.astype(np.float64) * r["f"]) + np.sum(dg.astype(np.float64) * r["g"]))
+
+
+def _loss_bh(orc, p, n, A, mu, x, eps, df, dg, beta=2.0):
+    r = orc.Tree(p, n, A, mu, 16).query(x, beta, eps)
+    return float(np.sum(df.astype(np.float64) * r["f"]) + np.sum(dg.astype(np.float64) * r["g"]))
+
+
+def test_direct_normal_and_eps_derivatives_fd(orc):
+    # L = sum df . f + sum dg . grad f; linear in each normal component, so
+    # central differences are exact up to rounding; smooth in eps
+    p, n, A, mu = workloads.sfm_cloud(400, 20, 10)
+    x = workloads.sphere_queries(150, 5, half=1.0)
+    df = workloads.cotangents(150, mu.shape[1], 17)
+    dg = np.random.default_rng(41).standard_normal((150, mu.shape[1], 3)).astype(np.float32)
+    eps = 0.05
+    _, _, dn, deps = orc.direct_adjoint(p, n, A, mu, x, eps, df, dg=dg, extra=True)
+    rng = np.random.default_rng(42)
+    for m in rng.choice(p.shape[0], size=6, replace=False):
+        for k in range(3):
+            npl, nmi = n.copy(), n.copy()
+            npl[m, k] += np.float32(2.0 ** -8)
+            nmi[m, k] -= np.float32(2.0 ** -8)
+            step = float(npl[m, k]) - float(nmi[m, k])
+            fd = (_loss_direct(orc, p, npl, A, mu, x, eps, df, dg) -
+                  _loss_direct(orc, p, nmi, A, mu, x, eps, df, dg)) / step
+            assert abs(fd - dn[m, k]) <= 1e-7 * (abs(dn[m, k]) + np.abs(dn).max())
+    cd = {h: (_loss_direct(orc, p, n, A, mu, x, eps + h, df, dg) -
+              _loss_direct(orc, p, n, A, mu, x, eps - h, df, dg)) / (2 * h) for h in (1e-4, 5e-5)}
+    fd = (4 * cd[5e-5] - cd[1e-4]) / 3
+    assert abs(fd - deps) <= 1e-6 * abs(deps)
+
+
+def test_bh_normal_and_eps_derivatives(orc):
+    p, n, A, mu = workloads.sfm_cloud(3000, 100, 10)
+    x = workloads.sphere_queries(200, 13, half=1.0)
+    df = workloads.cotangents(200, mu.shape[1], 17)
+    dg = np.random.default_rng(43).standard_normal((200, mu.shape[1], 3)).astype(np.float32)
+    eps = 0.05
+    T = orc.Tree(p, n, A, mu, 16)
+    a = T.adjoint(x, 2.0, eps, df, dg=dg, extra=True)
+    assert np.all(a["sdn"] >= np.linalg.norm(a["dn"], axis=1) * (1 - 1e-12))
+    assert a["sdeps"] >= abs(a["deps"])
+    # the Barnes-Hut sum is linear in the normals (node dipoles are sums of
+    # A mu n; the tree geometry does not involve normals)
+    rng = np.random.default_rng(44)
+    for m in rng.choice(p.shape[0], size=4, replace=False):
+        for k in range(3):
+            npl, nmi = n.copy(), n.copy()
+            npl[m, k] += np.float32(2.0 ** -8)
+            nmi[m, k] -= np.float32(2.0 ** -8)
+            step = float(npl[m, k]) - float(nmi[m, k])
+            fd = (_loss_bh(orc, p, npl, A, mu, x, eps, df, dg) - _loss_bh(orc, p, nmi, A, mu, x, eps, df, dg)) / step
+            assert abs(fd - a["dn"][m, k]) <= 1e-7 * (abs(a["dn"][m, k]) + np.abs(a["dn"]).max())
+    # eps does not enter the far decisions: the BH sum is smooth in eps
+    cd = {h: (_loss_bh(orc, p, n, A, mu, x, eps + h, df, dg) -
+              _loss_bh(orc, p, n, A, mu, x, eps - h, df, dg)) / (2 * h) for h in (1e-4, 5e-5)}
+    fd = (4 * cd[5e-5] - cd[1e-4]) / 3
+    assert abs(fd - a["deps"]) <= 1e-6 * a["sdeps"]
+    # large beta: the direct adjoint
+    b = T.adjoint(x, 1e4, eps, df, dg=dg, extra=True)
+    _, _, dn, deps = orc.direct_adjoint(p, n, A, mu, x, eps, df, dg=dg, extra=True)
+    assert np.allclose(b["dn"], dn, rtol=1e-10, atol=1e-14 * np.abs(dn).max())
+    assert abs(b["deps"] - deps) <= 1e-10 * b["sdeps"]
