@@ -232,6 +232,40 @@ dps_status dps_adjoint_accumulate_grad(dps_tree t, const float *x, int64_t Q, co
                                        float eps, int32_t c_begin, int32_t n_channels, const float *df,
                                        const float *dg, float *dx, void *stream);
 
+/*
+ * Derivatives in the point normals and in eps.  Sec. 5.2 optimises the
+ * normals and the global regularisation eps together with the attributes.
+ * A term depends on n_m only through its dipole A_m mu_m n_m (the tree
+ * geometry -- centroids, radii, far decisions -- does not involve normals), so
+ *   dL/dn_m = A_m sum_c mu_mc dL/dD_mc,
+ * with the far-field part pushed down from the node accumulators of all
+ * ancestors; eps enters kappa and lambda only:
+ *   d kappa / d eps = -exp(-t^2) / (pi^1.5 eps^4),
+ *   d lambda / d eps = -2 exp(-t^2) / (pi^1.5 eps^6),
+ * nonzero in practice inside the regularised zone t < 4.5 (beyond it the
+ * kernels use rho = 1, psi = 3 and the derivative is below FP32 resolution).
+ *
+ * dps_adjoint_accumulate_ext -- as dps_adjoint_accumulate_grad, with df and
+ *   dg each optional (not both NULL), and want a mask of DPS_WANT_NORMALS
+ *   (accumulate the near-field part of dL/dn) and DPS_WANT_EPS (accumulate
+ *   dL/deps in FP64).  All calls between a zero and a finalize must use the
+ *   same eps.
+ * dps_adjoint_finalize_ext -- as dps_adjoint_finalize, every output optional
+ *   (at least one): dattrs [M][C], dnormals [M][3] (caller order), deps one
+ *   FP64 value; all device pointers.
+ * dps_set_normals -- replaces the point normals (device [M][3], caller order;
+ *   A_m n_m is stored).  The node moments follow at the next
+ *   dps_set_attributes, which must be called before the next query.
+ * All graph-safe; DPS_ERR_INVALID for NULL or out-of-range arguments.
+ */
+#define DPS_WANT_NORMALS 1
+#define DPS_WANT_EPS 2
+dps_status dps_adjoint_accumulate_ext(dps_tree t, const float *x, int64_t Q, const int64_t *q_count, float beta,
+                                      float eps, int32_t c_begin, int32_t n_channels, const float *df,
+                                      const float *dg, int32_t want, float *dx, void *stream);
+dps_status dps_adjoint_finalize_ext(dps_tree t, float *dattrs, float *dnormals, double *deps, void *stream);
+dps_status dps_set_normals(dps_tree t, const float *n, void *stream);
+
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A
  * traversal that would walk more than N nodes stops and sets this flag. */

@@ -40,36 +40,44 @@ def _refit(tree: B.Tree, attrs: torch.Tensor, mode):
 
 
 class DipoleSum(torch.autograd.Function):
-    """f, grad = DipoleSum.apply(attrs[M,C], x[Q,3], tree, beta, eps, opts).
+    """f, grad = DipoleSum.apply(attrs[M,C], x[Q,3], normals, eps, tree, beta, opts).
 
     ``opts`` = (c_begin, n_channels, q_count, want_grad, refit) with
     n_channels None meaning all channels.  ``f`` [Q,n] and ``grad`` [Q,n,3]
     (or None) are both differentiable w.r.t. attrs and x: cotangents of grad
     go through the Hessian adjoint (``dps_adjoint_accumulate_grad``).
-    With a device row count ``q_count`` (int64 CUDA tensor [1]) only the first
-    min(Q, q_count) rows are evaluated; the other rows of f / grad and of the
-    position gradient are zero."""
+    ``normals`` is None (the tree's normals) or an [M,3] tensor that replaces
+    them (the moments are refitted) and is differentiable; ``eps`` is a float
+    or a tensor, differentiable when it requires grad (its value is read on the
+    host).  With a device row count ``q_count`` (int64 CUDA tensor [1]) only
+    the first min(Q, q_count) rows are evaluated; the other rows of f / grad
+    and of the position gradient are zero."""
 
     @staticmethod
-    def forward(ctx, attrs, x, tree, beta, eps, opts):
+    def forward(ctx, attrs, x, normals, eps, tree, beta, opts):
         c_begin, n_ch, q_count, want_grad, refit = opts
         ctx.set_materialize_grads(False)
+        eps_v = float(eps.detach()) if isinstance(eps, torch.Tensor) else float(eps)
         attrs_c = attrs.detach().contiguous()
         x_c = x.detach().contiguous()
+        if normals is not None:
+            B.dps_set_normals(tree, normals.detach().contiguous())
+            refit = True  # the moments hold A n mu
         _refit(tree, attrs_c, refit)
         full = n_ch is None and q_count is None
         if full:
-            f, g = B.dps_query(tree, x_c, beta, eps, grad=want_grad)
+            f, g = B.dps_query(tree, x_c, beta, eps_v, grad=want_grad)
         else:
             n = tree.C - c_begin if n_ch is None else n_ch
             Q = x_c.shape[0]
             # rows past the device count are never written by the kernels
             f = torch.zeros((Q, n), device=x_c.device, dtype=torch.float32)
             g = torch.zeros((Q, n, 3), device=x_c.device, dtype=torch.float32) if want_grad else None
-            B.dps_query_channels(tree, x_c, beta, eps, c_begin, n, f_out=f, g_out=g, q_count=q_count)
+            B.dps_query_channels(tree, x_c, beta, eps_v, c_begin, n, f_out=f, g_out=g, q_count=q_count)
         ctx.save_for_backward(x_c, attrs_c)
-        ctx.tree, ctx.beta, ctx.eps, ctx.opts, ctx.full = tree, float(beta), float(eps), opts, full
+        ctx.tree, ctx.beta, ctx.eps, ctx.opts, ctx.full = tree, float(beta), eps_v, opts, full
         ctx.n = f.shape[1]
+        ctx.eps_like = eps if isinstance(eps, torch.Tensor) else None
         return f, g
 
     @staticmethod
@@ -79,11 +87,23 @@ class DipoleSum(torch.autograd.Function):
         c_begin, n_ch, q_count, _, refit = ctx.opts
         if refit == "auto":
             _refit_if_changed(tree, attrs)
-        need_attr, need_x = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        if (df is None and dg is None) or not (need_attr or need_x):
-            return None, None, None, None, None, None
+        need_attr, need_x, need_n, need_eps = ctx.needs_input_grad[:4]
+        none = (None,) * 7
+        if (df is None and dg is None) or not (need_attr or need_x or need_n or need_eps):
+            return none
         df = None if df is None else df.contiguous().to(torch.float32)
-        if dg is not None:
+        dn = de = None
+        if need_n or need_eps:
+            dg = None if dg is None else dg.contiguous().to(torch.float32)
+            dx = torch.zeros((x.shape[0], 3), device=x.device, dtype=torch.float32) if need_x else None
+            want = (B.WANT_NORMALS if need_n else 0) | (B.WANT_EPS if need_eps else 0)
+            B.dps_adjoint_zero(tree)
+            B.dps_adjoint_accumulate_ext(tree, x, ctx.beta, ctx.eps, df=df, dg=dg, want=want, c_begin=c_begin,
+                                         n_channels=ctx.n, want_dx=need_x, dx_out=dx, q_count=q_count)
+            dattrs, dn, de = B.dps_adjoint_finalize_ext(tree, attrs=need_attr, normals=need_n, eps=need_eps)
+            if de is not None:
+                de = de.to(device=ctx.eps_like.device, dtype=ctx.eps_like.dtype).reshape(ctx.eps_like.shape)
+        elif dg is not None:
             # gradient cotangents (with the value cotangents, if any)
             dg = dg.contiguous().to(torch.float32)
             dx = torch.zeros((x.shape[0], 3), device=x.device, dtype=torch.float32) if need_x else None
@@ -100,20 +120,21 @@ class DipoleSum(torch.autograd.Function):
             B.dps_adjoint_accumulate_channels(tree, x, ctx.beta, ctx.eps, c_begin, n, df, want_dx=need_x,
                                               dx_out=dx, q_count=q_count)
             dattrs = B.dps_adjoint_finalize(tree)
-        dattrs = dattrs.reshape(attrs.shape) if need_attr else None
-        return dattrs, (dx if need_x else None), None, None, None, None
+        dattrs = dattrs.reshape(attrs.shape) if (need_attr and dattrs is not None) else None
+        return dattrs, (dx if need_x else None), dn, de, None, None, None
 
 
-def dipole_sum(attrs, x, tree, beta: float, eps: float, *, channels=None, q_count=None, grad: bool = True,
-               refit="auto"):
+def dipole_sum(attrs, x, tree, beta: float, eps, *, channels=None, q_count=None, grad: bool = True,
+               refit="auto", normals=None):
     """Functional form of ``DipoleSum``: returns (f, grad or None).
 
     channels: None (all) or (c_begin, n_channels); q_count: optional int64
     CUDA tensor [1] with the number of rows to evaluate; grad: also return the
     spatial gradients; refit: "auto" (refit when attrs changed since the last
     refit, judged from its storage and version), True (always, e.g. inside a
-    captured graph) or False (never)."""
+    captured graph) or False (never); normals: optional [M,3] tensor of point
+    normals (differentiable); eps: float, or a tensor to differentiate."""
     c_begin, n_ch = (0, None) if channels is None else (int(channels[0]), int(channels[1]))
     if channels is not None and c_begin == 0 and n_ch == tree.C:
         n_ch = None
-    return DipoleSum.apply(attrs, x, tree, beta, eps, (c_begin, n_ch, q_count, bool(grad), refit))
+    return DipoleSum.apply(attrs, x, normals, eps, tree, beta, (c_begin, n_ch, q_count, bool(grad), refit))

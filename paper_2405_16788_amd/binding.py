@@ -22,7 +22,8 @@ EXPORTED = (
     "dps_build", "dps_set_attributes", "dps_query", "dps_query_counts", "dps_adjoint_zero",
     "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
     "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_query_channels",
-    "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_check", "dps_destroy",
+    "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_adjoint_accumulate_ext",
+    "dps_adjoint_finalize_ext", "dps_set_normals", "dps_check", "dps_destroy",
     "dps_status_string", "dps_last_error",
 )
 
@@ -60,6 +61,9 @@ def load():
         "dps_query_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate_grad": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp, vp],
+        "dps_adjoint_accumulate_ext": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, i32, vp, vp],
+        "dps_adjoint_finalize_ext": [vp, vp, vp, vp, vp],
+        "dps_set_normals": [vp, vp, vp],
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
         "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
@@ -309,6 +313,55 @@ def dps_adjoint_accumulate_grad(tree: Tree, x, beta: float, eps: float, dg, df=N
         _ptr(dg, torch.float32, (Q, n, 3), tree.device, "dg"),
         _ptr(dx, torch.float32, (Q, 3), tree.device, "dx"), _stream(tree.device)), "dps_adjoint_accumulate_grad")
     return dx
+
+
+WANT_NORMALS = 1
+WANT_EPS = 2
+
+
+def dps_adjoint_accumulate_ext(tree: Tree, x, beta: float, eps: float, df=None, dg=None, want: int = 0,
+                               c_begin: int = 0, n_channels=None, want_dx: bool = True, dx_out=None, q_count=None):
+    """Stage 1 for value and/or gradient cotangents, optionally accumulating
+    the near-field part of dL/dnormals (WANT_NORMALS) and dL/deps (WANT_EPS);
+    returns dx[Q,3] (or None)."""
+    import torch
+    Q = x.shape[0]
+    n = tree.C - c_begin if n_channels is None else n_channels
+    dx = dx_out if dx_out is not None else (
+        torch.empty((Q, 3), device=tree.device, dtype=torch.float32) if want_dx else None)
+    _check(load().dps_adjoint_accumulate_ext(
+        tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q,
+        _ptr(q_count, torch.int64, (1,), tree.device, "q_count"), float(beta), float(eps), int(c_begin), int(n),
+        _ptr(df, torch.float32, (Q, n), tree.device, "df"), _ptr(dg, torch.float32, (Q, n, 3), tree.device, "dg"),
+        int(want), _ptr(dx, torch.float32, (Q, 3), tree.device, "dx"), _stream(tree.device)),
+        "dps_adjoint_accumulate_ext")
+    return dx
+
+
+def dps_adjoint_finalize_ext(tree: Tree, attrs: bool = True, normals: bool = False, eps: bool = False,
+                             dattrs_out=None, dnormals_out=None, deps_out=None):
+    """Stage 2 with optional outputs; returns (dattrs[M,C] or None,
+    dnormals[M,3] or None, deps float64 tensor [1] or None)."""
+    import torch
+    dev = tree.device
+    da = dattrs_out if dattrs_out is not None else (
+        torch.empty((tree.M, tree.C), device=dev, dtype=torch.float32) if attrs else None)
+    dn = dnormals_out if dnormals_out is not None else (
+        torch.empty((tree.M, 3), device=dev, dtype=torch.float32) if normals else None)
+    de = deps_out if deps_out is not None else (torch.empty(1, device=dev, dtype=torch.float64) if eps else None)
+    _check(load().dps_adjoint_finalize_ext(tree.handle, _ptr(da, torch.float32, (tree.M, tree.C), dev, "dattrs"),
+                                           _ptr(dn, torch.float32, (tree.M, 3), dev, "dnormals"),
+                                           _ptr(de, torch.float64, (1,), dev, "deps"), _stream(dev)),
+           "dps_adjoint_finalize_ext")
+    return da, dn, de
+
+
+def dps_set_normals(tree: Tree, normals):
+    """Replaces the point normals [M,3] (caller order); call dps_set_attributes
+    before the next query so the node moments follow."""
+    import torch
+    _check(load().dps_set_normals(tree.handle, _ptr(normals, torch.float32, (tree.M, 3), tree.device, "normals"),
+                                  _stream(tree.device)), "dps_set_normals")
 
 
 def dps_check(tree: Tree):

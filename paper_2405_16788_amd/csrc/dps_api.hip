@@ -127,12 +127,16 @@ dps_status dps_build(const float *p, const float *n, const float *A, const float
         if (st == DPS_OK) st = tree_alloc(t, &t->G, (size_t)t->N * 3 * C);
         if (st == DPS_OK) st = tree_alloc(t, &t->S, (size_t)t->N * 3 * C);
         if (st == DPS_OK) st = tree_alloc(t, &t->P, (size_t)M * C);
+        if (st == DPS_OK) st = tree_alloc(t, &t->PN, (size_t)M * 3);
+        if (st == DPS_OK) st = tree_alloc(t, &t->EACC, 1);
         if (st == DPS_OK) st = tree_alloc(t, &t->err, 1);
         if (st == DPS_OK) st = tree_alloc(t, &t->ctr, 16);
         if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->err, 0, sizeof(uint32_t), s), "zero err");
         if (st == DPS_OK) st = refit_moments(t, attrs, s);
         if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->G, 0, (size_t)t->N * 3 * C * sizeof(double), s), "zero G");
         if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->P, 0, (size_t)M * C * sizeof(double), s), "zero P");
+        if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->PN, 0, (size_t)M * 3 * sizeof(double), s), "zero PN");
+        if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->EACC, 0, sizeof(double), s), "zero eps");
         if (st == DPS_OK) st = hip_status(hipStreamSynchronize(s), "sync build");
     }
     if (st != DPS_OK) {
@@ -269,7 +273,39 @@ dps_status dps_adjoint_accumulate_grad(dps_tree t, const float *x, int64_t Q, co
     if (Q == 0) return DPS_OK;
     if (!x || !dg) return invalid("dps_adjoint_accumulate_grad: NULL x or dg");
     DeviceGuard guard(t->device);
-    return launch_adjoint_g(t, x, Q, q_count, beta, eps, c_begin, n_channels, df, dg, dx, (hipStream_t)stream);
+    return launch_adjoint_g(t, x, Q, q_count, beta, eps, c_begin, n_channels, df, dg, 0, dx, (hipStream_t)stream);
+}
+
+dps_status dps_adjoint_accumulate_ext(dps_tree t, const float *x, int64_t Q, const int64_t *q_count, float beta,
+                                      float eps, int32_t c_begin, int32_t n_channels, const float *df,
+                                      const float *dg, int32_t want, float *dx, void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint_accumulate_ext");
+    if (st != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate_ext")) != DPS_OK) return st;
+    if ((st = check_channels(t, c_begin, n_channels, "dps_adjoint_accumulate_ext")) != DPS_OK) return st;
+    if (want < 0 || want > (DPS_WANT_NORMALS | DPS_WANT_EPS))
+        return invalid("dps_adjoint_accumulate_ext: want must be a mask of DPS_WANT_NORMALS and DPS_WANT_EPS");
+    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint_accumulate_ext: Q out of range");
+    if (Q == 0) return DPS_OK;
+    if (!x || (!df && !dg)) return invalid("dps_adjoint_accumulate_ext: NULL x, or neither df nor dg");
+    DeviceGuard guard(t->device);
+    return launch_adjoint_g(t, x, Q, q_count, beta, eps, c_begin, n_channels, df, dg, want, dx, (hipStream_t)stream);
+}
+
+dps_status dps_adjoint_finalize_ext(dps_tree t, float *dattrs, float *dnormals, double *deps, void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint_finalize_ext");
+    if (st != DPS_OK) return st;
+    if (!dattrs && !dnormals && !deps) return invalid("dps_adjoint_finalize_ext: no output requested");
+    DeviceGuard guard(t->device);
+    return launch_finalize_ext(t, dattrs, dnormals, deps, (hipStream_t)stream);
+}
+
+dps_status dps_set_normals(dps_tree t, const float *n, void *stream) {
+    dps_status st = check_tree(t, "dps_set_normals");
+    if (st != DPS_OK) return st;
+    if (!n) return invalid("dps_set_normals: n is NULL");
+    DeviceGuard guard(t->device);
+    return launch_set_normals(t, n, (hipStream_t)stream);
 }
 
 dps_status dps_adjoint_finalize(dps_tree t, float *dattrs, void *stream) {

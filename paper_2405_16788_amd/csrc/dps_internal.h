@@ -99,6 +99,8 @@ struct KernelParams {
     float k3;        // 1/(4 pi eps^3)
     float k5;        // 1/(4 pi eps^5)
     float k7;        // 1/(4 pi eps^7)
+    float ke4;       // 1/(pi^1.5 eps^4):   d kappa / d eps = -exp(-t^2) ke4
+    float ke6;       // 2/(pi^1.5 eps^6):   d lambda / d eps = -exp(-t^2) ke6
 };
 
 __host__ inline KernelParams make_kernel_params(float eps) {
@@ -111,12 +113,16 @@ __host__ inline KernelParams make_kernel_params(float eps) {
         kp.k3 = (float)(0.0795774715459476679 / (e * e * e));
         kp.k5 = (float)(0.0795774715459476679 / (e * e * e * e * e));
         kp.k7 = (float)(0.0795774715459476679 / (e * e * e * e * e * e * e));
+        kp.ke4 = (float)(0.179587122125166564 / (e * e * e * e));
+        kp.ke6 = (float)(0.359174244250333128 / (e * e * e * e * e * e));
     } else {
         kp.ieps = 0.0f;
         kp.ieps2 = 0.0f;
         kp.k3 = 0.0f;
         kp.k5 = 0.0f;
         kp.k7 = 0.0f;
+        kp.ke4 = 0.0f;
+        kp.ke6 = 0.0f;
     }
     return kp;
 }

@@ -675,13 +675,20 @@ __global__ __launch_bounds__(kThreads, (CB == 4 && K == 4) ? DPS_ADJOINT_WAVES :
 //   dx += [sum_c lambda w_c s_c + nu s_c (d.h_c) - lambda (D_c.h_c)] d
 //         - sum_c beta_c D_c - lambda sum_c s_c h_c.
 // ---------------------------------------------------------------------------
-template <int CB, bool BF16, int K, bool DF>
+// EXT additionally accumulates, when the pointers are given, dL/deps into
+// eacc (d kappa / d eps = -exp(-t^2) ke4, d lambda / d eps = -exp(-t^2) ke6,
+// nonzero inside the regularised zone only) and the near-field part of dL/dn
+// into pn: A_j sum_c mu_jc dL/dD_jc per point (the far-field part is pushed
+// down from the node accumulators at the end).  dg may be NULL (zero).
+template <int CB, bool BF16, int K, bool DF, bool EXT>
 __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int C, const float *__restrict__ df,
                                                const float *__restrict__ dg, double *__restrict__ G,
-                                               double *__restrict__ P, float *__restrict__ dxout, int dx_mode) {
+                                               double *__restrict__ P, float *__restrict__ dxout, int dx_mode,
+                                               double *__restrict__ pn, double *__restrict__ eacc) {
     const int lane = lane_id();
     float px[K], py[K], pz[K], w[K][CB], h[K][CB][3], ax[K], ay[K], az[K];
     uint32_t bits[K];
+    float deps = 0.0f;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int64_t q = q0 + 64 * i;
@@ -695,7 +702,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         for (int c = 0; c < CB; ++c) {
             w[i][c] = (DF && valid) ? df[q * ldo + co + c] : 0.0f;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) h[i][c][j] = valid ? dg[(q * ldo + co + c) * 3 + j] : 0.0f;
+            for (int j = 0; j < 3; ++j) h[i][c][j] = (dg && valid) ? dg[(q * ldo + co + c) * 3 + j] : 0.0f;
         }
     }
     uint32_t t = 0;
@@ -740,6 +747,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                     radial3(s2[i], kp, kap, lam, nu);
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
                     float al = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
+                    float e1 = 0.0f, e2 = 0.0f;  // sum_c (w_c s_c - D_c.h_c), sum_c s_c (d.h_c)
 #pragma unroll
                     for (int c = 0; c < CB; ++c) {
                         const float Dx = D[3 * c], Dy = D[3 * c + 1], Dz = D[3 * c + 2];
@@ -756,10 +764,21 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                         acc[3 * c] = fmaf(be, dx, fmaf(-kap, hx, acc[3 * c]));
                         acc[3 * c + 1] = fmaf(be, dy, fmaf(-kap, hy, acc[3 * c + 1]));
                         acc[3 * c + 2] = fmaf(be, dz, fmaf(-kap, hz, acc[3 * c + 2]));
+                        if constexpr (EXT) {
+                            e1 = fmaf(w[i][c], sc, e1 - Dh);
+                            e2 = fmaf(sc, dh, e2);
+                        }
                     }
                     ax[i] += fmaf(al, dx, -vx);
                     ay[i] += fmaf(al, dy, -vy);
                     az[i] += fmaf(al, dz, -vz);
+                    if constexpr (EXT) {
+                        const float u = s2[i] * kp.ieps2;
+                        if (eacc && kp.eps > 0.0f && u < kFarT2) {
+                            const float e = expf(-u);
+                            deps = fmaf(-e, fmaf(kp.ke4, e1, kp.ke6 * e2), deps);
+                        }
+                    }
                 }
             }
             scatter_add_node(acc, lane, &G[((size_t)t * C + c0) * 3]);
@@ -776,6 +795,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                     float mu[CB];
                     load_attrs<CB, BF16>(attr, as, j, c0, mu);
                     float acc[CB];
+                    float nacc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
                     for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
 #pragma unroll
@@ -787,6 +807,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                             if (radial3(r2, kp, kap, lam, nu)) {
                                 const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
                                 float al = 0.0f, bsum = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
+                                float hmx = 0.0f, hmy = 0.0f, hmz = 0.0f, e1 = 0.0f, e2 = 0.0f;
 #pragma unroll
                                 for (int c = 0; c < CB; ++c) {
                                     const float hx = h[i][c][0], hy = h[i][c][1], hz = h[i][c][2];
@@ -802,14 +823,35 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                                     vx = fmaf(ls, hx, vx);
                                     vy = fmaf(ls, hy, vy);
                                     vz = fmaf(ls, hz, vz);
+                                    if constexpr (EXT) {
+                                        hmx = fmaf(mu[c], hx, hmx);
+                                        hmy = fmaf(mu[c], hy, hmy);
+                                        hmz = fmaf(mu[c], hz, hmz);
+                                        e1 = fmaf(w[i][c], sc, e1 - mu[c] * Ah);
+                                        e2 = fmaf(sc, dh, e2);
+                                    }
                                 }
                                 ax[i] += fmaf(al, dx, -fmaf(bsum, pr.anx, vx));
                                 ay[i] += fmaf(al, dy, -fmaf(bsum, pr.any, vy));
                                 az[i] += fmaf(al, dz, -fmaf(bsum, pr.anz, vz));
+                                if constexpr (EXT) {
+                                    // dL/dn_j of this term: A_j sum_c mu_c (beta_c d - kappa h_c)
+                                    nacc[0] += pr.a * fmaf(bsum, dx, -kap * hmx);
+                                    nacc[1] += pr.a * fmaf(bsum, dy, -kap * hmy);
+                                    nacc[2] += pr.a * fmaf(bsum, dz, -kap * hmz);
+                                    const float u = r2 * kp.ieps2;
+                                    if (eacc && kp.eps > 0.0f && u < kFarT2) {
+                                        const float e = expf(-u);
+                                        deps = fmaf(-e, fmaf(kp.ke4, e1, kp.ke6 * e2), deps);
+                                    }
+                                }
                             }
                         }
                     }
                     scatter_add_node(acc, lane, &P[(size_t)j * C + c0]);
+                    if constexpr (EXT) {
+                        if (pn) scatter_add_node(nacc, lane, &pn[(size_t)j * 3]);
+                    }
                 }
             }
         }
@@ -818,6 +860,12 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         nd = nn;
 #pragma unroll
         for (int v = 0; v < 3 * CB; ++v) D[v] = Dn[v];
+    }
+    if constexpr (EXT) {
+        if (eacc) {
+            const float tot = wave_sum(deps);
+            if (lane == 0) atomicAdd(eacc, (double)tot);
+        }
     }
     if (dx_mode != 0) {
 #pragma unroll
@@ -838,25 +886,28 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
     }
 }
 
-template <int CB, bool BF16, int K, bool DF>
+template <int CB, bool BF16, int K, bool DF, bool EXT>
 __global__ __launch_bounds__(kThreads) void k_adjoint_g(DPS_KERN_PARAMS, int C, const float *__restrict__ df,
                                                         const float *__restrict__ dg, double *__restrict__ G,
                                                         double *__restrict__ P, float *__restrict__ dxout,
-                                                        int dx_mode, int xcd_remap) {
+                                                        int dx_mode, double *__restrict__ pn,
+                                                        double *__restrict__ eacc, int xcd_remap) {
     DPS_ROWS;
     const int64_t blk = remap_block(xcd_remap);
     if (blk < 0 || blk * (int64_t)blockDim.x * K >= Q) return;  // whole block past the rows
     const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
-    adjoint_g_body<CB, BF16, K, DF>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, dg, G, P, dxout,
-                                    dx_mode);
+    adjoint_g_body<CB, BF16, K, DF, EXT>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, dg, G, P, dxout,
+                                         dx_mode, pn, eacc);
 }
 
-template <int CB, bool BF16, int K, bool DF>
+template <int CB, bool BF16, int K, bool DF, bool EXT>
 __global__ __launch_bounds__(kThreads) void k_adjoint_g_persistent(DPS_KERN_PARAMS, int C,
                                                                    const float *__restrict__ df,
                                                                    const float *__restrict__ dg,
                                                                    double *__restrict__ G, double *__restrict__ P,
                                                                    float *__restrict__ dxout, int dx_mode,
+                                                                   double *__restrict__ pn,
+                                                                   double *__restrict__ eacc,
                                                                    uint32_t *__restrict__ ctr) {
     DPS_ROWS;
     const int64_t ntiles = (Q + 64 * K - 1) / (64 * K);
@@ -864,9 +915,52 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_g_persistent(DPS_KERN_PARA
     for (;;) {
         const int64_t tile = next_tile(ctr, ntiles, part);
         if (tile < 0) break;
-        adjoint_g_body<CB, BF16, K, DF>(tile * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, dg, G, P, dxout,
-                                        dx_mode);
+        adjoint_g_body<CB, BF16, K, DF, EXT>(tile * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, dg, G, P,
+                                             dxout, dx_mode, pn, eacc);
     }
+}
+
+// dL/dn in caller order: the pushed-down node accumulators at the point's
+// leaf, A_j sum_c mu_jc S_leaf,c, plus the near-field accumulator
+template <bool BF16>
+__global__ void k_normals_out(int64_t M, int C, int as, const int32_t *__restrict__ leaf_of,
+                              const uint32_t *__restrict__ perm, const PointRec *__restrict__ pts,
+                              const void *__restrict__ attr, const double *__restrict__ PN,
+                              const double *__restrict__ S, float *__restrict__ dn) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    const int64_t l = leaf_of[j];
+    double v0 = PN[3 * j], v1 = PN[3 * j + 1], v2 = PN[3 * j + 2];
+    const double a = pts[j].a;
+    for (int c = 0; c < C; ++c) {
+        const float mu = BF16 ? __uint_as_float((uint32_t)((const uint16_t *)attr)[j * as + c] << 16)
+                              : ((const float *)attr)[j * as + c];
+        const double am = a * (double)mu;
+        const double *Sl = S + (l * C + c) * 3;
+        v0 += am * Sl[0];
+        v1 += am * Sl[1];
+        v2 += am * Sl[2];
+    }
+    const int64_t o = (int64_t)perm[j] * 3;
+    dn[o] = (float)v0;
+    dn[o + 1] = (float)v1;
+    dn[o + 2] = (float)v2;
+}
+
+__global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
+}
+
+// new normals: A n of every point record (sorted order), from caller order
+__global__ void k_set_normals(const float *__restrict__ n, const uint32_t *__restrict__ perm, int64_t M,
+                              PointRec *__restrict__ pts) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= M) return;
+    const int64_t i = perm[j];
+    const float a = pts[j].a;
+    pts[j].anx = mul_rn(a, n[3 * i]);
+    pts[j].any = mul_rn(a, n[3 * i + 1]);
+    pts[j].anz = mul_rn(a, n[3 * i + 2]);
 }
 
 __global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t n, uint32_t v) {
@@ -1062,47 +1156,59 @@ dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t
     return adjoint_launch<CB, false, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
 }
 
-template <int CB, bool BF, int K, bool DF>
+template <int CB, bool BF, int K, bool DF, bool EXT>
 dps_status adjoint_g_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp,
-                            Sub sb, const float *df, const float *dg, float *dx, int dx_mode, hipStream_t s) {
+                            Sub sb, const float *df, const float *dg, float *dx, int dx_mode, double *pn,
+                            double *eacc, hipStream_t s) {
     const uint32_t lim = (uint32_t)t->N;
     if (t->launch_flags & kFlagPersistentAdjoint) {
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
-        const void *fn = reinterpret_cast<const void *>(&k_adjoint_g_persistent<CB, BF, K, DF>);
-        k_adjoint_g_persistent<CB, BF, K, DF><<<persistent_grid(fn), kThreads, 0, s>>>(
+        const void *fn = reinterpret_cast<const void *>(&k_adjoint_g_persistent<CB, BF, K, DF, EXT>);
+        k_adjoint_g_persistent<CB, BF, K, DF, EXT><<<persistent_grid(fn), kThreads, 0, s>>>(
             t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
-            lim, t->err, t->C, df, dg, t->G, t->P, dx, dx_mode, t->ctr + 8);
+            lim, t->err, t->C, df, dg, t->G, t->P, dx, dx_mode, pn, eacc, t->ctr + 8);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdAdjoint) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
-        k_adjoint_g<CB, BF, K, DF><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
-                                                           t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
-                                                           lim, t->err, t->C, df, dg, t->G, t->P, dx, dx_mode,
-                                                           remap ? (int)nb : 0);
+        k_adjoint_g<CB, BF, K, DF, EXT><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+                                                                t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo,
+                                                                sb.co, lim, t->err, t->C, df, dg, t->G, t->P, dx,
+                                                                dx_mode, pn, eacc, remap ? (int)nb : 0);
     }
     return hip_status(hipGetLastError(), "adjoint launch");
 }
 
 // queries per lane of the gradient-cotangent adjoint: 2 up to 2 channels
 // per block, else 1 (each query carries 3 cotangents per channel)
-template <int CB, bool BF, bool DF>
+template <int CB, bool BF, bool DF, bool EXT>
 dps_status adjoint_g_k(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
-                       const float *df, const float *dg, float *dx, int dx_mode, hipStream_t s) {
+                       const float *df, const float *dg, float *dx, int dx_mode, double *pn, double *eacc,
+                       hipStream_t s) {
     if constexpr (CB <= 2) {
-        if (t->packet_adjoint >= 2) return adjoint_g_launch<CB, BF, 2, DF>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
+        if (t->packet_adjoint >= 2)
+            return adjoint_g_launch<CB, BF, 2, DF, EXT>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s);
     }
-    return adjoint_g_launch<CB, BF, 1, DF>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
+    return adjoint_g_launch<CB, BF, 1, DF, EXT>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s);
+}
+
+template <int CB, bool EXT>
+dps_status adjoint_g_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp,
+                           Sub sb, const float *df, const float *dg, float *dx, int dx_mode, double *pn,
+                           double *eacc, hipStream_t s) {
+    const bool bf = t->storage == DPS_STORE_BF16;
+    if (bf && df) return adjoint_g_k<CB, true, true, EXT>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s);
+    if (bf) return adjoint_g_k<CB, true, false, EXT>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s);
+    if (df) return adjoint_g_k<CB, false, true, EXT>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s);
+    return adjoint_g_k<CB, false, false, EXT>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s);
 }
 
 template <int CB>
-dps_status adjoint_g_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp,
-                           Sub sb, const float *df, const float *dg, float *dx, int dx_mode, hipStream_t s) {
-    const bool bf = t->storage == DPS_STORE_BF16;
-    if (bf && df) return adjoint_g_k<CB, true, true>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
-    if (bf) return adjoint_g_k<CB, true, false>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
-    if (df) return adjoint_g_k<CB, false, true>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
-    return adjoint_g_k<CB, false, false>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s);
+dps_status adjoint_g_block_any(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2,
+                               KernelParams kp, Sub sb, const float *df, const float *dg, float *dx, int dx_mode,
+                               double *pn, double *eacc, hipStream_t s) {
+    if (pn || eacc) return adjoint_g_block<CB, true>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s);
+    return adjoint_g_block<CB, false>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, nullptr, nullptr, s);
 }
 
 }  // namespace
@@ -1162,7 +1268,13 @@ dps_status launch_zero(dps_tree_s *t, hipStream_t s) {
     dps_status st = hip_status(hipGetLastError(), "zero node accumulators");
     if (st != DPS_OK) return st;
     k_fill_f64<<<(unsigned)std::min<int64_t>(cdiv(np, kThreads), 4096), kThreads, 0, s>>>(t->P, np);
-    return hip_status(hipGetLastError(), "zero point accumulators");
+    st = hip_status(hipGetLastError(), "zero point accumulators");
+    if (st != DPS_OK) return st;
+    k_fill_f64<<<(unsigned)std::min<int64_t>(cdiv(t->M * 3, kThreads), 4096), kThreads, 0, s>>>(t->PN, t->M * 3);
+    st = hip_status(hipGetLastError(), "zero normal accumulators");
+    if (st != DPS_OK) return st;
+    k_fill_f64<<<1, 64, 0, s>>>(t->EACC, 1);
+    return hip_status(hipGetLastError(), "zero eps accumulator");
 }
 
 dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s) {
@@ -1192,7 +1304,8 @@ dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *mome
 }
 
 dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
-                            int cbegin, int nc, const float *df, const float *dg, float *dx, hipStream_t s) {
+                            int cbegin, int nc, const float *df, const float *dg, int want, float *dx,
+                            hipStream_t s) {
     const float b2 = mul_rn(beta, beta);
     const KernelParams kp = make_kernel_params(eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
@@ -1200,18 +1313,55 @@ dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int6
         const int rem = cbegin + nc - c0;
         const int cb = rem >= 4 ? 4 : rem;
         const int dx_mode = dx ? (c0 == cbegin ? 1 : 2) : 0;
+        double *pn = (want & 1) ? t->PN : nullptr;
+        double *eacc = (want & 2) ? t->EACC : nullptr;
         const Sub sb{c0, nc, c0 - cbegin};
         dps_status st;
         switch (cb) {
-            case 4: st = adjoint_g_block<4>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s); break;
-            case 3: st = adjoint_g_block<3>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s); break;
-            case 2: st = adjoint_g_block<2>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s); break;
-            default: st = adjoint_g_block<1>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, s); break;
+            case 4: st = adjoint_g_block_any<4>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s); break;
+            case 3: st = adjoint_g_block_any<3>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s); break;
+            case 2: st = adjoint_g_block_any<2>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s); break;
+            default: st = adjoint_g_block_any<1>(t, x, Q, qdev, b2, kp, sb, df, dg, dx, dx_mode, pn, eacc, s); break;
         }
         if (st != DPS_OK) return st;
         c0 += cb;
     }
     return DPS_OK;
+}
+
+dps_status launch_finalize_ext(dps_tree_s *t, float *dattrs, float *dnormals, double *deps, hipStream_t s) {
+    if (dattrs || dnormals) {
+        k_leaf_sums<<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->nodes, t->parent, t->G, t->S);
+        dps_status st = hip_status(hipGetLastError(), "leaf sums");
+        if (st != DPS_OK) return st;
+    }
+    if (dattrs) {
+        k_points_out<<<grid(t->M * t->C), kThreads, 0, s>>>(t->M, t->C, t->leaf_of, t->perm, t->pts, t->P, t->S,
+                                                            dattrs);
+        dps_status st = hip_status(hipGetLastError(), "point gradients");
+        if (st != DPS_OK) return st;
+    }
+    if (dnormals) {
+        if (t->storage == DPS_STORE_BF16)
+            k_normals_out<true><<<grid(t->M), kThreads, 0, s>>>(t->M, t->C, t->attr_stride, t->leaf_of, t->perm,
+                                                                t->pts, t->attr, t->PN, t->S, dnormals);
+        else
+            k_normals_out<false><<<grid(t->M), kThreads, 0, s>>>(t->M, t->C, t->attr_stride, t->leaf_of, t->perm,
+                                                                 t->pts, t->attr, t->PN, t->S, dnormals);
+        dps_status st = hip_status(hipGetLastError(), "normal gradients");
+        if (st != DPS_OK) return st;
+    }
+    if (deps) {
+        k_copy_f64<<<1, 64, 0, s>>>(t->EACC, deps);
+        dps_status st = hip_status(hipGetLastError(), "eps gradient");
+        if (st != DPS_OK) return st;
+    }
+    return DPS_OK;
+}
+
+dps_status launch_set_normals(dps_tree_s *t, const float *n, hipStream_t s) {
+    k_set_normals<<<grid(t->M), kThreads, 0, s>>>(n, t->perm, t->M, t->pts);
+    return hip_status(hipGetLastError(), "set normals");
 }
 
 }  // namespace dps

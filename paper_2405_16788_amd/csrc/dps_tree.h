@@ -38,6 +38,8 @@ struct dps_tree_s {
     double *G;                // [N][C][3] node adjoint accumulators
     double *P;                // [M][C] point adjoint accumulators
     double *S;                // [N][C][3] push-down running sums
+    double *PN;               // [M][3] near-field dL/dn accumulators (sorted order)
+    double *EACC;             // [1] dL/deps accumulator
     uint32_t *err;            // sticky device error word (traversal guard)
 
     int64_t bytes;
@@ -75,7 +77,10 @@ dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta,
 dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                           int cbegin, int nc, const float *df, float *dx, hipStream_t s);
 dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
-                            int cbegin, int nc, const float *df, const float *dg, float *dx, hipStream_t s);
+                            int cbegin, int nc, const float *df, const float *dg, int want, float *dx,
+                            hipStream_t s);
+dps_status launch_finalize_ext(dps_tree_s *t, float *dattrs, float *dnormals, double *deps, hipStream_t s);
+dps_status launch_set_normals(dps_tree_s *t, const float *n, hipStream_t s);
 dps_status launch_zero(dps_tree_s *t, hipStream_t s);
 dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s);
 dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *moments,
