@@ -17,6 +17,10 @@ build time is reported separately.  value = Q / (time per step), FP32-stored
 attributes and moments, eager launches.  The same step is also timed with
 BF16 storage, eager and captured in one graph.
 
+Grid workload (reported under "grid_512"): the geometry channel at the 512^3
+points of the bounding cube (mesh extraction by marching cubes), positions
+generated in the kernels.
+
 Batched workload (sfm-8m, reported under "batched"): 8,388,608 points, 8 views
 of 256^2 .. 1024^2 rays x 128 samples (438,829,056 primary samples), one shadow
 ray of 64 samples per primary hit, BF16 storage, persistent autotuned
@@ -339,6 +343,29 @@ def time_batched(P, steps, warmup):
                     "row count) + render proxy + backward (both adjoints, autograd of the proxy), one graph"}
 
 
+def time_grid(P, dev_in, res, reps=3):
+    import torch
+    p, n, A, attrs = dev_in[:4]
+    tree = P.dps_build(p, n, A, attrs, leaf_size=LEAF)
+    dims, origin, spacing = (res,) * 3, (-1.05,) * 3, (2.1 / (res - 1),) * 3
+    f = torch.empty((res, res, res, 1), device="cuda")
+    P.dps_query_grid(tree, origin, spacing, dims, BETA, EPS, c_begin=0, n_channels=1, f_out=f)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        P.dps_query_grid(tree, origin, spacing, dims, BETA, EPS, c_begin=0, n_channels=1, f_out=f)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    P.dps_destroy(tree)
+    ms = sorted(ts)[len(ts) // 2]
+    return {"value": res ** 3 / (ms * 1e-3), "unit": "points/s", "ms": ms, "points": res ** 3,
+            "workload": f"{res}^3 grid over [-1.05, 1.05]^3 on the sfm-1m tree, geometry channel, values only, "
+                        f"FP32 storage"}
+
+
 def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
     import oracle
     oracle.build(force=False)
@@ -411,7 +438,6 @@ def main():
                                graph=(st == "bf16" and not args.no_graph))
         log(f"[bench] {st}: {res[st]['ms_per_step']:.2f} ms/step (graph {res[st]['graph_ms_per_step']}), "
             f"kernels {res[st]['kernel_ms']}")
-    del dev_in
     main_st = "fp32" if "fp32" in res else storages[0]
     r = res[main_st]
     visits, nfar, leaves, near = r["counts_total"]
@@ -472,10 +498,14 @@ def main():
             out[f"{st}_stored_graph"] = {"value": Q / (rr["graph_ms_per_step"] * 1e-3),
                                          "ms_per_step": rr["graph_ms_per_step"],
                                          "step": "the same step captured in one graph and replayed"}
+    # marching-cubes grid on the same tree: 512^3 points over the bounding
+    # cube, geometry channel only, positions generated in the kernels
+    log("[bench] 512^3 grid query")
+    out["grid_512"] = time_grid(P, dev_in, 512)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(np, p, n, A, attrs, x, df, args.cpu_seconds)
-    del p, n, A, attrs, x, df
+    del p, n, A, attrs, x, df, dev_in
     if not args.no_batched:
         import gc
         gc.collect()

@@ -266,6 +266,23 @@ dps_status dps_adjoint_accumulate_ext(dps_tree t, const float *x, int64_t Q, con
 dps_status dps_adjoint_finalize_ext(dps_tree t, float *dattrs, float *dnormals, double *deps, void *stream);
 dps_status dps_set_normals(dps_tree t, const float *n, void *stream);
 
+/*
+ * dps_query_grid -- dps_query_channels at the points of a regular grid, for
+ * mesh extraction by marching cubes on the geometry field (Sec. 7.1 extracts
+ * the 1/2 level set at 512^3 and 1024^3).  The positions are generated in the
+ * kernels, in 4 x 4 x 4 bricks (one wavefront per brick), so no position array
+ * is read.
+ *  origin, spacing  host float[3]; point (i, j, k) is
+ *                   origin + (i, j, k) * spacing, each coordinate computed in
+ *                   FP32 as o + (float)i * h with no fused multiply-add
+ *  dims             host int64[3] = (nx, ny, nz), each in [1, 2^24]
+ *  f                device [nz][ny][nx][n_channels]
+ *  grad             device [nz][ny][nx][n_channels][3] or NULL
+ * Persistent launch with the tree's queries-per-lane setting.  Graph-safe.
+ */
+dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing[3], const int64_t dims[3], float beta,
+                          float eps, int32_t c_begin, int32_t n_channels, float *f, float *grad, void *stream);
+
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A
  * traversal that would walk more than N nodes stops and sets this flag. */

@@ -23,7 +23,7 @@ EXPORTED = (
     "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
     "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_query_channels",
     "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_adjoint_accumulate_ext",
-    "dps_adjoint_finalize_ext", "dps_set_normals", "dps_check", "dps_destroy",
+    "dps_adjoint_finalize_ext", "dps_set_normals", "dps_query_grid", "dps_check", "dps_destroy",
     "dps_status_string", "dps_last_error",
 )
 
@@ -64,6 +64,7 @@ def load():
         "dps_adjoint_accumulate_ext": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, i32, vp, vp],
         "dps_adjoint_finalize_ext": [vp, vp, vp, vp, vp],
         "dps_set_normals": [vp, vp, vp],
+        "dps_query_grid": [vp, vp, vp, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
         "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
@@ -362,6 +363,27 @@ def dps_set_normals(tree: Tree, normals):
     import torch
     _check(load().dps_set_normals(tree.handle, _ptr(normals, torch.float32, (tree.M, 3), tree.device, "normals"),
                                   _stream(tree.device)), "dps_set_normals")
+
+
+def dps_query_grid(tree: Tree, origin, spacing, dims, beta: float, eps: float, c_begin: int = 0,
+                   n_channels=None, grad: bool = False, f_out=None, g_out=None):
+    """Field at the points origin + (i, j, k) * spacing of an nx x ny x nz grid
+    (dims = (nx, ny, nz)); returns (f[nz,ny,nx,n], grad[nz,ny,nx,n,3] or None)."""
+    import torch
+    n = tree.C - c_begin if n_channels is None else n_channels
+    nx, ny, nz = (int(v) for v in dims)
+    o = (ct.c_float * 3)(*[float(v) for v in origin])
+    h = (ct.c_float * 3)(*[float(v) for v in spacing])
+    d = (ct.c_int64 * 3)(nx, ny, nz)
+    f = f_out if f_out is not None else torch.empty((nz, ny, nx, n), device=tree.device, dtype=torch.float32)
+    g = g_out if g_out is not None else (
+        torch.empty((nz, ny, nx, n, 3), device=tree.device, dtype=torch.float32) if grad else None)
+    _check(load().dps_query_grid(tree.handle, ct.cast(o, ct.c_void_p), ct.cast(h, ct.c_void_p),
+                                 ct.cast(d, ct.c_void_p), float(beta), float(eps), int(c_begin), int(n),
+                                 _ptr(f, torch.float32, (nz, ny, nx, n), tree.device, "f"),
+                                 _ptr(g, torch.float32, (nz, ny, nx, n, 3), tree.device, "grad"),
+                                 _stream(tree.device)), "dps_query_grid")
+    return f, g
 
 
 def dps_check(tree: Tree):

@@ -300,6 +300,25 @@ dps_status dps_adjoint_finalize_ext(dps_tree t, float *dattrs, float *dnormals, 
     return launch_finalize_ext(t, dattrs, dnormals, deps, (hipStream_t)stream);
 }
 
+dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing[3], const int64_t dims[3], float beta,
+                          float eps, int32_t c_begin, int32_t n_channels, float *f, float *grad, void *stream) {
+    dps_status st = check_tree(t, "dps_query_grid");
+    if (st != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_query_grid")) != DPS_OK) return st;
+    if ((st = check_channels(t, c_begin, n_channels, "dps_query_grid")) != DPS_OK) return st;
+    if (!origin || !spacing || !dims || !f) return invalid("dps_query_grid: NULL origin, spacing, dims or f");
+    int64_t total = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (!(dims[a] > 0) || dims[a] > ((int64_t)1 << 24))
+            return invalid("dps_query_grid: each dimension must be in [1, 2^24]");
+        if (!isfinite(origin[a]) || !isfinite(spacing[a])) return invalid("dps_query_grid: non-finite origin or spacing");
+        total *= dims[a];
+        if (total > ((int64_t)1 << 40)) return invalid("dps_query_grid: grid too large");
+    }
+    DeviceGuard guard(t->device);
+    return launch_query_grid(t, origin, spacing, dims, beta, eps, c_begin, n_channels, f, grad, (hipStream_t)stream);
+}
+
 dps_status dps_set_normals(dps_tree t, const float *n, void *stream) {
     dps_status st = check_tree(t, "dps_set_normals");
     if (st != DPS_OK) return st;

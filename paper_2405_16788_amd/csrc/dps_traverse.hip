@@ -129,16 +129,51 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t
 #define DPS_ROWS const int64_t Q = qdev ? (qdev[0] < Qcap ? (qdev[0] > 0 ? qdev[0] : 0) : Qcap) : Qcap
 
 // ---------------------------------------------------------------------------
+// grid queries (marching cubes): query q is point (i, j, k) of brick q / 64,
+// bricks of 4 x 4 x 4 points in x-fastest order, so a wavefront covers one
+// brick and 64k consecutive queries k neighbouring bricks.  Coordinates are
+// origin + index * spacing in FP32 without contraction (reproducible).
+// ---------------------------------------------------------------------------
+struct GridSpec {
+    float o[3], h[3];
+    int64_t n[3];   // points per axis
+    int64_t nb[3];  // bricks per axis
+};
+
+__device__ __forceinline__ float grid_coord(float o, int64_t i, float h) {
+#pragma clang fp contract(off)
+    return o + (float)i * h;
+}
+
+// position and output row of grid query q; false outside the grid
+__device__ __forceinline__ bool grid_point(const GridSpec &g, int64_t q, float &x, float &y, float &z, int64_t &row) {
+    const int64_t b = q >> 6;
+    const int l = (int)(q & 63);
+    const int64_t bx = b % g.nb[0], byz = b / g.nb[0];
+    const int64_t by = byz % g.nb[1], bz = byz / g.nb[1];
+    const int64_t i = 4 * bx + (l & 3), j = 4 * by + ((l >> 2) & 3), k = 4 * bz + (l >> 4);
+    const bool in = i < g.n[0] && j < g.n[1] && k < g.n[2];
+    x = grid_coord(g.o[0], i, g.h[0]);
+    y = grid_coord(g.o[1], j, g.h[1]);
+    z = grid_coord(g.o[2], k, g.h[2]);
+    row = (k * g.n[1] + j) * g.n[0] + i;
+    return in;
+}
+
+// ---------------------------------------------------------------------------
 // primal query, one query per lane (register-lean).  Software-pipelined: the
 // next node is known right after the ballots, so its record and moments are
 // fetched before the far-field / leaf work of the current node.
 // ---------------------------------------------------------------------------
-template <int CB, bool BF16, bool GRAD>
+template <int CB, bool BF16, bool GRAD, bool GRID = false>
 __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *__restrict__ fout,
-                                            float *__restrict__ gout) {
-    const bool valid = q < Q;
+                                            float *__restrict__ gout, const GridSpec &gs = GridSpec{}) {
+    bool valid = q < Q;
     float px = 0.0f, py = 0.0f, pz = 0.0f;
-    if (valid) {
+    int64_t row = q;
+    if constexpr (GRID) {
+        valid = grid_point(gs, q, px, py, pz, row) && valid;
+    } else if (valid) {
         px = x[3 * q];
         py = x[3 * q + 1];
         pz = x[3 * q + 2];
@@ -232,7 +267,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
     if (valid) {
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const int64_t o = q * ldo + co + c;
+            const int64_t o = row * ldo + co + c;
             fout[o] = f[c];
             if (GRAD) {
                 gout[3 * o] = g[c][0];
@@ -248,19 +283,28 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
 // queries, lane l carrying queries q0 + 64 i (i < K), so node fetches, ballots
 // and loop control are shared by 64*K queries (packet traversal).
 // ---------------------------------------------------------------------------
-template <int CB, bool BF16, bool GRAD, int K>
+template <int CB, bool BF16, bool GRAD, int K, bool GRID = false>
 __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *__restrict__ fout,
-                                            float *__restrict__ gout) {
+                                            float *__restrict__ gout, const GridSpec &gs = GridSpec{}) {
     float px[K], py[K], pz[K];
     uint32_t bits[K];
     float f[K][CB], g[K][CB][3];
+    int64_t row[K];
+    bool vld[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int64_t q = q0 + 64 * i;
-        const bool valid = q < Q;
-        px[i] = valid ? x[3 * q] : 0.0f;
-        py[i] = valid ? x[3 * q + 1] : 0.0f;
-        pz[i] = valid ? x[3 * q + 2] : 0.0f;
+        bool valid = q < Q;
+        row[i] = q;
+        if constexpr (GRID) {
+            valid = grid_point(gs, q, px[i], py[i], pz[i], row[i]) && valid;
+        }
+        vld[i] = valid;
+        if constexpr (!GRID) {
+            px[i] = valid ? x[3 * q] : 0.0f;
+            py[i] = valid ? x[3 * q + 1] : 0.0f;
+            pz[i] = valid ? x[3 * q + 2] : 0.0f;
+        }
         bits[i] = valid ? 1u : 0u;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
@@ -367,11 +411,10 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
     }
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-        const int64_t q = q0 + 64 * i;
-        if (q < Q) {
+        if (vld[i]) {
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
-                const int64_t o = q * ldo + co + c;
+                const int64_t o = row[i] * ldo + co + c;
                 fout[o] = f[i][c];
                 if (GRAD) {
                     gout[3 * o] = g[i][c][0];
@@ -383,11 +426,11 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
     }
 }
 
-template <int CB, bool BF16, bool GRAD, int K>
+template <int CB, bool BF16, bool GRAD, int K, bool GRID = false>
 __device__ __forceinline__ void query_body(int64_t q0, DPS_TRAV_PARAMS, float *__restrict__ fout,
-                                           float *__restrict__ gout) {
-    if constexpr (K == 1) query1_body<CB, BF16, GRAD>(q0, DPS_TRAV_ARGS, fout, gout);
-    else queryk_body<CB, BF16, GRAD, K>(q0, DPS_TRAV_ARGS, fout, gout);
+                                           float *__restrict__ gout, const GridSpec &gs = GridSpec{}) {
+    if constexpr (K == 1) query1_body<CB, BF16, GRAD, GRID>(q0, DPS_TRAV_ARGS, fout, gout, gs);
+    else queryk_body<CB, BF16, GRAD, K, GRID>(q0, DPS_TRAV_ARGS, fout, gout, gs);
 }
 
 template <int CB, bool BF16, bool GRAD, int K>
@@ -411,6 +454,21 @@ __global__ __launch_bounds__(kThreads) void k_query_persistent(DPS_KERN_PARAMS, 
         const int64_t tile = next_tile(ctr, ntiles, part);
         if (tile < 0) break;
         query_body<CB, BF16, GRAD, K>(tile * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, fout, gout);
+    }
+}
+
+// grid queries: persistent tile queue over the bricks (Q = 64 * bricks)
+template <int CB, bool BF16, bool GRAD, int K>
+__global__ __launch_bounds__(kThreads) void k_query_grid(DPS_KERN_PARAMS, float *__restrict__ fout,
+                                                         float *__restrict__ gout, GridSpec gs,
+                                                         uint32_t *__restrict__ ctr) {
+    DPS_ROWS;
+    const int64_t ntiles = (Q + 64 * K - 1) / (64 * K);
+    int part = xcc_id();
+    for (;;) {
+        const int64_t tile = next_tile(ctr, ntiles, part);
+        if (tile < 0) break;
+        query_body<CB, BF16, GRAD, K, true>(tile * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, fout, gout, gs);
     }
 }
 
@@ -1120,6 +1178,42 @@ dps_status query_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t *
     return query_k<CB, false, false>(t, k, x, Q, qdev, b2, kp, sb, f, g, s);
 }
 
+template <int CB, bool BF, bool GR, int K>
+dps_status grid_launch(dps_tree_s *t, const GridSpec &gs, int64_t Q, float b2, KernelParams kp, Sub sb, float *f,
+                       float *g, hipStream_t s) {
+    k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
+    const void *fn = reinterpret_cast<const void *>(&k_query_grid<CB, BF, GR, K>);
+    k_query_grid<CB, BF, GR, K><<<persistent_grid(fn), kThreads, 0, s>>>(
+        t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, nullptr, Q, nullptr, b2, kp, sb.c0, sb.ldo,
+        sb.co, (uint32_t)t->N, t->err, f, g, gs, t->ctr);
+    return hip_status(hipGetLastError(), "grid query launch");
+}
+
+template <int CB, bool BF, bool GR>
+dps_status grid_k(dps_tree_s *t, const GridSpec &gs, int64_t Q, float b2, KernelParams kp, Sub sb, float *f, float *g,
+                  hipStream_t s) {
+    switch (clamp_packet(t->packet_query, CB, GR)) {
+        case 4:
+            if constexpr ((GR && CB <= 2) || (!GR && CB <= 4)) return grid_launch<CB, BF, GR, 4>(t, gs, Q, b2, kp, sb, f, g, s);
+            [[fallthrough]];
+        case 2:
+            if constexpr (GR ? CB <= 4 : true) return grid_launch<CB, BF, GR, 2>(t, gs, Q, b2, kp, sb, f, g, s);
+            [[fallthrough]];
+        default:
+            return grid_launch<CB, BF, GR, 1>(t, gs, Q, b2, kp, sb, f, g, s);
+    }
+}
+
+template <int CB>
+dps_status grid_block(dps_tree_s *t, const GridSpec &gs, int64_t Q, float b2, KernelParams kp, Sub sb, float *f,
+                      float *g, hipStream_t s) {
+    const bool bf = t->storage == DPS_STORE_BF16;
+    if (bf && g) return grid_k<CB, true, true>(t, gs, Q, b2, kp, sb, f, g, s);
+    if (bf) return grid_k<CB, true, false>(t, gs, Q, b2, kp, sb, f, g, s);
+    if (g) return grid_k<CB, false, true>(t, gs, Q, b2, kp, sb, f, g, s);
+    return grid_k<CB, false, false>(t, gs, Q, b2, kp, sb, f, g, s);
+}
+
 template <int CB, bool BF, int K>
 dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
                           const float *df, float *dx, int dx_mode, hipStream_t s) {
@@ -1362,6 +1456,35 @@ dps_status launch_finalize_ext(dps_tree_s *t, float *dattrs, float *dnormals, do
 dps_status launch_set_normals(dps_tree_s *t, const float *n, hipStream_t s) {
     k_set_normals<<<grid(t->M), kThreads, 0, s>>>(n, t->perm, t->M, t->pts);
     return hip_status(hipGetLastError(), "set normals");
+}
+
+dps_status launch_query_grid(dps_tree_s *t, const float origin[3], const float spacing[3], const int64_t dims[3],
+                             float beta, float eps, int cbegin, int nc, float *f, float *g, hipStream_t s) {
+    GridSpec gs;
+    for (int a = 0; a < 3; ++a) {
+        gs.o[a] = origin[a];
+        gs.h[a] = spacing[a];
+        gs.n[a] = dims[a];
+        gs.nb[a] = cdiv(dims[a], 4);
+    }
+    const int64_t Q = gs.nb[0] * gs.nb[1] * gs.nb[2] * 64;
+    const float b2 = mul_rn(beta, beta);
+    const KernelParams kp = make_kernel_params(eps);
+    for (int c0 = cbegin; c0 < cbegin + nc;) {
+        const int cb = next_block(cbegin + nc - c0);
+        const Sub sb{c0, nc, c0 - cbegin};
+        dps_status st;
+        switch (cb) {
+            case 8: st = grid_block<8>(t, gs, Q, b2, kp, sb, f, g, s); break;
+            case 4: st = grid_block<4>(t, gs, Q, b2, kp, sb, f, g, s); break;
+            case 3: st = grid_block<3>(t, gs, Q, b2, kp, sb, f, g, s); break;
+            case 2: st = grid_block<2>(t, gs, Q, b2, kp, sb, f, g, s); break;
+            default: st = grid_block<1>(t, gs, Q, b2, kp, sb, f, g, s); break;
+        }
+        if (st != DPS_OK) return st;
+        c0 += cb;
+    }
+    return DPS_OK;
 }
 
 }  // namespace dps

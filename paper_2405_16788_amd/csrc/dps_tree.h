@@ -81,6 +81,8 @@ dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int6
                             hipStream_t s);
 dps_status launch_finalize_ext(dps_tree_s *t, float *dattrs, float *dnormals, double *deps, hipStream_t s);
 dps_status launch_set_normals(dps_tree_s *t, const float *n, hipStream_t s);
+dps_status launch_query_grid(dps_tree_s *t, const float origin[3], const float spacing[3], const int64_t dims[3],
+                             float beta, float eps, int cbegin, int nc, float *f, float *g, hipStream_t s);
 dps_status launch_zero(dps_tree_s *t, hipStream_t s);
 dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s);
 dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *moments,
