@@ -51,6 +51,13 @@
  *                     = 15 rho(t) - (4/sqrt(pi)) (5 t^3 + 2 t^5) exp(-t^2).
  *              The paper does not write these; they are the derivatives of
  *              its terms, taken through the same accepted sources.
+ *  monopole    Sec. 7.1 interpolates the K = 32 appearance attributes with the
+ *  channels    foreshortening term n.(p - x)/|p - x| of the kernel skipped:
+ *              m(r) = rho(r/eps) / (4 pi r^2), value A_m mu_m m, gradient
+ *              A_m mu_m (r lambda - kappa / r) d; node moments are scalars
+ *              Q_t = sum A_m mu_m at the area-weighted centroid.  A coincident
+ *              query and source contribute nothing (m -> 0; the gradient's
+ *              direction is undefined there).
  *  normals,    Sec. 5.2 optimises the point normals and the global eps as
  *  eps         well.  A term depends on n_m through D = A_m mu_m n_m only (the
  *              tree geometry does not involve normals), so dL/dn_m =
@@ -272,6 +279,30 @@ static int add_term(const double c[3], const double *D, int C, const double x[3]
     return 1;
 }
 
+/* Monopole term with charges Qc[3*ch] (stride 3): value Q m, m = kappa r,
+ * gradient Q (r lambda - kappa / r) d; absolute scales |Q| m and
+ * |Q| |r lambda - kappa / r| r.  Returns 0 when the source coincides with
+ * the query (no contribution). */
+static int add_term_mono(const double c[3], const double *Qc, int C, const double x[3], double eps,
+                         double *f, double *g, double *sf, double *sg)
+{
+    double d[3] = {c[0] - x[0], c[1] - x[1], c[2] - x[2]};
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 == 0.0) return 0;
+    (void)eps;
+    double r = sqrt(r2), kap, lam;
+    radial(r, eps, &kap, &lam);
+    double m = kap * r, gv = r * lam - kap / r;
+    for (int ch = 0; ch < C; ++ch) {
+        double q = Qc[3 * ch];
+        if (f) f[ch] += q * m;
+        if (g) for (int k = 0; k < 3; ++k) g[3 * ch + k] += q * gv * d[k];
+        if (sf) sf[ch] += fabs(q) * m;
+        if (sg) sg[ch] += fabs(q) * fabs(gv) * r;
+    }
+    return 1;
+}
+
 static int nthreads_or_default(int nt)
 {
 #ifdef _OPENMP
@@ -447,6 +478,79 @@ int orc_direct_adjoint(const float *p, const float *n, const float *A, const flo
     return 0;
 }
 
+/* Direct sum of the monopole kernel (appearance channels with the
+ * foreshortening term skipped); outputs as orc_direct. */
+int orc_direct_mono(const float *p, const float *A, const float *mu, int64_t M, int C, const float *x,
+                    int64_t Q, double eps, double *f, double *g, double *sf, double *sg, int nthreads)
+{
+    if (M < 0 || Q < 0 || C < 1 || C > 64 || eps < 0) return 1;
+    int nt = nthreads_or_default(nthreads);
+#pragma omp parallel for schedule(static) num_threads(nt)
+    for (int64_t q = 0; q < Q; ++q) {
+        double xq[3] = {x[3 * q], x[3 * q + 1], x[3 * q + 2]};
+        double fl[64], gl[192], sfl[64], sgl[64], Qc[192];
+        memset(fl, 0, sizeof fl); memset(gl, 0, sizeof gl);
+        memset(sfl, 0, sizeof sfl); memset(sgl, 0, sizeof sgl);
+        for (int64_t m = 0; m < M; ++m) {
+            double c[3] = {p[3 * m], p[3 * m + 1], p[3 * m + 2]};
+            for (int ch = 0; ch < C; ++ch) Qc[3 * ch] = (double)A[m] * (double)mu[m * C + ch];
+            add_term_mono(c, Qc, C, xq, eps, fl, gl, sfl, sgl);
+        }
+        for (int ch = 0; ch < C; ++ch) {
+            if (f) f[q * C + ch] = fl[ch];
+            if (sf) sf[q * C + ch] = sfl[ch];
+            if (sg) sg[q * C + ch] = sgl[ch];
+            if (g) for (int k = 0; k < 3; ++k) g[(q * C + ch) * 3 + k] = gl[3 * ch + k];
+        }
+    }
+    return 0;
+}
+
+/* Exact transpose of orc_direct_mono: dmu[m][c] = sum_q df[q][c] A_m m(r_qm),
+ * dx[q] = sum_m sum_c df[q][c] A_m mu_mc (r lambda - kappa / r) d. */
+int orc_direct_mono_adjoint(const float *p, const float *A, const float *mu, int64_t M, int C, const float *x,
+                            int64_t Q, double eps, const float *df, double *dmu, double *dx, int nthreads)
+{
+    if (M < 0 || Q < 0 || C < 1 || C > 64 || eps < 0 || !df) return 1;
+    int nt = nthreads_or_default(nthreads);
+    if (dx) {
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t q = 0; q < Q; ++q) {
+            double xq[3] = {x[3 * q], x[3 * q + 1], x[3 * q + 2]}, acc[3] = {0, 0, 0};
+            for (int64_t m = 0; m < M; ++m) {
+                double d[3] = {p[3 * m] - xq[0], p[3 * m + 1] - xq[1], p[3 * m + 2] - xq[2]};
+                double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (r2 == 0.0) continue;
+                double r = sqrt(r2), kap, lam;
+                radial(r, eps, &kap, &lam);
+                double w = 0;
+                for (int ch = 0; ch < C; ++ch) w += (double)df[q * C + ch] * (double)mu[m * C + ch];
+                double gv = (r * lam - kap / r) * w * (double)A[m];
+                for (int k = 0; k < 3; ++k) acc[k] += gv * d[k];
+            }
+            for (int k = 0; k < 3; ++k) dx[3 * q + k] = acc[k];
+        }
+    }
+    if (dmu) {
+#pragma omp parallel for schedule(static) num_threads(nt)
+        for (int64_t m = 0; m < M; ++m) {
+            double acc[64];
+            memset(acc, 0, sizeof acc);
+            for (int64_t q = 0; q < Q; ++q) {
+                double d[3] = {p[3 * m] - (double)x[3 * q], p[3 * m + 1] - (double)x[3 * q + 1],
+                               p[3 * m + 2] - (double)x[3 * q + 2]};
+                double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (r2 == 0.0) continue;
+                double r = sqrt(r2), kap, lam;
+                radial(r, eps, &kap, &lam);
+                for (int ch = 0; ch < C; ++ch) acc[ch] += (double)df[q * C + ch] * (double)A[m] * kap * r;
+            }
+            for (int ch = 0; ch < C; ++ch) dmu[m * C + ch] = acc[ch];
+        }
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* canonical octree                                                          */
 /* ------------------------------------------------------------------------ */
@@ -468,7 +572,9 @@ typedef struct {
     double *cen64;        /* [N][3] FP64 centroid before rounding */
     int32_t *leaf_of;     /* [M] leaf node holding sorted point */
     double *mu;           /* [M][C] sorted attributes */
-    double *D;            /* [N][C][3] node dipoles D_t = sum A_m mu_m n_m */
+    double *D;            /* [N][C][3] node dipoles D_t = sum A_m mu_m n_m; monopole
+                             trees keep Q_t = sum A_m mu_m in D[t][c][0] */
+    int kind;             /* 0: dipole kernel, 1: monopole kernel */
 } orc_tree;
 
 static uint64_t spread3(uint64_t v)
@@ -646,15 +752,34 @@ int orc_tree_set_attrs(orc_tree *t, const float *mu, int C)
         double *Di = t->D + i * C * 3;
         if (nd[3] == 0) {
             for (int64_t j = nd[4]; j < (int64_t)nd[4] + nd[5]; ++j)
-                for (int c = 0; c < C; ++c)
+                for (int c = 0; c < C; ++c) {
+                    if (t->kind == 1) {
+                        Di[3 * c] += t->Am[j] * t->mu[j * C + c];
+                        continue;
+                    }
                     for (int k = 0; k < 3; ++k)
                         Di[3 * c + k] += t->Am[j] * t->mu[j * C + c] * t->nm[3 * j + k];
+                }
         } else {
             for (int64_t ch = nd[2]; ch < (int64_t)nd[2] + nd[3]; ++ch)
                 for (int c = 0; c < 3 * C; ++c) Di[c] += t->D[ch * C * 3 + c];
         }
     }
     return 0;
+}
+
+/* 0: dipole kernel (default), 1: monopole kernel; refits the node moments */
+int orc_tree_set_kind(orc_tree *t, int kind)
+{
+    if (!t || (kind != 0 && kind != 1)) return 1;
+    t->kind = kind;
+    if (!t->mu) return 0;
+    float *tmp = (float *)malloc(sizeof(float) * t->M * t->C);
+    for (int64_t i = 0; i < t->M; ++i)
+        for (int c = 0; c < t->C; ++c) tmp[(int64_t)t->perm[i] * t->C + c] = (float)t->mu[i * t->C + c];
+    int rc = orc_tree_set_attrs(t, tmp, t->C);
+    free(tmp);
+    return rc;
 }
 
 int64_t orc_tree_num_nodes(const orc_tree *t) { return t ? t->N : -1; }
@@ -712,6 +837,11 @@ static void add_point(const orc_tree *t, int64_t j, const double x[3], double ep
     int C = t->C;
     double D[192], c[3];
     for (int k = 0; k < 3; ++k) c[k] = (double)t->ps[3 * j + k];
+    if (t->kind == 1) {
+        for (int ch = 0; ch < C; ++ch) D[3 * ch] = t->Am[j] * t->mu[j * C + ch];
+        add_term_mono(c, D, C, x, eps, f, g, sf, sg);
+        return;
+    }
     for (int ch = 0; ch < C; ++ch)
         for (int k = 0; k < 3; ++k) D[3 * ch + k] = t->Am[j] * t->mu[j * C + ch] * t->nm[3 * j + k];
     add_term(c, D, C, x, eps, f, g, sf, sg);
@@ -726,7 +856,10 @@ static void primal(qstate *st, int64_t i)
         double c[3];
         for (int k = 0; k < 3; ++k) c[k] = (double)t->geom[4 * i + k];
         st->far++;
-        add_term(c, t->D + i * t->C * 3, t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
+        if (t->kind == 1)
+            add_term_mono(c, t->D + i * t->C * 3, t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
+        else
+            add_term(c, t->D + i * t->C * 3, t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
         return;
     }
     if (nd[3] == 0) {
@@ -811,6 +944,20 @@ static void adjoint(astate *st, int64_t i)
         double r = sqrt(r2), kap, lam;
         radial(r, st->eps, &kap, &lam);
         const double *Dt = t->D + i * C * 3;
+        if (t->kind == 1) {
+            /* monopole: node accumulator df m(r), dx through the charges */
+            if (r2 == 0.0) return;
+            double m = kap * r, gv = r * lam - kap / r, w = 0, aw = 0;
+            for (int ch = 0; ch < C; ++ch) {
+                st->G[(i * C + ch) * 3] += st->df[ch] * m;
+                st->H[i * C + ch] += fabs(st->df[ch]) * m;
+                w += st->df[ch] * Dt[3 * ch];
+                aw += fabs(st->df[ch] * Dt[3 * ch]);
+            }
+            for (int k = 0; k < 3; ++k) st->dx[k] += w * gv * d[k];
+            st->sdx += aw * fabs(gv) * r;
+            return;
+        }
         if (st->df) {
             double E[3] = {0, 0, 0};
             for (int ch = 0; ch < C; ++ch) {
@@ -850,6 +997,19 @@ static void adjoint(astate *st, int64_t i)
             if (r2 == 0.0 && st->eps == 0.0) continue;
             double r = sqrt(r2), kap, lam;
             radial(r, st->eps, &kap, &lam);
+            if (t->kind == 1) {
+                if (r2 == 0.0) continue;
+                double m = kap * r, gv = r * lam - kap / r, w = 0, aw = 0;
+                for (int ch = 0; ch < C; ++ch) {
+                    st->P[j * C + ch] += st->df[ch] * t->Am[j] * m;
+                    st->HP[j * C + ch] += fabs(st->df[ch]) * t->Am[j] * m;
+                    w += st->df[ch] * t->mu[j * C + ch];
+                    aw += fabs(st->df[ch] * t->mu[j * C + ch]);
+                }
+                for (int k = 0; k < 3; ++k) st->dx[k] += t->Am[j] * w * gv * d[k];
+                st->sdx += t->Am[j] * aw * fabs(gv) * r;
+                continue;
+            }
             double An[3] = {t->Am[j] * t->nm[3 * j], t->Am[j] * t->nm[3 * j + 1], t->Am[j] * t->nm[3 * j + 2]};
             double s = An[0] * d[0] + An[1] * d[1] + An[2] * d[2];
             double nAn = sqrt(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]);
@@ -924,6 +1084,7 @@ int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, dou
                    double *deps, double *sdmu, double *sdx, double *sdn, double *sdeps, int nthreads)
 {
     if (!t || !t->D || Q < 0 || !(beta > 0) || eps < 0 || (!df && !dg)) return 1;
+    if (t->kind == 1 && (dg || dn || deps || !df)) return 1;  /* value cotangents only */
     int C = t->C;
     int64_t N = t->N, M = t->M;
     int nt = nthreads_or_default(nthreads);
@@ -1000,9 +1161,10 @@ int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, dou
         double nAn = sqrt(An[0] * An[0] + An[1] * An[1] + An[2] * An[2]);
         for (int c = 0; c < C; ++c) {
             const double *S = G + (l * C + c) * 3;
-            double v = P[j * C + c] + An[0] * S[0] + An[1] * S[1] + An[2] * S[2];
+            double v = t->kind == 1 ? P[j * C + c] + t->Am[j] * S[0]
+                                    : P[j * C + c] + An[0] * S[0] + An[1] * S[1] + An[2] * S[2];
             if (dmu) dmu[orig * C + c] = v;
-            if (sdmu) sdmu[orig * C + c] = HP[j * C + c] + nAn * H[l * C + c];
+            if (sdmu) sdmu[orig * C + c] = HP[j * C + c] + (t->kind == 1 ? t->Am[j] : nAn) * H[l * C + c];
         }
         if (dn) {
             /* far field: every ancestor's node dipole holds A_j mu_jc n_j */

@@ -63,6 +63,14 @@ def load():
     lib.orc_tree_free.argtypes = [vp]
     lib.orc_tree_set_attrs.restype = ct.c_int
     lib.orc_tree_set_attrs.argtypes = [vp, vp, ct.c_int]
+    lib.orc_tree_set_kind.restype = ct.c_int
+    lib.orc_tree_set_kind.argtypes = [vp, ct.c_int]
+    lib.orc_direct_mono.restype = ct.c_int
+    lib.orc_direct_mono.argtypes = [vp, vp, vp, ct.c_int64, ct.c_int, vp, ct.c_int64, ct.c_double,
+                                    vp, vp, vp, vp, ct.c_int]
+    lib.orc_direct_mono_adjoint.restype = ct.c_int
+    lib.orc_direct_mono_adjoint.argtypes = [vp, vp, vp, ct.c_int64, ct.c_int, vp, ct.c_int64, ct.c_double,
+                                            vp, vp, vp, ct.c_int]
     lib.orc_tree_num_nodes.restype = ct.c_int64
     lib.orc_tree_num_nodes.argtypes = [vp]
     lib.orc_tree_depth.restype = ct.c_int
@@ -160,10 +168,49 @@ def direct_adjoint(p, n, A, mu, x, eps, df, nthreads=0, dg=None, extra=False):
     return (dmu, dx, dn, float(deps[0])) if extra else (dmu, dx)
 
 
+def direct_mono(p, A, mu, x, eps, want_grad=True, nthreads=0):
+    """FP64 direct sum of the monopole kernel rho(r/eps)/(4 pi r^2) (appearance
+    channels, foreshortening skipped).  Returns dict f, g, sf, sg."""
+    lib = load()
+    p, x = _c32(p, 3), _c32(x, 3)
+    A = _c32(A).reshape(-1)
+    mu = _c32(mu)
+    if mu.ndim == 1:
+        mu = mu[:, None]
+    M, C, Q = p.shape[0], mu.shape[1], x.shape[0]
+    f = np.zeros((Q, C)); sf = np.zeros((Q, C)); sg = np.zeros((Q, C))
+    g = np.zeros((Q, C, 3)) if want_grad else None
+    rc = lib.orc_direct_mono(_ptr(p), _ptr(A), _ptr(mu), M, C, _ptr(x), Q, float(eps), _ptr(f), _ptr(g),
+                             _ptr(sf), _ptr(sg), int(nthreads))
+    if rc:
+        raise ValueError("orc_direct_mono rejected its arguments")
+    return {"f": f, "g": g, "sf": sf, "sg": sg}
+
+
+def direct_mono_adjoint(p, A, mu, x, eps, df, nthreads=0):
+    """Exact transpose of ``direct_mono``: returns (dmu[M,C], dx[Q,3])."""
+    lib = load()
+    p, x = _c32(p, 3), _c32(x, 3)
+    A = _c32(A).reshape(-1)
+    mu = _c32(mu)
+    if mu.ndim == 1:
+        mu = mu[:, None]
+    M, C, Q = p.shape[0], mu.shape[1], x.shape[0]
+    df = _c32(df).reshape(Q, C)
+    dmu = np.zeros((M, C)); dx = np.zeros((Q, 3))
+    rc = lib.orc_direct_mono_adjoint(_ptr(p), _ptr(A), _ptr(mu), M, C, _ptr(x), Q, float(eps), _ptr(df),
+                                     _ptr(dmu), _ptr(dx), int(nthreads))
+    if rc:
+        raise ValueError("orc_direct_mono_adjoint rejected its arguments")
+    return dmu, dx
+
+
 class Tree:
     """Canonical octree + FP64 node dipoles + Barnes-Hut queries."""
 
-    def __init__(self, p, n, A, mu=None, leaf_size=16):
+    def __init__(self, p, n, A, mu=None, leaf_size=16, kind="dipole"):
+        """kind: "dipole" (eq. dipole_sum) or "monopole" (appearance channels
+        with the foreshortening term skipped: scalar moments sum A mu)."""
         lib = load()
         self._p = _c32(p, 3)
         self._n = _c32(n, 3)
@@ -176,6 +223,11 @@ class Tree:
         self.N = int(lib.orc_tree_num_nodes(self._h))
         self.depth = int(lib.orc_tree_depth(self._h))
         self.C = 0
+        if kind not in ("dipole", "monopole"):
+            raise ValueError(kind)
+        self.kind = kind
+        if kind == "monopole":
+            lib.orc_tree_set_kind(self._h, 1)
         if mu is not None:
             self.set_attrs(mu)
 

@@ -753,3 +753,101 @@ def test_bh_normal_and_eps_derivatives(orc):
     _, _, dn, deps = orc.direct_adjoint(p, n, A, mu, x, eps, df, dg=dg, extra=True)
     assert np.allclose(b["dn"], dn, rtol=1e-10, atol=1e-14 * np.abs(dn).max())
     assert abs(b["deps"] - deps) <= 1e-10 * b["sdeps"]
+
+
+# --------------------------------------------------------------------------
+# monopole kernel (appearance channels with the foreshortening term skipped)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("R,eps", [(1.0, 0.0), (0.5, 0.0), (0.5, 0.2), (1.0, 0.7)])
+def test_monopole_sphere_centre_closed_form(orc, R, eps):
+    # every point of a sphere of radius R is at distance R from the centre:
+    # sum_m A_m nu rho(R/eps)/(4 pi R^2) = nu rho(R/eps) when sum A = 4 pi R^2
+    p, n, A, mu = workloads.sphere_cloud(4096, 1)
+    p = (p * np.float32(R)).astype(np.float32)
+    A = (A * np.float32(R * R)).astype(np.float32)
+    r = orc.direct_mono(p, A, mu, np.zeros((1, 3), np.float32), eps)
+    pr = p.astype(np.float64)
+    dist = np.linalg.norm(pr, axis=1)
+    rho = np.array([orc.rho(v / eps) if eps > 0 else 1.0 for v in dist])
+    expect = np.sum(A.astype(np.float64)[:, None] * mu * (rho / (4 * math.pi * dist ** 2))[:, None], axis=0)
+    assert np.allclose(r["f"][0], expect, rtol=1e-12)
+    # and the closed form itself, up to the FP32 rounding of areas and radii
+    assert abs(r["f"][0, 0] - (orc.rho(R / eps) if eps > 0 else 1.0)) < 1e-5
+
+
+def test_monopole_numpy_crosscheck_tiny(orc):
+    from scipy.special import erf
+    rng = np.random.default_rng(61)
+    M, Q, C, eps = 40, 25, 3, 0.3
+    p = rng.uniform(-1, 1, (M, 3)).astype(np.float32)
+    A = rng.uniform(0.01, 0.1, M).astype(np.float32)
+    mu = rng.standard_normal((M, C)).astype(np.float32)
+    x = rng.uniform(-1, 1, (Q, 3)).astype(np.float32)
+    d = p[None].astype(np.float64) - x[:, None].astype(np.float64)
+    r = np.linalg.norm(d, axis=2)
+    t = r / eps
+    rho = erf(t) - 2 * t / math.sqrt(math.pi) * np.exp(-t * t)
+    drho = 4 / math.sqrt(math.pi) * t * t * np.exp(-t * t)
+    m = rho / (4 * math.pi * r * r)
+    dm = (drho / eps * r * r - 2 * r * rho) / (4 * math.pi * r ** 4)  # d m / d r
+    w = A.astype(np.float64)[None, :, None] * mu.astype(np.float64)[None]
+    f = np.sum(w * m[..., None], axis=1)
+    g = np.einsum("qmc,qmk->qck", w * (-dm / r)[..., None], d)  # grad_x r = -d / r
+    out = orc.direct_mono(p, A, mu, x, eps)
+    assert np.allclose(out["f"], f, rtol=1e-12, atol=1e-15)
+    assert np.allclose(out["g"], g, rtol=1e-10, atol=1e-14)
+
+
+def test_monopole_gradient_and_adjoint(orc):
+    p, n, A, mu = workloads.sfm_cloud(1500, 100, 10)
+    x = workloads.sphere_queries(200, 7, half=1.0).astype(np.float64)
+    eps = 0.05
+    r = orc.direct_mono(p, A, mu, x.astype(np.float32), eps)
+    h = 2.0 ** -14
+    for k in range(3):
+        xp, xm = x.copy(), x.copy()
+        xp[:, k] += h
+        xm[:, k] -= h
+        xp32, xm32 = xp.astype(np.float32), xm.astype(np.float32)
+        fp = orc.direct_mono(p, A, mu, xp32, eps)["f"]
+        fm = orc.direct_mono(p, A, mu, xm32, eps)["f"]
+        dxk = xp32[:, k].astype(np.float64) - xm32[:, k].astype(np.float64)
+        fd = (fp - fm) / dxk[:, None]
+        assert np.max(np.abs(fd - r["g"][:, :, k]) / r["sg"]) < 1e-4
+    df = workloads.cotangents(200, mu.shape[1], 17)
+    dmu, dx = orc.direct_mono_adjoint(p, A, mu, x.astype(np.float32), eps, df)
+    lhs = np.sum(df.astype(np.float64) * r["f"])
+    assert abs(lhs - np.sum(dmu * mu.astype(np.float64))) <= 1e-12 * np.sum(np.abs(df * r["f"]))
+    assert np.allclose(dx, np.einsum("qc,qck->qk", df.astype(np.float64), r["g"]), rtol=1e-10, atol=1e-13)
+
+
+def test_monopole_barnes_hut(orc):
+    p, n, A, mu = workloads.sfm_cloud(4000, 200, 10)
+    x = workloads.sphere_queries(400, 11, half=1.0)
+    df = workloads.cotangents(400, mu.shape[1], 17)
+    eps = 0.02
+    T = orc.Tree(p, n, A, mu, 16, kind="monopole")
+    ref = orc.direct_mono(p, A, mu, x, eps)
+    errs = []
+    for beta in (1.0, 2.0, 4.0):
+        q = T.query(x, beta, eps)
+        errs.append(np.max(np.abs(q["f"] - ref["f"]) / ref["sf"]))
+        # adjoint = transpose of the Barnes-Hut forward
+        a = T.adjoint(x, beta, eps, df)
+        lhs = np.sum(df.astype(np.float64) * q["f"])
+        assert abs(lhs - np.sum(a["dmu"] * mu.astype(np.float64))) <= 1e-12 * np.sum(np.abs(df * q["f"]))
+        assert np.allclose(a["dx"], np.einsum("qc,qck->qk", df.astype(np.float64), q["g"]), rtol=1e-10,
+                           atol=1e-13)
+        assert np.all(a["sdmu"] >= np.abs(a["dmu"]) * (1 - 1e-12))
+    assert errs[0] > errs[1] > errs[2]
+    # large beta: the direct sum and its adjoint
+    q = T.query(x, 1e4, eps)
+    assert np.allclose(q["f"], ref["f"], rtol=1e-10, atol=1e-14)
+    assert np.allclose(q["g"], ref["g"], rtol=1e-10, atol=1e-14)
+    a = T.adjoint(x, 1e4, eps, df)
+    dmu, dx = orc.direct_mono_adjoint(p, A, mu, x, eps, df)
+    assert np.allclose(a["dmu"], dmu, rtol=1e-10, atol=1e-14)
+    assert np.allclose(a["dx"], dx, rtol=1e-10, atol=1e-14)
+    # node charges are point sums; gradient cotangents are not defined here
+    with pytest.raises(ValueError):
+        T.adjoint(x, 2.0, eps, df, dg=np.zeros((400, mu.shape[1], 3), np.float32))
