@@ -56,6 +56,12 @@ typedef enum {
                             of trees with >= 4,194,304 points) */
 } dps_storage;
 
+typedef enum {
+    DPS_KERNEL_DIPOLE = 0,   /* the regularised dipole kernel of eq. regularized_poisson */
+    DPS_KERNEL_MONOPOLE = 1  /* the same kernel without the foreshortening factor n.(y-x)/|y-x|
+                                (appearance attributes, Sec. 7.1), see dps_build_kernel */
+} dps_kernel;
+
 /* Maximum number of attribute channels per tree. */
 #define DPS_MAX_CHANNELS 32
 /* Maximum leaf size (points per bucket leaf). */
@@ -92,6 +98,38 @@ typedef enum {
 dps_status dps_build(const float *p, const float *n, const float *A, const float *attrs,
                      int64_t M, int32_t C, int32_t leaf_size, dps_storage storage,
                      void *stream, dps_tree *out);
+
+/*
+ * dps_build_kernel -- as dps_build (same arguments, layout, synchronisation
+ * and errors) with the kernel of the sums chosen per tree.  Sec. 7.1 sums its
+ * 32 appearance attributes with the foreshortening term of the kernel skipped,
+ * i.e. with the monopole kernel
+ *   m(r) = rho(r/eps) / (4 pi r^2),   D_c(x) = sum_m A_m m(|p_m - x|) mu_{m,c},
+ *   grad D_c(x) = sum_m A_m mu_{m,c} (r lambda - kappa / r) (p_m - x),
+ * whose node moments are the scalar charges Q_tc = sum_{m in t} A_m mu_{m,c}
+ * placed at the node's area-weighted centroid; the octree, the far test and
+ * the traversal order are those of the dipole kernel (Algorithm 1).  A source
+ * at the query point itself contributes nothing.  Normals are stored but not
+ * used by the monopole kernel.  The geometry channel keeps the dipole kernel:
+ * callers build one tree per kernel over the same points (the two trees have
+ * identical node layouts).
+ *
+ * A DPS_KERNEL_MONOPOLE tree supports dps_set_attributes, dps_query,
+ * dps_query_channels, dps_query_counts, dps_adjoint_zero / _accumulate /
+ * _accumulate_channels / _finalize, dps_adjoint, dps_adjoint_finalize_ext
+ * (dattrs only), dps_export_tree (moments: the charge in component 0 of each
+ * channel, components 1 and 2 zero), dps_tree_info, dps_set_launch /
+ * dps_get_launch and dps_check.  The gradient-cotangent, normal and eps
+ * derivatives, dps_set_normals and dps_query_grid are defined for the dipole
+ * kernel only and return DPS_ERR_INVALID on a monopole tree.
+ *  kernel  DPS_KERNEL_DIPOLE or DPS_KERNEL_MONOPOLE (else DPS_ERR_INVALID)
+ */
+dps_status dps_build_kernel(const float *p, const float *n, const float *A, const float *attrs,
+                            int64_t M, int32_t C, int32_t leaf_size, dps_storage storage,
+                            dps_kernel kernel, void *stream, dps_tree *out);
+
+/* dps_get_kernel -- host output: the tree's kernel (a dps_kernel value). */
+dps_status dps_get_kernel(dps_tree t, int32_t *kernel);
 
 /*
  * dps_set_attributes -- moment refit after the attributes changed (Sec. 6.3:
@@ -156,7 +194,8 @@ dps_status dps_adjoint(dps_tree t, const float *x, int64_t Q, float beta, float 
  *          n_children, pt_begin, pt_count} in breadth-first order
  *  geom    [N][4] float {cx, cy, cz, r^2}
  *  moments [N][C][3] float node dipoles D_t = sum_{m in t} A_m mu_m n_m
- *          (decoded to float32 from the storage format)
+ *          (decoded to float32 from the storage format); for a monopole tree
+ *          the charge sum_{m in t} A_m mu_m in component 0, components 1, 2 zero
  * Synchronises `stream`.
  */
 dps_status dps_export_tree(dps_tree t, uint64_t *codes, uint32_t *perm, int32_t *nodes,

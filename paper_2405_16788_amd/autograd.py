@@ -42,6 +42,10 @@ def _refit(tree: B.Tree, attrs: torch.Tensor, mode):
 class DipoleSum(torch.autograd.Function):
     """f, grad = DipoleSum.apply(attrs[M,C], x[Q,3], normals, eps, tree, beta, opts).
 
+    For a monopole-kernel tree (appearance channels) f is differentiable and
+    grad is returned but carries no derivatives (no cotangents of it), and
+    neither normals nor eps may be differentiated.
+
     ``opts`` = (c_begin, n_channels, q_count, want_grad, refit) with
     n_channels None meaning all channels.  ``f`` [Q,n] and ``grad`` [Q,n,3]
     (or None) are both differentiable w.r.t. attrs and x: cotangents of grad
@@ -57,6 +61,9 @@ class DipoleSum(torch.autograd.Function):
     def forward(ctx, attrs, x, normals, eps, tree, beta, opts):
         c_begin, n_ch, q_count, want_grad, refit = opts
         ctx.set_materialize_grads(False)
+        if getattr(tree, "kernel", "dipole") == "monopole" and (
+                normals is not None or (isinstance(eps, torch.Tensor) and eps.requires_grad)):
+            raise ValueError("normal and eps derivatives are defined for dipole-kernel trees only")
         eps_v = float(eps.detach()) if isinstance(eps, torch.Tensor) else float(eps)
         attrs_c = attrs.detach().contiguous()
         x_c = x.detach().contiguous()
@@ -104,6 +111,9 @@ class DipoleSum(torch.autograd.Function):
             if de is not None:
                 de = de.to(device=ctx.eps_like.device, dtype=ctx.eps_like.dtype).reshape(ctx.eps_like.shape)
         elif dg is not None:
+            if getattr(tree, "kernel", "dipole") == "monopole":
+                raise RuntimeError("cotangents of the spatial gradients need the dipole kernel; a monopole-kernel "
+                                   "tree differentiates its values only")
             # gradient cotangents (with the value cotangents, if any)
             dg = dg.contiguous().to(torch.float32)
             dx = torch.zeros((x.shape[0], 3), device=x.device, dtype=torch.float32) if need_x else None

@@ -17,9 +17,11 @@ LIB_PATH = os.path.join(_HERE, "libdps.so")
 DPS_OK, DPS_ERR_INVALID, DPS_ERR_OOM, DPS_ERR_DEVICE, DPS_ERR_STATE = range(5)
 DPS_STORE_FP32, DPS_STORE_BF16 = 0, 1
 STORAGE = {"fp32": DPS_STORE_FP32, "bf16": DPS_STORE_BF16}
+DPS_KERNEL_DIPOLE, DPS_KERNEL_MONOPOLE = 0, 1
+KERNEL = {"dipole": DPS_KERNEL_DIPOLE, "monopole": DPS_KERNEL_MONOPOLE}
 
 EXPORTED = (
-    "dps_build", "dps_set_attributes", "dps_query", "dps_query_counts", "dps_adjoint_zero",
+    "dps_build", "dps_build_kernel", "dps_get_kernel", "dps_set_attributes", "dps_query", "dps_query_counts", "dps_adjoint_zero",
     "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
     "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_query_channels",
     "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_adjoint_accumulate_ext",
@@ -51,6 +53,8 @@ def load():
     vp, i64, i32, f32 = ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_float
     sig = {
         "dps_build": [vp, vp, vp, vp, i64, i32, i32, ct.c_int, vp, ct.POINTER(vp)],
+        "dps_build_kernel": [vp, vp, vp, vp, i64, i32, i32, ct.c_int, ct.c_int, vp, ct.POINTER(vp)],
+        "dps_get_kernel": [vp, ct.POINTER(i32)],
         "dps_set_attributes": [vp, vp, vp],
         "dps_query": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_query_counts": [vp, vp, i64, f32, vp, vp],
@@ -117,12 +121,13 @@ def _ptr(t, dtype=None, shape=None, device=None, name="tensor"):
 class Tree:
     """Owning handle of a dps_tree (destroyed with the object)."""
 
-    def __init__(self, handle, device, M, C, storage):
+    def __init__(self, handle, device, M, C, storage, kernel="dipole"):
         self._h = handle
         self.device = device
         self.M = M
         self.C = C
         self.storage = storage
+        self.kernel = kernel
 
     @property
     def handle(self):
@@ -136,9 +141,13 @@ class Tree:
             self._h = None
 
 
-def dps_build(p, n, A, attrs, leaf_size: int = 16, storage: str = "fp32") -> Tree:
+def dps_build(p, n, A, attrs, leaf_size: int = 16, storage: str = "fp32", kernel: str = "dipole") -> Tree:
+    """Builds a tree (``dps_build_kernel``); kernel "dipole" or "monopole"
+    (appearance channels with the foreshortening factor dropped)."""
     import torch
     lib = load()
+    if kernel not in KERNEL:
+        raise ValueError(f"kernel must be one of {sorted(KERNEL)}")
     M = p.shape[0]
     C = attrs.shape[1] if attrs.dim() == 2 else 1
     dev = p.device
@@ -147,9 +156,15 @@ def dps_build(p, n, A, attrs, leaf_size: int = 16, storage: str = "fp32") -> Tre
             _ptr(attrs, f, (M, C) if attrs.dim() == 2 else (M,), dev, "attrs"))
     h = ct.c_void_p()
     with torch.cuda.device(dev):
-        _check(lib.dps_build(*args, M, C, int(leaf_size), STORAGE[storage], _stream(dev), ct.byref(h)),
-               "dps_build")
-    return Tree(h, dev, M, C, storage)
+        _check(lib.dps_build_kernel(*args, M, C, int(leaf_size), STORAGE[storage], KERNEL[kernel], _stream(dev),
+                                    ct.byref(h)), "dps_build_kernel")
+    return Tree(h, dev, M, C, storage, kernel)
+
+
+def dps_get_kernel(tree: Tree) -> str:
+    k = ct.c_int32()
+    _check(load().dps_get_kernel(tree.handle, ct.byref(k)), "dps_get_kernel")
+    return {v: n for n, v in KERNEL.items()}[k.value]
 
 
 def dps_set_attributes(tree: Tree, attrs):

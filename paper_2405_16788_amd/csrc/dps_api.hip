@@ -81,12 +81,19 @@ const char *dps_last_error(void) { return g_last_error; }
 
 dps_status dps_build(const float *p, const float *n, const float *A, const float *attrs, int64_t M,
                      int32_t C, int32_t leaf_size, dps_storage storage, void *stream, dps_tree *out) {
+    return dps_build_kernel(p, n, A, attrs, M, C, leaf_size, storage, DPS_KERNEL_DIPOLE, stream, out);
+}
+
+dps_status dps_build_kernel(const float *p, const float *n, const float *A, const float *attrs, int64_t M,
+                            int32_t C, int32_t leaf_size, dps_storage storage, dps_kernel kernel, void *stream,
+                            dps_tree *out) {
     if (!out) return invalid("dps_build: out is NULL");
     *out = nullptr;
     if (M < 1 || M > 0x7fffffffLL) return invalid("dps_build: M must be in [1, 2^31-1]");
     if (C < 1 || C > DPS_MAX_CHANNELS) return invalid("dps_build: C must be in [1, 32]");
     if (leaf_size < 1 || leaf_size > DPS_MAX_LEAF) return invalid("dps_build: leaf_size must be in [1, 256]");
     if (storage != DPS_STORE_FP32 && storage != DPS_STORE_BF16) return invalid("dps_build: unknown storage mode");
+    if (kernel != DPS_KERNEL_DIPOLE && kernel != DPS_KERNEL_MONOPOLE) return invalid("dps_build: unknown kernel");
     if (!p || !n || !A || !attrs) return invalid("dps_build: NULL input array");
     hipStream_t s = (hipStream_t)stream;
     int dev = 0;
@@ -106,12 +113,15 @@ dps_status dps_build(const float *p, const float *n, const float *A, const float
     t->C = C;
     t->leaf_size = leaf_size;
     t->storage = storage;
+    t->kernel = kernel;
+    t->kw = kernel == DPS_KERNEL_MONOPOLE ? 1 : 3;
     t->wide_top = M >= kWideTopPoints;
     t->packet_query = kDefaultPacketQuery;
     t->packet_adjoint = kDefaultPacketAdjoint;
     t->launch_flags = kDefaultLaunchFlags;
     const bool bf = storage == DPS_STORE_BF16;
-    t->mom_stride = bf ? ((3 * C + 1) & ~1) : 3 * C;
+    const int kw = t->kw;
+    t->mom_stride = bf ? ((kw * C + 1) & ~1) : kw * C;
     t->attr_stride = bf ? ((C + 1) & ~1) : C;
 
     st = build_tree(t, p, n, A, s);
@@ -122,10 +132,10 @@ dps_status dps_build(const float *p, const float *n, const float *A, const float
         if (st == DPS_OK) st = tree_alloc(t, &attr, (size_t)M * t->attr_stride * esz);
         t->mom = mom;
         t->attr = attr;
-        if (st == DPS_OK) st = tree_alloc(t, &t->momw, (size_t)t->N * 3 * C);
-        if (st == DPS_OK && t->wide_top) st = tree_alloc(t, &t->momw64, (size_t)t->n_top * 3 * C);
-        if (st == DPS_OK) st = tree_alloc(t, &t->G, (size_t)t->N * 3 * C);
-        if (st == DPS_OK) st = tree_alloc(t, &t->S, (size_t)t->N * 3 * C);
+        if (st == DPS_OK) st = tree_alloc(t, &t->momw, (size_t)t->N * kw * C);
+        if (st == DPS_OK && t->wide_top) st = tree_alloc(t, &t->momw64, (size_t)t->n_top * kw * C);
+        if (st == DPS_OK) st = tree_alloc(t, &t->G, (size_t)t->N * kw * C);
+        if (st == DPS_OK) st = tree_alloc(t, &t->S, (size_t)t->N * kw * C);
         if (st == DPS_OK) st = tree_alloc(t, &t->P, (size_t)M * C);
         if (st == DPS_OK) st = tree_alloc(t, &t->PN, (size_t)M * 3);
         if (st == DPS_OK) st = tree_alloc(t, &t->EACC, 1);
@@ -133,7 +143,7 @@ dps_status dps_build(const float *p, const float *n, const float *A, const float
         if (st == DPS_OK) st = tree_alloc(t, &t->ctr, 16);
         if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->err, 0, sizeof(uint32_t), s), "zero err");
         if (st == DPS_OK) st = refit_moments(t, attrs, s);
-        if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->G, 0, (size_t)t->N * 3 * C * sizeof(double), s), "zero G");
+        if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->G, 0, (size_t)t->N * kw * C * sizeof(double), s), "zero G");
         if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->P, 0, (size_t)M * C * sizeof(double), s), "zero P");
         if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->PN, 0, (size_t)M * 3 * sizeof(double), s), "zero PN");
         if (st == DPS_OK) st = hip_status(hipMemsetAsync(t->EACC, 0, sizeof(double), s), "zero eps");
@@ -158,6 +168,13 @@ static dps_status check_tree(dps_tree t, const char *fn) {
         return DPS_ERR_STATE;
     }
     return DPS_OK;
+}
+
+// entry points defined for the dipole kernel only
+static dps_status need_dipole(dps_tree t, const char *fn) {
+    if (t->kernel == DPS_KERNEL_DIPOLE) return DPS_OK;
+    set_error("%s: not available for a monopole-kernel tree", fn);
+    return DPS_ERR_INVALID;
 }
 
 static dps_status check_beta_eps(float beta, float eps, const char *fn) {
@@ -267,6 +284,7 @@ dps_status dps_adjoint_accumulate_grad(dps_tree t, const float *x, int64_t Q, co
                                        const float *dg, float *dx, void *stream) {
     dps_status st = check_tree(t, "dps_adjoint_accumulate_grad");
     if (st != DPS_OK) return st;
+    if ((st = need_dipole(t, "dps_adjoint_accumulate_grad")) != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate_grad")) != DPS_OK) return st;
     if ((st = check_channels(t, c_begin, n_channels, "dps_adjoint_accumulate_grad")) != DPS_OK) return st;
     if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint_accumulate_grad: Q out of range");
@@ -281,6 +299,7 @@ dps_status dps_adjoint_accumulate_ext(dps_tree t, const float *x, int64_t Q, con
                                       const float *dg, int32_t want, float *dx, void *stream) {
     dps_status st = check_tree(t, "dps_adjoint_accumulate_ext");
     if (st != DPS_OK) return st;
+    if ((st = need_dipole(t, "dps_adjoint_accumulate_ext")) != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate_ext")) != DPS_OK) return st;
     if ((st = check_channels(t, c_begin, n_channels, "dps_adjoint_accumulate_ext")) != DPS_OK) return st;
     if (want < 0 || want > (DPS_WANT_NORMALS | DPS_WANT_EPS))
@@ -296,6 +315,7 @@ dps_status dps_adjoint_finalize_ext(dps_tree t, float *dattrs, float *dnormals, 
     dps_status st = check_tree(t, "dps_adjoint_finalize_ext");
     if (st != DPS_OK) return st;
     if (!dattrs && !dnormals && !deps) return invalid("dps_adjoint_finalize_ext: no output requested");
+    if ((dnormals || deps) && (st = need_dipole(t, "dps_adjoint_finalize_ext")) != DPS_OK) return st;
     DeviceGuard guard(t->device);
     return launch_finalize_ext(t, dattrs, dnormals, deps, (hipStream_t)stream);
 }
@@ -304,6 +324,7 @@ dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing
                           float eps, int32_t c_begin, int32_t n_channels, float *f, float *grad, void *stream) {
     dps_status st = check_tree(t, "dps_query_grid");
     if (st != DPS_OK) return st;
+    if ((st = need_dipole(t, "dps_query_grid")) != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_query_grid")) != DPS_OK) return st;
     if ((st = check_channels(t, c_begin, n_channels, "dps_query_grid")) != DPS_OK) return st;
     if (!origin || !spacing || !dims || !f) return invalid("dps_query_grid: NULL origin, spacing, dims or f");
@@ -322,6 +343,7 @@ dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing
 dps_status dps_set_normals(dps_tree t, const float *n, void *stream) {
     dps_status st = check_tree(t, "dps_set_normals");
     if (st != DPS_OK) return st;
+    if ((st = need_dipole(t, "dps_set_normals")) != DPS_OK) return st;
     if (!n) return invalid("dps_set_normals: n is NULL");
     DeviceGuard guard(t->device);
     return launch_set_normals(t, n, (hipStream_t)stream);
@@ -369,6 +391,14 @@ dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *
     if (bytes) *bytes = t->bytes;
     if (n_points) *n_points = t->M;
     if (channels) *channels = t->C;
+    return DPS_OK;
+}
+
+dps_status dps_get_kernel(dps_tree t, int32_t *kernel) {
+    dps_status st = check_tree(t, "dps_get_kernel");
+    if (st != DPS_OK) return st;
+    if (!kernel) return invalid("dps_get_kernel: kernel is NULL");
+    *kernel = t->kernel;
     return DPS_OK;
 }
 

@@ -1,0 +1,189 @@
+// dps_trav_common.h -- pieces shared by the traversal translation units:
+// moment / attribute loads, launch-shape helpers (XCD order, persistent tile
+// queue), the kernel parameter lists, grid query mapping, and the wavefront
+// reduce-scatter into FP64 accumulators.  Everything here has internal
+// linkage (each translation unit gets its own copy).
+#pragma once
+
+#include <algorithm>
+
+#include "dps_tree.h"
+
+namespace dps {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <int CB, bool BF16>
+__device__ __forceinline__ void load_moments(const void *__restrict__ mom, int ms, uint32_t t, int c0,
+                                             float (&D)[3 * CB]) {
+    if constexpr (!BF16) {
+        const float *b = (const float *)mom + (size_t)t * ms + 3 * c0;
+#pragma unroll
+        for (int i = 0; i < 3 * CB; ++i) D[i] = b[i];
+    } else {
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)t * ms + 3 * c0);
+        constexpr int W = (3 * CB + 1) / 2;
+        uint32_t w[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) w[i] = b[i];
+#pragma unroll
+        for (int i = 0; i < 3 * CB; ++i) D[i] = (i & 1) ? bf16_hi(w[i >> 1]) : bf16_lo(w[i >> 1]);
+    }
+}
+
+template <int CB, bool BF16>
+__device__ __forceinline__ void load_attrs(const void *__restrict__ attr, int as, uint32_t j, int c0,
+                                           float (&mu)[CB]) {
+    if constexpr (!BF16) {
+        const float *b = (const float *)attr + (size_t)j * as + c0;
+#pragma unroll
+        for (int i = 0; i < CB; ++i) mu[i] = b[i];
+    } else {
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)attr + (size_t)j * as + c0);
+        constexpr int W = (CB + 1) / 2;
+        uint32_t w[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) w[i] = b[i];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) mu[i] = (i & 1) ? bf16_hi(w[i >> 1]) : bf16_lo(w[i >> 1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch shapes
+//
+// Grid launch: one workgroup per 4 wavefronts of work.  Workgroups are handed
+// to the 8 XCDs round-robin; with `remap` the workgroups on one XCD take a
+// contiguous eighth of the work, so each XCD's L2 serves one spatial region of
+// a coherently ordered query set.
+//
+// Persistent launch: a grid sized to the resident wavefronts; each wavefront
+// pulls 64*K-query tiles from 8 counters, one per contiguous eighth of the
+// tiles, starting with the partition of its own XCD and then taking tiles from
+// the others, so uneven batches (views of different sizes, shadow rays)
+// balance inside one launch.  Every wavefront leaves once all partitions are
+// exhausted.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t remap_block(int remap) {
+    const int64_t b = blockIdx.x;
+    if (!remap) return b;
+    const int64_t nb = remap;  // number of logical blocks
+    const int64_t per = (nb + 7) / 8;
+    const int64_t l = (b % 8) * per + b / 8;
+    return l < nb ? l : -1;
+}
+
+__device__ __forceinline__ int xcc_id() {
+    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u);  // HW_REG_XCC_ID[3:0]
+}
+
+__device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t ntiles, int &part) {
+    const int64_t per = (ntiles + 7) / 8;
+    for (int a = 0; a < 8; ++a) {
+        const int pi = (part + a) & 7;
+        uint32_t got = 0;
+        if ((threadIdx.x & 63) == 0) got = atomicAdd(&ctr[pi], 1u);
+        got = __builtin_amdgcn_readfirstlane(got);
+        const int64_t tile = (int64_t)pi * per + got;
+        if ((int64_t)got < per && tile < ntiles) {
+            part = pi;
+            return tile;
+        }
+    }
+    return -1;
+}
+
+// Shared parameters of the traversal bodies.  f / grad / df rows have `ldo`
+// channels and tree channel c0 sits in column co of them (channel subsets).
+#define DPS_TRAV_PARAMS                                                                             \
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts,                           \
+        const void *__restrict__ mom, const void *__restrict__ attr, int ms, int as,               \
+        const float *__restrict__ x, int64_t Q, float b2, KernelParams kp, int c0, int ldo, int co, \
+        uint32_t limit, uint32_t *__restrict__ err
+#define DPS_TRAV_ARGS nodes, pts, mom, attr, ms, as, x, Q, b2, kp, c0, ldo, co, limit, err
+// Kernel entry: Qcap rows, of which the first min(Qcap, *qdev) are processed
+// when qdev is given (batch sizes decided on the device, e.g. inside a graph).
+#define DPS_KERN_PARAMS                                                                            \
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts,                           \
+        const void *__restrict__ mom, const void *__restrict__ attr, int ms, int as,               \
+        const float *__restrict__ x, int64_t Qcap, const int64_t *__restrict__ qdev, float b2,     \
+        KernelParams kp, int c0, int ldo, int co, uint32_t limit, uint32_t *__restrict__ err
+#define DPS_ROWS const int64_t Q = qdev ? (qdev[0] < Qcap ? (qdev[0] > 0 ? qdev[0] : 0) : Qcap) : Qcap
+
+// ---------------------------------------------------------------------------
+// grid queries (marching cubes): query q is point (i, j, k) of brick q / 64,
+// bricks of 4 x 4 x 4 points in x-fastest order, so a wavefront covers one
+// brick and 64k consecutive queries k neighbouring bricks.  Coordinates are
+// origin + index * spacing in FP32 without contraction (reproducible).
+// ---------------------------------------------------------------------------
+struct GridSpec {
+    float o[3], h[3];
+    int64_t n[3];   // points per axis
+    int64_t nb[3];  // bricks per axis
+};
+
+__device__ __forceinline__ float grid_coord(float o, int64_t i, float h) {
+#pragma clang fp contract(off)
+    return o + (float)i * h;
+}
+
+// position and output row of grid query q; false outside the grid
+__device__ __forceinline__ bool grid_point(const GridSpec &g, int64_t q, float &x, float &y, float &z, int64_t &row) {
+    const int64_t b = q >> 6;
+    const int l = (int)(q & 63);
+    const int64_t bx = b % g.nb[0], byz = b / g.nb[0];
+    const int64_t by = byz % g.nb[1], bz = byz / g.nb[1];
+    const int64_t i = 4 * bx + (l & 3), j = 4 * by + ((l >> 2) & 3), k = 4 * bz + (l >> 4);
+    const bool in = i < g.n[0] && j < g.n[1] && k < g.n[2];
+    x = grid_coord(g.o[0], i, g.h[0]);
+    y = grid_coord(g.o[1], j, g.h[1]);
+    z = grid_coord(g.o[2], k, g.h[2]);
+    row = (k * g.n[1] + j) * g.n[0] + i;
+    return in;
+}
+
+// Adds the wavefront totals of v[0..N) to dst[0..N) with one FP64 atomic per
+// value: reduce-scatter in chunks of at most 16 values; in each chunk lanes
+// 0 .. P-1 hold distinct values and issue the atomics.
+template <int N_, int B = 0>
+__device__ __forceinline__ void scatter_add_node(const float (&v)[N_], int lane, double *dst) {
+    constexpr int W = (N_ - B) < 16 ? (N_ - B) : 16;
+    float part[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) part[k] = v[B + k];
+    const float tot = wave_sum_scatter<W>(part);
+    const int slot = wave_slot<W>(lane);
+    if (lane < scatter_width<W>() && slot < W) atomicAdd(&dst[B + slot], (double)tot);
+    if constexpr (B + 16 < N_) scatter_add_node<N_, B + 16>(v, lane, dst);
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+__global__ void k_fill_f64(double *__restrict__ a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0.0;
+}
+
+inline unsigned grid(int64_t n) { return (unsigned)std::max<int64_t>(1, cdiv(n, kThreads)); }
+
+// resident workgroups of a kernel on the current device (persistent grid size)
+inline unsigned persistent_grid(const void *fn) {
+    int dev = 0, ncu = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, 0) != hipSuccess || per < 1) per = 1;
+    return (unsigned)(ncu * per);
+}
+
+struct Sub {       // one channel block of a (possibly partial) channel range
+    int c0;        // first tree channel of the block
+    int ldo;       // channels per row of f / grad / df
+    int co;        // column of c0 in those rows
+};
+
+}  // namespace
+}  // namespace dps

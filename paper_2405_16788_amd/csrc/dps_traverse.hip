@@ -23,142 +23,11 @@
 // parallel FP64 atomic per value; dL/dx is private to the lane.
 #include <algorithm>
 
-#include "dps_tree.h"
+#include "dps_trav_common.h"
 
 namespace dps {
 
 namespace {
-
-constexpr int kThreads = 256;
-
-template <int CB, bool BF16>
-__device__ __forceinline__ void load_moments(const void *__restrict__ mom, int ms, uint32_t t, int c0,
-                                             float (&D)[3 * CB]) {
-    if constexpr (!BF16) {
-        const float *b = (const float *)mom + (size_t)t * ms + 3 * c0;
-#pragma unroll
-        for (int i = 0; i < 3 * CB; ++i) D[i] = b[i];
-    } else {
-        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)t * ms + 3 * c0);
-        constexpr int W = (3 * CB + 1) / 2;
-        uint32_t w[W];
-#pragma unroll
-        for (int i = 0; i < W; ++i) w[i] = b[i];
-#pragma unroll
-        for (int i = 0; i < 3 * CB; ++i) D[i] = (i & 1) ? bf16_hi(w[i >> 1]) : bf16_lo(w[i >> 1]);
-    }
-}
-
-template <int CB, bool BF16>
-__device__ __forceinline__ void load_attrs(const void *__restrict__ attr, int as, uint32_t j, int c0,
-                                           float (&mu)[CB]) {
-    if constexpr (!BF16) {
-        const float *b = (const float *)attr + (size_t)j * as + c0;
-#pragma unroll
-        for (int i = 0; i < CB; ++i) mu[i] = b[i];
-    } else {
-        const uint32_t *b = (const uint32_t *)((const uint16_t *)attr + (size_t)j * as + c0);
-        constexpr int W = (CB + 1) / 2;
-        uint32_t w[W];
-#pragma unroll
-        for (int i = 0; i < W; ++i) w[i] = b[i];
-#pragma unroll
-        for (int i = 0; i < CB; ++i) mu[i] = (i & 1) ? bf16_hi(w[i >> 1]) : bf16_lo(w[i >> 1]);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// launch shapes
-//
-// Grid launch: one workgroup per 4 wavefronts of work.  Workgroups are handed
-// to the 8 XCDs round-robin; with `remap` the workgroups on one XCD take a
-// contiguous eighth of the work, so each XCD's L2 serves one spatial region of
-// a coherently ordered query set.
-//
-// Persistent launch: a grid sized to the resident wavefronts; each wavefront
-// pulls 64*K-query tiles from 8 counters, one per contiguous eighth of the
-// tiles, starting with the partition of its own XCD and then taking tiles from
-// the others, so uneven batches (views of different sizes, shadow rays)
-// balance inside one launch.  Every wavefront leaves once all partitions are
-// exhausted.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t remap_block(int remap) {
-    const int64_t b = blockIdx.x;
-    if (!remap) return b;
-    const int64_t nb = remap;  // number of logical blocks
-    const int64_t per = (nb + 7) / 8;
-    const int64_t l = (b % 8) * per + b / 8;
-    return l < nb ? l : -1;
-}
-
-__device__ __forceinline__ int xcc_id() {
-    return (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u);  // HW_REG_XCC_ID[3:0]
-}
-
-__device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t ntiles, int &part) {
-    const int64_t per = (ntiles + 7) / 8;
-    for (int a = 0; a < 8; ++a) {
-        const int pi = (part + a) & 7;
-        uint32_t got = 0;
-        if ((threadIdx.x & 63) == 0) got = atomicAdd(&ctr[pi], 1u);
-        got = __builtin_amdgcn_readfirstlane(got);
-        const int64_t tile = (int64_t)pi * per + got;
-        if ((int64_t)got < per && tile < ntiles) {
-            part = pi;
-            return tile;
-        }
-    }
-    return -1;
-}
-
-// Shared parameters of the traversal bodies.  f / grad / df rows have `ldo`
-// channels and tree channel c0 sits in column co of them (channel subsets).
-#define DPS_TRAV_PARAMS                                                                             \
-    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts,                           \
-        const void *__restrict__ mom, const void *__restrict__ attr, int ms, int as,               \
-        const float *__restrict__ x, int64_t Q, float b2, KernelParams kp, int c0, int ldo, int co, \
-        uint32_t limit, uint32_t *__restrict__ err
-#define DPS_TRAV_ARGS nodes, pts, mom, attr, ms, as, x, Q, b2, kp, c0, ldo, co, limit, err
-// Kernel entry: Qcap rows, of which the first min(Qcap, *qdev) are processed
-// when qdev is given (batch sizes decided on the device, e.g. inside a graph).
-#define DPS_KERN_PARAMS                                                                            \
-    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts,                           \
-        const void *__restrict__ mom, const void *__restrict__ attr, int ms, int as,               \
-        const float *__restrict__ x, int64_t Qcap, const int64_t *__restrict__ qdev, float b2,     \
-        KernelParams kp, int c0, int ldo, int co, uint32_t limit, uint32_t *__restrict__ err
-#define DPS_ROWS const int64_t Q = qdev ? (qdev[0] < Qcap ? (qdev[0] > 0 ? qdev[0] : 0) : Qcap) : Qcap
-
-// ---------------------------------------------------------------------------
-// grid queries (marching cubes): query q is point (i, j, k) of brick q / 64,
-// bricks of 4 x 4 x 4 points in x-fastest order, so a wavefront covers one
-// brick and 64k consecutive queries k neighbouring bricks.  Coordinates are
-// origin + index * spacing in FP32 without contraction (reproducible).
-// ---------------------------------------------------------------------------
-struct GridSpec {
-    float o[3], h[3];
-    int64_t n[3];   // points per axis
-    int64_t nb[3];  // bricks per axis
-};
-
-__device__ __forceinline__ float grid_coord(float o, int64_t i, float h) {
-#pragma clang fp contract(off)
-    return o + (float)i * h;
-}
-
-// position and output row of grid query q; false outside the grid
-__device__ __forceinline__ bool grid_point(const GridSpec &g, int64_t q, float &x, float &y, float &z, int64_t &row) {
-    const int64_t b = q >> 6;
-    const int l = (int)(q & 63);
-    const int64_t bx = b % g.nb[0], byz = b / g.nb[0];
-    const int64_t by = byz % g.nb[1], bz = byz / g.nb[1];
-    const int64_t i = 4 * bx + (l & 3), j = 4 * by + ((l >> 2) & 3), k = 4 * bz + (l >> 4);
-    const bool in = i < g.n[0] && j < g.n[1] && k < g.n[2];
-    x = grid_coord(g.o[0], i, g.h[0]);
-    y = grid_coord(g.o[1], j, g.h[1]);
-    z = grid_coord(g.o[2], k, g.h[2]);
-    row = (k * g.n[1] + j) * g.n[0] + i;
-    return in;
-}
 
 // ---------------------------------------------------------------------------
 // primal query, one query per lane (register-lean).  Software-pipelined: the
@@ -521,21 +390,6 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
         counts[4 * q + 2] = leaves;
         counts[4 * q + 3] = near;
     }
-}
-
-// Adds the wavefront totals of v[0..N) to dst[0..N) with one FP64 atomic per
-// value: reduce-scatter in chunks of at most 16 values; in each chunk lanes
-// 0 .. P-1 hold distinct values and issue the atomics.
-template <int N_, int B = 0>
-__device__ __forceinline__ void scatter_add_node(const float (&v)[N_], int lane, double *dst) {
-    constexpr int W = (N_ - B) < 16 ? (N_ - B) : 16;
-    float part[W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) part[k] = v[B + k];
-    const float tot = wave_sum_scatter<W>(part);
-    const int slot = wave_slot<W>(lane);
-    if (lane < scatter_width<W>() && slot < W) atomicAdd(&dst[B + slot], (double)tot);
-    if constexpr (B + 16 < N_) scatter_add_node<N_, B + 16>(v, lane, dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -1021,35 +875,27 @@ __global__ void k_set_normals(const float *__restrict__ n, const uint32_t *__res
     pts[j].anz = mul_rn(a, n[3 * i + 2]);
 }
 
-__global__ void k_fill_u32(uint32_t *__restrict__ a, int64_t n, uint32_t v) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = v;
-}
-
-__global__ void k_fill_f64(double *__restrict__ a, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        a[i] = 0.0;
-}
 
 // ---------------------------------------------------------------------------
 // adjoint stage 2 (eq. farfield_features_gradient): running sum of the node
 // accumulators from the root to each leaf, then each point adds
 // A_m n_m . (sum over its ancestors) to its own near-field accumulator.
 // ---------------------------------------------------------------------------
-__global__ void k_leaf_sums(int64_t N, int C, const NodeRec *__restrict__ nodes,
+__global__ void k_leaf_sums(int64_t N, int64_t W, const NodeRec *__restrict__ nodes,
                             const int32_t *__restrict__ parent, const double *__restrict__ G,
                             double *__restrict__ S) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t w3 = 3 * (int64_t)C;
-    if (i >= N * w3) return;
-    const int64_t t = i / w3;
-    const int64_t k = i - t * w3;
+    if (i >= N * W) return;  // W accumulators per node
+    const int64_t t = i / W;
+    const int64_t k = i - t * W;
     if (!(nodes[t].meta & kLeafFlag)) return;
     double sum = 0.0;
-    for (int64_t a = t; a >= 0; a = parent[a]) sum += G[a * w3 + k];
-    S[t * w3 + k] = sum;
+    for (int64_t a = t; a >= 0; a = parent[a]) sum += G[a * W + k];
+    S[t * W + k] = sum;
 }
 
+// dL/dmu_mc = P_mc + A_m n_m . S_lc (dipole) or P_mc + A_m S_lc (monopole)
+template <bool MONO>
 __global__ void k_points_out(int64_t M, int C, const int32_t *__restrict__ leaf_of,
                              const uint32_t *__restrict__ perm, const PointRec *__restrict__ pts,
                              const double *__restrict__ P, const double *__restrict__ S,
@@ -1059,9 +905,13 @@ __global__ void k_points_out(int64_t M, int C, const int32_t *__restrict__ leaf_
     const int64_t j = i / C;
     const int c = (int)(i - j * C);
     const int64_t l = leaf_of[j];
-    const double *Sl = S + (l * C + c) * 3;
-    const double v = P[j * C + c] + (double)pts[j].anx * Sl[0] + (double)pts[j].any * Sl[1] +
-                     (double)pts[j].anz * Sl[2];
+    double v;
+    if constexpr (MONO) {
+        v = P[j * C + c] + (double)pts[j].a * S[l * C + c];
+    } else {
+        const double *Sl = S + (l * C + c) * 3;
+        v = P[j * C + c] + (double)pts[j].anx * Sl[0] + (double)pts[j].any * Sl[1] + (double)pts[j].anz * Sl[2];
+    }
     dattrs[(int64_t)perm[j] * C + c] = (float)v;
 }
 
@@ -1093,18 +943,22 @@ __global__ void k_export_nodes(int64_t N, const int32_t *__restrict__ lvl, const
 }
 
 template <bool BF16>
-__global__ void k_export_moments(int64_t N, int C, int ms, const void *__restrict__ mom,
+__global__ void k_export_moments(int64_t N, int C, int kw, int ms, const void *__restrict__ mom,
                                  float *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t w3 = 3 * (int64_t)C;
     if (i >= N * w3) return;
     const int64_t t = i / w3;
-    const int64_t k = i - t * w3;
-    if (BF16) out[i] = __uint_as_float((uint32_t)((const uint16_t *)mom)[t * ms + k] << 16);
-    else out[i] = ((const float *)mom)[t * ms + k];
+    const int64_t k = i - t * w3;  // channel k / 3, component k % 3
+    if (kw == 1 && k % 3 != 0) {   // monopole: scalar charge in component 0
+        out[i] = 0.0f;
+        return;
+    }
+    const int64_t e = t * ms + (kw == 1 ? k / 3 : k);
+    if (BF16) out[i] = __uint_as_float((uint32_t)((const uint16_t *)mom)[e] << 16);
+    else out[i] = ((const float *)mom)[e];
 }
 
-inline unsigned grid(int64_t n) { return (unsigned)std::max<int64_t>(1, cdiv(n, kThreads)); }
 
 // channel blocks: 8s, then a 4, then the remainder
 inline int next_block(int rem) { return rem >= 8 ? 8 : (rem >= 4 ? 4 : rem); }
@@ -1116,20 +970,6 @@ inline int clamp_packet(int k, int cb, bool grad) {
     return k < cap ? k : cap;
 }
 
-// resident workgroups of a kernel on the current device (persistent grid size)
-inline unsigned persistent_grid(const void *fn) {
-    int dev = 0, ncu = 0, per = 0;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kThreads, 0) != hipSuccess || per < 1) per = 1;
-    return (unsigned)(ncu * per);
-}
-
-struct Sub {       // one channel block of a (possibly partial) channel range
-    int c0;        // first tree channel of the block
-    int ldo;       // channels per row of f / grad / df
-    int co;        // column of c0 in those rows
-};
 
 template <int CB, bool BF, bool GR, int K>
 dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
@@ -1309,6 +1149,7 @@ dps_status adjoint_g_block_any(dps_tree_s *t, const float *x, int64_t Q, const i
 
 dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                         int cbegin, int nc, float *f, float *g, hipStream_t s) {
+    if (t->kernel == DPS_KERNEL_MONOPOLE) return launch_query_mono(t, x, Q, qdev, beta, eps, cbegin, nc, f, g, s);
     const float b2 = mul_rn(beta, beta);
     const KernelParams kp = make_kernel_params(eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
@@ -1336,6 +1177,7 @@ dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta, i
 
 dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                           int cbegin, int nc, const float *df, float *dx, hipStream_t s) {
+    if (t->kernel == DPS_KERNEL_MONOPOLE) return launch_adjoint_mono(t, x, Q, qdev, beta, eps, cbegin, nc, df, dx, s);
     const float b2 = mul_rn(beta, beta);
     const KernelParams kp = make_kernel_params(eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
@@ -1357,7 +1199,7 @@ dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_
 }
 
 dps_status launch_zero(dps_tree_s *t, hipStream_t s) {
-    const int64_t ng = t->N * 3 * t->C, np = t->M * t->C;
+    const int64_t ng = t->N * t->kw * t->C, np = t->M * t->C;
     k_fill_f64<<<(unsigned)std::min<int64_t>(cdiv(ng, kThreads), 4096), kThreads, 0, s>>>(t->G, ng);
     dps_status st = hip_status(hipGetLastError(), "zero node accumulators");
     if (st != DPS_OK) return st;
@@ -1372,11 +1214,7 @@ dps_status launch_zero(dps_tree_s *t, hipStream_t s) {
 }
 
 dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s) {
-    k_leaf_sums<<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->nodes, t->parent, t->G, t->S);
-    dps_status st = hip_status(hipGetLastError(), "leaf sums");
-    if (st != DPS_OK) return st;
-    k_points_out<<<grid(t->M * t->C), kThreads, 0, s>>>(t->M, t->C, t->leaf_of, t->perm, t->pts, t->P, t->S, dattrs);
-    return hip_status(hipGetLastError(), "point gradients");
+    return launch_finalize_ext(t, dattrs, nullptr, nullptr, s);
 }
 
 dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *moments, hipStream_t s) {
@@ -1388,9 +1226,11 @@ dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *mome
     }
     if (moments) {
         if (t->storage == DPS_STORE_BF16)
-            k_export_moments<true><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->mom_stride, t->mom, moments);
+            k_export_moments<true><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->kw, t->mom_stride, t->mom,
+                                                                                moments);
         else
-            k_export_moments<false><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->mom_stride, t->mom, moments);
+            k_export_moments<false><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->kw, t->mom_stride,
+                                                                                 t->mom, moments);
         dps_status st = hip_status(hipGetLastError(), "export moments");
         if (st != DPS_OK) return st;
     }
@@ -1425,13 +1265,18 @@ dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int6
 
 dps_status launch_finalize_ext(dps_tree_s *t, float *dattrs, float *dnormals, double *deps, hipStream_t s) {
     if (dattrs || dnormals) {
-        k_leaf_sums<<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->nodes, t->parent, t->G, t->S);
+        const int64_t w = (int64_t)t->kw * t->C;
+        k_leaf_sums<<<grid(t->N * w), kThreads, 0, s>>>(t->N, w, t->nodes, t->parent, t->G, t->S);
         dps_status st = hip_status(hipGetLastError(), "leaf sums");
         if (st != DPS_OK) return st;
     }
     if (dattrs) {
-        k_points_out<<<grid(t->M * t->C), kThreads, 0, s>>>(t->M, t->C, t->leaf_of, t->perm, t->pts, t->P, t->S,
-                                                            dattrs);
+        if (t->kernel == DPS_KERNEL_MONOPOLE)
+            k_points_out<true><<<grid(t->M * t->C), kThreads, 0, s>>>(t->M, t->C, t->leaf_of, t->perm, t->pts, t->P,
+                                                                      t->S, dattrs);
+        else
+            k_points_out<false><<<grid(t->M * t->C), kThreads, 0, s>>>(t->M, t->C, t->leaf_of, t->perm, t->pts,
+                                                                       t->P, t->S, dattrs);
         dps_status st = hip_status(hipGetLastError(), "point gradients");
         if (st != DPS_OK) return st;
     }

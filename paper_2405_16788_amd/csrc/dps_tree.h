@@ -15,6 +15,8 @@ struct dps_tree_s {
     int64_t M, N;
     int C, leaf_size, depth;
     dps_storage storage;
+    int kernel;       // DPS_KERNEL_DIPOLE or DPS_KERNEL_MONOPOLE
+    int kw;           // moment components per channel: 3 (dipole vectors) or 1 (monopole charges)
     int mom_stride;   // elements per node row of `mom`
     int attr_stride;  // elements per point row of `attr`
     int64_t level_start[dps::kLevels + 2];  // nodes of level l: [level_start[l], level_start[l+1])
@@ -33,11 +35,11 @@ struct dps_tree_s {
     int32_t *leaf_of;         // [M] leaf holding each sorted point
     void *mom;                // [N][mom_stride] FP32 or BF16
     void *attr;               // [M][attr_stride] FP32 or BF16
-    float *momw;              // [N][3C] FP32 working sums of the refit
-    double *momw64;           // [n_top][3C] FP64 working sums (wide_top only)
-    double *G;                // [N][C][3] node adjoint accumulators
+    float *momw;              // [N][kw C] FP32 working sums of the refit
+    double *momw64;           // [n_top][kw C] FP64 working sums (wide_top only)
+    double *G;                // [N][C][kw] node adjoint accumulators
     double *P;                // [M][C] point adjoint accumulators
-    double *S;                // [N][C][3] push-down running sums
+    double *S;                // [N][C][kw] push-down running sums
     double *PN;               // [M][3] near-field dL/dn accumulators (sorted order)
     double *EACC;             // [1] dL/deps accumulator
     uint32_t *err;            // sticky device error word (traversal guard)
@@ -72,6 +74,11 @@ dps_status build_tree(dps_tree_s *t, const float *p, const float *n, const float
 dps_status refit_moments(dps_tree_s *t, const float *attrs, hipStream_t s);
 dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                         int cbegin, int nc, float *f, float *g, hipStream_t s);
+// monopole-kernel trees (dps_mono.hip)
+dps_status launch_query_mono(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
+                             int cbegin, int nc, float *f, float *g, hipStream_t s);
+dps_status launch_adjoint_mono(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
+                               int cbegin, int nc, const float *df, float *dx, hipStream_t s);
 dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta,
                          int32_t *counts, hipStream_t s);
 dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,

@@ -9,7 +9,7 @@ FP32 bits without sharing any of the method's code.
 """
 from .scenes import (  # noqa: F401
     sphere_cloud, sphere_queries, sphere_probes, sfm_cloud, camera_rays,
-    ray_samples, tile_order, cotangents, sfm_camera, sfm_1m, fibonacci_sphere, pixel_ray_samples,
+    ray_samples, tile_order, cotangents, appearance_attrs, sfm_camera, sfm_1m, fibonacci_sphere, pixel_ray_samples,
     CONFIGS,
     SFM_1M_SURFACE, SFM_1M_OUTLIERS, SFM_8M_SURFACE, SFM_8M_OUTLIERS,
 )

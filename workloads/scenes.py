@@ -290,6 +290,19 @@ def cotangents(Q: int, C: int, seed: int):
     return out
 
 
+def appearance_attrs(M: int, K: int, seed: int):
+    """K appearance attributes per point (the learned features that Sec. 7.1
+    feeds to its radiance network), drawn N(0,1) as at a random
+    initialisation.  float32 [M, K]."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((M, K), dtype=np.float32)
+    step = 1 << 20
+    for a in range(0, M, step):
+        b = min(M, a + step)
+        out[a:b] = rng.standard_normal((b - a, K))
+    return out
+
+
 def sfm_1m(order: str = "tile", H: int = 512, W: int = 512, S: int = 128):
     """The 1M-point scene with its 512x512x128 query set."""
     p, n, A, attrs = sfm_cloud(SFM_1M_SURFACE, SFM_1M_OUTLIERS, 10)
