@@ -10,3 +10,4 @@ from .oracle import (  # noqa: F401
     psi_series, rho_closed, radial, chi, chi_series, radial_nu, radial_eps, direct_mono,
     direct_mono_adjoint,
 )
+from . import rays  # noqa: F401,E402
