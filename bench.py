@@ -21,6 +21,10 @@ Grid workload (reported under "grid_512"): the geometry channel at the 512^3
 points of the bounding cube (mesh extraction by marching cubes), positions
 generated in the kernels.
 
+Appearance workload (reported under "appearance_k32"): the same queries with
+the geometry channel on a dipole tree and K = 32 appearance attributes on a
+monopole-kernel tree (foreshortening dropped), forward and adjoint of both.
+
 Batched workload (sfm-8m, reported under "batched"): 8,388,608 points, 8 views
 of 256^2 .. 1024^2 rays x 128 samples (438,829,056 primary samples), one shadow
 ray of 64 samples per primary hit, BF16 storage, persistent autotuned
@@ -68,14 +72,30 @@ def flops_adj(C):
     return {"test": 10, "far": 27 + 13 * C, "near": 35 + 5 * C}
 
 
+# monopole kernel (appearance channels, foreshortening dropped), same
+# conventions:
+#   far source, fwd:   d (3), radial (6), m = kappa (r^2 rsqrt) (2), per channel f += Q m (2)
+#   near point, fwd:   d (3), r^2 (5), radial (6), m (2), A m (1), per channel f += mu A m (2)
+#   far source, adj:   d (3), radial (6), m (2), gv = (lambda r^2 - kappa) rsqrt (2),
+#                      per channel w Q (2), w m (2), wavefront sum (1); gv sum (1), dx (6)
+#   near point, adj:   d (3), r^2 (5), radial (6), m (2), gv (2), A m (1), per channel as
+#                      above (5); A gv sum (2), dx (6)
+def flops_mono_fwd(C):
+    return {"test": 10, "far": 11 + 2 * C, "near": 17 + 2 * C}
+
+
+def flops_mono_adj(C):
+    return {"test": 10, "far": 20 + 5 * C, "near": 27 + 5 * C}
+
+
 MI355X_FP32_VECTOR_TFLOPS = 157.3   # published peak (packed FP32)
 MI355X_FP32_VECTOR_NONPACKED_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 MI355X_HBM_TBS = 8.0
 
 # sources that determine the traversal kernels; the HBM byte counters committed
 # under profiles/ are used only while these are unchanged
-KERNEL_SOURCES = ("paper_2405_16788_amd/csrc/dps_traverse.hip", "paper_2405_16788_amd/csrc/dps_internal.h",
-                  "paper_2405_16788_amd/csrc/dps_tree.h")
+KERNEL_SOURCES = ("paper_2405_16788_amd/csrc/dps_traverse.hip", "paper_2405_16788_amd/csrc/dps_trav_common.h",
+                  "paper_2405_16788_amd/csrc/dps_internal.h", "paper_2405_16788_amd/csrc/dps_tree.h")
 COUNTER_SUMMARY = "profiles/sfm1m_fp32_hbm_counters.md"
 
 
@@ -140,6 +160,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 8M-point workload")
     ap.add_argument("--batched-only", action="store_true", help="only run the batched workload")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--no-appearance", action="store_true", help="skip the geometry + 32 appearance channel step")
     return ap.parse_args()
 
 
@@ -366,6 +387,91 @@ def time_grid(P, dev_in, res, reps=3):
                         f"FP32 storage"}
 
 
+def time_appearance(P, dev_in, steps, warmup, K=32):
+    """Geometry plus appearance channels (C = 1 + K): the geometry channel
+    with the dipole kernel (values and gradients), K appearance attributes
+    with the monopole kernel (values), forward and adjoint of both, on two
+    trees over the same points."""
+    import torch
+    import workloads
+    p, n, A, attrs, x = dev_in[:5]
+    Q, M = x.shape[0], p.shape[0]
+    app = torch.from_numpy(workloads.appearance_attrs(M, K, 73)).cuda()
+    geo = attrs[:, :1].contiguous()
+    from paper_2405_16788_amd import autotune
+    tg = P.dps_build(p, n, A, geo, leaf_size=LEAF)
+    ta = P.dps_build(p, n, A, app, leaf_size=LEAF, kernel="monopole")
+    gen = torch.Generator(device="cuda").manual_seed(77)
+    dfg = torch.randn((Q, 1), device="cuda", generator=gen)
+    dfa = torch.randn((Q, K), device="cuda", generator=gen)
+    tuned = {"geometry": autotune.tune(tg, x, dfg, BETA, EPS, cache="", verbose=True),
+             "appearance": autotune.tune(ta, x, dfa, BETA, EPS, cache="", verbose=True, grad=False)}
+    fg, gg = torch.empty((Q, 1), device="cuda"), torch.empty((Q, 1, 3), device="cuda")
+    fa = torch.empty((Q, K), device="cuda")
+    dxg, dxa = torch.empty((Q, 3), device="cuda"), torch.empty((Q, 3), device="cuda")
+    dag, daa = torch.empty((M, 1), device="cuda"), torch.empty((M, K), device="cuda")
+    names = ["refit", "geometry_query", "appearance_query", "geometry_adjoint", "appearance_adjoint_zero",
+             "appearance_adjoint_accumulate", "appearance_adjoint_finalize"]
+    ev = {k: [] for k in names}
+
+    def step(record):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] if record else None
+        if record: e[0].record()
+        P.dps_set_attributes(tg, geo)
+        P.dps_set_attributes(ta, app)
+        if record: e[1].record()
+        P.dps_query(tg, x, BETA, EPS, f_out=fg, g_out=gg)
+        if record: e[2].record()
+        P.dps_query(ta, x, BETA, EPS, grad=False, f_out=fa)
+        if record: e[3].record()
+        P.dps_adjoint_zero(tg)
+        P.dps_adjoint_accumulate(tg, x, BETA, EPS, dfg, dx_out=dxg)
+        P.dps_adjoint_finalize(tg, dattrs_out=dag)
+        if record: e[4].record()
+        P.dps_adjoint_zero(ta)
+        if record: e[5].record()
+        P.dps_adjoint_accumulate(ta, x, BETA, EPS, dfa, dx_out=dxa)
+        if record: e[6].record()
+        P.dps_adjoint_finalize(ta, dattrs_out=daa)
+        if record: e[7].record()
+        if record:
+            for i, k in enumerate(names):
+                ev[k].append((e[i], e[i + 1]))
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        step(True)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    per = {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in ev.items()}
+    visits, nfar, leaves, near = P.dps_query_counts(ta, x, BETA).to(torch.int64).sum(0).tolist()
+    P.dps_check(tg)
+    P.dps_check(ta)
+    P.dps_destroy(tg)
+    P.dps_destroy(ta)
+    rl = {}
+    for kname, flops, kms in (("appearance_query", flops_mono_fwd(K), per["appearance_query"]),
+                              ("appearance_adjoint_accumulate", flops_mono_adj(K),
+                               per["appearance_adjoint_accumulate"])):
+        fl = flops["test"] * visits + flops["far"] * nfar + flops["near"] * near
+        ach = fl / (kms * 1e-3) / 1e12
+        rl[kname] = {"bound": "alu", "achieved": ach, "peak": MI355X_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": ach / MI355X_FP32_VECTOR_TFLOPS, "flops_per_launch": fl, "avg_launch_ms": kms,
+                     "frac_nonpacked": ach / MI355X_FP32_VECTOR_NONPACKED_TFLOPS}
+    return {"value": Q / (ms * 1e-3), "unit": "queries/s", "ms_per_step": ms, "steps": steps, "kernel_ms": per,
+            "roofline": rl, "packet": {k: {"query": v["query"], "adjoint": v["adjoint"], "flags": v["flags"]}
+                                       for k, v in tuned.items()},
+            "workload": f"sfm-1m: {M} points, {Q} queries; geometry channel (dipole kernel, values + gradients) "
+                        f"and K={K} appearance attributes N(0,1) (monopole kernel, values), C={1 + K}, FP32 storage",
+            "step": "refit both trees + geometry query + appearance query + both adjoints (zero, accumulate with "
+                    "dL/dx, finalize)"}
+
+
 def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
     import oracle
     oracle.build(force=False)
@@ -502,6 +608,11 @@ def main():
     # cube, geometry channel only, positions generated in the kernels
     log("[bench] 512^3 grid query")
     out["grid_512"] = time_grid(P, dev_in, 512)
+    if not args.no_appearance:
+        log("[bench] geometry + 32 appearance channels")
+        out["appearance_k32"] = time_appearance(P, dev_in, max(1, min(args.steps, 5)), 1)
+        log(f"[bench] appearance: {out['appearance_k32']['ms_per_step']:.1f} ms/step, "
+            f"kernels {out['appearance_k32']['kernel_ms']}")
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(np, p, n, A, attrs, x, df, args.cpu_seconds)

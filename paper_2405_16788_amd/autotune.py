@@ -20,8 +20,9 @@ SCHEDULES = {"grid": (0, 0), "xcd": (B.LAUNCH_XCD_QUERY, B.LAUNCH_XCD_ADJOINT),
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dps_autotune.json")
 
 
-def _key(tree, Q, beta, eps):
-    return f"M{tree.M}_C{tree.C}_{tree.storage}_Q{Q}_b{beta:g}_e{eps:g}"
+def _key(tree, Q, beta, eps, grad):
+    kind = getattr(tree, "kernel", "dipole")
+    return f"M{tree.M}_C{tree.C}_{tree.storage}_{kind}_Q{Q}_b{beta:g}_e{eps:g}" + ("" if grad else "_values")
 
 
 def _time(fn, reps):
@@ -37,12 +38,13 @@ def _time(fn, reps):
     return a.elapsed_time(b) / reps
 
 
-def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=False):
+def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=False, grad=True):
     """Picks and applies the fastest packet sizes; returns
-    {"query": k, "adjoint": k, "ms": {...}}."""
+    {"query": k, "adjoint": k, "ms": {...}}.  grad=False times the query
+    without spatial gradients (the call the caller will make)."""
     import torch
     cache = cache if cache is not None else os.environ.get("DPS_AUTOTUNE_CACHE", DEFAULT_CACHE)
-    key = _key(tree, x.shape[0], beta, eps)
+    key = _key(tree, x.shape[0], beta, eps, grad)
     table = {}
     if cache and os.path.exists(cache):
         try:
@@ -61,13 +63,14 @@ def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=Fal
     xs = x[start:start + n].contiguous()
     dfs = df[start:start + n].contiguous()
     f = torch.empty((n, tree.C), device=x.device)
-    g = torch.empty((n, tree.C, 3), device=x.device)
+    g = torch.empty((n, tree.C, 3), device=x.device) if grad else None
     dx = torch.empty((n, 3), device=x.device)
     ms = {"query": {}, "adjoint": {}}
     for mode, (qbit, abit) in SCHEDULES.items():
         for k in PACKETS:
             B.dps_set_launch(tree, k, k, qbit | abit)
-            ms["query"][(k, mode)] = _time(lambda: B.dps_query(tree, xs, beta, eps, f_out=f, g_out=g), reps)
+            ms["query"][(k, mode)] = _time(
+                lambda: B.dps_query(tree, xs, beta, eps, grad=grad, f_out=f, g_out=g), reps)
             B.dps_adjoint_zero(tree)
             ms["adjoint"][(k, mode)] = _time(
                 lambda: B.dps_adjoint_accumulate(tree, xs, beta, eps, dfs, dx_out=dx), reps)
