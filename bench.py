@@ -25,6 +25,11 @@ Appearance workload (reported under "appearance_k32"): the same queries with
 the geometry channel on a dipole tree and K = 32 appearance attributes on a
 monopole-kernel tree (foreshortening dropped), forward and adjoint of both.
 
+Ray front-end (reported under "ray_frontend"): one 512^2 view of the sfm-1m
+cloud with unit geometry attributes: a 1024-sample march for each ray's first
+crossing of the 1/2 level, 24/48/8 samples placed around it (80 uniform
+without one), and the query of the placed samples.
+
 Batched workload (sfm-8m, reported under "batched"): 8,388,608 points, 8 views
 of 256^2 .. 1024^2 rays x 128 samples (438,829,056 primary samples), one shadow
 ray of 64 samples per primary hit, BF16 storage, persistent autotuned
@@ -86,6 +91,13 @@ def flops_mono_fwd(C):
 
 def flops_mono_adj(C):
     return {"test": 10, "far": 20 + 5 * C, "near": 27 + 5 * C}
+
+
+# values-only dipole query (the ray march, one channel):
+#   far source:  d (3), radial (6), per channel D.d (5), f += kappa s (2)
+#   near point:  d (3), r^2 (5), radial (6), An.d (5), kappa s (1), per channel f (2)
+def flops_values(C):
+    return {"test": 10, "far": 9 + 7 * C, "near": 20 + 2 * C}
 
 
 MI355X_FP32_VECTOR_TFLOPS = 157.3   # published peak (packed FP32)
@@ -161,6 +173,7 @@ def parse():
     ap.add_argument("--batched-only", action="store_true", help="only run the batched workload")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-appearance", action="store_true", help="skip the geometry + 32 appearance channel step")
+    ap.add_argument("--no-frontend", action="store_true", help="skip the ray front-end (march + resample + query)")
     return ap.parse_args()
 
 
@@ -472,6 +485,90 @@ def time_appearance(P, dev_in, steps, warmup, K=32):
                     "dL/dx, finalize)"}
 
 
+def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8)):
+    """The ray front-end of one view: dense march for each ray's first
+    crossing, sample placement around it, and the query (values and
+    gradients, all channels) of the placed samples."""
+    import torch
+    import workloads
+    p, n, A, attrs = workloads.winding_cloud(workloads.SFM_1M_SURFACE, workloads.SFM_1M_OUTLIERS, 10)
+    o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(11), RES)
+    dev = [torch.from_numpy(a).cuda() for a in (p, n, A, attrs, o, d, tn, tf)]
+    tree = P.dps_build(*dev[:4], leaf_size=LEAF)
+    P.dps_set_launch(tree, 4, 4, P.LAUNCH_PERSISTENT_QUERY | P.LAUNCH_PERSISTENT_ADJOINT)
+    od, dd, tnd, tfd = dev[4:]
+    R, C, S = o.shape[0], attrs.shape[1], sum(counts)
+    gen = torch.Generator(device="cuda").manual_seed(78)
+    u = torch.rand((R, S), device="cuda", generator=gen)
+    hit = torch.empty(R, device="cuda", dtype=torch.int32)
+    hv = torch.empty((R, 2), device="cuda")
+    t = torch.empty((R, S), device="cuda")
+    x = torch.empty((R * S, 3), device="cuda")
+    f = torch.empty((R * S, C), device="cuda")
+    g = torch.empty((R * S, C, 3), device="cuda")
+    names = ["march", "resample", "query"]
+    ev = {k: [] for k in names}
+
+    def step(record):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+        if record: e[0].record()
+        P.dps_ray_march(tree, od, dd, tnd, tfd, n_march, BETA, EPS, hit_out=hit, values_out=hv)
+        if record: e[1].record()
+        P.dps_ray_resample(od, dd, tnd, tfd, n_march, hit, hv, u, counts=counts, tile_layout=True, t_out=t, x_out=x)
+        if record: e[2].record()
+        P.dps_query(tree, x, BETA, EPS, f_out=f, g_out=g)
+        if record: e[3].record()
+        if record:
+            for i, k in enumerate(names):
+                ev[k].append((e[i], e[i + 1]))
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        step(True)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    per = {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in ev.items()}
+    # samples the march evaluated: up to and including j + 1 on a crossing, all n otherwise
+    n_eval = torch.where(hit >= 0, hit.to(torch.int64) + 2, torch.full_like(hit, n_march, dtype=torch.int64))
+    total = int(n_eval.sum().item())
+    hit_frac = float((hit >= 0).float().mean().item())
+    # traversal counts per evaluated sample, from dps_query_counts on the evaluated
+    # samples of every 128th ray (the positions of the march formula)
+    sel = torch.arange(0, R, 128, device="cuda")
+    ks = torch.arange(n_march, device="cuda", dtype=torch.float32)
+    h = (tfd[sel] - tnd[sel]) / n_march
+    ts = tnd[sel, None] + (ks[None, :] + 0.5) * h[:, None]
+    keep = ks[None, :] < n_eval[sel, None].to(torch.float32)
+    xs = (od[sel, None, :] + ts[..., None] * dd[sel, None, :])[keep].contiguous()
+    c = P.dps_query_counts(tree, xs, BETA).to(torch.int64).sum(0).tolist()
+    m = xs.shape[0]
+    fv = flops_values(1)
+    fl = total * (fv["test"] * c[0] + fv["far"] * c[1] + fv["near"] * c[3]) / m
+    ach = fl / (per["march"] * 1e-3) / 1e12
+    P.dps_check(tree)
+    P.dps_destroy(tree)
+    return {"value": R / (ms * 1e-3), "unit": "rays/s", "ms_per_step": ms, "steps": steps, "kernel_ms": per,
+            "march": {"samples_evaluated": total, "samples_per_s": total / (per["march"] * 1e-3),
+                      "hit_fraction": hit_frac, "per_sample": {"nodes_visited": c[0] / m, "far_nodes": c[1] / m,
+                                                                "near_points": c[3] / m},
+                      "roofline": {"bound": "alu", "achieved": ach, "peak": MI355X_FP32_VECTOR_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": ach / MI355X_FP32_VECTOR_TFLOPS,
+                                   "frac_nonpacked": ach / MI355X_FP32_VECTOR_NONPACKED_TFLOPS,
+                                   "flops_per_launch": fl,
+                                   "counts_from": f"dps_query_counts over the {m} evaluated samples of every "
+                                                  f"128th ray"}},
+            "workload": f"sfm-1m with unit geometry attributes (winding number), one {RES}x{RES} view in 8x8 "
+                        f"tiles: {n_march}-sample march on channel 0, {'/'.join(map(str, counts))} samples placed "
+                        f"(or {S} uniform), query of the {R * S} placed samples (values + gradients, C={C}), "
+                        f"FP32 storage, persistent k=4",
+            "step": "ray march + resample + query of the placed samples"}
+
+
 def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
     import oracle
     oracle.build(force=False)
@@ -613,6 +710,11 @@ def main():
         out["appearance_k32"] = time_appearance(P, dev_in, max(1, min(args.steps, 5)), 1)
         log(f"[bench] appearance: {out['appearance_k32']['ms_per_step']:.1f} ms/step, "
             f"kernels {out['appearance_k32']['kernel_ms']}")
+    if not args.no_frontend:
+        log("[bench] ray front-end (march + resample + query)")
+        out["ray_frontend"] = time_frontend(P, max(1, min(args.steps, 3)), 1)
+        log(f"[bench] ray front-end: {out['ray_frontend']['ms_per_step']:.1f} ms/view, "
+            f"kernels {out['ray_frontend']['kernel_ms']}")
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(np, p, n, A, attrs, x, df, args.cpu_seconds)

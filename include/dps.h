@@ -322,6 +322,48 @@ dps_status dps_set_normals(dps_tree t, const float *n, void *stream);
 dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing[3], const int64_t dims[3], float beta,
                           float eps, int32_t c_begin, int32_t n_channels, float *f, float *grad, void *stream);
 
+/*
+ * Ray front-end (Sec. 7.1, ray sampling): each camera ray's first crossing of
+ * the geometry level set is found with a dense march, and the quadrature
+ * samples are then placed around it (the paper uses 1024 march samples and
+ * 24 / 48 / 8 samples before / around / after the crossing, or 80 uniform
+ * samples for a ray without one).  Rays: o, d device [R][3] (d need not be
+ * unit), tnear, tfar device [R] near and far limits.
+ *
+ * dps_ray_march -- march sample k of ray r is x_k = o + t_k d with
+ *   t_k = tnear + (k + 1/2) h, h = (tfar - tnear) / n_samples, in FP32 with
+ *   one rounding per operation; D is channel `channel` of the tree's dipole
+ *   sum (beta, eps as dps_query).  Output hit_index [R] int32: the smallest j
+ *   with (D(x_j) >= level) != (D(x_{j+1}) >= level), or -1; hit_values [R][2]
+ *   float: D(x_j), D(x_{j+1}) (0, 0 without a crossing).  A ray stops at its
+ *   first crossing, so its cost is the samples up to it.  Rays are handled 64
+ *   at a time (lane = ray): consecutive rays should be neighbouring pixels
+ *   (e.g. 8 x 8 tiles) for coherent traversals.  n_samples in [2, 2^20];
+ *   dipole-kernel trees only; with BF16 storage the channel must be even.
+ *   Uses the tree's query packet setting and its tile counters (order calls
+ *   on one tree).  Graph-safe.
+ * dps_ray_resample -- no tree.  With a crossing (hit_index >= 0):
+ *   t* = t_j + w (t_{j+1} - t_j), w = (level - D_j) / (D_{j+1} - D_j), window
+ *   [a, b] = [max(tnear, t* - window h), min(tfar, t* + window h)]
+ *   (h = (tfar - tnear) / n_march), n_before samples in [tnear, a], n_dense in
+ *   [a, b], n_after in [b, tfar]; without one, S = n_before + n_dense + n_after
+ *   samples in [tnear, tfar].  Sample i of the m in [lo, hi] is at
+ *   t = lo + (i + u) (hi - lo) / m, u = jitter[r][s] in [0, 1) (device
+ *   [R][S]), FP32 with one rounding per operation, x = o + t d.  Outputs
+ *   t_out [R][S] and x_out [R * S][3]: row r * S + s (tile_layout = 0) or
+ *   ((r / 64) * S + s) * 64 + r % 64 (tile_layout = 1, R a multiple of 64:
+ *   a wavefront then holds one sample of 64 neighbouring rays, the layout of
+ *   the point queries that follow).  Counts >= 1 with S <= 4096, window >= 0.
+ *   Runs on the current device.  Graph-safe.
+ */
+dps_status dps_ray_march(dps_tree t, const float *o, const float *d, const float *tnear, const float *tfar, int64_t R,
+                         int32_t n_samples, float beta, float eps, int32_t channel, float level, int32_t *hit_index,
+                         float *hit_values, void *stream);
+dps_status dps_ray_resample(const float *o, const float *d, const float *tnear, const float *tfar, int64_t R,
+                            int32_t n_march, const int32_t *hit_index, const float *hit_values, float level,
+                            const float *jitter, int32_t n_before, int32_t n_dense, int32_t n_after, float window,
+                            int32_t tile_layout, float *t_out, float *x_out, void *stream);
+
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A
  * traversal that would walk more than N nodes stops and sets this flag. */

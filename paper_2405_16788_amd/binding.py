@@ -25,7 +25,8 @@ EXPORTED = (
     "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
     "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_query_channels",
     "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_adjoint_accumulate_ext",
-    "dps_adjoint_finalize_ext", "dps_set_normals", "dps_query_grid", "dps_check", "dps_destroy",
+    "dps_adjoint_finalize_ext", "dps_set_normals", "dps_query_grid", "dps_ray_march", "dps_ray_resample",
+    "dps_check", "dps_destroy",
     "dps_status_string", "dps_last_error",
 )
 
@@ -69,6 +70,8 @@ def load():
         "dps_adjoint_finalize_ext": [vp, vp, vp, vp, vp],
         "dps_set_normals": [vp, vp, vp],
         "dps_query_grid": [vp, vp, vp, vp, f32, f32, i32, i32, vp, vp, vp],
+        "dps_ray_march": [vp, vp, vp, vp, vp, i64, i32, f32, f32, i32, f32, vp, vp, vp],
+        "dps_ray_resample": [vp, vp, vp, vp, i64, i32, vp, vp, f32, vp, i32, i32, i32, f32, i32, vp, vp, vp],
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
         "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
@@ -399,6 +402,48 @@ def dps_query_grid(tree: Tree, origin, spacing, dims, beta: float, eps: float, c
                                  _ptr(g, torch.float32, (nz, ny, nx, n, 3), tree.device, "grad"),
                                  _stream(tree.device)), "dps_query_grid")
     return f, g
+
+
+def dps_ray_march(tree: Tree, o, d, tnear, tfar, n_samples: int = 1024, beta: float = 2.0, eps: float = 0.0,
+                  channel: int = 0, level: float = 0.5, hit_out=None, values_out=None):
+    """First crossing of channel ``channel`` through ``level`` along each ray
+    (dense march of n_samples midpoints between tnear and tfar).  Returns
+    (hit_index int32[R], -1 without a crossing; hit_values float32[R, 2])."""
+    import torch
+    R = o.shape[0]
+    dev = tree.device
+    hit = hit_out if hit_out is not None else torch.empty(R, device=dev, dtype=torch.int32)
+    hv = values_out if values_out is not None else torch.empty((R, 2), device=dev, dtype=torch.float32)
+    f = torch.float32
+    _check(load().dps_ray_march(tree.handle, _ptr(o, f, (R, 3), dev, "o"), _ptr(d, f, (R, 3), dev, "d"),
+                                _ptr(tnear, f, (R,), dev, "tnear"), _ptr(tfar, f, (R,), dev, "tfar"), R,
+                                int(n_samples), float(beta), float(eps), int(channel), float(level),
+                                _ptr(hit, torch.int32, (R,), dev, "hit_index"), _ptr(hv, f, (R, 2), dev, "hit_values"),
+                                _stream(dev)), "dps_ray_march")
+    return hit, hv
+
+
+def dps_ray_resample(o, d, tnear, tfar, n_march: int, hit_index, hit_values, jitter, level: float = 0.5,
+                     counts=(24, 48, 8), window: float = 8.0, tile_layout: bool = False, t_out=None, x_out=None):
+    """Quadrature samples around each ray's first crossing (``dps_ray_resample``).
+    jitter [R, S] in [0, 1), S = sum(counts).  Returns (t[R, S], x[R * S, 3])."""
+    import torch
+    R = o.shape[0]
+    nb, nd, na = (int(c) for c in counts)
+    S = nb + nd + na
+    dev = o.device
+    t = t_out if t_out is not None else torch.empty((R, S), device=dev, dtype=torch.float32)
+    x = x_out if x_out is not None else torch.empty((R * S, 3), device=dev, dtype=torch.float32)
+    f = torch.float32
+    with torch.cuda.device(dev):
+        _check(load().dps_ray_resample(_ptr(o, f, (R, 3), dev, "o"), _ptr(d, f, (R, 3), dev, "d"),
+                                       _ptr(tnear, f, (R,), dev, "tnear"), _ptr(tfar, f, (R,), dev, "tfar"), R,
+                                       int(n_march), _ptr(hit_index, torch.int32, (R,), dev, "hit_index"),
+                                       _ptr(hit_values, f, (R, 2), dev, "hit_values"), float(level),
+                                       _ptr(jitter, f, (R, S), dev, "jitter"), nb, nd, na, float(window),
+                                       int(bool(tile_layout)), _ptr(t, f, (R, S), dev, "t_out"),
+                                       _ptr(x, f, (R * S, 3), dev, "x_out"), _stream(dev)), "dps_ray_resample")
+    return t, x
 
 
 def dps_check(tree: Tree):

@@ -394,6 +394,43 @@ dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *
     return DPS_OK;
 }
 
+dps_status dps_ray_march(dps_tree t, const float *o, const float *d, const float *tnear, const float *tfar, int64_t R,
+                         int32_t n_samples, float beta, float eps, int32_t channel, float level, int32_t *hit_index,
+                         float *hit_values, void *stream) {
+    dps_status st = check_tree(t, "dps_ray_march");
+    if (st != DPS_OK) return st;
+    if ((st = need_dipole(t, "dps_ray_march")) != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_ray_march")) != DPS_OK) return st;
+    if ((st = check_channels(t, channel, 1, "dps_ray_march")) != DPS_OK) return st;
+    if (n_samples < 2 || n_samples > (1 << 20)) return invalid("dps_ray_march: n_samples must be in [2, 2^20]");
+    if (!isfinite(level)) return invalid("dps_ray_march: level must be finite");
+    if (R < 0 || R > ((int64_t)1 << 40)) return invalid("dps_ray_march: R out of range");
+    if (R == 0) return DPS_OK;
+    if (!o || !d || !tnear || !tfar || !hit_index || !hit_values) return invalid("dps_ray_march: NULL array");
+    DeviceGuard guard(t->device);
+    return launch_ray_march(t, o, d, tnear, tfar, R, n_samples, beta, eps, channel, level, hit_index, hit_values,
+                            (hipStream_t)stream);
+}
+
+dps_status dps_ray_resample(const float *o, const float *d, const float *tnear, const float *tfar, int64_t R,
+                            int32_t n_march, const int32_t *hit_index, const float *hit_values, float level,
+                            const float *jitter, int32_t n_before, int32_t n_dense, int32_t n_after, float window,
+                            int32_t tile_layout, float *t_out, float *x_out, void *stream) {
+    if (n_march < 1 || n_march > (1 << 20)) return invalid("dps_ray_resample: n_march must be in [1, 2^20]");
+    if (n_before < 1 || n_dense < 1 || n_after < 1 || (int64_t)n_before + n_dense + n_after > 4096)
+        return invalid("dps_ray_resample: sample counts must be >= 1 with a total of at most 4096");
+    if (!isfinite(level) || !isfinite(window) || !(window >= 0.0f))
+        return invalid("dps_ray_resample: level must be finite and window finite and >= 0");
+    if (tile_layout != 0 && tile_layout != 1) return invalid("dps_ray_resample: tile_layout must be 0 or 1");
+    if (R < 0 || R > ((int64_t)1 << 34)) return invalid("dps_ray_resample: R out of range");
+    if (tile_layout && (R % 64)) return invalid("dps_ray_resample: the tile layout needs R to be a multiple of 64");
+    if (R == 0) return DPS_OK;
+    if (!o || !d || !tnear || !tfar || !hit_index || !hit_values || !jitter || !t_out || !x_out)
+        return invalid("dps_ray_resample: NULL array");
+    return launch_ray_resample(o, d, tnear, tfar, R, n_march, hit_index, hit_values, level, jitter, n_before, n_dense,
+                               n_after, window, tile_layout, t_out, x_out, (hipStream_t)stream);
+}
+
 dps_status dps_get_kernel(dps_tree t, int32_t *kernel) {
     dps_status st = check_tree(t, "dps_get_kernel");
     if (st != DPS_OK) return st;

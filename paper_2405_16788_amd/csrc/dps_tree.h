@@ -79,6 +79,14 @@ dps_status launch_query_mono(dps_tree_s *t, const float *x, int64_t Q, const int
                              int cbegin, int nc, float *f, float *g, hipStream_t s);
 dps_status launch_adjoint_mono(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                                int cbegin, int nc, const float *df, float *dx, hipStream_t s);
+// ray front-end (dps_rays.hip)
+dps_status launch_ray_march(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf,
+                            int64_t R, int n, float beta, float eps, int channel, float level, int32_t *hit,
+                            float *hv, hipStream_t s);
+dps_status launch_ray_resample(const float *o, const float *d, const float *tn, const float *tf, int64_t R,
+                               int n_march, const int32_t *hit, const float *hv, float level, const float *u, int nb,
+                               int nd, int na, float window, int tile_layout, float *t_out, float *x_out,
+                               hipStream_t s);
 dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta,
                          int32_t *counts, hipStream_t s);
 dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,

@@ -1,0 +1,199 @@
+"""Ray front-end on the GPU (Sec. 7.1, ray sampling): the dense march
+(``dps_ray_march``) against the oracle's march on the same FP32 sample
+positions, and the sample placement (``dps_ray_resample``) bit for bit against
+the oracle's FP32 placement on the same synthetic inputs, plus argument
+checks and the march at the benchmark's 512 x 512 view of sfm-1m."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from parity import TOL_BF16, TOL_FP32, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+BETA = 2.0
+EPS = math.sqrt(2.0) * 0.01
+N_MARCH = 1024
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    import paper_2405_16788_amd as lib
+    lib.load()
+    assert torch.cuda.is_available()
+    return lib
+
+
+@pytest.fixture(scope="module")
+def scene(orc):
+    """A 21,000-point cloud with unit geometry attributes (channel 0 is the
+    regularized winding number), 32 x 32 tile-ordered camera rays."""
+    from oracle import rays
+    p, n, A, mu = workloads.winding_cloud(20000, 1000, 90)
+    o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(91), 32)
+    T = orc.Tree(p, n, A, mu, 16)
+    ref = rays.march(T, o, d, tn, tf, N_MARCH, BETA, EPS)
+    return (p, n, A, mu), (o, d, tn, tf), ref
+
+
+def _check_march(hit, hv, ref, tol, level=0.5):
+    """The GPU's crossing index equals the oracle's, except where a sample
+    between the two lies within the tolerance band of the level (its side is
+    then not fixed by the precision); the GPU's values at its own index match
+    the oracle's there, and straddle the level."""
+    j_o, v, sv = ref["j"], ref["v"], ref["sv"]
+    n = v.shape[1]
+    same = hit == j_o
+    for r in np.nonzero(~same)[0]:
+        a = n - 1 if hit[r] < 0 else hit[r]
+        b = n - 1 if j_o[r] < 0 else j_o[r]
+        lo, hi = min(a, b), min(max(a, b) + 1, n - 1)
+        band = np.abs(v[r, lo:hi + 1] - level) <= tol * sv[r, lo:hi + 1]
+        assert np.any(band), (r, hit[r], j_o[r])
+    assert np.mean(same) >= 0.98
+    h = hit >= 0
+    assert np.all((hv[h, 0] >= level) != (hv[h, 1] >= level))
+    rr = np.nonzero(h)[0]
+    jj = hit[h]
+    assert np.all(np.abs(hv[h, 0] - v[rr, jj]) <= tol * sv[rr, jj])
+    assert np.all(np.abs(hv[h, 1] - v[rr, jj + 1]) <= tol * sv[rr, jj + 1])
+    assert np.all(hv[~h] == 0.0)
+    return int(np.sum(h))
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_march_matches_oracle(P, scene, storage, k):
+    (p, n, A, mu), (o, d, tn, tf), ref = scene
+    print(f"[rays] march storage={storage} k={k} R={o.shape[0]} n={N_MARCH}", flush=True)
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16, storage=storage)
+    P.dps_set_launch(tree, k, 0, -1)
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    hit, hv = P.dps_ray_march(tree, od, dd, tnd, tfd, N_MARCH, BETA, EPS)
+    P.dps_check(tree)
+    hits = _check_march(to_host(hit), to_host(hv), ref, TOL_BF16 if storage == "bf16" else TOL_FP32)
+    print(f"[rays] {hits} of {o.shape[0]} rays cross the level set", flush=True)
+    assert 0 < hits < o.shape[0]
+
+
+def test_march_values_are_the_point_query_values(P, scene):
+    """At the sample positions around each crossing (computed by the oracle's
+    FP32 position formula) the point query gives the march's values."""
+    from oracle import rays
+    (p, n, A, mu), (o, d, tn, tf), ref = scene
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    hit, hv = P.dps_ray_march(tree, od, dd, tnd, tfd, N_MARCH, BETA, EPS)
+    hit, hv = to_host(hit), to_host(hv)
+    rr = np.nonzero(hit >= 0)[0]
+    t, _ = rays.march_t(tn[rr], tf[rr], N_MARCH)
+    x = rays.positions(o[rr], d[rr], t)
+    xs = np.concatenate([x[np.arange(len(rr)), hit[rr]], x[np.arange(len(rr)), hit[rr] + 1]]).astype(np.float32)
+    f, _ = P.dps_query_channels(tree, to_dev(xs)[0], BETA, EPS, 0, 1, grad=False)
+    f = to_host(f)[:, 0]
+    want = np.concatenate([hv[rr, 0], hv[rr, 1]])
+    print(f"[rays] march vs point query: bitwise equal {np.array_equal(f, want)}, "
+          f"max |diff| {np.max(np.abs(f - want)):.3g}", flush=True)
+    sv = np.concatenate([ref["sv"][rr, hit[rr]], ref["sv"][rr, hit[rr] + 1]])
+    assert np.all(np.abs(f - want) <= 2 * TOL_FP32 * sv)
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+@pytest.mark.parametrize("counts,window", [((24, 48, 8), 8.0), ((3, 5, 2), 2.5)])
+def test_resample_bitwise(P, orc, layout, counts, window):
+    import torch
+    from oracle import rays
+    o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(92), 32)
+    R = o.shape[0] if layout else 1000
+    o, d, tn, tf = o[:R], d[:R], tn[:R], tf[:R]
+    S = sum(counts)
+    j, vj, vj1, u = workloads.synthetic_crossings(R, N_MARCH, 93, S)
+    hv = np.stack([vj, vj1], axis=1)
+    dev = to_dev(o, d, tn, tf, j, hv, u)
+    t, x = P.dps_ray_resample(*dev[:4], N_MARCH, dev[4], dev[5], dev[6], counts=counts, window=window,
+                              tile_layout=bool(layout))
+    torch.cuda.synchronize()
+    tr, xr, _ = rays.resample(o, d, tn, tf, N_MARCH, j, vj, vj1, u, counts=counts, window=window)
+    t, x = to_host(t), to_host(x)
+    assert np.array_equal(t, tr)
+    if layout:
+        rows = ((np.arange(R)[:, None] // 64) * S + np.arange(S)[None, :]) * 64 + (np.arange(R)[:, None] % 64)
+        xr_rows = np.empty((R * S, 3), np.float32)
+        xr_rows[rows.reshape(-1)] = xr.reshape(-1, 3)
+        assert np.array_equal(x, xr_rows)
+    else:
+        assert np.array_equal(x, xr.reshape(-1, 3))
+
+
+def test_ray_arguments(P):
+    import torch
+    p, n, A, mu = workloads.winding_cloud(4000, 100, 94)
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    mono = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16, kernel="monopole")
+    o, d, tn, tf = to_dev(*workloads.tile_camera_rays(workloads.sfm_camera(95), 8))
+    with pytest.raises(P.DpsError):
+        P.dps_ray_march(mono, o, d, tn, tf, 64, BETA, EPS)
+    with pytest.raises(P.DpsError):
+        P.dps_ray_march(tree, o, d, tn, tf, 1, BETA, EPS)
+    with pytest.raises(P.DpsError):
+        P.dps_ray_march(tree, o, d, tn, tf, 64, BETA, EPS, channel=4)
+    with pytest.raises(P.DpsError):
+        P.dps_ray_march(tree, o, d, tn, tf, 64, -1.0, EPS)
+    e = torch.empty((0, 3), device="cuda")
+    z = torch.empty(0, device="cuda")
+    hit, hv = P.dps_ray_march(tree, e, e, z, z, 64, BETA, EPS)
+    assert hit.numel() == 0
+    R = 60
+    j, vj, vj1, u = (torch.from_numpy(a).cuda() for a in workloads.synthetic_crossings(R, 64, 96))
+    hv = torch.stack([vj, vj1], dim=1).contiguous()
+    with pytest.raises(P.DpsError):  # the tile layout needs whole tiles of 64 rays
+        P.dps_ray_resample(o[:R], d[:R], tn[:R], tf[:R], 64, j, hv, u, tile_layout=True)
+    with pytest.raises(P.DpsError):
+        P.dps_ray_resample(o[:R], d[:R], tn[:R], tf[:R], 0, j, hv, u)
+    with pytest.raises(P.DpsError):
+        P.dps_ray_resample(o[:R], d[:R], tn[:R], tf[:R], 64, j, hv, u, window=-1.0)
+    P.dps_check(tree)
+
+
+def test_march_sfm_1m_512(P, orc):
+    """The march at the benchmark's size: the 1M-point cloud with unit
+    geometry attributes and the 512 x 512 view (262,144 rays x 1024 samples),
+    sampled rays against the oracle's march, then the 80-sample placement in
+    the tile layout and the query of the placed samples."""
+    import torch
+    from oracle import rays
+    p, n, A, mu = workloads.winding_cloud(workloads.SFM_1M_SURFACE, workloads.SFM_1M_OUTLIERS, 10)
+    o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(11), 512)
+    R = o.shape[0]
+    print(f"[rays] sfm-1m march R={R} n={N_MARCH}", flush=True)
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    hit, hv = P.dps_ray_march(tree, od, dd, tnd, tfd, N_MARCH, BETA, EPS)
+    P.dps_check(tree)
+    hit_h, hv_h = to_host(hit), to_host(hv)
+    frac = float(np.mean(hit_h >= 0))
+    print(f"[rays] hit fraction {frac:.4f}", flush=True)
+    assert 0.02 < frac < 0.9
+    idx = np.sort(np.random.default_rng(97).choice(R, 160, replace=False))
+    idx = np.union1d(idx, np.nonzero(hit_h >= 0)[0][:96])
+    T = orc.Tree(p, n, A, mu, 16)
+    ref = rays.march(T, o[idx], d[idx], tn[idx], tf[idx], N_MARCH, BETA, EPS)
+    _check_march(hit_h[idx], hv_h[idx], ref, TOL_FP32)
+    u = torch.rand((R, 80), device="cuda", generator=torch.Generator(device="cuda").manual_seed(98))
+    t, x = P.dps_ray_resample(od, dd, tnd, tfd, N_MARCH, hit, hv, u, tile_layout=True)
+    f, g = P.dps_query(tree, x, BETA, EPS)
+    P.dps_check(tree)
+    assert torch.isfinite(f).all() and torch.isfinite(g).all()
+    assert bool((t[:, 1:] >= t[:, :-1]).all())
+    # rays with a crossing: the dense window holds the level set, so placed
+    # samples of the ray lie on both sides of it (a ray that only grazes the
+    # level may miss one side)
+    hits = torch.nonzero(hit >= 0).squeeze(1)[:256]
+    rows = ((hits[:, None] // 64) * 80 + torch.arange(80, device="cuda")[None, :]) * 64 + (hits[:, None] % 64)
+    fv = f[rows.reshape(-1), 0].reshape(-1, 80)
+    both = ((fv >= 0.5).any(dim=1) & (fv < 0.5).any(dim=1)).float().mean().item()
+    print(f"[rays] hit rays with placed samples on both sides of the level: {both:.3f}", flush=True)
+    assert both >= 0.9

@@ -109,19 +109,8 @@ def test_march_finds_the_blurred_sphere_surface(orc, eps):
 
 
 def _synthetic_march(R, n, seed):
-    """Rays with made-up march results: a crossing index (or -1) and the two
-    field values around it, straddling 1/2 in either direction."""
-    rng = np.random.default_rng(seed)
     o, d, tn, tf = _rays(R, seed)
-    j = rng.integers(-1, n - 1, size=R)
-    j[:4] = [0, n - 2, -1, 1]
-    lo = rng.uniform(0.0, 0.5, R).astype(F)
-    hi = rng.uniform(0.5, 1.0, R).astype(F)
-    hi[hi == F(0.5)] = F(0.75)
-    up = rng.uniform(size=R) < 0.5
-    vj = np.where(up, lo, hi).astype(F)
-    vj1 = np.where(up, hi, lo).astype(F)
-    u = rng.uniform(size=(R, 80)).astype(F)
+    j, vj, vj1, u = workloads.synthetic_crossings(R, n, seed)
     return o, d, tn, tf, j, vj, vj1, u
 
 

@@ -15,5 +15,6 @@ from .scenes import (  # noqa: F401
 )
 from .batched import (  # noqa: F401
     SFM_8M_RES, PRIMARY_SAMPLES, SHADOW_SAMPLES, RayBatch, make_ray_batch, sfm_8m_cloud, tile_rays,
+    tile_camera_rays, synthetic_crossings,
     view_eyes, winding_cloud,
 )

@@ -70,6 +70,36 @@ def tile_rays(res: int, tile: int = TILE):
     return (i * res + j).reshape(-1)
 
 
+def tile_camera_rays(eye, res: int, fov_deg: float = 50.0):
+    """The rays of a res x res pinhole camera at ``eye`` (``camera_rays``) in
+    tile order (``tile_rays``), FP32: o, d [R, 3], t_in, t_out [R]."""
+    o, d, t0, t1 = camera_rays(eye, res, res, fov_deg)
+    pix = tile_rays(res)
+    return (np.ascontiguousarray(o.reshape(-1, 3)[pix], dtype=np.float32),
+            np.ascontiguousarray(d.reshape(-1, 3)[pix], dtype=np.float32),
+            np.ascontiguousarray(t0.reshape(-1)[pix], dtype=np.float32),
+            np.ascontiguousarray(t1.reshape(-1)[pix], dtype=np.float32))
+
+
+def synthetic_crossings(R: int, n: int, seed: int, S: int = 80):
+    """Made-up results of a dense march over R rays of n samples, for testing
+    the sample placement on its own: a crossing index j in [-1, n-2] (the
+    first four rays fixed to 0, n-2, -1, 1), the two field values around it
+    straddling 1/2 in either direction, and the placement jitter u [R, S] in
+    [0, 1).  Returns (j int32, vj, vj1, u) as float32 arrays."""
+    rng = np.random.default_rng(seed)
+    j = rng.integers(-1, n - 1, size=R).astype(np.int32)
+    j[:4] = np.array([0, n - 2, -1, 1])[:min(4, R)]
+    lo = rng.uniform(0.0, 0.5, R).astype(np.float32)
+    hi = rng.uniform(0.5, 1.0, R).astype(np.float32)
+    hi[hi == np.float32(0.5)] = np.float32(0.75)
+    up = rng.uniform(size=R) < 0.5
+    vj = np.where(up, lo, hi).astype(np.float32)
+    vj1 = np.where(up, hi, lo).astype(np.float32)
+    u = rng.uniform(size=(R, S)).astype(np.float32)
+    return j, vj, vj1, u
+
+
 @dataclass
 class RayBatch:
     """Device tensors of a multi-view batch (all rays in tile order, views
