@@ -32,8 +32,10 @@ without one), and the query of the placed samples.
 
 Batched workload (sfm-8m, reported under "batched"): 8,388,608 points, 8 views
 of 256^2 .. 1024^2 rays x 128 samples (438,829,056 primary samples), one shadow
-ray of 64 samples per primary hit, BF16 storage, persistent autotuned
-launches, the whole forward + backward of the render proxy in one graph.
+ray of 64 samples and one hit-point query (values and gradients, for the
+albedo and normal of the direct shadow term) per primary hit, BF16 storage,
+persistent autotuned launches, the whole forward + backward of the render
+proxy in one graph.
 
     python bench.py [--steps K] [--warmup W] [--storage fp32|bf16|both] [--no-batched]
 """
@@ -364,17 +366,20 @@ def time_batched(P, steps, warmup):
     del graph, g_out
     P.dps_destroy(tree)
     K = batch.S_shadow
-    queries = batch.Q + n_hits * K
+    queries = batch.Q + n_hits * K + n_hits
     return {"value": queries / (ms * 1e-3), "unit": "queries/s", "ms_per_step": ms, "eager_ms_per_step": eager_ms,
             "steps": steps, "queries_per_step": queries, "primary_queries": batch.Q,
-            "shadow_rays": n_hits, "shadow_queries": n_hits * K, "shadow_rows_evaluated": q_count,
+            "shadow_rays": n_hits, "shadow_queries": n_hits * K, "hit_point_queries": n_hits,
+            "shadow_rows_evaluated": q_count,
             "build_ms": build_ms, "tree_nodes": info["n_nodes"], "tree_depth": info["depth"],
             "storage": "bf16", "packet": {"query": tuned["query"], "adjoint": tuned["adjoint"], "flags": tuned["flags"]},
             "workload": f"sfm-8m: {M} points, views {'/'.join(str(r) for r in batch.res)} squared x "
-                        f"{batch.S} samples = {batch.Q} primary samples + {K} per shadow ray, C={C}, "
+                        f"{batch.S} samples = {batch.Q} primary samples + {K} per shadow ray + 1 hit-point query per hit, C={C}, "
                         f"beta={BETA}, eps={EPS:.5f}, leaf {LEAF}",
             "step": "refit + primary query (values, gradients) + hit search + shadow query (channel 0, device "
-                    "row count) + render proxy + backward (both adjoints, autograd of the proxy), one graph"}
+                    "row count) + hit-point query (values, gradients, device row count) + render proxy with the "
+                    "direct shadow term + backward (value, gradient-cotangent and shadow adjoints, autograd of the "
+                    "proxy), one graph"}
 
 
 def time_grid(P, dev_in, res, reps=3):

@@ -146,12 +146,30 @@ class OracleBatch:
             cnt[has] = ra["counts"].reshape(-1, K, 4)
         return fs, cnt
 
+    def hit_values(self, hit, has, alpha):
+        """Values and gradients of all channels at the hits (FP32 positions)
+        and the traversal counts of those queries."""
+        n, C = hit.shape[0], self.fa.shape[2]
+        fh, gh = np.zeros((n, C)), np.zeros((n, C, 3))
+        cnt = np.zeros((n, 4), dtype=np.int64)
+        if has.any():
+            q = hit[has].astype(np.float32)
+            ra = self.Ta.query(q, BETA, EPS)
+            fv, gv = ra["f"], ra["g"]
+            if alpha != 0.0:
+                rd = self.Td.query(q, BETA, EPS)
+                fv, gv = fv + alpha * rd["f"], gv + alpha * rd["g"]
+            fh[has], gh[has], cnt[has] = fv, gv, ra["counts"]
+        return fh, gh, cnt
+
     def terms(self, alpha):
         f = self.fa + alpha * self.fd
         has, j, hit = R.primary_hits_numpy(f[..., 0], self.xr)
         xs = R.shadow_samples_numpy(hit, has, self.b["light"], self.b["u"])
         fs, cnt = self.shadow_values(xs, has, alpha)
-        return R.batched_ray_terms_numpy(f, fs, has, self.b["target"]), has, j, cnt, xs
+        fh, gh, hcnt = self.hit_values(hit, has, alpha)
+        t = R.batched_ray_terms_numpy(f, fs, has, self.b["target"], fh, gh, hit, self.b["light"])
+        return t, has, j, (cnt, hcnt), xs
 
 
 def _small_batch(P, orc, storage):
@@ -226,7 +244,7 @@ def test_batched_small_against_oracle(P, orc):
     keep = robust.copy()
     for a, (_, has_a, j_a, cnt_a, _) in runs.items():
         keep &= (has_a == has_o) & ((j_a == j_o) | ~has_o)
-        keep &= np.all(cnt_a == cnt0, axis=(1, 2))
+        keep &= np.all(cnt_a[0] == cnt0[0], axis=(1, 2)) & np.all(cnt_a[1] == cnt0[1], axis=1)
     assert keep.sum() > 0.8 * n_rays and (keep & has_o).sum() >= 10
     w = keep.astype(np.float64)
     cd = {h: (np.sum(w * runs[h][0]) - np.sum(w * runs[-h][0])) / (2 * h) for h in (step, step / 2)}
@@ -283,8 +301,9 @@ def _fd_position_ray(ob, r, dirx, h):
         has, j, hit = R.primary_hits_numpy(f[..., 0], xp.astype(np.float64)[None])
         xs = R.shadow_samples_numpy(hit, has, b["light"][r:r + 1], b["u"][r:r + 1])
         fs, cnt = ob.shadow_values(xs, has, 0.0)
-        val = R.batched_ray_terms_numpy(f, fs, has, b["target"][r:r + 1])[0]
-        return val, bool(has[0]), int(j[0]), cnt, xp.astype(np.float64) - x0
+        fh, gh, hcnt = ob.hit_values(hit, has, 0.0)
+        val = R.batched_ray_terms_numpy(f, fs, has, b["target"][r:r + 1], fh, gh, hit, b["light"][r:r + 1])[0]
+        return val, bool(has[0]), int(j[0]), (cnt, hcnt), xp.astype(np.float64) - x0
 
     vals = {s: term(s) for s in (h, -h, h / 2, -h / 2)}
     if any(v is None for v in vals.values()):
@@ -292,7 +311,7 @@ def _fd_position_ray(ob, r, dirx, h):
     if len({(v[1], v[2]) for v in vals.values()}) != 1:
         return None
     c0 = vals[h][3]
-    if not all(np.array_equal(v[3], c0) for v in vals.values()):
+    if not all(np.array_equal(v[3][0], c0[0]) and np.array_equal(v[3][1], c0[1]) for v in vals.values()):
         return None
     cd = {s: (vals[s][0] - vals[-s][0]) / (2 * s) for s in (h, h / 2)}
     dd = {s: (vals[s][4] - vals[-s][4]) / (2 * s) for s in (h, h / 2)}

@@ -22,10 +22,16 @@ the primary hit of a ray is the first sample interval [j, j+1] where D_0
 crosses 1/2, placed by linear interpolation of D_0 between the two samples.
 A ray with a hit casts one shadow ray from hit + 1e-3 l (l the unit direction
 to its view's light) to the exit of the |x| <= sqrt(3) bound, with stratified
-samples; its shadow transmittance is T_s = exp(-sum_k sigma(D_0(x_k))) and the
-pixel colour is scaled by 0.5 + 0.5 T_s (1 for rays without a hit).  The
-shadow batch is compacted so that hits come first, in ray order, 64 hits per
-group; inside a group the query rows are [sample, lane], like the primaries.
+samples; its shadow transmittance is T_s = exp(-sum_k sigma(D_0(x_k))).  The
+pixel adds the direct illumination of eq. direct at the hit x_h,
+L_d = albedo T_s n.(l - x_h) / |l - x_h|^3 with the albedo D_{1:3}(x_h) and the
+implicit normal n = grad g / |grad g| = -grad D_0 / |grad D_0| (Sec. 5.1),
+both from a query at the hit point itself (values and gradients, one row per
+ray), to the volume colour: C + L_d (C alone for rays without a hit), the
+volume colour standing in for the MLP term of eq. radiance_field_shadow_rays.
+The shadow batch and the hit queries are compacted so that hits come first,
+in ray order, 64 hits per group; inside a shadow group the query rows are
+[sample, lane], like the primaries.
 """
 import math
 
@@ -175,9 +181,9 @@ def shadow_layout(has, K):
 
     Returns (rows[n,K] int64: query row of sample k of each ray, inv[n*K]:
     the ray-sample index held by each row, q_count[1] int64: rows to evaluate,
-    i.e. 64*K per started group of hits, n_hits 0-d tensor).  Rays with a hit
-    take slots 0..n_hits-1 in ray order, the others follow, so every row holds
-    exactly one ray-sample."""
+    i.e. 64*K per started group of hits, n_hits 0-d tensor, slot[n]: the
+    ray's slot).  Rays with a hit take slots 0..n_hits-1 in ray order, the
+    others follow, so every row holds exactly one ray-sample."""
     import torch
     n = has.numel()
     hi = has.reshape(-1).to(torch.int64)
@@ -189,7 +195,20 @@ def shadow_layout(has, K):
     inv = torch.empty(n * K, device=has.device, dtype=torch.int64)
     inv[rows.reshape(-1)] = torch.arange(n * K, device=has.device, dtype=torch.int64)
     q_count = (((n_hits + (GROUP - 1)) // GROUP) * (GROUP * K)).reshape(1)
-    return rows, inv, q_count, n_hits
+    return rows, inv, q_count, n_hits, slot
+
+
+def direct_term_torch(fh, gh, hit, light):
+    """eq. direct without the transmittance: albedo D_{1:3}(x_h) times
+    n.(l - x_h) / |l - x_h|^3, n = -grad D_0 / |grad D_0|.  fh [n,C], gh [n,C,3]
+    at the hits, hit, light [n,3]."""
+    import torch
+    l = light - hit
+    r2 = torch.clamp(torch.sum(l * l, dim=1), min=1e-12)
+    g0 = gh[:, 0, :]
+    gn = torch.sqrt(torch.clamp(torch.sum(g0 * g0, dim=1), min=1e-30))
+    cos = -torch.sum(g0 * l, dim=1) / (gn * r2 * torch.sqrt(r2))
+    return fh[:, 1:4] * cos[:, None]
 
 
 def tree_sum(v):
@@ -214,7 +233,9 @@ def batched_forward(dipole_sum, attrs, x, tree, batch, beta, eps, primary_grad=T
     x [Q,3] the primary samples (batch layout), batch a ``RayBatch``.
     ray_weight: optional [n_rays] weights of the per-ray loss terms.
     Returns (loss, aux) with aux holding f [Q,C], has, hit, xs_rows, rows,
-    q_count, n_hits, fs [n_rays*K, 1], shade."""
+    q_count, n_hits, fs [n_rays*K, 1], fh [n_rays, C] and gh [n_rays, C, 3]
+    (hit queries in slot order), hit_count (their device row count) and
+    direct [n_rays, 3] (L_d before masking)."""
     import torch
     S, K = batch.S, batch.S_shadow
     f, _ = dipole_sum(attrs, x, tree, beta, eps, grad=primary_grad, refit=refit)
@@ -226,19 +247,28 @@ def batched_forward(dipole_sum, attrs, x, tree, batch, beta, eps, primary_grad=T
     has, hit = primary_hits_torch(ft[..., 0], x.view(T, S, GROUP, 3))
     has, hit = has.reshape(-1), hit.reshape(-1, 3)
     xs = shadow_samples_torch(hit, has, batch.ray_light, batch.shadow_u)
-    rows, inv, q_count, n_hits = shadow_layout(has, K)
+    rows, inv, q_count, n_hits, slot = shadow_layout(has, K)
     xs_rows = xs.reshape(-1, 3).index_select(0, inv)
     fs, _ = dipole_sum(attrs, xs_rows, tree, beta, eps, channels=(0, 1), q_count=q_count, grad=False,
                        refit=False)
     fsr = fs.reshape(-1).index_select(0, rows.reshape(-1)).reshape(-1, K)
     ts = torch.exp(-torch.sum(sigma_torch(fsr), dim=1))
-    shade = 0.5 + 0.5 * torch.where(has, ts, torch.ones_like(ts))
-    terms = torch.sum((col * shade[:, None] - batch.target) ** 2, dim=1)
+    # values and gradients at the hit points, one row per ray in slot order
+    n = has.numel()
+    inv_slot = torch.empty(n, device=has.device, dtype=torch.int64)
+    inv_slot[slot] = torch.arange(n, device=has.device, dtype=torch.int64)
+    x_hit = hit.index_select(0, inv_slot)
+    qh = (((n_hits + (GROUP - 1)) // GROUP) * GROUP).reshape(1)
+    fh_rows, gh_rows = dipole_sum(attrs, x_hit, tree, beta, eps, q_count=qh, grad=True, refit=False)
+    fh, gh = fh_rows.index_select(0, slot), gh_rows.index_select(0, slot)
+    ld = direct_term_torch(fh, gh, hit, batch.ray_light) * ts[:, None]
+    pix = col + torch.where(has[:, None], ld, torch.zeros_like(ld))
+    terms = torch.sum((pix - batch.target) ** 2, dim=1)
     if ray_weight is not None:
         terms = terms * ray_weight
     loss = tree_sum(terms)
     aux = {"f": f, "has": has, "hit": hit, "xs_rows": xs_rows, "rows": rows, "q_count": q_count,
-           "n_hits": n_hits, "fs": fs, "shade": shade}
+           "n_hits": n_hits, "fs": fs, "fh": fh_rows, "gh": gh_rows, "hit_count": qh, "direct": ld}
     return loss, aux
 
 
@@ -269,11 +299,22 @@ def shadow_samples_numpy(hit, has, light, u):
     return np.where(has[:, None, None], xs, np.broadcast_to(light[:, None, :], xs.shape))
 
 
-def batched_ray_terms_numpy(f, fs, has, target):
-    """Per-ray loss terms from primary values f [n,S,C] (ray-major) and shadow
-    channel-0 values fs [n,K]."""
+def direct_term_numpy(fh, gh, hit, light):
+    l = light - hit
+    r2 = np.maximum(np.sum(l * l, axis=1), 1e-12)
+    g0 = gh[:, 0, :]
+    gn = np.sqrt(np.maximum(np.sum(g0 * g0, axis=1), 1e-30))
+    cos = -np.sum(g0 * l, axis=1) / (gn * r2 * np.sqrt(r2))
+    return fh[:, 1:4] * cos[:, None]
+
+
+def batched_ray_terms_numpy(f, fs, has, target, fh, gh, hit, light):
+    """Per-ray loss terms from primary values f [n,S,C] (ray-major), shadow
+    channel-0 values fs [n,K], and the values fh [n,C] and gradients gh
+    [n,C,3] at the hits."""
     w = _weights_numpy(sigma_numpy(f[..., 0]), 1)
     col = np.sum(w[..., None] * f[..., 1:4], axis=1)
     ts = np.exp(-np.sum(sigma_numpy(fs), axis=1))
-    shade = 0.5 + 0.5 * np.where(has, ts, 1.0)
-    return np.sum((col * shade[:, None] - target) ** 2, axis=1)
+    ld = direct_term_numpy(fh, gh, hit, light) * ts[:, None]
+    pix = col + np.where(has[:, None], ld, 0.0)
+    return np.sum((pix - target) ** 2, axis=1)
