@@ -106,10 +106,12 @@ MI355X_FP32_VECTOR_TFLOPS = 157.3   # published peak (packed FP32)
 MI355X_FP32_VECTOR_NONPACKED_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 MI355X_HBM_TBS = 8.0
 
-# sources that determine the traversal kernels; the HBM byte counters committed
-# under profiles/ are used only while these are unchanged
+# sources holding the device code of the point-query traversal kernels (the
+# kernels take raw pointers, so the host-side tree header is not among them);
+# the HBM byte counters committed under profiles/ are used only while these
+# are unchanged
 KERNEL_SOURCES = ("paper_2405_16788_amd/csrc/dps_traverse.hip", "paper_2405_16788_amd/csrc/dps_trav_common.h",
-                  "paper_2405_16788_amd/csrc/dps_internal.h", "paper_2405_16788_amd/csrc/dps_tree.h")
+                  "paper_2405_16788_amd/csrc/dps_internal.h")
 COUNTER_SUMMARY = "profiles/sfm1m_fp32_hbm_counters.md"
 
 

@@ -369,9 +369,14 @@ __global__ __launch_bounds__(kThreads) void k_mono_adjoint_persistent(DPS_KERN_P
 // host dispatch
 // ---------------------------------------------------------------------------
 
-// channel blocks: 16s (8s with gradients), then halving
+// channels per walk without gradients (16 or 32)
+#ifndef DPS_MONO_TOP
+#define DPS_MONO_TOP 16
+#endif
+
+// channel blocks: DPS_MONO_TOP (8 with gradients), then halving
 inline int mono_block(int rem, bool grad) {
-    const int top = grad ? 8 : 16;
+    const int top = grad ? 8 : DPS_MONO_TOP;
     for (int b = top; b > 1; b >>= 1)
         if (rem >= b) return b;
     return 1;
@@ -501,6 +506,9 @@ dps_status launch_query_mono(dps_tree_s *t, const float *x, int64_t Q, const int
         const Sub sb{c0, nc, c0 - cbegin};
         dps_status st;
         switch (cb) {
+#if DPS_MONO_TOP >= 32
+            case 32: st = mono_query_block<32>(t, x, Q, qdev, b2, kp, sb, f, g, s); break;
+#endif
             case 16: st = mono_query_block<16>(t, x, Q, qdev, b2, kp, sb, f, g, s); break;
             case 8: st = mono_query_block<8>(t, x, Q, qdev, b2, kp, sb, f, g, s); break;
             case 4: st = mono_query_block<4>(t, x, Q, qdev, b2, kp, sb, f, g, s); break;
@@ -523,6 +531,9 @@ dps_status launch_adjoint_mono(dps_tree_s *t, const float *x, int64_t Q, const i
         const Sub sb{c0, nc, c0 - cbegin};
         dps_status st;
         switch (cb) {
+#if DPS_MONO_TOP >= 32
+            case 32: st = mono_adjoint_block<32>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
+#endif
             case 16: st = mono_adjoint_block<16>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
             case 8: st = mono_adjoint_block<8>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
             case 4: st = mono_adjoint_block<4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
