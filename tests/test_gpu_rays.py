@@ -197,3 +197,64 @@ def test_march_sfm_1m_512(P, orc):
     both = ((fv >= 0.5).any(dim=1) & (fv < 0.5).any(dim=1)).float().mean().item()
     print(f"[rays] hit rays with placed samples on both sides of the level: {both:.3f}", flush=True)
     assert both >= 0.9
+
+
+def test_front_end_graph_replays(P):
+    """March, placement and the query of the placed samples captured in one
+    graph: every replay equals the eager result, with eager work between the
+    replays, and rays moved in place between replays reach the captured
+    kernels."""
+    import torch
+    p, n, A, mu = workloads.winding_cloud(40000, 2000, 99)
+    o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(100), 64)
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    P.dps_set_launch(tree, 2, 2, P.LAUNCH_PERSISTENT_QUERY | P.LAUNCH_PERSISTENT_ADJOINT)
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    R = o.shape[0]
+    u = torch.rand((R, 80), device="cuda", generator=torch.Generator(device="cuda").manual_seed(101))
+    hit = torch.empty(R, device="cuda", dtype=torch.int32)
+    hv = torch.empty((R, 2), device="cuda")
+    t = torch.empty((R, 80), device="cuda")
+    x = torch.empty((R * 80, 3), device="cuda")
+    f = torch.empty((R * 80, mu.shape[1]), device="cuda")
+    g = torch.empty((R * 80, mu.shape[1], 3), device="cuda")
+
+    def step():
+        P.dps_ray_march(tree, od, dd, tnd, tfd, N_MARCH, BETA, EPS, hit_out=hit, values_out=hv)
+        P.dps_ray_resample(od, dd, tnd, tfd, N_MARCH, hit, hv, u, tile_layout=True, t_out=t, x_out=x)
+        P.dps_query(tree, x, BETA, EPS, f_out=f, g_out=g)
+
+    def snapshot():
+        torch.cuda.synchronize()
+        return [to_host(v).copy() for v in (hit, hv, t, x, f, g)]
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+        ref = snapshot()
+    torch.cuda.current_stream().wait_stream(side)
+    assert 0 < int((ref[0] >= 0).sum()) < R
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for r in range(3):
+        for v in (hv, t, x, f, g):
+            v.fill_(float("nan"))
+        hit.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        got = snapshot()
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), f"replay {r}"
+        P.dps_query(tree, x[:4096], BETA, EPS)  # eager work between replays
+    # the rays move (in place): the captured march follows them
+    od.mul_(1.05)
+    step()
+    ref2 = snapshot()
+    graph.replay()
+    got = snapshot()
+    for a, b in zip(got, ref2):
+        assert np.array_equal(a, b), "replay after the rays moved"
+    assert not np.array_equal(ref2[3], ref[3])
+    P.dps_check(tree)
