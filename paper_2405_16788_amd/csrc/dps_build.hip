@@ -368,7 +368,13 @@ __global__ void k_geom(int64_t nb, int64_t ne, const int32_t *__restrict__ first
     nodes[t].cz = (float)(s2 / a);
 }
 
-// squared radius: one wavefront per node, max of FP32 squared distances
+// squared radius: the max of FP32 squared distances from the centroid.  The
+// max is exact and order-free, so the two kernels below give the same bits as
+// any other evaluation order.
+constexpr int32_t kBigNode = 16384;  // nodes with more points: k_radius_big
+
+// nodes with at most kBigNode points: one wavefront per node; larger nodes
+// are set to 0 here and raised by k_radius_big afterwards
 __global__ __launch_bounds__(kThreads) void k_radius(int64_t N, const int32_t *__restrict__ ptb,
                                                      const int32_t *__restrict__ ptc,
                                                      const PointRec *__restrict__ pts,
@@ -376,6 +382,10 @@ __global__ __launch_bounds__(kThreads) void k_radius(int64_t N, const int32_t *_
     const int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
     if (t >= N) return;  // uniform per wavefront
     const int lane = lane_id();
+    if (ptc[t] > kBigNode) {
+        if (lane == 0) nodes[t].r2 = 0.0f;
+        return;
+    }
     const float cx = nodes[t].cx, cy = nodes[t].cy, cz = nodes[t].cz;
     const int64_t jb = ptb[t], je = jb + ptc[t];
     float m = 0.0f;
@@ -383,6 +393,50 @@ __global__ __launch_bounds__(kThreads) void k_radius(int64_t N, const int32_t *_
         m = fmaxf(m, dist2_rn(pts[j].x, pts[j].y, pts[j].z, cx, cy, cz));
     m = wave_max_nonneg(m);
     if (lane == 0) nodes[t].r2 = m;
+}
+
+// nodes with more than kBigNode points: one thread per sorted point descends
+// from the root through its ancestors that hold more than kBigNode points (the
+// child holding the point is found among the contiguous children).  When all
+// 64 points of a wavefront share the ancestor, the wavefront reduces first and
+// issues one atomic max, otherwise each point does; the atomic max acts on the
+// bit pattern of the non-negative float, which orders like the value.
+__global__ __launch_bounds__(kThreads) void k_radius_big(int64_t M, const int32_t *__restrict__ first_child,
+                                                         const int32_t *__restrict__ nchild,
+                                                         const int32_t *__restrict__ ptb,
+                                                         const int32_t *__restrict__ ptc,
+                                                         const PointRec *__restrict__ pts,
+                                                         NodeRec *__restrict__ nodes) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = lane_id();
+    const bool valid = j < M;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    if (valid) {
+        px = pts[j].x;
+        py = pts[j].y;
+        pz = pts[j].z;
+    }
+    int32_t a = valid ? 0 : -1;
+    for (int l = 0; l <= kLevels; ++l) {  // wave-uniform: ends when no lane has a large ancestor left
+        const bool big = a >= 0 && ptc[a] > kBigNode;
+        if (__ballot(big) == 0) break;
+        float d2 = 0.0f;
+        if (big) d2 = dist2_rn(px, py, pz, nodes[a].cx, nodes[a].cy, nodes[a].cz);
+        const int32_t a0 = __builtin_amdgcn_readfirstlane(a);
+        if (__ballot(!(big && a == a0)) == 0) {
+            const float m = wave_max_nonneg(d2);
+            if (lane == 0) atomicMax((unsigned int *)&nodes[a0].r2, __float_as_uint(m));
+        } else if (big) {
+            atomicMax((unsigned int *)&nodes[a].r2, __float_as_uint(d2));
+        }
+        int32_t next = -1;
+        if (big) {  // a large node is never a leaf: its children partition its points
+            const int32_t cb = first_child[a], ce = cb + nchild[a];
+            for (int32_t c = cb; c < ce; ++c)
+                if (j >= ptb[c] && j < (int64_t)ptb[c] + ptc[c]) next = c;
+        }
+        a = next;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -652,6 +706,10 @@ dps_status build_tree(dps_tree_s *t, const float *p, const float *n, const float
     }
     k_radius<<<grid(N, kThreads / 64), kThreads, 0, s>>>(N, t->ptb, t->ptc, t->pts, t->nodes);
     DPS_LAUNCHED("radius");
+    if (M > kBigNode) {
+        k_radius_big<<<grid(M), kThreads, 0, s>>>(M, t->first_child, t->nchild, t->ptb, t->ptc, t->pts, t->nodes);
+        DPS_LAUNCHED("radius of large nodes");
+    }
     for (int l = 0; l <= depth; ++l) {
         const int64_t nb = t->level_start[l], ne = t->level_start[l + 1];
         k_escape<<<grid(ne - nb), kThreads, 0, s>>>(nb, ne, t->parent, t->first_child, t->nchild, esc);
