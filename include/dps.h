@@ -29,6 +29,8 @@
  *    returned by dps_last_error().
  *  - Point order: "caller order" is the order of the arrays given to
  *    dps_build.  Internally points are kept in Morton order.
+ *  - One call processes at most DPS_MAX_ROWS rows (queries, rays times
+ *    samples, grid points); larger counts return DPS_ERR_INVALID.
  */
 #ifndef DPS_H
 #define DPS_H
@@ -61,6 +63,9 @@ typedef enum {
     DPS_KERNEL_MONOPOLE = 1  /* the same kernel without the foreshortening factor n.(y-x)/|y-x|
                                 (appearance attributes, Sec. 7.1), see dps_build_kernel */
 } dps_kernel;
+
+/* Maximum rows (queries, placed ray samples, grid points) of one call: 2^38. */
+#define DPS_MAX_ROWS ((int64_t)1 << 38)
 
 /* Maximum number of attribute channels per tree. */
 #define DPS_MAX_CHANNELS 32

@@ -43,6 +43,10 @@ static void free_tree(dps_tree_s *t) {
     delete t;
 }
 
+// largest row count of one call (DPS_MAX_ROWS): keeps every launch's
+// workgroup count (rows / 256) within the grid limit of 2^31 - 1
+constexpr int64_t kMaxRows = DPS_MAX_ROWS;
+
 static dps_status invalid(const char *msg) {
     set_error("%s", msg);
     return DPS_ERR_INVALID;
@@ -202,7 +206,7 @@ dps_status dps_query(dps_tree t, const float *x, int64_t Q, float beta, float ep
     dps_status st = check_tree(t, "dps_query");
     if (st != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_query")) != DPS_OK) return st;
-    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_query: Q out of range");
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_query: Q out of range");
     if (Q == 0) return DPS_OK;
     if (!x || !f) return invalid("dps_query: NULL x or f");
     DeviceGuard dg(t->device);
@@ -227,7 +231,7 @@ dps_status dps_query_channels(dps_tree t, const float *x, int64_t Q, const int64
     if (st != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_query_channels")) != DPS_OK) return st;
     if ((st = check_channels(t, c_begin, n_channels, "dps_query_channels")) != DPS_OK) return st;
-    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_query_channels: Q out of range");
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_query_channels: Q out of range");
     if (Q == 0) return DPS_OK;
     if (!x || !f) return invalid("dps_query_channels: NULL x or f");
     DeviceGuard dg(t->device);
@@ -239,7 +243,7 @@ dps_status dps_query_counts(dps_tree t, const float *x, int64_t Q, float beta, i
     dps_status st = check_tree(t, "dps_query_counts");
     if (st != DPS_OK) return st;
     if ((st = check_beta_eps(beta, 0.0f, "dps_query_counts")) != DPS_OK) return st;
-    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_query_counts: Q out of range");
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_query_counts: Q out of range");
     if (Q == 0) return DPS_OK;
     if (!x || !counts) return invalid("dps_query_counts: NULL x or counts");
     DeviceGuard dg(t->device);
@@ -258,7 +262,7 @@ dps_status dps_adjoint_accumulate(dps_tree t, const float *x, int64_t Q, float b
     dps_status st = check_tree(t, "dps_adjoint_accumulate");
     if (st != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate")) != DPS_OK) return st;
-    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint_accumulate: Q out of range");
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_adjoint_accumulate: Q out of range");
     if (Q == 0) return DPS_OK;
     if (!x || !df) return invalid("dps_adjoint_accumulate: NULL x or df");
     DeviceGuard dg(t->device);
@@ -272,7 +276,7 @@ dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q
     if (st != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate_channels")) != DPS_OK) return st;
     if ((st = check_channels(t, c_begin, n_channels, "dps_adjoint_accumulate_channels")) != DPS_OK) return st;
-    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint_accumulate_channels: Q out of range");
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_adjoint_accumulate_channels: Q out of range");
     if (Q == 0) return DPS_OK;
     if (!x || !df) return invalid("dps_adjoint_accumulate_channels: NULL x or df");
     DeviceGuard dg(t->device);
@@ -287,7 +291,7 @@ dps_status dps_adjoint_accumulate_grad(dps_tree t, const float *x, int64_t Q, co
     if ((st = need_dipole(t, "dps_adjoint_accumulate_grad")) != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate_grad")) != DPS_OK) return st;
     if ((st = check_channels(t, c_begin, n_channels, "dps_adjoint_accumulate_grad")) != DPS_OK) return st;
-    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint_accumulate_grad: Q out of range");
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_adjoint_accumulate_grad: Q out of range");
     if (Q == 0) return DPS_OK;
     if (!x || !dg) return invalid("dps_adjoint_accumulate_grad: NULL x or dg");
     DeviceGuard guard(t->device);
@@ -304,7 +308,7 @@ dps_status dps_adjoint_accumulate_ext(dps_tree t, const float *x, int64_t Q, con
     if ((st = check_channels(t, c_begin, n_channels, "dps_adjoint_accumulate_ext")) != DPS_OK) return st;
     if (want < 0 || want > (DPS_WANT_NORMALS | DPS_WANT_EPS))
         return invalid("dps_adjoint_accumulate_ext: want must be a mask of DPS_WANT_NORMALS and DPS_WANT_EPS");
-    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint_accumulate_ext: Q out of range");
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_adjoint_accumulate_ext: Q out of range");
     if (Q == 0) return DPS_OK;
     if (!x || (!df && !dg)) return invalid("dps_adjoint_accumulate_ext: NULL x, or neither df nor dg");
     DeviceGuard guard(t->device);
@@ -334,7 +338,7 @@ dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing
             return invalid("dps_query_grid: each dimension must be in [1, 2^24]");
         if (!isfinite(origin[a]) || !isfinite(spacing[a])) return invalid("dps_query_grid: non-finite origin or spacing");
         total *= dims[a];
-        if (total > ((int64_t)1 << 40)) return invalid("dps_query_grid: grid too large");
+        if (total > kMaxRows) return invalid("dps_query_grid: grid too large");
     }
     DeviceGuard guard(t->device);
     return launch_query_grid(t, origin, spacing, dims, beta, eps, c_begin, n_channels, f, grad, (hipStream_t)stream);
@@ -362,7 +366,7 @@ dps_status dps_adjoint(dps_tree t, const float *x, int64_t Q, float beta, float 
     dps_status st = check_tree(t, "dps_adjoint");
     if (st != DPS_OK) return st;
     if ((st = check_beta_eps(beta, eps, "dps_adjoint")) != DPS_OK) return st;
-    if (Q < 0 || Q > ((int64_t)1 << 40)) return invalid("dps_adjoint: Q out of range");
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_adjoint: Q out of range");
     if (!dattrs) return invalid("dps_adjoint: dattrs is NULL");
     if (Q > 0 && (!x || !df)) return invalid("dps_adjoint: NULL x or df");
     if ((st = dps_adjoint_zero(t, stream)) != DPS_OK) return st;
@@ -404,7 +408,7 @@ dps_status dps_ray_march(dps_tree t, const float *o, const float *d, const float
     if ((st = check_channels(t, channel, 1, "dps_ray_march")) != DPS_OK) return st;
     if (n_samples < 2 || n_samples > (1 << 20)) return invalid("dps_ray_march: n_samples must be in [2, 2^20]");
     if (!isfinite(level)) return invalid("dps_ray_march: level must be finite");
-    if (R < 0 || R > ((int64_t)1 << 40)) return invalid("dps_ray_march: R out of range");
+    if (R < 0 || R > kMaxRows) return invalid("dps_ray_march: R out of range");
     if (R == 0) return DPS_OK;
     if (!o || !d || !tnear || !tfar || !hit_index || !hit_values) return invalid("dps_ray_march: NULL array");
     DeviceGuard guard(t->device);
@@ -422,7 +426,7 @@ dps_status dps_ray_resample(const float *o, const float *d, const float *tnear, 
     if (!isfinite(level) || !isfinite(window) || !(window >= 0.0f))
         return invalid("dps_ray_resample: level must be finite and window finite and >= 0");
     if (tile_layout != 0 && tile_layout != 1) return invalid("dps_ray_resample: tile_layout must be 0 or 1");
-    if (R < 0 || R > ((int64_t)1 << 34)) return invalid("dps_ray_resample: R out of range");
+    if (R < 0 || R > kMaxRows / (n_before + n_dense + n_after)) return invalid("dps_ray_resample: R out of range");
     if (tile_layout && (R % 64)) return invalid("dps_ray_resample: the tile layout needs R to be a multiple of 64");
     if (R == 0) return DPS_OK;
     if (!o || !d || !tnear || !tfar || !hit_index || !hit_values || !jitter || !t_out || !x_out)

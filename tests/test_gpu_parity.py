@@ -193,6 +193,29 @@ def test_invalid_data_rejected(dps):
         assert e.value.status == 1
 
 
+def test_row_counts_beyond_the_limit_rejected(dps):
+    """Counts above DPS_MAX_ROWS (2^38) are rejected before any launch (the
+    raw C entry points, with small buffers that are never written)."""
+    import ctypes as ct
+    import torch
+    tree = dps.dps_build(*to_dev(*workloads.sphere_cloud(256, 1)))
+    lib = dps.load()
+    buf = torch.zeros(4096, device="cuda")
+    ptr = ct.c_void_p(buf.data_ptr())
+    big = (1 << 38) + 1
+    assert lib.dps_query(tree.handle, ptr, big, 2.0, 0.05, ptr, None, None) == 1
+    assert lib.dps_query_channels(tree.handle, ptr, big, None, 2.0, 0.05, 0, 1, ptr, None, None) == 1
+    assert lib.dps_adjoint_accumulate(tree.handle, ptr, big, 2.0, 0.05, ptr, None, None) == 1
+    assert lib.dps_ray_march(tree.handle, ptr, ptr, ptr, ptr, big, 64, 2.0, 0.05, 0, 0.5, ptr, ptr, None) == 1
+    iptr = ct.c_void_p(buf.data_ptr())
+    # 2^38 / 80 + 1 rays of 80 placed samples exceed the limit
+    assert lib.dps_ray_resample(ptr, ptr, ptr, ptr, (1 << 38) // 80 + 1, 64, iptr, ptr, 0.5, ptr, 24, 48, 8, 8.0, 0,
+                                ptr, ptr, None) == 1
+    torch.cuda.synchronize()
+    assert not torch.any(buf != 0)
+    dps.dps_check(tree)
+
+
 @pytest.mark.parametrize("flags", [0, 3, 12])
 @pytest.mark.parametrize("k", [1, 2, 4])
 @pytest.mark.parametrize("name,Q", [("sphere-8k", 4099), ("random-3001-c5", 1000), ("random-2000-c1", 257),
