@@ -258,3 +258,25 @@ def test_front_end_graph_replays(P):
         assert np.array_equal(a, b), "replay after the rays moved"
     assert not np.array_equal(ref2[3], ref[3])
     P.dps_check(tree)
+
+
+def test_march_edge_cases(P, orc):
+    """Two march samples, zero-length rays (t_near = t_far: every sample at
+    one point, no crossing) and a ray count that is not a multiple of 64,
+    against the oracle's march."""
+    from oracle import rays
+    p, n, A, mu = workloads.winding_cloud(20000, 1000, 90)
+    o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(91), 16)
+    R = 200
+    o, d, tn, tf = o[:R].copy(), d[:R].copy(), tn[:R].copy(), tf[:R].copy()
+    tf[::7] = tn[::7]
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    T = orc.Tree(p, n, A, mu, 16)
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    for n_s in (2, 3, 97):
+        print(f"[rays] edge cases: R={R} n={n_s}", flush=True)
+        hit, hv = P.dps_ray_march(tree, od, dd, tnd, tfd, n_s, BETA, EPS)
+        ref = rays.march(T, o, d, tn, tf, n_s, BETA, EPS)
+        _check_march(to_host(hit), to_host(hv), ref, TOL_FP32)
+        assert np.all(to_host(hit)[::7] == -1)
+    P.dps_check(tree)
