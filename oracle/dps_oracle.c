@@ -210,18 +210,22 @@ static void radial_eps(double r, double eps, double *kap_e, double *lam_e)
 
 void orc_radial_eps(double r, double eps, double *kap_e, double *lam_e) { radial_eps(r, eps, kap_e, lam_e); }
 
+static double norm3(const double v[3]) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
 /* dL/deps of one term with dipole D, value cotangent w (or 0) and gradient
- * cotangent h (or NULL), and its absolute scale */
-static double term_eps(const double d[3], double kap_e, double lam_e, const double D[3], double w,
+ * cotangent h (or NULL), and its absolute scale, with |D.d| <= wD r and
+ * |D.h| <= wD |h| for the absolute mass wD of the term (< 0: |D|) */
+static double term_eps(const double d[3], double kap_e, double lam_e, const double D[3], double wD, double w,
                        const double *h, double *scale)
 {
     double s = D[0] * d[0] + D[1] * d[1] + D[2] * d[2];
-    double v = w * kap_e * s, a = fabs(w * kap_e * s);
+    double r = norm3(d), m = wD < 0.0 ? norm3(D) : wD;
+    double v = w * kap_e * s, a = fabs(w * kap_e) * m * r;
     if (h) {
         double dh = d[0] * h[0] + d[1] * h[1] + d[2] * h[2];
         double Dh = D[0] * h[0] + D[1] * h[1] + D[2] * h[2];
         v += lam_e * s * dh - kap_e * Dh;
-        a += fabs(lam_e * s * dh) + fabs(kap_e * Dh);
+        a += fabs(lam_e * dh) * m * r + fabs(kap_e) * m * norm3(h);
     }
     if (scale) *scale += a;
     return v;
@@ -233,7 +237,7 @@ static double term_eps(const double d[3], double kap_e, double lam_e, const doub
  *   dx += nu s (d.h) d - lambda (d (D.h) + D (d.h)) - lambda s h
  * and the matching absolute scales. */
 static void grad_cotangent(const double d[3], double r, double kap, double lam, double nu,
-                           const double D[3], const double h[3], double dD[3], double dx[3],
+                           const double D[3], double wD, const double h[3], double dD[3], double dx[3],
                            double *sdD, double *sdx)
 {
     double s = D[0] * d[0] + D[1] * d[1] + D[2] * d[2];
@@ -244,7 +248,7 @@ static void grad_cotangent(const double d[3], double r, double kap, double lam, 
         if (dx) dx[k] += nu * s * dh * d[k] - lam * (d[k] * Dh + D[k] * dh) - lam * s * h[k];
     }
     double nh = sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]);
-    double nD = sqrt(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    double nD = wD < 0.0 ? norm3(D) : wD;
     if (sdD) *sdD += nh * (fabs(lam) * r * r + kap);
     if (sdx) *sdx += nh * nD * (fabs(nu) * r * r * r + 3.0 * fabs(lam) * r);
 }
@@ -255,9 +259,13 @@ static void grad_cotangent(const double d[3], double r, double kap, double lam, 
 
 /* Adds, for channels c < C, the value kappa (D_c.d), the gradient
  * -kappa D_c + lambda (D_c.d) d, and the absolute scales
- * kappa |D_c| r and |D_c| (kappa + |lambda| r^2).  Returns 0 if the source
- * coincides with the query and eps = 0 (term excluded). */
-static int add_term(const double c[3], const double *D, int C, const double x[3],
+ * kappa W_c r and W_c (kappa + |lambda| r^2), W_c the absolute dipole mass of
+ * the source: |D_c| for a point (W = NULL), and for a node the sum of |D_mc|
+ * over its points (its moment aggregates them, so any FP32 formation of the
+ * moment errs in proportion to that sum, however much the moment cancels).
+ * Returns 0 if the source coincides with the query and eps = 0 (term
+ * excluded). */
+static int add_term(const double c[3], const double *D, const double *W, int C, const double x[3],
                     double eps, double *f, double *g, double *sf, double *sg)
 {
     double d[3] = {c[0] - x[0], c[1] - x[1], c[2] - x[2]};
@@ -272,7 +280,7 @@ static int add_term(const double c[3], const double *D, int C, const double x[3]
         if (g) {
             for (int k = 0; k < 3; ++k) g[3 * ch + k] += -kap * Dc[k] + lam * s * d[k];
         }
-        double nd = sqrt(Dc[0] * Dc[0] + Dc[1] * Dc[1] + Dc[2] * Dc[2]);
+        double nd = W ? W[ch] : sqrt(Dc[0] * Dc[0] + Dc[1] * Dc[1] + Dc[2] * Dc[2]);
         if (sf) sf[ch] += kap * nd * r;
         if (sg) sg[ch] += nd * (kap + fabs(lam) * r2);
     }
@@ -280,11 +288,12 @@ static int add_term(const double c[3], const double *D, int C, const double x[3]
 }
 
 /* Monopole term with charges Qc[3*ch] (stride 3): value Q m, m = kappa r,
- * gradient Q (r lambda - kappa / r) d; absolute scales |Q| m and
- * |Q| |r lambda - kappa / r| r.  Returns 0 when the source coincides with
+ * gradient Q (r lambda - kappa / r) d; absolute scales W m and
+ * W |r lambda - kappa / r| r with W = |Q| for a point (W = NULL) or the sum of
+ * A_m |mu_m| over a node's points.  Returns 0 when the source coincides with
  * the query (no contribution). */
-static int add_term_mono(const double c[3], const double *Qc, int C, const double x[3], double eps,
-                         double *f, double *g, double *sf, double *sg)
+static int add_term_mono(const double c[3], const double *Qc, const double *W, int C, const double x[3],
+                         double eps, double *f, double *g, double *sf, double *sg)
 {
     double d[3] = {c[0] - x[0], c[1] - x[1], c[2] - x[2]};
     double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
@@ -294,11 +303,11 @@ static int add_term_mono(const double c[3], const double *Qc, int C, const doubl
     radial(r, eps, &kap, &lam);
     double m = kap * r, gv = r * lam - kap / r;
     for (int ch = 0; ch < C; ++ch) {
-        double q = Qc[3 * ch];
+        double q = Qc[3 * ch], aq = W ? W[ch] : fabs(q);
         if (f) f[ch] += q * m;
         if (g) for (int k = 0; k < 3; ++k) g[3 * ch + k] += q * gv * d[k];
-        if (sf) sf[ch] += fabs(q) * m;
-        if (sg) sg[ch] += fabs(q) * fabs(gv) * r;
+        if (sf) sf[ch] += aq * m;
+        if (sg) sg[ch] += aq * fabs(gv) * r;
     }
     return 1;
 }
@@ -336,7 +345,7 @@ int orc_direct(const float *p, const float *n, const float *A, const float *mu,
             for (int ch = 0; ch < C; ++ch)
                 for (int k = 0; k < 3; ++k)
                     D[3 * ch + k] = (double)A[m] * (double)mu[m * C + ch] * (double)n[3 * m + k];
-            add_term(c, D, C, xq, eps, fl, gl, sfl, sgl);
+            add_term(c, D, NULL, C, xq, eps, fl, gl, sfl, sgl);
         }
         for (int ch = 0; ch < C; ++ch) {
             if (f) f[q * C + ch] = fl[ch];
@@ -389,7 +398,7 @@ int orc_direct_adjoint(const float *p, const float *n, const float *A, const flo
                             D[k] = (double)A[m] * (double)mu[m * C + ch] * (double)n[3 * m + k];
                             h[k] = (double)dg[(q * C + ch) * 3 + k];
                         }
-                        grad_cotangent(d, r, kap, lam, nu, D, h, NULL, acc, NULL, NULL);
+                        grad_cotangent(d, r, kap, lam, nu, D, -1.0, h, NULL, acc, NULL, NULL);
                     }
                 }
             }
@@ -469,7 +478,7 @@ int orc_direct_adjoint(const float *p, const float *n, const float *A, const flo
                         D[k] = (double)A[m] * (double)mu[m * C + ch] * (double)n[3 * m + k];
                         if (dg) h[k] = (double)dg[(q * C + ch) * 3 + k];
                     }
-                    tot += term_eps(d, ke, le, D, df ? (double)df[q * C + ch] : 0.0, dg ? h : NULL, NULL);
+                    tot += term_eps(d, ke, le, D, -1.0, df ? (double)df[q * C + ch] : 0.0, dg ? h : NULL, NULL);
                 }
             }
         }
@@ -494,7 +503,7 @@ int orc_direct_mono(const float *p, const float *A, const float *mu, int64_t M, 
         for (int64_t m = 0; m < M; ++m) {
             double c[3] = {p[3 * m], p[3 * m + 1], p[3 * m + 2]};
             for (int ch = 0; ch < C; ++ch) Qc[3 * ch] = (double)A[m] * (double)mu[m * C + ch];
-            add_term_mono(c, Qc, C, xq, eps, fl, gl, sfl, sgl);
+            add_term_mono(c, Qc, NULL, C, xq, eps, fl, gl, sfl, sgl);
         }
         for (int ch = 0; ch < C; ++ch) {
             if (f) f[q * C + ch] = fl[ch];
@@ -574,6 +583,8 @@ typedef struct {
     double *mu;           /* [M][C] sorted attributes */
     double *D;            /* [N][C][3] node dipoles D_t = sum A_m mu_m n_m; monopole
                              trees keep Q_t = sum A_m mu_m in D[t][c][0] */
+    double *W;            /* [N][C] absolute masses sum_m A_m |mu_m| |n_m| (monopole:
+                             sum_m A_m |mu_m|), the scale of a node term */
     int kind;             /* 0: dipole kernel, 1: monopole kernel */
 } orc_tree;
 
@@ -608,7 +619,7 @@ void orc_tree_free(orc_tree *t)
     if (!t) return;
     free(t->codes_in); free(t->codes); free(t->perm); free(t->ps); free(t->Am); free(t->nm);
     free(t->node); free(t->geom); free(t->area); free(t->cen64); free(t->leaf_of);
-    free(t->mu); free(t->D);
+    free(t->mu); free(t->D); free(t->W);
     free(t);
 }
 
@@ -741,28 +752,35 @@ orc_tree *orc_tree_build(const float *p, const float *n, const float *A, int64_t
 int orc_tree_set_attrs(orc_tree *t, const float *mu, int C)
 {
     if (!t || C < 1 || C > 64) return 1;
-    free(t->mu); free(t->D);
+    free(t->mu); free(t->D); free(t->W);
     t->C = C;
     t->mu = (double *)malloc(sizeof(double) * t->M * C);
     for (int64_t i = 0; i < t->M; ++i)
         for (int c = 0; c < C; ++c) t->mu[i * C + c] = (double)mu[(int64_t)t->perm[i] * C + c];
     t->D = (double *)calloc((size_t)t->N * C * 3, sizeof(double));
+    t->W = (double *)calloc((size_t)t->N * C, sizeof(double));
     for (int64_t i = t->N - 1; i >= 0; --i) {
         const int32_t *nd = t->node + 6 * i;
-        double *Di = t->D + i * C * 3;
+        double *Di = t->D + i * C * 3, *Wi = t->W + i * C;
         if (nd[3] == 0) {
-            for (int64_t j = nd[4]; j < (int64_t)nd[4] + nd[5]; ++j)
+            for (int64_t j = nd[4]; j < (int64_t)nd[4] + nd[5]; ++j) {
+                const double nn = norm3(t->nm + 3 * j);
                 for (int c = 0; c < C; ++c) {
+                    const double am = t->Am[j] * t->mu[j * C + c];
                     if (t->kind == 1) {
-                        Di[3 * c] += t->Am[j] * t->mu[j * C + c];
+                        Di[3 * c] += am;
+                        Wi[c] += fabs(am);
                         continue;
                     }
-                    for (int k = 0; k < 3; ++k)
-                        Di[3 * c + k] += t->Am[j] * t->mu[j * C + c] * t->nm[3 * j + k];
+                    for (int k = 0; k < 3; ++k) Di[3 * c + k] += am * t->nm[3 * j + k];
+                    Wi[c] += fabs(am) * nn;
                 }
+            }
         } else {
-            for (int64_t ch = nd[2]; ch < (int64_t)nd[2] + nd[3]; ++ch)
+            for (int64_t ch = nd[2]; ch < (int64_t)nd[2] + nd[3]; ++ch) {
                 for (int c = 0; c < 3 * C; ++c) Di[c] += t->D[ch * C * 3 + c];
+                for (int c = 0; c < C; ++c) Wi[c] += t->W[ch * C + c];
+            }
         }
     }
     return 0;
@@ -839,12 +857,12 @@ static void add_point(const orc_tree *t, int64_t j, const double x[3], double ep
     for (int k = 0; k < 3; ++k) c[k] = (double)t->ps[3 * j + k];
     if (t->kind == 1) {
         for (int ch = 0; ch < C; ++ch) D[3 * ch] = t->Am[j] * t->mu[j * C + ch];
-        add_term_mono(c, D, C, x, eps, f, g, sf, sg);
+        add_term_mono(c, D, NULL, C, x, eps, f, g, sf, sg);
         return;
     }
     for (int ch = 0; ch < C; ++ch)
         for (int k = 0; k < 3; ++k) D[3 * ch + k] = t->Am[j] * t->mu[j * C + ch] * t->nm[3 * j + k];
-    add_term(c, D, C, x, eps, f, g, sf, sg);
+    add_term(c, D, NULL, C, x, eps, f, g, sf, sg);
 }
 
 static void primal(qstate *st, int64_t i)
@@ -857,9 +875,9 @@ static void primal(qstate *st, int64_t i)
         for (int k = 0; k < 3; ++k) c[k] = (double)t->geom[4 * i + k];
         st->far++;
         if (t->kind == 1)
-            add_term_mono(c, t->D + i * t->C * 3, t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
+            add_term_mono(c, t->D + i * t->C * 3, t->W + i * t->C, t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
         else
-            add_term(c, t->D + i * t->C * 3, t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
+            add_term(c, t->D + i * t->C * 3, t->W + i * t->C, t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
         return;
     }
     if (nd[3] == 0) {
@@ -944,6 +962,7 @@ static void adjoint(astate *st, int64_t i)
         double r = sqrt(r2), kap, lam;
         radial(r, st->eps, &kap, &lam);
         const double *Dt = t->D + i * C * 3;
+        const double *Wt = t->W + i * C;  /* absolute masses: the scales of the node's terms */
         if (t->kind == 1) {
             /* monopole: node accumulator df m(r), dx through the charges */
             if (r2 == 0.0) return;
@@ -952,7 +971,7 @@ static void adjoint(astate *st, int64_t i)
                 st->G[(i * C + ch) * 3] += st->df[ch] * m;
                 st->H[i * C + ch] += fabs(st->df[ch]) * m;
                 w += st->df[ch] * Dt[3 * ch];
-                aw += fabs(st->df[ch] * Dt[3 * ch]);
+                aw += fabs(st->df[ch]) * Wt[ch];
             }
             for (int k = 0; k < 3; ++k) st->dx[k] += w * gv * d[k];
             st->sdx += aw * fabs(gv) * r;
@@ -967,9 +986,7 @@ static void adjoint(astate *st, int64_t i)
                     E[k] += st->df[ch] * Dt[3 * ch + k];
                 }
                 st->H[i * C + ch] += fabs(st->df[ch]) * kap * r;
-                double nD = sqrt(Dt[3 * ch] * Dt[3 * ch] + Dt[3 * ch + 1] * Dt[3 * ch + 1] +
-                                 Dt[3 * ch + 2] * Dt[3 * ch + 2]);
-                st->sdx += fabs(st->df[ch]) * nD * (kap + fabs(lam) * r2);
+                st->sdx += fabs(st->df[ch]) * Wt[ch] * (kap + fabs(lam) * r2);
             }
             double s = E[0] * d[0] + E[1] * d[1] + E[2] * d[2];
             for (int k = 0; k < 3; ++k) st->dx[k] += -kap * E[k] + lam * s * d[k];
@@ -977,14 +994,14 @@ static void adjoint(astate *st, int64_t i)
         if (st->dg) {
             double nu = radial_nu(r, st->eps);
             for (int ch = 0; ch < C; ++ch)
-                grad_cotangent(d, r, kap, lam, nu, Dt + 3 * ch, st->dg + 3 * ch, st->G + (i * C + ch) * 3,
-                               st->dx, st->H + i * C + ch, &st->sdx);
+                grad_cotangent(d, r, kap, lam, nu, Dt + 3 * ch, Wt[ch], st->dg + 3 * ch,
+                               st->G + (i * C + ch) * 3, st->dx, st->H + i * C + ch, &st->sdx);
         }
         if (st->want_eps) {
             double ke, le;
             radial_eps(r, st->eps, &ke, &le);
             for (int ch = 0; ch < C; ++ch)
-                st->deps += term_eps(d, ke, le, Dt + 3 * ch, st->df ? st->df[ch] : 0.0,
+                st->deps += term_eps(d, ke, le, Dt + 3 * ch, Wt[ch], st->df ? st->df[ch] : 0.0,
                                      st->dg ? st->dg + 3 * ch : NULL, &st->sdeps);
         }
         return;
@@ -1032,7 +1049,7 @@ static void adjoint(astate *st, int64_t i)
                     double D[3] = {mu * An[0], mu * An[1], mu * An[2]};
                     double dAn[3] = {0, 0, 0}, sc = 0;
                     /* derivative in the point's dipole, then through D = mu A n */
-                    grad_cotangent(d, r, kap, lam, nu, D, st->dg + 3 * ch, dAn, st->dx, &sc, &st->sdx);
+                    grad_cotangent(d, r, kap, lam, nu, D, -1.0, st->dg + 3 * ch, dAn, st->dx, &sc, &st->sdx);
                     st->P[j * C + ch] += An[0] * dAn[0] + An[1] * dAn[1] + An[2] * dAn[2];
                     st->HP[j * C + ch] += sc * nAn;
                 }
@@ -1063,7 +1080,7 @@ static void adjoint(astate *st, int64_t i)
                 for (int ch = 0; ch < C; ++ch) {
                     double mu = t->mu[j * C + ch];
                     double D[3] = {mu * An[0], mu * An[1], mu * An[2]};
-                    st->deps += term_eps(d, ke, le, D, st->df ? st->df[ch] : 0.0,
+                    st->deps += term_eps(d, ke, le, D, -1.0, st->df ? st->df[ch] : 0.0,
                                          st->dg ? st->dg + 3 * ch : NULL, &st->sdeps);
                 }
             }

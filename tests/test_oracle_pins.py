@@ -492,6 +492,40 @@ def test_far_test_worked_example(orc):
     assert r["f"][1, 0] == pytest.approx(orc.direct(p, n, A, mu, x[1:2], 0.0)["f"][0, 0], rel=1e-12)
 
 
+def test_far_field_scale_is_the_absolute_mass(orc):
+    # The error scale of a far-field node term is kappa r times the node's
+    # absolute dipole mass sum_m |A_m mu_m n_m|, not |D_t|: two points whose
+    # dipoles cancel exactly (D_t = 0) still give the scale of two unit
+    # sources, while the value is 0.  With beta large enough to open the root
+    # the scale is the direct sum's, each leaf being one point.
+    p = np.array([[-0.5, 0, 0], [0.5, 0, 0]], np.float32)
+    n = np.array([[0, 0, 1], [0, 0, 1]], np.float32)
+    A = np.ones(2, np.float32)
+    mu = np.array([[1.0], [-1.0]], np.float32)
+    T = orc.Tree(p, n, A, mu, 1)
+    x = np.array([[0, 3.0, 0]], np.float32)
+    far = T.query(x, 2.0, 0.0)
+    assert far["counts"][0].tolist() == [1, 1, 0, 0]
+    assert far["f"][0, 0] == 0.0
+    d = -x[0].astype(np.float64)
+    r = np.linalg.norm(d)
+    kap = 1.0 / (4 * math.pi * r ** 3)
+    assert far["sf"][0, 0] == pytest.approx(kap * 2.0 * r, rel=1e-12)
+    assert far["sg"][0, 0] == pytest.approx(2.0 * (kap + 3 * kap / r ** 2 * r ** 2), rel=1e-12)
+    opened = T.query(x, 10.0, 0.0)
+    direct = orc.direct(p, n, A, mu, x, 0.0)
+    assert opened["counts"][0].tolist() == [3, 2, 0, 0]
+    assert opened["sf"][0, 0] == pytest.approx(direct["sf"][0, 0], rel=1e-12)
+    # the same for the monopole kernel: charges +1 and -1 cancel, scale 2 m(r)
+    Tm = orc.Tree(p, n, A, mu, 1, kind="monopole")
+    fm = Tm.query(x, 2.0, 0.0)
+    assert fm["f"][0, 0] == 0.0
+    assert fm["sf"][0, 0] == pytest.approx(2.0 / (4 * math.pi * r ** 2), rel=1e-12)
+    # and in the adjoint: the dL/dx scale of the far node uses the mass too
+    a = T.adjoint(x, 2.0, 0.0, np.ones((1, 1), np.float32))
+    assert a["sdx"][0] == pytest.approx(2.0 * (kap + 3 * kap), rel=1e-12)
+
+
 def test_bh_adjoint_through_render_loss_matches_fd(orc):
     # the oracle adjoint, driven by dL/df of the render proxy, against central
     # differences of the same loss: attributes perturbed through linearity,

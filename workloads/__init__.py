@@ -11,7 +11,7 @@ from .scenes import (  # noqa: F401
     sphere_cloud, sphere_queries, sphere_probes, sfm_cloud, camera_rays,
     ray_samples, tile_order, cotangents, appearance_attrs, sfm_camera, sfm_1m, fibonacci_sphere, pixel_ray_samples,
     CONFIGS,
-    SFM_1M_SURFACE, SFM_1M_OUTLIERS, SFM_8M_SURFACE, SFM_8M_OUTLIERS,
+    SFM_1M_SURFACE, SFM_1M_OUTLIERS, SFM_4M_SURFACE, SFM_4M_OUTLIERS, SFM_8M_SURFACE, SFM_8M_OUTLIERS,
 )
 from .batched import (  # noqa: F401
     SFM_8M_RES, PRIMARY_SAMPLES, SHADOW_SAMPLES, RayBatch, make_ray_batch, sfm_8m_cloud, tile_rays,

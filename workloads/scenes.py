@@ -37,12 +37,17 @@ CONFIGS = {
     "sfm-1m": Config("sfm-1m", 1_000_000, 2.0, math.sqrt(2.0) * 0.01, 16, (10, 11, 12)),
     # 4,194,304 points on the unit sphere (precision study, beta in {1,2,4}).
     "sphere-4m": Config("sphere-4m", 4_194_304, 2.0, 0.05, 16, (20, 21)),
+    # 4,194,304-point SfM-like cloud (the 1M scene's distributions), 32,768 ray
+    # samples of its camera (precision study, beta in {1,2,4}).
+    "sfm-4m": Config("sfm-4m", 4_194_304, 2.0, math.sqrt(2.0) * 0.01, 16, (40, 11, 41)),
     # 8,388,608-point SfM-like cloud, 8 uneven views + shadow rays.
     "sfm-8m": Config("sfm-8m", 8_388_608, 2.0, math.sqrt(2.0) * 0.01, 16, (30, 31, 32)),
 }
 
 SFM_1M_SURFACE = 950_000
 SFM_1M_OUTLIERS = 50_000
+SFM_4M_SURFACE = 3_984_589   # 4,194,304 points with 5% outliers
+SFM_4M_OUTLIERS = 209_715
 SFM_8M_SURFACE = 7_969_178
 SFM_8M_OUTLIERS = 419_430
 
