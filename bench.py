@@ -698,6 +698,12 @@ def main():
                     "loads through the caches, so this exceeds HBM peak"},
         "per_query": {"nodes_visited": visits / Q, "far_nodes": nfar / Q, "leaves_opened": leaves / Q,
                       "near_points": near / Q},
+        "paper_timings": {
+            "hardware": "1x NVIDIA RTX 4090 (Sec. 7.1)",
+            "figures": "training 1000 iterations in 3 min, 3000 in 8 min, 20000 in 1 h, 4096 rays per iteration, "
+                       "1024 march + 80 samples per ray (whole training step: MLP, renderer, optimiser)",
+            "note": "the paper gives no kernel-level query rate, so there is no number for this metric to compare "
+                    "against (vs_baseline null)"},
     }
     for st, rr in res.items():
         out[f"{st}_stored"] = {"value": Q / (rr["ms_per_step"] * 1e-3), "ms_per_step": rr["ms_per_step"],
