@@ -492,19 +492,30 @@ def time_appearance(P, dev_in, steps, warmup, K=32):
                     "dL/dx, finalize)"}
 
 
-def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8)):
-    """The ray front-end of one view: dense march for each ray's first
+def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=None):
+    """The ray front-end of one view (or of n_rays random pixels of it, a
+    training batch, kept in tile order): dense march for each ray's first
     crossing, sample placement around it, and the query (values and
-    gradients, all channels) of the placed samples."""
+    gradients, all channels) of the placed samples.  The march runs ray-major
+    with 2 samples per lane; the placed samples of a whole view are queried in
+    the [tile, sample, lane] layout (neighbouring pixels share a wavefront),
+    those of a sparse batch ray-major (one ray's window samples share one),
+    the faster layout for each."""
+    import numpy as np
     import torch
     import workloads
     p, n, A, attrs = workloads.winding_cloud(workloads.SFM_1M_SURFACE, workloads.SFM_1M_OUTLIERS, 10)
     o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(11), RES)
+    if n_rays is not None:
+        sel = np.sort(np.random.default_rng(79).choice(o.shape[0], n_rays, replace=False))
+        o, d, tn, tf = (np.ascontiguousarray(a[sel]) for a in (o, d, tn, tf))
     dev = [torch.from_numpy(a).cuda() for a in (p, n, A, attrs, o, d, tn, tf)]
     tree = P.dps_build(*dev[:4], leaf_size=LEAF)
-    P.dps_set_launch(tree, 4, 4, P.LAUNCH_PERSISTENT_QUERY | P.LAUNCH_PERSISTENT_ADJOINT)
     od, dd, tnd, tfd = dev[4:]
     R, C, S = o.shape[0], attrs.shape[1], sum(counts)
+    sparse = n_rays is not None
+    march_k = 2
+    query_k, tile_layout = (1, False) if sparse else (2, True)
     gen = torch.Generator(device="cuda").manual_seed(78)
     u = torch.rand((R, S), device="cuda", generator=gen)
     hit = torch.empty(R, device="cuda", dtype=torch.int32)
@@ -519,10 +530,13 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8)):
     def step(record):
         e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
         if record: e[0].record()
+        P.dps_set_launch(tree, march_k, 0, 0)
         P.dps_ray_march(tree, od, dd, tnd, tfd, n_march, BETA, EPS, hit_out=hit, values_out=hv)
         if record: e[1].record()
-        P.dps_ray_resample(od, dd, tnd, tfd, n_march, hit, hv, u, counts=counts, tile_layout=True, t_out=t, x_out=x)
+        P.dps_ray_resample(od, dd, tnd, tfd, n_march, hit, hv, u, counts=counts, tile_layout=tile_layout, t_out=t,
+                           x_out=x)
         if record: e[2].record()
+        P.dps_set_launch(tree, query_k, 0, 0)
         P.dps_query(tree, x, BETA, EPS, f_out=f, g_out=g)
         if record: e[3].record()
         if record:
@@ -540,13 +554,16 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8)):
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / steps
     per = {k: sum(a.elapsed_time(b) for a, b in v) / len(v) for k, v in ev.items()}
-    # samples the march evaluated: up to and including j + 1 on a crossing, all n otherwise
+    # samples the march needs: up to and including j + 1 on a crossing, all n
+    # otherwise (the ray-major march also walks chunks past a crossing that
+    # were already running when it was found)
     n_eval = torch.where(hit >= 0, hit.to(torch.int64) + 2, torch.full_like(hit, n_march, dtype=torch.int64))
     total = int(n_eval.sum().item())
     hit_frac = float((hit >= 0).float().mean().item())
     # traversal counts per evaluated sample, from dps_query_counts on the evaluated
-    # samples of every 128th ray (the positions of the march formula)
-    sel = torch.arange(0, R, 128, device="cuda")
+    # samples of every stride-th ray (the positions of the march formula)
+    stride = max(1, R // 2048)
+    sel = torch.arange(0, R, stride, device="cuda")
     ks = torch.arange(n_march, device="cuda", dtype=torch.float32)
     h = (tfd[sel] - tnd[sel]) / n_march
     ts = tnd[sel, None] + (ks[None, :] + 0.5) * h[:, None]
@@ -568,11 +585,16 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8)):
                                    "frac_nonpacked": ach / MI355X_FP32_VECTOR_NONPACKED_TFLOPS,
                                    "flops_per_launch": fl,
                                    "counts_from": f"dps_query_counts over the {m} evaluated samples of every "
-                                                  f"128th ray"}},
-            "workload": f"sfm-1m with unit geometry attributes (winding number), one {RES}x{RES} view in 8x8 "
-                        f"tiles: {n_march}-sample march on channel 0, {'/'.join(map(str, counts))} samples placed "
-                        f"(or {S} uniform), query of the {R * S} placed samples (values + gradients, C={C}), "
-                        f"FP32 storage, persistent k=4",
+                                                  f"{stride}th ray"}},
+            "workload": f"sfm-1m with unit geometry attributes (winding number), "
+                        + (f"{R} random pixels of " if n_rays is not None else "one ")
+                        + f"{RES}x{RES} view in 8x8 tiles"
+                        + (" (ray order kept)" if n_rays is not None else "")
+                        + f": {n_march}-sample march on channel 0 (ray-major, k={march_k}), "
+                        + f"{'/'.join(map(str, counts))} samples placed "
+                        f"(or {S} uniform), query of the {R * S} placed samples (values + gradients, C={C}, "
+                        f"k={query_k}, {'[tile, sample, lane]' if tile_layout else 'ray-major'} order), "
+                        f"FP32 storage",
             "step": "ray march + resample + query of the placed samples"}
 
 
@@ -726,8 +748,11 @@ def main():
     if not args.no_frontend:
         log("[bench] ray front-end (march + resample + query)")
         out["ray_frontend"] = time_frontend(P, max(1, min(args.steps, 3)), 1)
+        out["ray_frontend_batch"] = time_frontend(P, max(1, min(args.steps, 5)), 1, n_rays=4096)
         log(f"[bench] ray front-end: {out['ray_frontend']['ms_per_step']:.1f} ms/view, "
             f"kernels {out['ray_frontend']['kernel_ms']}")
+        log(f"[bench] ray front-end, 4096-ray batch: {out['ray_frontend_batch']['ms_per_step']:.2f} ms, "
+            f"kernels {out['ray_frontend_batch']['kernel_ms']}")
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(np, p, n, A, attrs, x, df, args.cpu_seconds)

@@ -225,7 +225,8 @@ dps_status dps_tree_info(dps_tree t, int64_t *n_nodes, int32_t *depth, int64_t *
  *      the queries, so each XCD's L2 serves one region of a coherently ordered
  *      query set; bit 2 / bit 3: persistent launch -- a grid of resident
  *      workgroups pulls 64*k-query tiles from per-XCD counters (own eighth
- *      first, then the others), balancing uneven batches inside one launch.
+ *      first, then the others), balancing uneven batches inside one launch;
+ *      bit 4: dps_ray_march marches one ray per lane (see dps_ray_march).
  * Host-only; applies to later launches.  The defaults are k = 2 / 4 with the
  * XCD-contiguous order.
  */
@@ -340,10 +341,13 @@ dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing
  *   one rounding per operation; D is channel `channel` of the tree's dipole
  *   sum (beta, eps as dps_query).  Output hit_index [R] int32: the smallest j
  *   with (D(x_j) >= level) != (D(x_{j+1}) >= level), or -1; hit_values [R][2]
- *   float: D(x_j), D(x_{j+1}) (0, 0 without a crossing).  A ray stops at its
- *   first crossing, so its cost is the samples up to it.  Rays are handled 64
- *   at a time (lane = ray): consecutive rays should be neighbouring pixels
- *   (e.g. 8 x 8 tiles) for coherent traversals.  n_samples in [2, 2^20];
+ *   float: D(x_j), D(x_{j+1}) (0, 0 without a crossing).  A wavefront walks
+ *   128 consecutive samples of one ray (64 with query packet 1): all chunks of
+ *   all rays run at once and a chunk past a crossing already found is skipped,
+ *   so any ray order and any batch size keep the GPU busy.  Launch flag bit 4
+ *   of dps_set_launch instead gives each lane one ray, walking its samples in
+ *   order up to its crossing (consecutive rays should then be neighbouring
+ *   pixels, e.g. 8 x 8 tiles); results are identical either way.  n_samples in [2, 2^20];
  *   dipole-kernel trees only; with BF16 storage the channel must be even.
  *   Uses the tree's query packet setting and its tile counters (order calls
  *   on one tree).  Graph-safe.

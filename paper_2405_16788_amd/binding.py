@@ -269,6 +269,7 @@ def dps_export_tree(tree: Tree) -> dict:
 
 
 LAUNCH_XCD_QUERY, LAUNCH_XCD_ADJOINT, LAUNCH_PERSISTENT_QUERY, LAUNCH_PERSISTENT_ADJOINT = 1, 2, 4, 8
+LAUNCH_MARCH_WHOLE = 16  # dps_ray_march: one ray per lane instead of ray-major chunks
 
 
 def dps_set_launch(tree: Tree, query_k: int = 0, adjoint_k: int = 0, flags: int = -1):

@@ -448,7 +448,7 @@ dps_status dps_set_launch(dps_tree t, int32_t query_k, int32_t adjoint_k, int32_
     if (st != DPS_OK) return st;
     auto ok = [](int32_t k) { return k == 0 || k == 1 || k == 2 || k == 4; };
     if (!ok(query_k) || !ok(adjoint_k)) return invalid("dps_set_launch: packet sizes must be 0 (keep), 1, 2 or 4");
-    if (flags < -1 || flags > 15) return invalid("dps_set_launch: flags must be -1 (keep) or a 4-bit mask");
+    if (flags < -1 || flags > 31) return invalid("dps_set_launch: flags must be -1 (keep) or a 5-bit mask");
     if (query_k) t->packet_query = query_k;
     if (adjoint_k) t->packet_adjoint = adjoint_k;
     if (flags >= 0) t->launch_flags = flags;

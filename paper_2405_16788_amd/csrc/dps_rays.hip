@@ -6,12 +6,17 @@
 // March.  Ray r has n samples at t_k = t_n + (k + 1/2) h, h = (t_f - t_n) / n,
 // x_k = o + t_k d (FP32, one rounding per operation).  Its first crossing is
 // the smallest j with (D(x_j) >= level) != (D(x_{j+1}) >= level), D one
-// channel of the dipole sum.  A wavefront owns 64 consecutive rays (lane =
-// ray) and walks their samples in order, K per lane at a time through the
-// packet walk; a lane stops at its first crossing, since the samples after it
-// do not change the result, and the wavefront stops once all its lanes have.
-// A ray therefore costs the samples up to its crossing, all n only when it
-// misses.  Tiles of 64 rays come from the persistent per-XCD queue.
+// channel of the dipole sum.  By default a wavefront takes 64 K consecutive
+// samples of one ray (ray-major: its points lie on a short piece of one line,
+// the most coherent packet a ray offers), all chunks of all rays run at once,
+// each lowers the ray's crossing index with an atomic min, and a chunk that
+// starts past a crossing already found is skipped; a second pass evaluates the
+// field at j and j + 1 (a wavefront per ray).  The alternative (launch flag) gives each lane one ray
+// of 64 consecutive rays and walks its samples in order, the lane stopping at
+// its first crossing; it needs neighbouring pixels in neighbouring lanes and
+// enough rays to fill the GPU, and is kept for comparison.  The two give the
+// same results bit for bit: the walk adds a point's terms in tree order
+// whatever else its packet holds.
 //
 // Placement.  With a crossing, t* = t_j + w (t_{j+1} - t_j),
 // w = (level - D_j) / (D_{j+1} - D_j), and the dense window
@@ -105,6 +110,103 @@ __global__ __launch_bounds__(kThreads) void k_ray_march(
     }
 }
 
+// Ray-major march: a wavefront owns 64 K consecutive
+// samples of one ray (lane l holds samples s0 + l K .. s0 + l K + K - 1), so
+// its points lie on a short piece of one line.  Work item w is chunk
+// c = w / R of ray r = w % R (chunk-major, so early chunks of every ray are
+// dispatched first); chunk c covers the pairs (s, s + 1) with s in
+// [c P, c P + P), P = 64 K - 1, the last lane's last sample being the next
+// chunk's first.  The wavefront lowers hit[r] to its first crossing (atomic
+// min; hit starts at INT32_MAX) and skips its chunk when hit[r] already lies
+// before it.
+template <bool BF16, int K>
+__global__ __launch_bounds__(kThreads) void k_ray_march_along(
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
+    const void *__restrict__ attr, int ms, int as, float b2, KernelParams kp, int c0, uint32_t limit,
+    uint32_t *__restrict__ err, const float *__restrict__ o, const float *__restrict__ d,
+    const float *__restrict__ tnear, const float *__restrict__ tfar, int64_t R, int n, int64_t nitems, float level,
+    int32_t *__restrict__ hit) {
+    constexpr int P = 64 * K - 1;
+    const int lane = lane_id();
+    const int64_t item = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (item >= nitems) return;  // wave-uniform
+    const int64_t c = item / R, r = item - c * R;
+    const int s0 = (int)c * P;
+    if (__hip_atomic_load(&hit[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < s0) return;  // wave-uniform
+    const float ox = o[3 * r], oy = o[3 * r + 1], oz = o[3 * r + 2];
+    const float dx = d[3 * r], dy = d[3 * r + 1], dz = d[3 * r + 2];
+    const float tn = tnear[r], h = (tfar[r] - tn) / (float)n;
+    float px[K], py[K], pz[K], f[K][1], g[K][1][3];
+    uint32_t bits[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int s = s0 + lane * K + i;
+        const float t = march_param(tn, s, h);
+        px[i] = ray_at(ox, t, dx);
+        py[i] = ray_at(oy, t, dy);
+        pz[i] = ray_at(oz, t, dz);
+        bits[i] = s < n ? 1u : 0u;
+        f[i][0] = 0.0f;
+        g[i][0][0] = g[i][0][1] = g[i][0][2] = 0.0f;
+    }
+    dipole_walk<1, BF16, false, K>(px, py, pz, bits, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit, err);
+    const float next = __shfl_down(f[0][0], 1);  // the next lane's first sample
+    int32_t j = INT32_MAX;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const int s = s0 + lane * K + i;
+        const bool pair = s + 1 < n && (lane < 63 || i < K - 1);
+        const float w = i + 1 < K ? f[i + 1 < K ? i + 1 : i][0] : next;
+        if (j == INT32_MAX && pair && ((f[i][0] >= level) != (w >= level))) j = s;
+    }
+    const uint64_t m = __ballot(j != INT32_MAX);
+    if (m != 0 && lane == __ffsll((unsigned long long)m) - 1) atomicMin(&hit[r], j);
+}
+
+// After the ray-major march: the field at samples j and j + 1 of each ray
+// with a crossing, through the same walk at the same FP32 positions (so the
+// same values), and hit = -1, zero values for the others.  A wavefront takes
+// G rays, lanes 2i and 2i + 1 holding samples j and j + 1 of its ray i: the
+// walk of two neighbouring points is as short as that of one, so G = 1 keeps
+// a wavefront's walk short when rays are far apart, and larger G (up to 32)
+// fills the lanes when they are many and neighbouring.
+template <bool BF16>
+__global__ __launch_bounds__(kThreads) void k_ray_hit_values(
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
+    const void *__restrict__ attr, int ms, int as, float b2, KernelParams kp, int c0, uint32_t limit,
+    uint32_t *__restrict__ err, const float *__restrict__ o, const float *__restrict__ d,
+    const float *__restrict__ tnear, const float *__restrict__ tfar, int64_t R, int n, int G,
+    int32_t *__restrict__ hit, float *__restrict__ hv) {
+    const int lane = lane_id();
+    const int64_t w = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int64_t r = w * G + (lane >> 1);
+    const int side = lane & 1;
+    const bool mine = (lane >> 1) < G && r < R;
+    const int32_t j = mine ? hit[r] : INT32_MAX;
+    const bool on = j != INT32_MAX;
+    if (mine && !on) {
+        if (side == 0) hit[r] = -1;
+        hv[2 * r + side] = 0.0f;
+    }
+    if (__ballot(on) == 0) return;  // wave-uniform
+    float px[1] = {0.0f}, py[1] = {0.0f}, pz[1] = {0.0f}, f[1][1] = {{0.0f}}, g[1][1][3] = {{{0.0f, 0.0f, 0.0f}}};
+    uint32_t bits[1] = {on ? 1u : 0u};
+    if (on) {
+        const float tn = tnear[r], h = (tfar[r] - tn) / (float)n;
+        const float t = march_param(tn, j + side, h);
+        px[0] = ray_at(o[3 * r], t, d[3 * r]);
+        py[0] = ray_at(o[3 * r + 1], t, d[3 * r + 1]);
+        pz[0] = ray_at(o[3 * r + 2], t, d[3 * r + 2]);
+    }
+    dipole_walk<1, BF16, false, 1>(px, py, pz, bits, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit, err);
+    if (on) hv[2 * r + side] = f[0][0];
+}
+
+__global__ void k_fill_i32_max(int32_t *__restrict__ a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = INT32_MAX;
+}
+
 __global__ void k_ray_resample(const float *__restrict__ o, const float *__restrict__ d,
                                const float *__restrict__ tnear, const float *__restrict__ tfar, int64_t R,
                                int n_march, const int32_t *__restrict__ hit, const float *__restrict__ hv, float level,
@@ -165,13 +267,43 @@ dps_status march_launch(dps_tree_s *t, const float *o, const float *d, const flo
     return hip_status(hipGetLastError(), "ray march launch");
 }
 
+template <bool BF16, int K>
+dps_status march_along_launch(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf,
+                              int64_t R, int n, float b2, KernelParams kp, int channel, float level, int32_t *hit,
+                              float *hv, hipStream_t s) {
+    const int64_t nitems = cdiv(n - 1, 64 * K - 1) * R;
+    const int64_t wgs = cdiv(nitems, kThreads / 64);
+    if (wgs > INT32_MAX) {
+        set_error("ray march: %lld workgroups exceed the launch grid", (long long)wgs);
+        return DPS_ERR_INVALID;
+    }
+    k_fill_i32_max<<<(unsigned)std::min<int64_t>(cdiv(R, kThreads), 4096), kThreads, 0, s>>>(hit, R);
+    k_ray_march_along<BF16, K><<<(unsigned)wgs, kThreads, 0, s>>>(
+        t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, (uint32_t)t->N, t->err,
+        o, d, tn, tf, R, n, nitems, level, hit);
+    dps_status st = hip_status(hipGetLastError(), "ray-major march launch");
+    if (st != DPS_OK) return st;
+    int G = 1;  // rays per wavefront of the values pass: at least 16384 wavefronts
+    while (G < 32 && R / (2 * G) >= 16384) G *= 2;
+    k_ray_hit_values<BF16><<<(unsigned)cdiv(cdiv(R, G), kThreads / 64), kThreads, 0, s>>>(
+        t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, (uint32_t)t->N, t->err, o,
+        d, tn, tf, R, n, G, hit, hv);
+    return hip_status(hipGetLastError(), "ray hit values launch");
+}
+
 template <bool BF16>
 dps_status march_k(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf, int64_t R, int n,
                    float b2, KernelParams kp, int channel, float level, int32_t *hit, float *hv, hipStream_t s) {
     const int k = t->packet_query;
-    if (k >= 4) return march_launch<BF16, 4>(t, o, d, tn, tf, R, n, b2, kp, channel, level, hit, hv, s);
-    if (k >= 2) return march_launch<BF16, 2>(t, o, d, tn, tf, R, n, b2, kp, channel, level, hit, hv, s);
-    return march_launch<BF16, 1>(t, o, d, tn, tf, R, n, b2, kp, channel, level, hit, hv, s);
+    if (t->launch_flags & kFlagMarchWhole) {
+        if (k >= 4) return march_launch<BF16, 4>(t, o, d, tn, tf, R, n, b2, kp, channel, level, hit, hv, s);
+        if (k >= 2) return march_launch<BF16, 2>(t, o, d, tn, tf, R, n, b2, kp, channel, level, hit, hv, s);
+        return march_launch<BF16, 1>(t, o, d, tn, tf, R, n, b2, kp, channel, level, hit, hv, s);
+    }
+    // ray-major: 2 samples per lane whenever k >= 2 (4 per lane spreads one
+    // wavefront's points over too long a piece of the ray)
+    if (k >= 2) return march_along_launch<BF16, 2>(t, o, d, tn, tf, R, n, b2, kp, channel, level, hit, hv, s);
+    return march_along_launch<BF16, 1>(t, o, d, tn, tf, R, n, b2, kp, channel, level, hit, hv, s);
 }
 
 }  // namespace

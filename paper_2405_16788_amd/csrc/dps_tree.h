@@ -9,6 +9,11 @@
 #include "dps.h"
 #include "dps_internal.h"
 
+// launch flag (dps_set_launch) beyond the traversal bits of dps_internal.h:
+// the ray march gives each lane one ray (64 consecutive rays per wavefront)
+// instead of each wavefront a chunk of one ray's samples
+constexpr int kFlagMarchWhole = 16;
+
 struct dps_tree_s {
     uint64_t magic;
     int device;

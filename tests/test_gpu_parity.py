@@ -248,12 +248,12 @@ def test_set_launch_rejects_bad_shapes(dps):
     for k in (3, 5, -1, 8):
         with pytest.raises(dps.DpsError):
             dps.dps_set_launch(tree, k, 1)
-    for fl in (-2, 16):
+    for fl in (-2, 32):
         with pytest.raises(dps.DpsError):
             dps.dps_set_launch(tree, 1, 1, fl)
     dps.dps_set_launch(tree, 0, 4)
-    dps.dps_set_launch(tree, 2, 0, 15)
-    assert dps.dps_get_launch(tree) == {"query": 2, "adjoint": 4, "flags": 15}
+    dps.dps_set_launch(tree, 2, 0, 31)
+    assert dps.dps_get_launch(tree) == {"query": 2, "adjoint": 4, "flags": 31}
 
 
 @pytest.mark.parametrize("storage", ["fp32", "bf16"])

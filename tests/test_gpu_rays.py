@@ -280,3 +280,30 @@ def test_march_edge_cases(P, orc):
         _check_march(to_host(hit), to_host(hv), ref, TOL_FP32)
         assert np.all(to_host(hit)[::7] == -1)
     P.dps_check(tree)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+@pytest.mark.parametrize("R,n_s", [(1024, 1024), (200, 97), (64, 40), (4096, 1024), (1, 2), (37, 128), (37, 129), (300, 255)])
+def test_march_ray_major_equals_ray_per_lane(P, storage, R, n_s):
+    """The ray-major march (a wavefront per chunk of one ray's samples) and
+    the ray-per-lane march give the same crossing index and values bit for
+    bit, for packets 1, 2 and 4."""
+    import torch
+    p, n, A, mu = workloads.winding_cloud(20000, 1000, 90)
+    o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(91), 64)
+    sel = np.linspace(0, o.shape[0] - 1, R).astype(np.int64)  # spread over the view
+    o, d, tn, tf = o[sel].copy(), d[sel].copy(), tn[sel].copy(), tf[sel].copy()
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16, storage=storage)
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    for k in (1, 2, 4):
+        print(f"[rays] ray-major vs ray per lane: {storage} R={R} n={n_s} k={k}", flush=True)
+        P.dps_set_launch(tree, k, 0, P.LAUNCH_PERSISTENT_QUERY)
+        hs, vs = P.dps_ray_march(tree, od, dd, tnd, tfd, n_s, BETA, EPS)
+        P.dps_set_launch(tree, k, 0, P.LAUNCH_PERSISTENT_QUERY | P.LAUNCH_MARCH_WHOLE)
+        hw, vw = P.dps_ray_march(tree, od, dd, tnd, tfd, n_s, BETA, EPS)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(hs), to_host(hw))
+        assert np.array_equal(to_host(vs), to_host(vw))
+        if R >= 200:
+            assert int((hs >= 0).sum()) > 0
+    P.dps_check(tree)
