@@ -9,15 +9,47 @@
 // The next node's record and moments are fetched before the current node's
 // far-field and leaf work (software pipelining).  Points with bits[i] = 0 take
 // no part; f and g are accumulated into (the caller zeroes them).  The
-// arithmetic per point is that of the point-query kernels, which keep the
-// same loop inline (compiled through this function their register
-// allocation grew from 72 to 92 VGPRs).
+// arithmetic per point is that of the point-query kernels, so the values are
+// the same bit for bit, but the terms are predicated instead of branched per
+// point (see radial_k): with one channel a node carries so little arithmetic
+// that the exec-mask updates of per-point branches made the scalar unit the
+// busier pipe.  The point-query kernels keep their own loop inline (compiled
+// through this function their register allocation grew from 72 to 92 VGPRs).
 #pragma once
 
 #include "dps_trav_common.h"
 
 namespace dps {
 namespace {
+
+// squared distance given to radial() for points that take no part in a term
+constexpr float kHugeR2 = 1.0e30f;
+
+// radial() for the K points of a lane at once, for the points with take[i]:
+// the plain factors 1/(4 pi r^3), 3/(4 pi r^5) without branches, and radial()
+// itself (same values) only when some point of the wavefront lies in the
+// regularised range, which far nodes seldom are.  Returns per point whether
+// the term exists (radial's convention: not for r = 0 without eps).
+template <int K>
+__device__ __forceinline__ void radial_k(const float (&r2)[K], const bool (&take)[K], const KernelParams &kp,
+                                         float (&kap)[K], float (&lam)[K], bool (&on)[K]) {
+    bool slow = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const float x = take[i] ? r2[i] : kHugeR2;
+        const float ir = __builtin_amdgcn_rsqf(x);
+        const float ir2 = ir * ir;
+        kap[i] = kInv4Pi * ir * ir2;
+        lam[i] = 3.0f * kap[i] * ir2;
+        on[i] = take[i] && (kp.eps != 0.0f || x > 0.0f);
+        slow |= take[i] && kp.eps > 0.0f && x * kp.ieps2 < kFarT2;
+    }
+    if (__ballot(slow) != 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (take[i]) radial(r2[i], kp, kap[i], lam[i]);
+    }
+}
 
 template <int CB, bool BF16, bool GRAD, int K>
 __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&py)[K], const float (&pz)[K],
@@ -58,22 +90,29 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
         float Dn[3 * CB];
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
         if (any_far) {
+            // predicated rather than branched per point: a lane's terms are
+            // computed under the wavefront's mask either way, and selects
+            // spare the scalar unit the exec-mask updates of a branch.  A
+            // point that is not far sees a huge distance, so it takes no
+            // part in the regularised branch of radial().
+            float kap[K], lam[K];
+            bool on[K];
+            radial_k<K>(s, far, kp, kap, lam, on);
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                if (far[i]) {
-                    float kap, lam;
-                    radial(s[i], kp, kap, lam);
-                    const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
+                const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
 #pragma unroll
-                    for (int c = 0; c < CB; ++c) {
-                        const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
-                        f[i][c] = fmaf(kap, sd, f[i][c]);
-                        if (GRAD) {
-                            const float ls = lam * sd;
-                            g[i][c][0] = fmaf(-kap, D[3 * c], fmaf(ls, dx, g[i][c][0]));
-                            g[i][c][1] = fmaf(-kap, D[3 * c + 1], fmaf(ls, dy, g[i][c][1]));
-                            g[i][c][2] = fmaf(-kap, D[3 * c + 2], fmaf(ls, dz, g[i][c][2]));
-                        }
+                for (int c = 0; c < CB; ++c) {
+                    const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
+                    f[i][c] = far[i] ? fmaf(kap[i], sd, f[i][c]) : f[i][c];
+                    if (GRAD) {
+                        const float ls = lam[i] * sd;
+                        const float g0 = fmaf(-kap[i], D[3 * c], fmaf(ls, dx, g[i][c][0]));
+                        const float g1 = fmaf(-kap[i], D[3 * c + 1], fmaf(ls, dy, g[i][c][1]));
+                        const float g2 = fmaf(-kap[i], D[3 * c + 2], fmaf(ls, dz, g[i][c][2]));
+                        g[i][c][0] = far[i] ? g0 : g[i][c][0];
+                        g[i][c][1] = far[i] ? g1 : g[i][c][1];
+                        g[i][c][2] = far[i] ? g2 : g[i][c][2];
                     }
                 }
             }
@@ -89,28 +128,34 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
                     const PointRec pr = pts[j];
                     float mu[CB];
                     load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                    float dx[K], dy[K], dz[K], r2[K], kap[K], lam[K];
+                    bool on[K];
 #pragma unroll
                     for (int i = 0; i < K; ++i) {
-                        if (open[i]) {
-                            const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
-                            const float r2 = dx * dx + dy * dy + dz * dz;
-                            float kap, lam;
-                            if (radial(r2, kp, kap, lam)) {
-                                const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
-                                const float ks = kap * sa;
-                                const float ls = lam * sa;
-                                const float G0 = fmaf(ls, dx, -kap * pr.anx);
-                                const float G1 = fmaf(ls, dy, -kap * pr.any);
-                                const float G2 = fmaf(ls, dz, -kap * pr.anz);
+                        dx[i] = pr.x - px[i];
+                        dy[i] = pr.y - py[i];
+                        dz[i] = pr.z - pz[i];
+                        r2[i] = dx[i] * dx[i] + dy[i] * dy[i] + dz[i] * dz[i];
+                    }
+                    radial_k<K>(r2, open, kp, kap, lam, on);
 #pragma unroll
-                                for (int c = 0; c < CB; ++c) {
-                                    f[i][c] = fmaf(mu[c], ks, f[i][c]);
-                                    if (GRAD) {
-                                        g[i][c][0] = fmaf(mu[c], G0, g[i][c][0]);
-                                        g[i][c][1] = fmaf(mu[c], G1, g[i][c][1]);
-                                        g[i][c][2] = fmaf(mu[c], G2, g[i][c][2]);
-                                    }
-                                }
+                    for (int i = 0; i < K; ++i) {  // predicated as the far terms
+                        const float sa = pr.anx * dx[i] + pr.any * dy[i] + pr.anz * dz[i];
+                        const float ks = kap[i] * sa;
+                        const float ls = lam[i] * sa;
+                        const float G0 = fmaf(ls, dx[i], -kap[i] * pr.anx);
+                        const float G1 = fmaf(ls, dy[i], -kap[i] * pr.any);
+                        const float G2 = fmaf(ls, dz[i], -kap[i] * pr.anz);
+#pragma unroll
+                        for (int c = 0; c < CB; ++c) {
+                            f[i][c] = on[i] ? fmaf(mu[c], ks, f[i][c]) : f[i][c];
+                            if (GRAD) {
+                                const float g0 = fmaf(mu[c], G0, g[i][c][0]);
+                                const float g1 = fmaf(mu[c], G1, g[i][c][1]);
+                                const float g2 = fmaf(mu[c], G2, g[i][c][2]);
+                                g[i][c][0] = on[i] ? g0 : g[i][c][0];
+                                g[i][c][1] = on[i] ? g1 : g[i][c][1];
+                                g[i][c][2] = on[i] ? g2 : g[i][c][2];
                             }
                         }
                     }
