@@ -111,7 +111,7 @@ MI355X_HBM_TBS = 8.0
 # the HBM byte counters committed under profiles/ are used only while these
 # are unchanged
 KERNEL_SOURCES = ("paper_2405_16788_amd/csrc/dps_traverse.hip", "paper_2405_16788_amd/csrc/dps_trav_common.h",
-                  "paper_2405_16788_amd/csrc/dps_internal.h")
+                  "paper_2405_16788_amd/csrc/dps_internal.h", "paper_2405_16788_amd/csrc/dps_walk.h")
 COUNTER_SUMMARY = "profiles/sfm1m_fp32_hbm_counters.md"
 
 
