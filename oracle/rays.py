@@ -2,12 +2,12 @@
 march that finds each ray's first crossing of the geometry level set, and the
 sample placement that follows it (Sec. 7.1, ray sampling).
 
-The paper places 1024 samples between the near and far limits of a camera
-ray, finds the first interval where the geometry field f = 1/2 - D_0 changes
-sign, and then places 24 samples between the near limit and the crossing, 48
-around it and 8 between it and the far limit; a ray without a crossing gets
-80 samples spread uniformly.  It does not fix the positions inside those
-ranges; the readings taken here are:
+The paper marches 1024 samples from the near to the far limit of a camera
+ray, takes the first interval over which the geometry field f = 1/2 - D_0
+changes sign, and then puts 24 samples from the near limit up to that
+crossing, 48 close to it and 8 from it to the far limit; a ray without a
+crossing gets 80 evenly spread samples.  Where the samples sit inside those
+ranges is left open; the readings taken here are:
 
   march positions  t_k = t_n + (k + 1/2) h, h = (t_f - t_n) / n, k < n (the
                    midpoints of n equal intervals), x_k = o + t_k d;
