@@ -9,9 +9,12 @@
 // The next node's record and moments are fetched before the current node's
 // far-field and leaf work (software pipelining).  Points with bits[i] = 0 take
 // no part; f and g are accumulated into (the caller zeroes them).  The
-// arithmetic per point is that of the point-query kernels, so the values are
-// the same bit for bit, but the terms are predicated instead of branched per
-// point (see radial_k): with one channel a node carries so little arithmetic
+// arithmetic per point is that of the point-query kernels, with its dot
+// products written as explicit fused chains: left to contraction, the
+// compiler may fuse a different product of a sum of products in each kernel,
+// and every caller of this walk (marches, the values pass, one-channel value
+// queries) is meant to produce the same bits.  The terms are predicated
+// instead of branched per point (see radial_k): with one channel a node carries so little arithmetic
 // that the exec-mask updates of per-point branches made the scalar unit the
 // busier pipe.  The point-query kernels keep their own loop inline (compiled
 // through this function their register allocation grew from 72 to 92 VGPRs).
@@ -103,7 +106,7 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
                 const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
 #pragma unroll
                 for (int c = 0; c < CB; ++c) {
-                    const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
+                    const float sd = fmaf(D[3 * c + 2], dz, fmaf(D[3 * c + 1], dy, D[3 * c] * dx));
                     f[i][c] = far[i] ? fmaf(kap[i], sd, f[i][c]) : f[i][c];
                     if (GRAD) {
                         const float ls = lam[i] * sd;
@@ -135,12 +138,12 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
                         dx[i] = pr.x - px[i];
                         dy[i] = pr.y - py[i];
                         dz[i] = pr.z - pz[i];
-                        r2[i] = dx[i] * dx[i] + dy[i] * dy[i] + dz[i] * dz[i];
+                        r2[i] = fmaf(dz[i], dz[i], fmaf(dy[i], dy[i], dx[i] * dx[i]));
                     }
                     radial_k<K>(r2, open, kp, kap, lam, on);
 #pragma unroll
                     for (int i = 0; i < K; ++i) {  // predicated as the far terms
-                        const float sa = pr.anx * dx[i] + pr.any * dy[i] + pr.anz * dz[i];
+                        const float sa = fmaf(pr.anz, dz[i], fmaf(pr.any, dy[i], pr.anx * dx[i]));
                         const float ks = kap[i] * sa;
                         const float ls = lam[i] * sa;
                         const float G0 = fmaf(ls, dx[i], -kap[i] * pr.anx);

@@ -287,3 +287,31 @@ def test_channel_subsets(dps, orc, storage, c_begin, nc):
     for cb, k in ((-1, 1), (0, 0), (4, 2), (5, 1)):
         with pytest.raises(dps.DpsError):
             dps.dps_query_channels(tree, xd, 2.0, 0.05, cb, k)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+@pytest.mark.parametrize("eps", [0.05, 0.0])
+def test_values_only_one_channel(dps, orc, storage, eps):
+    """One channel without gradients runs the predicated walk: its values
+    match the oracle and the values of the query with gradients to FP32
+    rounding (the two kernels may fuse different products of a dot product),
+    for packets 1, 2 and 4, with queries exactly at points (no term for a
+    coincident point without regularisation)."""
+    p, n, A, mu = CLOUDS["sphere-8k"]()
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16, storage)
+    on, ins, out = workloads.sphere_probes(256, 3)
+    x = np.concatenate([workloads.sphere_queries(3001, 44), on, ins, out, p[:64]])
+    (xd,) = to_dev(x)
+    ref = T.query(x, 2.0, eps)
+    tol = TOL_BF16 if storage == "bf16" else TOL_FP32
+    for k in (1, 2, 4):
+        for flags in (0, dps.LAUNCH_PERSISTENT_QUERY):
+            dps.dps_set_launch(tree, k, 0, flags)
+            fv, gv = dps.dps_query_channels(tree, xd, 2.0, eps, 0, 1, grad=False)
+            assert gv is None
+            fg, _ = dps.dps_query_channels(tree, xd, 2.0, eps, 0, 1, grad=True)
+            fv, fg = to_host(fv), to_host(fg)
+            assert np.all(np.isfinite(fv))
+            assert norm_err(fv, ref["f"][:, :1], ref["sf"][:, :1]) <= tol, (k, flags)
+            assert norm_err(fv, fg, ref["sf"][:, :1]) <= 1e-6, (k, flags)
+    dps.dps_check(tree)
