@@ -467,15 +467,16 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                     radial(s[i], kp, kap, lam);
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
                     float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
+                    // kappa (p_t - x_q) once, then one FMA per channel and axis
+                    const float kx = kap * dx, ky = kap * dy, kz = kap * dz;
 #pragma unroll
                     for (int c = 0; c < CB; ++c) {
                         E0 += w[i][c] * D[3 * c];
                         E1 += w[i][c] * D[3 * c + 1];
                         E2 += w[i][c] * D[3 * c + 2];
-                        const float wk = w[i][c] * kap;
-                        acc[3 * c] += wk * dx;
-                        acc[3 * c + 1] += wk * dy;
-                        acc[3 * c + 2] += wk * dz;
+                        acc[3 * c] = fmaf(w[i][c], kx, acc[3 * c]);
+                        acc[3 * c + 1] = fmaf(w[i][c], ky, acc[3 * c + 1]);
+                        acc[3 * c + 2] = fmaf(w[i][c], kz, acc[3 * c + 2]);
                     }
                     const float les = lam * (E0 * dx + E1 * dy + E2 * dz);
                     ax[i] = fmaf(-kap, E0, fmaf(les, dx, ax[i]));
