@@ -80,7 +80,8 @@ class DipoleSum(torch.autograd.Function):
             # rows past the device count are never written by the kernels
             f = torch.zeros((Q, n), device=x_c.device, dtype=torch.float32)
             g = torch.zeros((Q, n, 3), device=x_c.device, dtype=torch.float32) if want_grad else None
-            B.dps_query_channels(tree, x_c, beta, eps_v, c_begin, n, f_out=f, g_out=g, q_count=q_count)
+            B.dps_query_channels(tree, x_c, beta, eps_v, c_begin, n, grad=want_grad, f_out=f, g_out=g,
+                                 q_count=q_count)
         ctx.save_for_backward(x_c, attrs_c)
         ctx.tree, ctx.beta, ctx.eps, ctx.opts, ctx.full = tree, float(beta), eps_v, opts, full
         ctx.n = f.shape[1]
