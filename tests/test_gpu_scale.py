@@ -1,8 +1,9 @@
 """GPU parity at the benchmark's full size (sfm-1m: 1,000,000 points,
 512x512 rays x 128 samples = 33,554,432 queries), in the launch
-configuration the benchmark times: the whole query set in one call, outputs
-compared on a seeded sample that the oracle evaluates one by one, plus
-properties that hold at any size."""
+configurations the benchmark times: the whole query set in one call, with
+the library's default launch and with the autotuned one the benchmark uses,
+outputs compared on a seeded sample that the oracle evaluates one by one,
+plus properties that hold at any size."""
 import math
 
 import numpy as np
@@ -30,12 +31,26 @@ def scene(orc):
     return P, T, (p, n, A, mu, x), dev
 
 
+def _launch(P, tree, d, launch):
+    """'default' keeps the library's launch; 'tuned' runs the autotuner on the
+    full query set as the benchmark does (no cache) and keeps its choice."""
+    import torch
+    if launch == "tuned":
+        from paper_2405_16788_amd import autotune
+        df = torch.ones((d["x"].shape[0], d["mu"].shape[1]), device="cuda")
+        tuned = autotune.tune(tree, d["x"], df, BETA, EPS, cache="")
+        print(f"[scale] autotuned launch {tuned['query']},{tuned['adjoint']},{tuned['flags']}", flush=True)
+    return P.dps_get_launch(tree)
+
+
+@pytest.mark.parametrize("launch", ["default", "tuned"])
 @pytest.mark.parametrize("storage", ["fp32", "bf16"])
-def test_sfm_1m_full_query(scene, storage):
+def test_sfm_1m_full_query(scene, storage, launch):
     import torch
     P, T, (p, n, A, mu, x), d = scene
-    print(f"[scale] build M={p.shape[0]} storage={storage}", flush=True)
+    print(f"[scale] build M={p.shape[0]} storage={storage} launch={launch}", flush=True)
     tree = P.dps_build(d["p"], d["n"], d["A"], d["mu"], leaf_size=16, storage=storage)
+    _launch(P, tree, d, launch)
     ex = P.dps_export_tree(tree)
     oe = T.export()
     assert np.array_equal(to_host(ex["codes"]).view(np.uint64), oe["codes"])
@@ -62,10 +77,12 @@ def test_sfm_1m_full_query(scene, storage):
     P.dps_destroy(tree)
 
 
-def test_sfm_1m_adjoint(scene):
+@pytest.mark.parametrize("launch", ["default", "tuned"])
+def test_sfm_1m_adjoint(scene, launch):
     import torch
     P, T, (p, n, A, mu, x), d = scene
     tree = P.dps_build(d["p"], d["n"], d["A"], d["mu"], leaf_size=16)
+    print(f"[scale] adjoint launch {_launch(P, tree, d, launch)}", flush=True)
     Q = x.shape[0]
     df = workloads.cotangents(Q, mu.shape[1], 17)
     (dfd,) = to_dev(df)
