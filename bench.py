@@ -524,11 +524,18 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=Non
     x = torch.empty((R * S, 3), device="cuda")
     f = torch.empty((R * S, C), device="cuda")
     g = torch.empty((R * S, C, 3), device="cuda")
-    names = ["march", "resample", "query"]
+    # a training batch also runs the backward of its placed samples: the
+    # two-stage adjoint with N(0,1) cotangents (seed 80) standing in for the
+    # loss gradient, dL/dattrs in caller order and dL/dx per sample
+    if sparse:
+        df = torch.randn((R * S, C), device="cuda", generator=torch.Generator(device="cuda").manual_seed(80))
+        dx = torch.empty((R * S, 3), device="cuda")
+        dattrs = torch.empty((p.shape[0], C), device="cuda")
+    names = ["march", "resample", "query"] + (["adjoint"] if sparse else [])
     ev = {k: [] for k in names}
 
     def step(record):
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] if record else None
         if record: e[0].record()
         P.dps_set_launch(tree, march_k, 0, 0)
         P.dps_ray_march(tree, od, dd, tnd, tfd, n_march, BETA, EPS, hit_out=hit, values_out=hv)
@@ -539,6 +546,12 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=Non
         P.dps_set_launch(tree, query_k, 0, 0)
         P.dps_query(tree, x, BETA, EPS, f_out=f, g_out=g)
         if record: e[3].record()
+        if sparse:
+            P.dps_set_launch(tree, 0, 1, 0)
+            P.dps_adjoint_zero(tree)
+            P.dps_adjoint_accumulate(tree, x, BETA, EPS, df, dx_out=dx)
+            P.dps_adjoint_finalize(tree, dattrs_out=dattrs)
+            if record: e[4].record()
         if record:
             for i, k in enumerate(names):
                 ev[k].append((e[i], e[i + 1]))
@@ -593,9 +606,11 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=Non
                         + f": {n_march}-sample march on channel 0 (ray-major, k={march_k}), "
                         + f"{'/'.join(map(str, counts))} samples placed "
                         f"(or {S} uniform), query of the {R * S} placed samples (values + gradients, C={C}, "
-                        f"k={query_k}, {'[tile, sample, lane]' if tile_layout else 'ray-major'} order), "
-                        f"FP32 storage",
-            "step": "ray march + resample + query of the placed samples"}
+                        f"k={query_k}, {'[tile, sample, lane]' if tile_layout else 'ray-major'} order)"
+                        + (", adjoint of the placed samples (N(0,1) cotangents, k=1)" if sparse else "")
+                        + ", FP32 storage",
+            "step": "ray march + resample + query of the placed samples"
+                    + (" + their adjoint (zero, accumulate, finalize)" if sparse else "")}
 
 
 def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
