@@ -68,9 +68,10 @@
  *
  * Precision: everything is FP64 except two things that the GPU must decide
  * bit-identically: the far test, evaluated in FP32 as
- * s = ((x-cx)^2 + (y-cy)^2) + (z-cz)^2 > (beta*beta) * r2 with no fused
- * multiply-add, and the node centroid / squared radius, which are FP64 sums
- * rounded once to FP32.  Build with -ffp-contract=off.
+ * s = fma(dz, dz, fma(dy, dy, dx*dx)) > (beta*beta) * r2 (d = c - x; the two
+ * fused multiply-adds explicit, no other contraction), and the node centroid
+ * / squared radius, which are FP64 sums rounded once to FP32 (the radius the
+ * largest such s over the node's points).  Build with -ffp-contract=off.
  */
 #include <math.h>
 #include <stdint.h>
@@ -604,14 +605,15 @@ static int cmp_keyidx(const void *a, const void *b)
     return (x->idx > y->idx) - (x->idx < y->idx);
 }
 
-/* FP32 squared distance with a fixed operation order and no contraction. */
+/* FP32 squared distance as a fixed sequence of correctly rounded operations:
+   three differences, dx*dx, then two fused multiply-adds (fmaf rounds once),
+   no other contraction.  The far decisions and node radii depend on it. */
 static float dist2_f32(const float a[3], const float b[3])
 {
     float dx = a[0] - b[0];
     float dy = a[1] - b[1];
     float dz = a[2] - b[2];
-    float sxy = dx * dx + dy * dy;
-    return sxy + dz * dz;
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
 void orc_tree_free(orc_tree *t)

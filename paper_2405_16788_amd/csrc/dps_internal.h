@@ -67,15 +67,17 @@ __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w 
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 // ---------------------------------------------------------------------------
-// decision-critical FP32 arithmetic: fixed order, no contraction
+// decision-critical FP32 arithmetic: a fixed sequence of correctly rounded
+// operations (explicit fused multiply-adds, no other contraction), so that
+// the far decisions and node radii match any other IEEE evaluation of the
+// same sequence bit for bit
 // ---------------------------------------------------------------------------
 __host__ __device__ inline float dist2_rn(float ax, float ay, float az, float bx, float by, float bz) {
 #pragma clang fp contract(off)
     float dx = ax - bx;
     float dy = ay - by;
     float dz = az - bz;
-    float sxy = dx * dx + dy * dy;
-    return sxy + dz * dz;
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
 __host__ __device__ inline float mul_rn(float a, float b) {
