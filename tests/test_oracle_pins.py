@@ -885,3 +885,53 @@ def test_monopole_barnes_hut(orc):
     # node charges are point sums; gradient cotangents are not defined here
     with pytest.raises(ValueError):
         T.adjoint(x, 2.0, eps, df, dg=np.zeros((400, mu.shape[1], 3), np.float32))
+
+
+def _f32_nearest(fr):
+    """The float32 nearest to the rational fr, ties to even (exact)."""
+    from fractions import Fraction
+    c = np.float32(float(fr))
+    best = None
+    for cand in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        key = (abs(Fraction(float(cand)) - fr), int(np.float32(cand).view(np.uint32)) & 1)
+        if best is None or key < best[0]:
+            best = (key, np.float32(cand))
+    return best[1]
+
+
+def _dist2_fused(a, b):
+    """The far-test squared distance of Algorithm 1 as read here (R31): FP32
+    differences, dx*dx rounded, then two fused multiply-adds each rounded
+    once, evaluated in exact rational arithmetic."""
+    from fractions import Fraction
+    d = [np.float32(np.float32(a[k]) - np.float32(b[k])) for k in range(3)]
+    t = np.float32(d[0] * d[0])
+    u = _f32_nearest(Fraction(float(d[1])) ** 2 + Fraction(float(t)))
+    return _f32_nearest(Fraction(float(d[2])) ** 2 + Fraction(float(u)))
+
+
+def test_node_radius_is_the_fused_squared_distance(orc):
+    """R31: a node's squared radius is the largest far-test squared distance
+    between its centroid and its points.  Every exported radius equals the
+    exact-rational evaluation of the fused sequence bit for bit, and an
+    unfused evaluation of the same distances differs for some nodes, so the
+    pin tells the two readings apart."""
+    rng = np.random.default_rng(61)
+    p = rng.uniform(-1, 1, (2000, 3)).astype(np.float32)
+    n = rng.standard_normal((2000, 3)).astype(np.float32)
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    A = np.full(2000, 1e-3, np.float32)
+    mu = np.ones((2000, 1), np.float32)
+    T = orc.Tree(p, n, A, mu, 16)
+    e = T.export()
+    ps = p[e["perm"].astype(np.int64)]
+    differs = 0
+    for i in range(e["nodes"].shape[0]):
+        b, c = int(e["nodes"][i, 4]), int(e["nodes"][i, 5])
+        ctr = e["geom"][i, :3]
+        fused = max(_dist2_fused(ps[j], ctr) for j in range(b, b + c))
+        assert fused.view(np.uint32) == e["geom"][i, 3].view(np.uint32), i
+        d = ps[b:b + c] - ctr
+        unfused = np.max((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2])
+        differs += int(unfused.view(np.uint32) != fused.view(np.uint32))
+    assert differs > 0
