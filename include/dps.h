@@ -347,10 +347,14 @@ dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing
  *   so any ray order and any batch size keep the GPU busy.  Launch flag bit 4
  *   of dps_set_launch instead gives each lane one ray, walking its samples in
  *   order up to its crossing (consecutive rays should then be neighbouring
- *   pixels, e.g. 8 x 8 tiles); results are identical either way.  n_samples in [2, 2^20];
- *   dipole-kernel trees only; with BF16 storage the channel must be even.
- *   Uses the tree's query packet setting and its tile counters (order calls
- *   on one tree).  Graph-safe.
+ *   pixels, e.g. 8 x 8 tiles); results are identical either way.  The
+ *   ray-major march uses hit_index itself as its working buffer (an atomic
+ *   minimum over chunks), so no memory beyond the caller's is needed.
+ *   n_samples in [2, 2^20]; dipole-kernel trees only; with BF16 storage the
+ *   channel must be even.  R = 0 is a no-op.  DPS_ERR_INVALID (nothing
+ *   launched) for a bad argument or NULL array, or for more rays x samples
+ *   than one launch grid holds.  Uses the tree's query packet setting and
+ *   its tile counters (order calls on one tree).  Graph-safe.
  * dps_ray_resample -- no tree.  With a crossing (hit_index >= 0):
  *   t* = t_j + w (t_{j+1} - t_j), w = (level - D_j) / (D_{j+1} - D_j), window
  *   [a, b] = [max(tnear, t* - window h), min(tfar, t* + window h)]
