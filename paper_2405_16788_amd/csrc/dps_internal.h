@@ -48,10 +48,29 @@ constexpr float kInv4Pi = 0.0795774715459476679f;
 constexpr float k2SqrtPi = 1.12837916709551257f;
 constexpr float k4SqrtPi = 2.25675833419102515f;
 
-// Radial-factor branch points, in t^2 = (r/eps)^2: Taylor series below 0.5^2,
-// erf/exp in between, rho = 1 and psi = 3 above 4.5^2 (rho(4.5) = 1 - 8e-9).
+// Radial-factor branch points, in t^2 = (r/eps)^2: rho = 1 and psi = 3 above
+// 4.5^2 (rho(4.5) = 1 - 8e-9).  radial(): Taylor series below 1, the erfcx
+// form in between.  radial3() and the eps derivatives: series below 0.5^2,
+// erf / exp in between.
 constexpr float kSeriesT2 = 0.25f;
+constexpr float kSeriesWideT2 = 1.0f;
 constexpr float kFarT2 = 20.25f;
+
+// erfcx(t) = exp(t^2) erfc(t) on [1, 4.5] as sum_k kErfcx[k] s^k,
+// s = 1/(1 + t/2): a least-squares fit with relative weighting
+// (csrc/gen_erfcx.py; 1.1e-9 relative in FP64, about 3e-7 evaluated in FP32)
+constexpr float kErfcx0 = -0.0001324968907283619f;
+constexpr float kErfcx1 = 0.284586638212204f;
+constexpr float kErfcx2 = 0.26176685094833374f;
+constexpr float kErfcx3 = 0.3405025601387024f;
+constexpr float kErfcx4 = -0.0883762538433075f;
+constexpr float kErfcx5 = 0.54436856508255f;
+constexpr float kErfcx6 = -0.4582943618297577f;
+constexpr float kErfcx7 = 0.1156064048409462f;
+// log2(e) as a float and the remainder of its rounding; ln 2
+constexpr float kLog2e = 1.44269502162933349609f;
+constexpr float kLog2eLo = 1.92596298909109e-08f;
+constexpr float kLn2 = 0.693147180559945309f;
 
 // ---------------------------------------------------------------------------
 // bf16 storage (round to nearest even; inputs are finite)
@@ -129,16 +148,47 @@ __host__ inline KernelParams make_kernel_params(float eps) {
     return kp;
 }
 
+// rho/t^3 and psi/t^5, ten terms: 2e-7 relative in FP32 up to t^2 = 1
 __device__ __forceinline__ float series_rho_t3(float u) {  // u = t^2
     constexpr float c = 2.25675833419102515f;
     return c * (1.0f / 3.0f + u * (-1.0f / 5.0f + u * (1.0f / 14.0f + u * (-1.0f / 54.0f +
-           u * (1.0f / 264.0f + u * (-1.0f / 1560.0f + u * (1.0f / 10800.0f + u * (-1.0f / 85680.0f))))))));
+           u * (1.0f / 264.0f + u * (-1.0f / 1560.0f + u * (1.0f / 10800.0f + u * (-1.0f / 85680.0f +
+           u * (1.0f / 766080.0f + u * (-1.0f / 7620480.0f))))))))));
 }
 
 __device__ __forceinline__ float series_psi_t5(float u) {  // u = t^2
     constexpr float c = 4.51351666838205030f;
     return c * (1.0f / 5.0f + u * (-1.0f / 7.0f + u * (1.0f / 18.0f + u * (-1.0f / 66.0f +
-           u * (1.0f / 312.0f + u * (-1.0f / 1800.0f + u * (1.0f / 12240.0f + u * (-1.0f / 95760.0f))))))));
+           u * (1.0f / 312.0f + u * (-1.0f / 1800.0f + u * (1.0f / 12240.0f + u * (-1.0f / 95760.0f +
+           u * (1.0f / 846720.0f + u * (-1.0f / 8346240.0f))))))))));
+}
+
+// exp(-u) for u in [1, 20.25] through the hardware 2^x (1 ulp): -u log2(e)
+// as its rounded product hi and the residual lo (an FMA, plus the rounding
+// of the constant), then 2^hi (1 + lo ln 2).  No range reduction is needed
+// on this interval.
+__device__ __forceinline__ float exp_neg(float u) {
+    const float hi = -u * kLog2e;
+    const float lo = fmaf(-u, kLog2e, -hi) - u * kLog2eLo;
+    const float e = __builtin_amdgcn_exp2f(hi);
+    return fmaf(e, lo * kLn2, e);
+}
+
+// rho and psi for t^2 = u in [1, 20.25]: with e = exp(-t^2),
+// 1 - rho = erfc(t) + (2/sqrt pi) t e = e (erfcx(t) + (2/sqrt pi) t), so one
+// exponential serves both terms and rho has no cancellation worse than 1.4x
+__device__ __forceinline__ void rho_psi_erfcx(float u, float t, float &rho, float &psi) {
+    const float e = exp_neg(u);
+    const float s = __builtin_amdgcn_rcpf(fmaf(0.5f, t, 1.0f));
+    float r = fmaf(kErfcx7, s, kErfcx6);
+    r = fmaf(r, s, kErfcx5);
+    r = fmaf(r, s, kErfcx4);
+    r = fmaf(r, s, kErfcx3);
+    r = fmaf(r, s, kErfcx2);
+    r = fmaf(r, s, kErfcx1);
+    r = fmaf(r, s, kErfcx0);
+    rho = fmaf(-e, fmaf(k2SqrtPi, t, r), 1.0f);
+    psi = fmaf(3.0f, rho, -(k4SqrtPi * (t * u) * e));
 }
 
 __device__ __forceinline__ float series_chi_t7(float u) {  // u = t^2
@@ -150,8 +200,8 @@ __device__ __forceinline__ float series_chi_t7(float u) {  // u = t^2
 // r2 = |d|^2.  Returns false when the term is excluded (r = 0 with eps = 0).
 // Common case first, without branches: rho = 1, psi = 3 (t >= 4.5 or eps = 0),
 // with the hardware reciprocal square root (1 ulp).  Inside the regularised
-// zone t < 4.5 (a minority of interactions) the factors are recomputed:
-// series below t = 0.5 (finite at r = 0), erf / exp above.
+// zone t < 4.5 (near points and the nearest far nodes) the factors are
+// recomputed: series below t = 1 (finite at r = 0), the erfcx form above.
 __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &kappa, float &lambda) {
     if (kp.eps == 0.0f && !(r2 > 0.0f)) return false;
     const float ir = __builtin_amdgcn_rsqf(r2);
@@ -161,14 +211,12 @@ __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &
     if (kp.eps > 0.0f) {
         const float u = r2 * kp.ieps2;
         if (u < kFarT2) {
-            if (u < kSeriesT2) {
+            if (u < kSeriesWideT2) {
                 kappa = kp.k3 * series_rho_t3(u);
                 lambda = kp.k5 * series_psi_t5(u);
             } else {
-                const float t = r2 * ir * kp.ieps;
-                const float e = expf(-u);
-                const float rho = erff(t) - k2SqrtPi * t * e;
-                const float psi = 3.0f * rho - k4SqrtPi * t * u * e;
+                float rho, psi;
+                rho_psi_erfcx(u, r2 * ir * kp.ieps, rho, psi);
                 kappa = kappa * rho;
                 lambda = kInv4Pi * ir * ir2 * ir2 * psi;
             }
