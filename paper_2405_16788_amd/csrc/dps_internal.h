@@ -49,10 +49,8 @@ constexpr float k2SqrtPi = 1.12837916709551257f;
 constexpr float k4SqrtPi = 2.25675833419102515f;
 
 // Radial-factor branch points, in t^2 = (r/eps)^2: rho = 1 and psi = 3 above
-// 4.5^2 (rho(4.5) = 1 - 8e-9).  radial(): Taylor series below 1, the erfcx
-// form in between.  radial3() and the eps derivatives: series below 0.5^2,
-// erf / exp in between.
-constexpr float kSeriesT2 = 0.25f;
+// 4.5^2 (rho(4.5) = 1 - 8e-9).  radial() and radial3(): Taylor series below
+// 1, the erfcx form in between (the eps derivatives need exp(-t^2) only).
 constexpr float kSeriesWideT2 = 1.0f;
 constexpr float kFarT2 = 20.25f;
 
@@ -177,8 +175,8 @@ __device__ __forceinline__ float exp_neg(float u) {
 // rho and psi for t^2 = u in [1, 20.25]: with e = exp(-t^2),
 // 1 - rho = erfc(t) + (2/sqrt pi) t e = e (erfcx(t) + (2/sqrt pi) t), so one
 // exponential serves both terms and rho has no cancellation worse than 1.4x
-__device__ __forceinline__ void rho_psi_erfcx(float u, float t, float &rho, float &psi) {
-    const float e = exp_neg(u);
+__device__ __forceinline__ void rho_psi_erfcx(float u, float t, float &rho, float &psi, float &e) {
+    e = exp_neg(u);
     const float s = __builtin_amdgcn_rcpf(fmaf(0.5f, t, 1.0f));
     float r = fmaf(kErfcx7, s, kErfcx6);
     r = fmaf(r, s, kErfcx5);
@@ -194,7 +192,8 @@ __device__ __forceinline__ void rho_psi_erfcx(float u, float t, float &rho, floa
 __device__ __forceinline__ float series_chi_t7(float u) {  // u = t^2
     constexpr float c = 9.02703333676410060f;
     return c * (1.0f / 7.0f + u * (-1.0f / 9.0f + u * (1.0f / 22.0f + u * (-1.0f / 78.0f +
-           u * (1.0f / 360.0f + u * (-1.0f / 2040.0f + u * (1.0f / 13680.0f + u * (-1.0f / 105840.0f))))))));
+           u * (1.0f / 360.0f + u * (-1.0f / 2040.0f + u * (1.0f / 13680.0f + u * (-1.0f / 105840.0f +
+           u * (1.0f / 927360.0f + u * (-1.0f / 9072000.0f))))))))));
 }
 
 // r2 = |d|^2.  Returns false when the term is excluded (r = 0 with eps = 0).
@@ -215,8 +214,8 @@ __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &
                 kappa = kp.k3 * series_rho_t3(u);
                 lambda = kp.k5 * series_psi_t5(u);
             } else {
-                float rho, psi;
-                rho_psi_erfcx(u, r2 * ir * kp.ieps, rho, psi);
+                float rho, psi, e;
+                rho_psi_erfcx(u, r2 * ir * kp.ieps, rho, psi, e);
                 kappa = kappa * rho;
                 lambda = kInv4Pi * ir * ir2 * ir2 * psi;
             }
@@ -238,16 +237,15 @@ __device__ __forceinline__ bool radial3(float r2, const KernelParams &kp, float 
     if (kp.eps > 0.0f) {
         const float u = r2 * kp.ieps2;
         if (u < kFarT2) {
-            if (u < kSeriesT2) {
+            if (u < kSeriesWideT2) {
                 kappa = kp.k3 * series_rho_t3(u);
                 lambda = kp.k5 * series_psi_t5(u);
                 nu = kp.k7 * series_chi_t7(u);
             } else {
                 const float t = r2 * ir * kp.ieps;
-                const float e = expf(-u);
-                const float rho = erff(t) - k2SqrtPi * t * e;
-                const float psi = 3.0f * rho - k4SqrtPi * t * u * e;
-                const float chi = 15.0f * rho - k4SqrtPi * t * u * (5.0f + 2.0f * u) * e;
+                float rho, psi, e;
+                rho_psi_erfcx(u, t, rho, psi, e);
+                const float chi = fmaf(15.0f, rho, -(k4SqrtPi * (t * u) * fmaf(2.0f, u, 5.0f) * e));
                 const float ir5 = ir * ir2 * ir2;
                 kappa = kappa * rho;
                 lambda = kInv4Pi * ir5 * psi;
