@@ -49,11 +49,8 @@ constexpr float k2SqrtPi = 1.12837916709551257f;
 constexpr float k4SqrtPi = 2.25675833419102515f;
 
 // Radial-factor branch points, in t^2 = (r/eps)^2: rho = 1 and psi = 3 above
-// 4.5^2 (rho(4.5) = 1 - 8e-9).  radial(): Taylor series below 1, the erfcx
-// form in between.  radial3() (the Hessian factor): series
-// below 0.5^2, erf / exp in between -- the erfcx form made the
-// gradient-cotangent adjoint 19% slower (47.6 -> 56.6 ms on sfm-1m).
-constexpr float kSeriesT2 = 0.25f;
+// 4.5^2 (rho(4.5) = 1 - 8e-9).  radial() and radial3(): Taylor series below
+// 1, the erfcx form in between.
 constexpr float kSeriesWideT2 = 1.0f;
 constexpr float kFarT2 = 20.25f;
 
@@ -239,17 +236,18 @@ __device__ __forceinline__ bool radial3(float r2, const KernelParams &kp, float 
     nu = 5.0f * lambda * ir2;
     if (kp.eps > 0.0f) {
         const float u = r2 * kp.ieps2;
-        if (u < kFarT2) {
-            if (u < kSeriesT2) {
+        // the wavefront-uniform test keeps the branch-free block below a real
+        // branch: without it the compiler evaluated it for every term
+        if (__ballot(u < kFarT2) != 0 && u < kFarT2) {
+            if (u < kSeriesWideT2) {
                 kappa = kp.k3 * series_rho_t3(u);
                 lambda = kp.k5 * series_psi_t5(u);
                 nu = kp.k7 * series_chi_t7(u);
             } else {
                 const float t = r2 * ir * kp.ieps;
-                const float e = expf(-u);
-                const float rho = erff(t) - k2SqrtPi * t * e;
-                const float psi = 3.0f * rho - k4SqrtPi * t * u * e;
-                const float chi = 15.0f * rho - k4SqrtPi * t * u * (5.0f + 2.0f * u) * e;
+                float rho, psi, e;
+                rho_psi_erfcx(u, t, rho, psi, e);
+                const float chi = fmaf(15.0f, rho, -(k4SqrtPi * (t * u) * fmaf(2.0f, u, 5.0f) * e));
                 const float ir5 = ir * ir2 * ir2;
                 kappa = kappa * rho;
                 lambda = kInv4Pi * ir5 * psi;
