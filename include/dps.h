@@ -53,9 +53,11 @@ typedef enum {
 
 typedef enum {
     DPS_STORE_FP32 = 0,  /* attributes and node moments stored as float32 */
-    DPS_STORE_BF16 = 1   /* attributes and node moments stored as bfloat16 (RNE),
-                            accumulated in float32 (float64 for the top levels
-                            of trees with >= 4,194,304 points) */
+    DPS_STORE_BF16 = 1   /* attributes and node moments stored as bfloat16 (round
+                            to nearest even), except the moments of the nodes of
+                            depth <= 3, which stay float32 (a query far from the
+                            geometry takes a few such nodes as its whole far
+                            field, so their rounding would not average out) */
 } dps_storage;
 
 typedef enum {
@@ -93,8 +95,18 @@ typedef enum {
  * (FP64; 1 if zero), quantised as q = min(floor((p - lo) * 2^21/side), 2^21-1)
  * in FP64, Morton code with x at bit 3i+2, y at 3i+1, z at 3i; points stably
  * sorted by code; nodes numbered breadth-first with children contiguous in
- * ascending octant order; node centroid and squared radius are FP64 sums
- * rounded once to FP32.
+ * ascending octant order; the node centroid is the FP64 area-weighted mean
+ * rounded once to FP32, and the node's squared radius r_t^2 is the largest
+ * FP32 value fma(dz, dz, fma(dy, dy, dx*dx)) over its points, d = p_m - p_t
+ * against that FP32 centroid (each operation rounded once, nothing else
+ * fused).
+ *
+ * Moments (eq. farfield_dipole_features, refreshed by dps_set_attributes):
+ * D_t = sum A_m mu_m n_m, formed from A_m, mu_m and n_m with compensated FP32
+ * sums (FP64 for the nodes of depth <= 3 when M >= 4,194,304) and stored
+ * rounded once from the working sum: FP32 storage holds the exact moment
+ * rounded to FP32 (up to a rare one-ulp tie); BF16 storage rounds that FP32
+ * value to bfloat16 below depth 3.
  *
  * Synchronises `stream` (node counts are needed on the host).  Returns
  * DPS_ERR_INVALID for bad sizes / NULL pointers, or if any p, n, A, attrs
@@ -148,7 +160,9 @@ dps_status dps_set_attributes(dps_tree t, const float *attrs, void *stream);
  * eq. farfield) at Q points, all channels in one traversal.
  *  x     [Q][3] query points
  *  beta  > 0, finite: a node is used as far field iff |x - p_t| > beta r_t,
- *        evaluated in FP32 as ((x-cx)^2+(y-cy)^2)+(z-cz)^2 > (beta*beta)*r_t^2
+ *        evaluated in FP32 as fma(dz, dz, fma(dy, dy, dx*dx)) > (beta*beta)*r_t^2
+ *        with d = p_t - x, each operation rounded once and nothing else fused
+ *        (strict: a tie opens the node)
  *  eps   >= 0, finite: regularisation; 0 gives the unregularised dipole sum
  *  f     [Q][C] output values D_c(x)
  *  grad  [Q][C][3] output spatial gradients dD_c/dx, or NULL
@@ -175,14 +189,22 @@ dps_status dps_query_counts(dps_tree t, const float *x, int64_t Q, float beta,
  *
  * dps_adjoint_zero       clears the accumulators.
  * dps_adjoint_accumulate x [Q][3], df [Q][C] = dL/dD_c(x); dx [Q][3] output
- *                        dL/dx (overwritten), or NULL.  Same beta/eps rules
- *                        as dps_query.  Accumulates across calls.
+ *                        dL/dx (overwritten), or NULL (the walk then skips the
+ *                        gradient terms).  Same beta/eps rules as dps_query.
+ *                        Accumulates across calls.
  * dps_adjoint_finalize   dattrs [M][C] output dL/dmu in caller point order.
  * dps_adjoint            zero + accumulate + finalize.
  * All asynchronous and free of host synchronisation and memory set / copy
  * nodes, so a training step (set_attributes, query, adjoint) can be captured
- * in a hipGraph and replayed.  Calls that mutate the tree (set_attributes,
- * adjoint_*) must be ordered by the caller against other calls on the same tree.
+ * in a hipGraph and replayed.
+ *
+ * Ordering: calls on one tree must be ordered by the caller (one stream, or
+ * events between streams).  set_attributes and adjoint_* mutate the tree, and
+ * every traversal (dps_query*, dps_adjoint*, dps_query_grid, dps_ray_march)
+ * resets and consumes the tree's tile counters when the launch is persistent
+ * (dps_set_launch bits 2, 3) or a ray march, so two such calls running at
+ * the same time on one tree would share its tile queue.  Trees are
+ * independent of each other.
  */
 dps_status dps_adjoint_zero(dps_tree t, void *stream);
 dps_status dps_adjoint_accumulate(dps_tree t, const float *x, int64_t Q, float beta, float eps,
@@ -251,6 +273,34 @@ dps_status dps_query_channels(dps_tree t, const float *x, int64_t Q, const int64
 dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q, const int64_t *q_count,
                                            float beta, float eps, int32_t c_begin, int32_t n_channels,
                                            const float *df, float *dx, void *stream);
+
+/*
+ * dps_adjoint_accumulate_from_forward -- as dps_adjoint_accumulate_channels,
+ * with dL/dx formed from the spatial gradients the forward query already
+ * returned for these points instead of a second evaluation of every term's
+ * gradient in the walk:
+ *   dL/dx_q = sum_c df_qc grad_qc,
+ * the same sum as the walk's (the Barnes-Hut gradient is the sum of the
+ * gradient terms of the sources the value accepts, and both calls make the
+ * same far decisions).  The walk then accumulates only the node and point
+ * increments of Algorithm 1 (AdjointQuery).  For a step that queries values
+ * with gradients and then back-propagates (the usual training step), this
+ * is the cheaper call.
+ *  x        device [Q][3]
+ *  q_count  device row count or NULL (as dps_query_channels)
+ *  c_begin, n_channels  channel range (BF16 storage: c_begin even)
+ *  df       device [Q][n_channels] cotangents (required)
+ *  grad     device [Q][n_channels][3]: dps_query / dps_query_channels
+ *           gradients at the same x with the same beta and eps and the
+ *           attributes as they are now (required; the result is only as
+ *           right as these are)
+ *  dx       device [Q][3] output (overwritten), or NULL (grad then unused)
+ * Accumulates like dps_adjoint_accumulate.  Graph-safe.  DPS_ERR_INVALID for
+ * a NULL x, df or grad, bad ranges, or a monopole-kernel tree.
+ */
+dps_status dps_adjoint_accumulate_from_forward(dps_tree t, const float *x, int64_t Q, const int64_t *q_count,
+                                               float beta, float eps, int32_t c_begin, int32_t n_channels,
+                                               const float *df, const float *grad, float *dx, void *stream);
 
 /*
  * dps_adjoint_accumulate_grad -- stage 1 of the adjoint for cotangents of the
@@ -379,8 +429,26 @@ dps_status dps_ray_resample(const float *o, const float *d, const float *tnear, 
 
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A
- * traversal that would walk more than N nodes stops and sets this flag. */
+ * traversal that would walk more than N nodes stops and sets this flag; its
+ * outputs are then incomplete. */
 dps_status dps_check(dps_tree t, void *stream);
+
+/* dps_set_step_limit -- caps the nodes one traversal of this tree may walk
+ * (0 restores the default, the node count N, which a well-formed tree never
+ * exceeds; otherwise 1 <= limit <= N).  Reaching the cap is the failure that
+ * dps_check reports: the traversal stops, every kernel exits normally, the
+ * outputs are incomplete, and the tree's sticky error is set.  A diagnostic,
+ * for exercising that failure path from the host.  Host-only; applies to
+ * later launches.  DPS_ERR_INVALID outside [0, N]. */
+dps_status dps_set_step_limit(dps_tree t, int64_t limit);
+
+/* dps_set_memory_limit -- process-wide cap on the device bytes one build may
+ * hold at once (the tree's storage plus its temporary buffers), 0 = no cap
+ * (the default).  A build that would exceed it returns DPS_ERR_OOM, frees
+ * everything it allocated and sets *out = NULL, exactly as when the device
+ * runs out of memory.  Applies to later builds.  DPS_ERR_INVALID for
+ * bytes < 0. */
+dps_status dps_set_memory_limit(int64_t bytes);
 
 /* dps_destroy -- frees the tree (synchronises the device first).  NULL is a no-op. */
 void dps_destroy(dps_tree t);

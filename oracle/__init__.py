@@ -8,6 +8,6 @@ paper each part follows.
 from .oracle import (  # noqa: F401
     build, load, direct, direct_adjoint, Tree, rho, psi, rho_series,
     psi_series, rho_closed, radial, chi, chi_series, radial_nu, radial_eps, direct_mono,
-    direct_mono_adjoint,
+    direct_mono_adjoint, round_bf16, STORAGE_MODES,
 )
 from . import rays  # noqa: F401,E402

@@ -587,6 +587,14 @@ typedef struct {
     double *W;            /* [N][C] absolute masses sum_m A_m |mu_m| |n_m| (monopole:
                              sum_m A_m |mu_m|), the scale of a node term */
     int kind;             /* 0: dipole kernel, 1: monopole kernel */
+    /* storage emulation (orc_tree_set_storage): the values the sums read */
+    int store_mode;       /* 0: exact (FP64 moments, attributes as given) */
+    int store_levels;     /* mode 1: nodes of level <= store_levels keep FP32 moments */
+    int scale_mode;       /* error scale of a node term: 0 its absolute mass W,
+                             1 the magnitude of its own moment (Wm) */
+    double *Wm;           /* [N][C] |D_t,c| (monopole: |Q_t,c|) of the exact moments */
+    double *Ds;           /* [N][C][3] node moments as stored (== D in mode 0) */
+    double *mus;          /* [M][C] sorted attributes as stored (== mu in mode 0) */
 } orc_tree;
 
 static uint64_t spread3(uint64_t v)
@@ -616,12 +624,96 @@ static float dist2_f32(const float a[3], const float b[3])
     return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
 }
 
+/* ------------------------------------------------------------------------ */
+/* storage emulation                                                         */
+/* ------------------------------------------------------------------------ */
+
+/* The library stores attributes and node moments either as FP32 or as
+ * bfloat16 (8 significant bits, FP32's exponent range), the reduced-precision
+ * storage that the error study of the method asks to quantify.  These helpers
+ * let the oracle evaluate its FP64 sums from values rounded exactly as such a
+ * store would hold them, so that a reduced-precision GPU result can be
+ * compared with the arithmetic it claims to perform, not only bounded.
+ *
+ * orc_round_bf16: nearest bfloat16 value (ties to even) of the FP32 value v,
+ * returned as a double.  Written from the format's definition: the quantum is
+ * 2^(e-8) for |v| in [2^(e-1), 2^e) and 2^-133 below the normal range;
+ * values past the largest finite bfloat16 (after rounding) become infinite. */
+double orc_round_bf16(float v)
+{
+    double a = fabs((double)v);
+    if (a == 0.0 || !isfinite(a)) return (double)v;
+    int e;
+    (void)frexp(a, &e);            /* a = m 2^e, m in [0.5, 1) */
+    int qe = e - 8;
+    if (qe < -133) qe = -133;
+    double q = ldexp(nearbyint(ldexp(a, -qe)), qe);  /* default mode: ties to even */
+    if (q >= 0x1p128) q = INFINITY;
+    return copysign(q, (double)v);
+}
+
+static void free_stored(orc_tree *t)
+{
+    if (t->Ds && t->Ds != t->D) free(t->Ds);
+    if (t->mus && t->mus != t->mu) free(t->mus);
+    t->Ds = NULL; t->mus = NULL;
+}
+
+/* (Re)derives the stored views from the exact attributes and moments.
+ * Mode 0: the exact values themselves.  Mode 2 (FP32 store): moments rounded
+ * once to FP32 (attributes are FP32 inputs already).  Mode 1 (bfloat16 store):
+ * attributes rounded to bfloat16; node moments rounded to FP32 and then to
+ * bfloat16 (the store rounds an FP32 value), except nodes of level <=
+ * store_levels, which keep the FP32 rounding (store_levels = -1: none). */
+static void apply_storage(orc_tree *t)
+{
+    free_stored(t);
+    if (!t->D) return;
+    int C = t->C;
+    if (t->store_mode == 0) {
+        t->Ds = t->D; t->mus = t->mu;
+        return;
+    }
+    t->Ds = (double *)malloc(sizeof(double) * (size_t)t->N * C * 3);
+    t->mus = (double *)malloc(sizeof(double) * (size_t)t->M * C);
+    for (int64_t i = 0; i < t->M * C; ++i)
+        t->mus[i] = t->store_mode == 1 ? orc_round_bf16((float)t->mu[i]) : t->mu[i];
+    for (int64_t i = 0; i < t->N; ++i) {
+        int keep32 = t->store_mode == 2 || t->node[6 * i] <= t->store_levels;
+        for (int c = 0; c < 3 * C; ++c) {
+            float v = (float)t->D[i * C * 3 + c];
+            t->Ds[i * C * 3 + c] = keep32 ? (double)v : orc_round_bf16(v);
+        }
+    }
+}
+
+/* mode: 0 exact, 1 bfloat16 (levels <= fp32_levels kept FP32), 2 FP32. */
+int orc_tree_set_storage(orc_tree *t, int mode, int fp32_levels)
+{
+    if (!t || mode < 0 || mode > 2 || fp32_levels < -1) return 1;
+    t->store_mode = mode;
+    t->store_levels = fp32_levels;
+    apply_storage(t);
+    return 0;
+}
+
+/* Node moments [N][C][3] and sorted attributes [M][C] as stored (either may
+ * be NULL). */
+int orc_tree_export_stored(const orc_tree *t, double *Ds, double *mus)
+{
+    if (!t || !t->Ds) return 1;
+    if (Ds) memcpy(Ds, t->Ds, sizeof(double) * (size_t)t->N * t->C * 3);
+    if (mus) memcpy(mus, t->mus, sizeof(double) * (size_t)t->M * t->C);
+    return 0;
+}
+
 void orc_tree_free(orc_tree *t)
 {
     if (!t) return;
     free(t->codes_in); free(t->codes); free(t->perm); free(t->ps); free(t->Am); free(t->nm);
     free(t->node); free(t->geom); free(t->area); free(t->cen64); free(t->leaf_of);
-    free(t->mu); free(t->D); free(t->W);
+    free_stored(t);
+    free(t->mu); free(t->D); free(t->W); free(t->Wm);
     free(t);
 }
 
@@ -754,7 +846,8 @@ orc_tree *orc_tree_build(const float *p, const float *n, const float *A, int64_t
 int orc_tree_set_attrs(orc_tree *t, const float *mu, int C)
 {
     if (!t || C < 1 || C > 64) return 1;
-    free(t->mu); free(t->D); free(t->W);
+    free_stored(t);
+    free(t->mu); free(t->D); free(t->W); free(t->Wm);
     t->C = C;
     t->mu = (double *)malloc(sizeof(double) * t->M * C);
     for (int64_t i = 0; i < t->M; ++i)
@@ -785,6 +878,10 @@ int orc_tree_set_attrs(orc_tree *t, const float *mu, int C)
             }
         }
     }
+    t->Wm = (double *)malloc(sizeof(double) * (size_t)t->N * C);
+    for (int64_t i = 0; i < t->N; ++i)
+        for (int c = 0; c < C; ++c) t->Wm[i * C + c] = t->kind == 1 ? fabs(t->D[(i * C + c) * 3]) : norm3(t->D + (i * C + c) * 3);
+    apply_storage(t);
     return 0;
 }
 
@@ -843,6 +940,21 @@ typedef struct {
     int32_t visits, far, leaves, near;
 } qstate;
 
+/* per-channel error scale of node i's far-field term */
+static const double *node_scale(const orc_tree *t, int64_t i)
+{
+    return (t->scale_mode ? t->Wm : t->W) + i * t->C;
+}
+
+/* 0: absolute masses (the default), 1: moment magnitudes |D_t| (stricter
+ * where a node's moment cancels) */
+int orc_tree_set_scale(orc_tree *t, int mode)
+{
+    if (!t || (mode != 0 && mode != 1)) return 1;
+    t->scale_mode = mode;
+    return 0;
+}
+
 static int far_test(const orc_tree *t, int64_t i, const float *xf, float b2)
 {
     const float *gm = t->geom + 4 * i;
@@ -858,12 +970,12 @@ static void add_point(const orc_tree *t, int64_t j, const double x[3], double ep
     double D[192], c[3];
     for (int k = 0; k < 3; ++k) c[k] = (double)t->ps[3 * j + k];
     if (t->kind == 1) {
-        for (int ch = 0; ch < C; ++ch) D[3 * ch] = t->Am[j] * t->mu[j * C + ch];
+        for (int ch = 0; ch < C; ++ch) D[3 * ch] = t->Am[j] * t->mus[j * C + ch];
         add_term_mono(c, D, NULL, C, x, eps, f, g, sf, sg);
         return;
     }
     for (int ch = 0; ch < C; ++ch)
-        for (int k = 0; k < 3; ++k) D[3 * ch + k] = t->Am[j] * t->mu[j * C + ch] * t->nm[3 * j + k];
+        for (int k = 0; k < 3; ++k) D[3 * ch + k] = t->Am[j] * t->mus[j * C + ch] * t->nm[3 * j + k];
     add_term(c, D, NULL, C, x, eps, f, g, sf, sg);
 }
 
@@ -877,9 +989,9 @@ static void primal(qstate *st, int64_t i)
         for (int k = 0; k < 3; ++k) c[k] = (double)t->geom[4 * i + k];
         st->far++;
         if (t->kind == 1)
-            add_term_mono(c, t->D + i * t->C * 3, t->W + i * t->C, t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
+            add_term_mono(c, t->Ds + i * t->C * 3, node_scale(t, i), t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
         else
-            add_term(c, t->D + i * t->C * 3, t->W + i * t->C, t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
+            add_term(c, t->Ds + i * t->C * 3, node_scale(t, i), t->C, st->x, st->eps, st->f, st->g, st->sf, st->sg);
         return;
     }
     if (nd[3] == 0) {
@@ -900,7 +1012,7 @@ static void primal(qstate *st, int64_t i)
 int orc_bh_query(const orc_tree *t, const float *x, int64_t Q, float beta, double eps,
                  double *f, double *g, double *sf, double *sg, int32_t *counts, int nthreads)
 {
-    if (!t || !t->D || Q < 0 || !(beta > 0) || eps < 0) return 1;
+    if (!t || !t->Ds || Q < 0 || !(beta > 0) || eps < 0) return 1;
     int C = t->C;
     int nt = nthreads_or_default(nthreads);
     float b2 = beta * beta;
@@ -963,8 +1075,8 @@ static void adjoint(astate *st, int64_t i)
         double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
         double r = sqrt(r2), kap, lam;
         radial(r, st->eps, &kap, &lam);
-        const double *Dt = t->D + i * C * 3;
-        const double *Wt = t->W + i * C;  /* absolute masses: the scales of the node's terms */
+        const double *Dt = t->Ds + i * C * 3;
+        const double *Wt = node_scale(t, i);  /* the scales of the node's terms */
         if (t->kind == 1) {
             /* monopole: node accumulator df m(r), dx through the charges */
             if (r2 == 0.0) return;
@@ -1022,8 +1134,8 @@ static void adjoint(astate *st, int64_t i)
                 for (int ch = 0; ch < C; ++ch) {
                     st->P[j * C + ch] += st->df[ch] * t->Am[j] * m;
                     st->HP[j * C + ch] += fabs(st->df[ch]) * t->Am[j] * m;
-                    w += st->df[ch] * t->mu[j * C + ch];
-                    aw += fabs(st->df[ch] * t->mu[j * C + ch]);
+                    w += st->df[ch] * t->mus[j * C + ch];
+                    aw += fabs(st->df[ch] * t->mus[j * C + ch]);
                 }
                 for (int k = 0; k < 3; ++k) st->dx[k] += t->Am[j] * w * gv * d[k];
                 st->sdx += t->Am[j] * aw * fabs(gv) * r;
@@ -1035,7 +1147,7 @@ static void adjoint(astate *st, int64_t i)
             if (st->df) {
                 double w = 0;
                 for (int ch = 0; ch < C; ++ch) {
-                    double mu = t->mu[j * C + ch];
+                    double mu = t->mus[j * C + ch];
                     st->P[j * C + ch] += st->df[ch] * kap * s;
                     st->HP[j * C + ch] += fabs(st->df[ch]) * kap * nAn * r;
                     w += st->df[ch] * mu;
@@ -1047,7 +1159,7 @@ static void adjoint(astate *st, int64_t i)
             if (st->dg) {
                 double nu = radial_nu(r, st->eps);
                 for (int ch = 0; ch < C; ++ch) {
-                    double mu = t->mu[j * C + ch];
+                    double mu = t->mus[j * C + ch];
                     double D[3] = {mu * An[0], mu * An[1], mu * An[2]};
                     double dAn[3] = {0, 0, 0}, sc = 0;
                     /* derivative in the point's dipole, then through D = mu A n */
@@ -1070,7 +1182,7 @@ static void adjoint(astate *st, int64_t i)
                         for (int k = 0; k < 3; ++k) dD[k] += lam * dh * d[k] - kap * h[k];
                         s1 += sqrt(h[0] * h[0] + h[1] * h[1] + h[2] * h[2]) * (fabs(lam) * r2 + kap);
                     }
-                    double am = t->Am[j] * t->mu[j * C + ch];
+                    double am = t->Am[j] * t->mus[j * C + ch];
                     for (int k = 0; k < 3; ++k) st->PN[3 * j + k] += am * dD[k];
                     sc += fabs(am) * s1;
                 }
@@ -1080,7 +1192,7 @@ static void adjoint(astate *st, int64_t i)
                 double ke, le;
                 radial_eps(r, st->eps, &ke, &le);
                 for (int ch = 0; ch < C; ++ch) {
-                    double mu = t->mu[j * C + ch];
+                    double mu = t->mus[j * C + ch];
                     double D[3] = {mu * An[0], mu * An[1], mu * An[2]};
                     st->deps += term_eps(d, ke, le, D, -1.0, st->df ? st->df[ch] : 0.0,
                                          st->dg ? st->dg + 3 * ch : NULL, &st->sdeps);
@@ -1102,7 +1214,7 @@ int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, dou
                    const float *df, const float *dg, double *dmu, double *dx, double *dn,
                    double *deps, double *sdmu, double *sdx, double *sdn, double *sdeps, int nthreads)
 {
-    if (!t || !t->D || Q < 0 || !(beta > 0) || eps < 0 || (!df && !dg)) return 1;
+    if (!t || !t->Ds || Q < 0 || !(beta > 0) || eps < 0 || (!df && !dg)) return 1;
     if (t->kind == 1 && (dg || dn || deps || !df)) return 1;  /* value cotangents only */
     int C = t->C;
     int64_t N = t->N, M = t->M;
@@ -1189,7 +1301,7 @@ int orc_bh_adjoint(const orc_tree *t, const float *x, int64_t Q, float beta, dou
             /* far field: every ancestor's node dipole holds A_j mu_jc n_j */
             double v[3] = {PN[3 * j], PN[3 * j + 1], PN[3 * j + 2]}, sc = HPN[j];
             for (int c = 0; c < C; ++c) {
-                double am = t->Am[j] * t->mu[j * C + c];
+                double am = t->Am[j] * t->mus[j * C + c];
                 const double *S = G + (l * C + c) * 3;
                 for (int k = 0; k < 3; ++k) v[k] += am * S[k];
                 sc += fabs(am) * H[l * C + c];

@@ -71,6 +71,14 @@ def load():
     lib.orc_direct_mono_adjoint.restype = ct.c_int
     lib.orc_direct_mono_adjoint.argtypes = [vp, vp, vp, ct.c_int64, ct.c_int, vp, ct.c_int64, ct.c_double,
                                             vp, vp, vp, ct.c_int]
+    lib.orc_round_bf16.restype = ct.c_double
+    lib.orc_round_bf16.argtypes = [ct.c_float]
+    lib.orc_tree_set_storage.restype = ct.c_int
+    lib.orc_tree_set_storage.argtypes = [vp, ct.c_int, ct.c_int]
+    lib.orc_tree_set_scale.restype = ct.c_int
+    lib.orc_tree_set_scale.argtypes = [vp, ct.c_int]
+    lib.orc_tree_export_stored.restype = ct.c_int
+    lib.orc_tree_export_stored.argtypes = [vp, vp, vp]
     lib.orc_tree_num_nodes.restype = ct.c_int64
     lib.orc_tree_num_nodes.argtypes = [vp]
     lib.orc_tree_depth.restype = ct.c_int
@@ -124,6 +132,14 @@ def radial(r, eps):
     k, l = ct.c_double(), ct.c_double()
     load().orc_radial(float(r), float(eps), ct.byref(k), ct.byref(l))
     return k.value, l.value
+
+
+def round_bf16(v):
+    """Nearest bfloat16 value (ties to even) of an FP32 value, as a float."""
+    return load().orc_round_bf16(float(np.float32(v)))
+
+
+STORAGE_MODES = {"exact": 0, "bf16": 1, "fp32": 2}
 
 
 def direct(p, n, A, mu, x, eps, want_grad=True, nthreads=0):
@@ -246,6 +262,31 @@ class Tree:
         self.C = mu.shape[1]
         if load().orc_tree_set_attrs(self._h, _ptr(mu), self.C):
             raise ValueError("orc_tree_set_attrs rejected its arguments")
+
+    def set_storage(self, mode="exact", fp32_levels=-1):
+        """Evaluate from values rounded as a store holds them: "exact" (FP64
+        moments, the default), "fp32" (moments rounded once to FP32) or
+        "bf16" (attributes and moments rounded to bfloat16, moments through
+        FP32; nodes of level <= fp32_levels keep the FP32 rounding).  Applies
+        to later queries and adjoints, and survives set_attrs."""
+        if load().orc_tree_set_storage(self._h, STORAGE_MODES[mode], int(fp32_levels)):
+            raise ValueError("orc_tree_set_storage rejected its arguments")
+
+    def set_scale(self, mode="mass"):
+        """Error scale of a node's far-field term in sf, sg, sdx and friends:
+        "mass" (the sum of its points' absolute dipoles, the default) or
+        "moment" (the magnitude of its own moment |D_t|, stricter where the
+        moment cancels)."""
+        if load().orc_tree_set_scale(self._h, {"mass": 0, "moment": 1}[mode]):
+            raise ValueError("orc_tree_set_scale rejected its arguments")
+
+    def export_stored(self):
+        """(moments [N,C,3], sorted attributes [M,C]) as the sums read them."""
+        Ds = np.zeros((self.N, self.C, 3))
+        mus = np.zeros((self.M, self.C))
+        if load().orc_tree_export_stored(self._h, _ptr(Ds), _ptr(mus)):
+            raise ValueError("no attributes set")
+        return Ds, mus
 
     def export(self):
         M, N, C = self.M, self.N, self.C

@@ -10,7 +10,9 @@ from .binding import (  # noqa: F401
     dps_adjoint_zero, dps_adjoint_accumulate, dps_adjoint_finalize, dps_adjoint,
     dps_export_tree, dps_tree_info, dps_set_launch, dps_get_launch, dps_query_channels,
     dps_adjoint_accumulate_channels, dps_adjoint_accumulate_grad, dps_adjoint_accumulate_ext,
-    dps_adjoint_finalize_ext, dps_set_normals, dps_query_grid, dps_ray_march, dps_ray_resample, WANT_NORMALS, WANT_EPS, dps_check, dps_destroy, LAUNCH_XCD_QUERY,
+    dps_adjoint_accumulate_from_forward,
+    dps_adjoint_finalize_ext, dps_set_normals, dps_query_grid, dps_ray_march, dps_ray_resample, WANT_NORMALS, WANT_EPS, dps_check, dps_set_step_limit,
+    dps_set_memory_limit, dps_destroy, LAUNCH_XCD_QUERY,
     LAUNCH_XCD_ADJOINT,
     LAUNCH_PERSISTENT_QUERY, LAUNCH_PERSISTENT_ADJOINT, LAUNCH_MARCH_WHOLE, dps_status_string, dps_last_error,
     load, LIB_PATH, EXPORTED, DPS_KERNEL_DIPOLE, DPS_KERNEL_MONOPOLE,

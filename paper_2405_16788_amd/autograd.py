@@ -5,6 +5,9 @@ gradients) with ``dps_query`` / ``dps_query_channels``; backward runs the
 two-stage adjoint of Sec. 6.2 / App. C (node accumulation with a recomputed
 traversal, then the push-down to the points).  Nothing about the traversal is
 stored between the two passes: the adjoint walks the tree again for each query.
+When the forward computed the spatial gradients, the backward forms dL/dx
+from them (``dps_adjoint_accumulate_from_forward``) and its walk only
+accumulates the attribute derivatives.
 
 The value D(x) and its gradient are linear in the attributes, and the
 traversal depends only on x and the fixed geometry, so dL/dattrs is the exact
@@ -82,7 +85,10 @@ class DipoleSum(torch.autograd.Function):
             g = torch.zeros((Q, n, 3), device=x_c.device, dtype=torch.float32) if want_grad else None
             B.dps_query_channels(tree, x_c, beta, eps_v, c_begin, n, grad=want_grad, f_out=f, g_out=g,
                                  q_count=q_count)
-        ctx.save_for_backward(x_c, attrs_c)
+        # the gradients, when computed, give the backward its dL/dx directly
+        # (dps_adjoint_accumulate_from_forward)
+        ctx.has_g = g is not None and getattr(tree, "kernel", "dipole") == "dipole"
+        ctx.save_for_backward(x_c, attrs_c, g if ctx.has_g else None)
         ctx.tree, ctx.beta, ctx.eps, ctx.opts, ctx.full = tree, float(beta), eps_v, opts, full
         ctx.n = f.shape[1]
         ctx.eps_like = eps if isinstance(eps, torch.Tensor) else None
@@ -90,7 +96,7 @@ class DipoleSum(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, df, dg):
-        x, attrs = ctx.saved_tensors
+        x, attrs, g_fwd = ctx.saved_tensors
         tree = ctx.tree
         c_begin, n_ch, q_count, _, refit = ctx.opts
         if refit == "auto":
@@ -121,6 +127,14 @@ class DipoleSum(torch.autograd.Function):
             B.dps_adjoint_zero(tree)
             B.dps_adjoint_accumulate_grad(tree, x, ctx.beta, ctx.eps, dg, df=df, c_begin=c_begin, n_channels=ctx.n,
                                           want_dx=need_x, dx_out=dx, q_count=q_count)
+            dattrs = B.dps_adjoint_finalize(tree)
+        elif need_x and ctx.has_g:
+            # dL/dx = sum_c df_c grad_c from the forward's gradients; the walk
+            # accumulates the attribute derivatives only
+            dx = torch.zeros((x.shape[0], 3), device=x.device, dtype=torch.float32)
+            B.dps_adjoint_zero(tree)
+            B.dps_adjoint_accumulate_from_forward(tree, x, ctx.beta, ctx.eps, df, g_fwd, c_begin=c_begin,
+                                                  n_channels=ctx.n, dx_out=dx, q_count=q_count)
             dattrs = B.dps_adjoint_finalize(tree)
         elif ctx.full:
             dattrs, dx = B.dps_adjoint(tree, x, ctx.beta, ctx.eps, df, want_dx=need_x)

@@ -25,8 +25,9 @@ EXPORTED = (
     "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
     "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_query_channels",
     "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_adjoint_accumulate_ext",
+    "dps_adjoint_accumulate_from_forward",
     "dps_adjoint_finalize_ext", "dps_set_normals", "dps_query_grid", "dps_ray_march", "dps_ray_resample",
-    "dps_check", "dps_destroy",
+    "dps_check", "dps_set_step_limit", "dps_set_memory_limit", "dps_destroy",
     "dps_status_string", "dps_last_error",
 )
 
@@ -66,6 +67,7 @@ def load():
         "dps_query_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate_grad": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp, vp],
+        "dps_adjoint_accumulate_from_forward": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp, vp],
         "dps_adjoint_accumulate_ext": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, i32, vp, vp],
         "dps_adjoint_finalize_ext": [vp, vp, vp, vp, vp],
         "dps_set_normals": [vp, vp, vp],
@@ -78,6 +80,8 @@ def load():
         "dps_export_tree": [vp, vp, vp, vp, vp, vp, vp],
         "dps_tree_info": [vp, ct.POINTER(i64), ct.POINTER(i32), ct.POINTER(i64), ct.POINTER(i64),
                           ct.POINTER(i32)],
+        "dps_set_step_limit": [vp, i64],
+        "dps_set_memory_limit": [i64],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -335,6 +339,26 @@ def dps_adjoint_accumulate_grad(tree: Tree, x, beta: float, eps: float, dg, df=N
     return dx
 
 
+def dps_adjoint_accumulate_from_forward(tree: Tree, x, beta: float, eps: float, df, grad, c_begin: int = 0,
+                                        n_channels=None, want_dx: bool = True, dx_out=None, q_count=None):
+    """Stage 1 for value cotangents df[Q,n] of channels [c_begin, c_begin+n)
+    with dL/dx = sum_c df_c grad_c formed from the forward's gradients
+    grad[Q,n,3] (same x, beta, eps and attributes); returns dx[Q,3] (or None)."""
+    import torch
+    Q = x.shape[0]
+    n = tree.C - c_begin if n_channels is None else n_channels
+    dx = dx_out if dx_out is not None else (
+        torch.empty((Q, 3), device=tree.device, dtype=torch.float32) if want_dx else None)
+    _check(load().dps_adjoint_accumulate_from_forward(
+        tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q,
+        _ptr(q_count, torch.int64, (1,), tree.device, "q_count"), float(beta), float(eps), int(c_begin), int(n),
+        _ptr(df, torch.float32, (Q, n), tree.device, "df"),
+        _ptr(grad, torch.float32, (Q, n, 3), tree.device, "grad"),
+        _ptr(dx, torch.float32, (Q, 3), tree.device, "dx"), _stream(tree.device)),
+        "dps_adjoint_accumulate_from_forward")
+    return dx
+
+
 WANT_NORMALS = 1
 WANT_EPS = 2
 
@@ -450,6 +474,17 @@ def dps_ray_resample(o, d, tnear, tfar, n_march: int, hit_index, hit_values, jit
 def dps_check(tree: Tree):
     """Synchronises and raises if a device-side failure was recorded."""
     _check(load().dps_check(tree.handle, _stream(tree.device)), "dps_check")
+
+
+def dps_set_step_limit(tree: Tree, limit: int):
+    """Caps the nodes one traversal may walk (0: the node count, the default).
+    A diagnostic: a traversal reaching the cap stops and dps_check raises."""
+    _check(load().dps_set_step_limit(tree.handle, int(limit)), "dps_set_step_limit")
+
+
+def dps_set_memory_limit(nbytes: int):
+    """Process-wide cap on the device bytes one build may hold (0: none)."""
+    _check(load().dps_set_memory_limit(int(nbytes)), "dps_set_memory_limit")
 
 
 def dps_destroy(tree: Tree):

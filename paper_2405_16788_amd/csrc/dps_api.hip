@@ -4,6 +4,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <unordered_set>
@@ -16,12 +17,20 @@ namespace {
 thread_local char g_last_error[512] = "";
 std::mutex g_mu;
 std::unordered_set<dps_tree_s *> g_live;
+std::atomic<int64_t> g_mem_limit{0};  // dps_set_memory_limit (0: no cap)
 
 bool live(dps_tree_s *t) {
     std::lock_guard<std::mutex> lk(g_mu);
     return t && g_live.count(t) && t->magic == kMagic;
 }
 }  // namespace
+
+bool memory_fits(const dps_tree_s *t, size_t more) {
+    const int64_t lim = g_mem_limit.load();
+    if (lim <= 0) return true;
+    const int64_t held = t ? t->bytes + t->scratch_bytes : 0;
+    return (int64_t)more <= lim - held;
+}
 
 void set_error(const char *fmt, ...) {
     va_list ap;
@@ -132,11 +141,12 @@ dps_status dps_build_kernel(const float *p, const float *n, const float *A, cons
     if (st == DPS_OK) {
         const size_t esz = bf ? 2 : 4;
         uint8_t *mom = nullptr, *attr = nullptr;
-        st = tree_alloc(t, &mom, (size_t)t->N * t->mom_stride * esz);
+        st = tree_alloc(t, &mom, moment_bytes(t));
         if (st == DPS_OK) st = tree_alloc(t, &attr, (size_t)M * t->attr_stride * esz);
         t->mom = mom;
         t->attr = attr;
         if (st == DPS_OK) st = tree_alloc(t, &t->momw, (size_t)t->N * kw * C);
+        if (st == DPS_OK) st = tree_alloc(t, &t->momw_lo, (size_t)t->N * kw * C);
         if (st == DPS_OK && t->wide_top) st = tree_alloc(t, &t->momw64, (size_t)t->n_top * kw * C);
         if (st == DPS_OK) st = tree_alloc(t, &t->G, (size_t)t->N * kw * C);
         if (st == DPS_OK) st = tree_alloc(t, &t->S, (size_t)t->N * kw * C);
@@ -266,7 +276,7 @@ dps_status dps_adjoint_accumulate(dps_tree t, const float *x, int64_t Q, float b
     if (Q == 0) return DPS_OK;
     if (!x || !df) return invalid("dps_adjoint_accumulate: NULL x or df");
     DeviceGuard dg(t->device);
-    return launch_adjoint(t, x, Q, nullptr, beta, eps, 0, t->C, df, dx, (hipStream_t)stream);
+    return launch_adjoint(t, x, Q, nullptr, beta, eps, 0, t->C, df, dx, nullptr, (hipStream_t)stream);
 }
 
 dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q, const int64_t *q_count,
@@ -280,7 +290,22 @@ dps_status dps_adjoint_accumulate_channels(dps_tree t, const float *x, int64_t Q
     if (Q == 0) return DPS_OK;
     if (!x || !df) return invalid("dps_adjoint_accumulate_channels: NULL x or df");
     DeviceGuard dg(t->device);
-    return launch_adjoint(t, x, Q, q_count, beta, eps, c_begin, n_channels, df, dx, (hipStream_t)stream);
+    return launch_adjoint(t, x, Q, q_count, beta, eps, c_begin, n_channels, df, dx, nullptr, (hipStream_t)stream);
+}
+
+dps_status dps_adjoint_accumulate_from_forward(dps_tree t, const float *x, int64_t Q, const int64_t *q_count,
+                                               float beta, float eps, int32_t c_begin, int32_t n_channels,
+                                               const float *df, const float *grad, float *dx, void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint_accumulate_from_forward");
+    if (st != DPS_OK) return st;
+    if ((st = need_dipole(t, "dps_adjoint_accumulate_from_forward")) != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_adjoint_accumulate_from_forward")) != DPS_OK) return st;
+    if ((st = check_channels(t, c_begin, n_channels, "dps_adjoint_accumulate_from_forward")) != DPS_OK) return st;
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_adjoint_accumulate_from_forward: Q out of range");
+    if (Q == 0) return DPS_OK;
+    if (!x || !df || !grad) return invalid("dps_adjoint_accumulate_from_forward: NULL x, df or grad");
+    DeviceGuard dg(t->device);
+    return launch_adjoint(t, x, Q, q_count, beta, eps, c_begin, n_channels, df, dx, grad, (hipStream_t)stream);
 }
 
 dps_status dps_adjoint_accumulate_grad(dps_tree t, const float *x, int64_t Q, const int64_t *q_count, float beta,
@@ -461,6 +486,20 @@ dps_status dps_get_launch(dps_tree t, int32_t *query_k, int32_t *adjoint_k, int3
     if (query_k) *query_k = t->packet_query;
     if (adjoint_k) *adjoint_k = t->packet_adjoint;
     if (flags) *flags = t->launch_flags;
+    return DPS_OK;
+}
+
+dps_status dps_set_step_limit(dps_tree t, int64_t limit) {
+    dps_status st = check_tree(t, "dps_set_step_limit");
+    if (st != DPS_OK) return st;
+    if (limit < 0 || limit > t->N) return invalid("dps_set_step_limit: limit must be in [0, node count]");
+    t->step_limit = (uint32_t)limit;
+    return DPS_OK;
+}
+
+dps_status dps_set_memory_limit(int64_t bytes) {
+    if (bytes < 0) return invalid("dps_set_memory_limit: bytes must be >= 0");
+    g_mem_limit.store(bytes);
     return DPS_OK;
 }
 

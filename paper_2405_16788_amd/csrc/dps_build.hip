@@ -313,7 +313,7 @@ __global__ void k_child_counts(int64_t nb, int64_t ne, const int32_t *__restrict
 // ---------------------------------------------------------------------------
 __global__ void k_points(const float *__restrict__ p, const float *__restrict__ n,
                          const float *__restrict__ A, const uint32_t *__restrict__ perm, int64_t M,
-                         PointRec *__restrict__ pts) {
+                         PointRec *__restrict__ pts, float *__restrict__ nrm) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
     const int64_t i = perm[j];
@@ -328,6 +328,9 @@ __global__ void k_points(const float *__restrict__ p, const float *__restrict__ 
     r.a = a;
     r.pad = 0.0f;
     pts[j] = r;
+    nrm[3 * j] = n[3 * i];
+    nrm[3 * j + 1] = n[3 * i + 1];
+    nrm[3 * j + 2] = n[3 * i + 2];
 }
 
 // ---------------------------------------------------------------------------
@@ -495,23 +498,40 @@ __global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
 }
 
 // temporaries freed on scope exit
+// temporary device buffers, freed when the owner returns; with a tree their
+// bytes count against its build's memory limit while they are held
 struct Scratch {
-    std::vector<void *> blocks;
+    dps_tree_s *t;
+    std::vector<std::pair<void *, size_t>> blocks;
+    explicit Scratch(dps_tree_s *tree) : t(tree) {}
     ~Scratch() {
-        for (void *b : blocks) (void)hipFree(b);
+        for (auto &b : blocks)
+            if (b.first) (void)hipFree(b.first);
+        if (t) t->scratch_bytes = 0;
     }
     template <class T>
     dps_status get(T **p, size_t count) {
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        *p = nullptr;
+        if (!memory_fits(t, bytes)) {
+            set_error("device memory limit of dps_set_memory_limit reached (build scratch)");
+            return DPS_ERR_OOM;
+        }
         void *q = nullptr;
-        hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
-        if (e != hipSuccess) { *p = nullptr; return hip_status(e, "hipMalloc (build scratch)"); }
-        blocks.push_back(q);
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) return hip_status(e, "hipMalloc (build scratch)");
+        blocks.push_back({q, bytes});
+        if (t) t->scratch_bytes += (int64_t)bytes;
         *p = (T *)q;
         return DPS_OK;
     }
     void release(void *q) {
         for (auto &b : blocks)
-            if (b == q) { (void)hipFree(b); b = nullptr; }
+            if (b.first == q) {
+                (void)hipFree(b.first);
+                b.first = nullptr;
+                if (t) t->scratch_bytes -= (int64_t)b.second;
+            }
     }
 };
 
@@ -548,7 +568,7 @@ dps_status device_scan(const uint32_t *in, uint32_t *out, int64_t n, bool inclus
 
 dps_status check_inputs(const float *p, const float *n, const float *A, const float *attrs,
                         int64_t M, int C, hipStream_t s, bool *ok) {
-    Scratch sc;
+    Scratch sc(nullptr);
     uint32_t *bad;
     DPS_TRY(sc.get(&bad, 1));
     DPS_TRY(hip_status(hipMemsetAsync(bad, 0, sizeof(uint32_t), s), "hipMemsetAsync"));
@@ -563,7 +583,7 @@ dps_status check_inputs(const float *p, const float *n, const float *A, const fl
 
 dps_status build_tree(dps_tree_s *t, const float *p, const float *n, const float *A, hipStream_t s) {
     const int64_t M = t->M;
-    Scratch sc;
+    Scratch sc(t);
 
     // bounding box and Morton codes
     uint32_t *box, *err;
@@ -690,8 +710,9 @@ dps_status build_tree(dps_tree_s *t, const float *p, const float *n, const float
 
     // points, node geometry, escape pointers, records
     DPS_TRY(tree_alloc(t, &t->pts, M));
+    DPS_TRY(tree_alloc(t, &t->nrm, 3 * M));
     DPS_TRY(tree_alloc(t, &t->nodes, N));
-    k_points<<<grid(M), kThreads, 0, s>>>(p, n, A, t->perm, M, t->pts);
+    k_points<<<grid(M), kThreads, 0, s>>>(p, n, A, t->perm, M, t->pts, t->nrm);
     DPS_LAUNCHED("points");
     double *nA, *nS;
     uint32_t *esc;

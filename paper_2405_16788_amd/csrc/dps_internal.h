@@ -4,7 +4,10 @@
 //   NodeRec  [N]      32 B: centroid, squared radius, link fields (one 8-dword scalar load)
 //   PointRec [M]      32 B: position, A*n, A (one 8-dword scalar load)
 //   moments  [N][ms]  node dipoles D_t = sum A_m mu_m n_m, channel-major 3-vectors,
-//                     FP32 (ms = 3C) or BF16 (ms = 3C rounded up to even)
+//                     FP32 (ms = 3C), or with BF16 storage (ms = 3C rounded up to
+//                     even) the first nhi nodes (levels <= kTopLevels) as FP32 rows of
+//                     ms floats followed by BF16 rows: node t >= nhi at bf16 element
+//                     (t + nhi) * ms
 //   attrs    [M][as]  point attributes, FP32 (as = C) or BF16 (as = C rounded up to even)
 #pragma once
 
@@ -120,11 +123,13 @@ struct KernelParams {
     float k7;        // 1/(4 pi eps^7)
     float ke4;       // 1/(pi^1.5 eps^4):   d kappa / d eps = -exp(-t^2) ke4
     float ke6;       // 2/(pi^1.5 eps^6):   d lambda / d eps = -exp(-t^2) ke6
+    uint32_t nhi;    // BF16 storage: nodes [0, nhi) keep FP32 moments (0 otherwise)
 };
 
 __host__ inline KernelParams make_kernel_params(float eps) {
     KernelParams kp;
     kp.eps = eps;
+    kp.nhi = 0;
     if (eps > 0.0f) {
         double e = eps;
         kp.ieps = (float)(1.0 / e);
@@ -175,7 +180,7 @@ __device__ __forceinline__ float exp_neg(float u) {
 // rho and psi for t^2 = u in [1, 20.25]: with e = exp(-t^2),
 // 1 - rho = erfc(t) + (2/sqrt pi) t e = e (erfcx(t) + (2/sqrt pi) t), so one
 // exponential serves both terms and rho has no cancellation worse than 1.4x
-__device__ __forceinline__ void rho_psi_erfcx(float u, float t, float &rho, float &psi, float &e) {
+__device__ __forceinline__ float rho_erfcx(float u, float t, float &e) {
     e = exp_neg(u);
     const float s = __builtin_amdgcn_rcpf(fmaf(0.5f, t, 1.0f));
     float r = fmaf(kErfcx7, s, kErfcx6);
@@ -185,7 +190,11 @@ __device__ __forceinline__ void rho_psi_erfcx(float u, float t, float &rho, floa
     r = fmaf(r, s, kErfcx2);
     r = fmaf(r, s, kErfcx1);
     r = fmaf(r, s, kErfcx0);
-    rho = fmaf(-e, fmaf(k2SqrtPi, t, r), 1.0f);
+    return fmaf(-e, fmaf(k2SqrtPi, t, r), 1.0f);
+}
+
+__device__ __forceinline__ void rho_psi_erfcx(float u, float t, float &rho, float &psi, float &e) {
+    rho = rho_erfcx(u, t, e);
     psi = fmaf(3.0f, rho, -(k4SqrtPi * (t * u) * e));
 }
 
@@ -218,6 +227,27 @@ __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &
                 rho_psi_erfcx(u, r2 * ir * kp.ieps, rho, psi, e);
                 kappa = kappa * rho;
                 lambda = kInv4Pi * ir * ir2 * ir2 * psi;
+            }
+        }
+    }
+    return true;
+}
+
+// kappa alone, same branches as radial() (the adjoint's node and point
+// increments need no lambda when dL/dx comes from the forward's gradients)
+__device__ __forceinline__ bool radial_k(float r2, const KernelParams &kp, float &kappa) {
+    if (kp.eps == 0.0f && !(r2 > 0.0f)) return false;
+    const float ir = __builtin_amdgcn_rsqf(r2);
+    const float ir2 = ir * ir;
+    kappa = kInv4Pi * ir * ir2;
+    if (kp.eps > 0.0f) {
+        const float u = r2 * kp.ieps2;
+        if (u < kFarT2) {
+            if (u < kSeriesWideT2) {
+                kappa = kp.k3 * series_rho_t3(u);
+            } else {
+                float e;
+                kappa = kappa * rho_erfcx(u, r2 * ir * kp.ieps, e);
             }
         }
     }

@@ -59,7 +59,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float Qc[CB];
-    load_attrs<CB, BF16>(mom, ms, 0, c0, Qc);
+    load_charges<CB, BF16>(mom, ms, 0, c0, Qc, kp.nhi);
     uint32_t steps = 0;
     for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
@@ -86,7 +86,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
         const uint32_t pf = next == kEnd ? t : next;
         const NodeRec nn = nodes[pf];
         float Qn[CB];
-        load_attrs<CB, BF16>(mom, ms, pf, c0, Qn);
+        load_charges<CB, BF16>(mom, ms, pf, c0, Qn, kp.nhi);
         if (any_far) {
 #pragma unroll
             for (int i = 0; i < K; ++i) {
@@ -218,7 +218,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float Qc[CB];
-    load_attrs<CB, BF16>(mom, ms, 0, c0, Qc);
+    load_charges<CB, BF16>(mom, ms, 0, c0, Qc, kp.nhi);
     uint32_t steps = 0;
     for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
@@ -245,7 +245,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
         const uint32_t pf = next == kEnd ? t : next;
         const NodeRec nn = nodes[pf];
         float Qn[CB];
-        load_attrs<CB, BF16>(mom, ms, pf, c0, Qn);
+        load_charges<CB, BF16>(mom, ms, pf, c0, Qn, kp.nhi);
         if (any_far) {
             // node increment sum_q df_c m, first over the lane's queries
             float acc[CB];
@@ -398,7 +398,7 @@ constexpr int kMonoAdjointBudget = 40;  // df per channel and dL/dx
 template <int CB, bool BF, bool GR, int K>
 dps_status mono_query_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2,
                              KernelParams kp, Sub sb, float *f, float *g, hipStream_t s) {
-    const uint32_t lim = (uint32_t)t->N;
+    const uint32_t lim = walk_limit(t);
     if (t->launch_flags & kFlagPersistentQuery) {
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_mono_query_persistent<CB, BF, GR, K>);
@@ -451,7 +451,7 @@ dps_status mono_query_block(dps_tree_s *t, const float *x, int64_t Q, const int6
 template <int CB, bool BF, int K>
 dps_status mono_adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2,
                                KernelParams kp, Sub sb, const float *df, float *dx, int dx_mode, hipStream_t s) {
-    const uint32_t lim = (uint32_t)t->N;
+    const uint32_t lim = walk_limit(t);
     if (t->launch_flags & kFlagPersistentAdjoint) {
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_mono_adjoint_persistent<CB, BF, K>);
@@ -500,7 +500,7 @@ dps_status mono_adjoint_block(dps_tree_s *t, const float *x, int64_t Q, const in
 dps_status launch_query_mono(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                              int cbegin, int nc, float *f, float *g, hipStream_t s) {
     const float b2 = mul_rn(beta, beta);
-    const KernelParams kp = make_kernel_params(eps);
+    const KernelParams kp = tree_kernel_params(t, eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
         const int cb = mono_block(cbegin + nc - c0, g != nullptr);
         const Sub sb{c0, nc, c0 - cbegin};
@@ -524,7 +524,7 @@ dps_status launch_query_mono(dps_tree_s *t, const float *x, int64_t Q, const int
 dps_status launch_adjoint_mono(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                                int cbegin, int nc, const float *df, float *dx, hipStream_t s) {
     const float b2 = mul_rn(beta, beta);
-    const KernelParams kp = make_kernel_params(eps);
+    const KernelParams kp = tree_kernel_params(t, eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
         const int cb = mono_block(cbegin + nc - c0, false);
         const int dx_mode = dx ? (c0 == cbegin ? 1 : 2) : 0;

@@ -6,9 +6,11 @@
 //
 // Bottom-up, one launch per level, every node summing its points (leaves, in
 // Morton order) or its children (internal nodes, in child order): deterministic.
-// Accumulation is FP32, except nodes of depth <= 3 in trees of >= 4,194,304
-// points, which accumulate in FP64.  The stored copy is FP32 or BF16 (RNE); the
-// working sums are kept separately so rounding never compounds up the tree.
+// Accumulation is compensated FP32 (a high and a low part per sum), except
+// nodes of depth <= 3 in trees of >= 4,194,304 points, which accumulate in
+// FP64.  The stored copy is the working sum rounded once: FP32, or BF16 (RNE)
+// with the nodes of depth <= 3 kept in FP32; the working sums are kept
+// separately so rounding never compounds up the tree.
 #include <algorithm>
 
 #include "dps_tree.h"
@@ -33,84 +35,126 @@ __global__ void k_gather_attrs(const float *__restrict__ attrs, const uint32_t *
     else ((float *)out)[i] = v;
 }
 
+// Compensated FP32 accumulation: a working sum is a pair (h, l) whose value
+// is h + l.  Each addend is itself a pair; two_sum gives the exact rounding
+// error of h + a_hi (Knuth), which joins the low part.  Contraction is off so
+// that every operation rounds once as written.
+__device__ __forceinline__ void acc2(float &h, float &l, float a_hi, float a_lo) {
+#pragma clang fp contract(off)
+    const float s = h + a_hi;
+    const float bp = s - h;
+    const float e = (h - (s - bp)) + (a_hi - bp);
+    h = s;
+    l = l + (e + a_lo);
+}
+
+// a * b * c of three FP32 values as hi + lo: a * b = p + pe exactly (FMA
+// residual), p * c = hi + its FMA residual exactly; only pe * c rounds (2^-48
+// of the product).
+__device__ __forceinline__ void prod3(float a, float b, float c, float &hi, float &lo) {
+#pragma clang fp contract(off)
+    const float p = a * b;
+    const float pe = fmaf(a, b, -p);
+    hi = p * c;
+    lo = fmaf(pe, c, fmaf(p, c, -hi));
+}
+
 // one thread per (node, channel) of the level [nb, ne).  KW = 3: the dipole
 // D_t = sum A_m mu_m n_m; KW = 1: the monopole charge Q_t = sum A_m mu_m.
+// Leaves sum their points' products A_m mu_m n_m (computed from A, mu and the
+// unit normal, not from the rounded A n of the point records), internal nodes
+// their children's working sums, in a fixed order, compensated in FP32 (or in
+// FP64 for the top levels of large trees, `wide`).  The stored value is the
+// working sum rounded once to FP32, and then to BF16 for nodes past the nhi
+// FP32 rows of BF16 storage.
 template <bool BF16, int KW>
-__global__ void k_moments(int64_t nb, int64_t ne, int C, int ms, bool wide, int64_t n_top,
+__global__ void k_moments(int64_t nb, int64_t ne, int C, int ms, bool wide, int64_t n_top, int64_t nhi,
                           const float *__restrict__ attrs, const uint32_t *__restrict__ perm,
-                          const PointRec *__restrict__ pts, const int32_t *__restrict__ first_child,
-                          const int32_t *__restrict__ nchild, const int32_t *__restrict__ ptb,
-                          const int32_t *__restrict__ ptc, float *__restrict__ momw,
-                          double *__restrict__ momw64, void *__restrict__ mom) {
+                          const PointRec *__restrict__ pts, const float *__restrict__ nrm,
+                          const int32_t *__restrict__ first_child, const int32_t *__restrict__ nchild,
+                          const int32_t *__restrict__ ptb, const int32_t *__restrict__ ptc,
+                          float *__restrict__ momw, float *__restrict__ momw_lo, double *__restrict__ momw64,
+                          void *__restrict__ mom) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (ne - nb) * C) return;
     const int64_t t = nb + i / C;
     const int c = (int)(i % C);
-    double out[KW];
-    if (nchild[t] == 0) {
-        const int64_t jb = ptb[t], je = jb + ptc[t];
-        if (wide) {
-            double a[KW] = {};
+    const int64_t o = t * KW * C + KW * c;
+    float hi[KW], lo[KW];
+    if (wide) {
+        double a[KW] = {};
+        if (nchild[t] == 0) {
+            const int64_t jb = ptb[t], je = jb + ptc[t];
             for (int64_t j = jb; j < je; ++j) {
-                const double mu = attrs[(int64_t)perm[j] * C + c];
+                const double am = (double)pts[j].a * (double)attrs[(int64_t)perm[j] * C + c];  // exact
                 if constexpr (KW == 3) {
-                    a[0] += mu * (double)pts[j].anx;
-                    a[1] += mu * (double)pts[j].any;
-                    a[2] += mu * (double)pts[j].anz;
+                    for (int k = 0; k < 3; ++k) a[k] += am * (double)nrm[3 * j + k];
                 } else {
-                    a[0] += mu * (double)pts[j].a;
+                    a[0] += am;
                 }
             }
-            for (int k = 0; k < KW; ++k) out[k] = a[k];
         } else {
-            float a[KW] = {};
-            for (int64_t j = jb; j < je; ++j) {
-                const float mu = attrs[(int64_t)perm[j] * C + c];
-                if constexpr (KW == 3) {
-                    a[0] += mu * pts[j].anx;
-                    a[1] += mu * pts[j].any;
-                    a[2] += mu * pts[j].anz;
-                } else {
-                    a[0] += mu * pts[j].a;
-                }
+            const int64_t cb = first_child[t], ce = cb + nchild[t];
+            for (int64_t ch = cb; ch < ce; ++ch) {
+                const int64_t oc = ch * KW * C + KW * c;
+                for (int k = 0; k < KW; ++k)
+                    a[k] += ch < n_top ? momw64[oc + k] : (double)momw[oc + k] + (double)momw_lo[oc + k];
             }
-            for (int k = 0; k < KW; ++k) out[k] = a[k];
+        }
+        for (int k = 0; k < KW; ++k) {
+            momw64[o + k] = a[k];
+            hi[k] = (float)a[k];
+            lo[k] = (float)(a[k] - (double)hi[k]);
         }
     } else {
-        const int64_t cb = first_child[t], ce = cb + nchild[t];
-        if (wide) {
-            double a[KW] = {};
-            for (int64_t ch = cb; ch < ce; ++ch) {
-                const int64_t o = ch * KW * C + KW * c;
-                for (int k = 0; k < KW; ++k) a[k] += ch < n_top ? momw64[o + k] : (double)momw[o + k];
+        for (int k = 0; k < KW; ++k) hi[k] = lo[k] = 0.0f;
+        if (nchild[t] == 0) {
+            const int64_t jb = ptb[t], je = jb + ptc[t];
+            for (int64_t j = jb; j < je; ++j) {
+                const float am = pts[j].a, mu = attrs[(int64_t)perm[j] * C + c];
+                if constexpr (KW == 3) {
+                    for (int k = 0; k < 3; ++k) {
+                        float ph, pl;
+                        prod3(am, mu, nrm[3 * j + k], ph, pl);
+                        acc2(hi[k], lo[k], ph, pl);
+                    }
+                } else {
+                    const float ph = mul_rn(am, mu);
+                    acc2(hi[0], lo[0], ph, fmaf(am, mu, -ph));
+                }
             }
-            for (int k = 0; k < KW; ++k) out[k] = a[k];
         } else {
-            float a[KW] = {};
+            const int64_t cb = first_child[t], ce = cb + nchild[t];
             for (int64_t ch = cb; ch < ce; ++ch) {
-                const int64_t o = ch * KW * C + KW * c;
-                for (int k = 0; k < KW; ++k) a[k] += momw[o + k];
+                const int64_t oc = ch * KW * C + KW * c;
+                for (int k = 0; k < KW; ++k) acc2(hi[k], lo[k], momw[oc + k], momw_lo[oc + k]);
             }
-            for (int k = 0; k < KW; ++k) out[k] = a[k];
         }
     }
-    const int64_t o = t * KW * C + KW * c;
+    const bool f32row = !BF16 || t < nhi;
     for (int k = 0; k < KW; ++k) {
-        if (wide) momw64[o + k] = out[k];
-        momw[o + k] = (float)out[k];
-        const int64_t so = t * ms + KW * c + k;
-        if (BF16) ((uint16_t *)mom)[so] = f32_to_bf16((float)out[k]);
-        else ((float *)mom)[so] = (float)out[k];
+        momw[o + k] = hi[k];
+        momw_lo[o + k] = lo[k];
+        float v;
+        if (wide) v = (float)momw64[o + k];
+        else {
+#pragma clang fp contract(off)
+            v = hi[k] + lo[k];
+        }
+        if (f32row) ((float *)mom)[t * ms + KW * c + k] = v;
+        else ((uint16_t *)mom)[(t + nhi) * ms + KW * c + k] = f32_to_bf16(v);
     }
-    if (BF16 && c == C - 1 && ms > KW * C) ((uint16_t *)mom)[t * ms + KW * C] = 0;
+    if (c == C - 1 && ms > KW * C) {  // row padding
+        if (f32row) ((float *)mom)[t * ms + KW * C] = 0.0f;
+        else ((uint16_t *)mom)[(t + nhi) * ms + KW * C] = 0;
+    }
 }
 
 template <bool BF16, int KW>
 void launch_moments(dps_tree_s *t, int64_t nb, int64_t ne, bool wide, const float *attrs, hipStream_t s) {
-    k_moments<BF16, KW><<<grid((ne - nb) * t->C), kThreads, 0, s>>>(nb, ne, t->C, t->mom_stride, wide, t->n_top,
-                                                                    attrs, t->perm, t->pts, t->first_child,
-                                                                    t->nchild, t->ptb, t->ptc, t->momw, t->momw64,
-                                                                    t->mom);
+    k_moments<BF16, KW><<<grid((ne - nb) * t->C), kThreads, 0, s>>>(
+        nb, ne, t->C, t->mom_stride, wide, t->n_top, BF16 ? t->n_top : 0, attrs, t->perm, t->pts, t->nrm,
+        t->first_child, t->nchild, t->ptb, t->ptc, t->momw, t->momw_lo, t->momw64, t->mom);
 }
 
 }  // namespace

@@ -14,21 +14,44 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Node moments of channels [c0, c0 + CB) of node t (wave-uniform), as
+// floats.  BF16 storage keeps the first nhi nodes (the top levels, whose
+// moments dominate queries that use few far-field sources) as FP32 rows.
 template <int CB, bool BF16>
 __device__ __forceinline__ void load_moments(const void *__restrict__ mom, int ms, uint32_t t, int c0,
-                                             float (&D)[3 * CB]) {
-    if constexpr (!BF16) {
+                                             float (&D)[3 * CB], uint32_t nhi) {
+    if (!BF16 || t < nhi) {
         const float *b = (const float *)mom + (size_t)t * ms + 3 * c0;
 #pragma unroll
         for (int i = 0; i < 3 * CB; ++i) D[i] = b[i];
     } else {
-        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)t * ms + 3 * c0);
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)(t + nhi) * ms + 3 * c0);
         constexpr int W = (3 * CB + 1) / 2;
         uint32_t w[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) w[i] = b[i];
 #pragma unroll
         for (int i = 0; i < 3 * CB; ++i) D[i] = (i & 1) ? bf16_hi(w[i >> 1]) : bf16_lo(w[i >> 1]);
+    }
+}
+
+// Scalar node charges (monopole trees) of channels [c0, c0 + CB), same layout
+// rules as load_moments with one component per channel.
+template <int CB, bool BF16>
+__device__ __forceinline__ void load_charges(const void *__restrict__ mom, int ms, uint32_t t, int c0,
+                                             float (&Q)[CB], uint32_t nhi) {
+    if (!BF16 || t < nhi) {
+        const float *b = (const float *)mom + (size_t)t * ms + c0;
+#pragma unroll
+        for (int i = 0; i < CB; ++i) Q[i] = b[i];
+    } else {
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)(t + nhi) * ms + c0);
+        constexpr int W = (CB + 1) / 2;
+        uint32_t w[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) w[i] = b[i];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) Q[i] = (i & 1) ? bf16_hi(w[i >> 1]) : bf16_lo(w[i >> 1]);
     }
 }
 

@@ -58,7 +58,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float D[3 * CB];
-    load_moments<CB, BF16>(mom, ms, 0, c0, D);
+    load_moments<CB, BF16>(mom, ms, 0, c0, D, kp.nhi);
     uint32_t steps = 0;
     for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
@@ -77,7 +77,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         const uint32_t pf = next == kEnd ? t : next;
         const NodeRec nn = nodes[pf];
         float Dn[3 * CB];
-        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+        load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far && far) {
             float kap, lam;
             radial(s, kp, kap, lam);
@@ -192,7 +192,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
         uint32_t t = 0;
         NodeRec nd = nodes[0];
         float D[3 * CB];
-        load_moments<CB, BF16>(mom, ms, 0, c0, D);
+        load_moments<CB, BF16>(mom, ms, 0, c0, D, kp.nhi);
         uint32_t steps = 0;
         for (;;) {
             if (++steps > limit) {  // a well-formed tree is walked in at most N steps
@@ -219,7 +219,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
             const uint32_t pf = next == kEnd ? t : next;
             const NodeRec nn = nodes[pf];
             float Dn[3 * CB];
-            load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+            load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
             if (any_far) {
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
@@ -403,12 +403,21 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
 
 // ---------------------------------------------------------------------------
 // adjoint stage 1 (Algorithm 1, AdjointQuery): node accumulators G[N][C][3]
-// (eq. farfield_gradient), point accumulators P[M][C], dL/dx per query
+// (eq. farfield_gradient), point accumulators P[M][C], dL/dx per query.
+//
+// DX: dL/dx = sum_c df_c grad D_c is formed in the walk from the same
+// accepted sources.  Without DX the walk only accumulates the node and point
+// increments (kappa alone per term); dL/dx is then either not wanted
+// (dx_mode 0) or formed from the gradients the forward query already
+// computed at these points (gin [Q][ldo][3], same tree state, beta and eps):
+// the identical sum, 3 CB multiply-adds per query instead of a second
+// evaluation of every term's gradient.
 // ---------------------------------------------------------------------------
-template <int CB, bool BF16, int K>
+template <int CB, bool BF16, int K, bool DX>
 __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C, const float *__restrict__ df,
                                              double *__restrict__ G, double *__restrict__ P,
-                                             float *__restrict__ dxout, int dx_mode) {
+                                             float *__restrict__ dxout, int dx_mode,
+                                             const float *__restrict__ gin) {
     const int lane = lane_id();
     float px[K], py[K], pz[K], w[K][CB], ax[K], ay[K], az[K];
     uint32_t bits[K];
@@ -427,7 +436,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float D[3 * CB];
-    load_moments<CB, BF16>(mom, ms, 0, c0, D);
+    load_moments<CB, BF16>(mom, ms, 0, c0, D, kp.nhi);
     uint32_t steps = 0;
     for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
@@ -454,7 +463,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         const uint32_t pf = next == kEnd ? t : next;
         const NodeRec nn = nodes[pf];
         float Dn[3 * CB];
-        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+        load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far) {
             // node increment sum_q df_c kappa (p_t - x_q), first over the lane's queries
             float acc[3 * CB];
@@ -463,25 +472,30 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 if (far[i]) {
-                    float kap, lam;
-                    radial(s[i], kp, kap, lam);
+                    float kap, lam = 0.0f;
+                    if constexpr (DX) radial(s[i], kp, kap, lam);
+                    else radial_k(s[i], kp, kap);
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
                     float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
                     // kappa (p_t - x_q) once, then one FMA per channel and axis
                     const float kx = kap * dx, ky = kap * dy, kz = kap * dz;
 #pragma unroll
                     for (int c = 0; c < CB; ++c) {
-                        E0 += w[i][c] * D[3 * c];
-                        E1 += w[i][c] * D[3 * c + 1];
-                        E2 += w[i][c] * D[3 * c + 2];
+                        if constexpr (DX) {
+                            E0 += w[i][c] * D[3 * c];
+                            E1 += w[i][c] * D[3 * c + 1];
+                            E2 += w[i][c] * D[3 * c + 2];
+                        }
                         acc[3 * c] = fmaf(w[i][c], kx, acc[3 * c]);
                         acc[3 * c + 1] = fmaf(w[i][c], ky, acc[3 * c + 1]);
                         acc[3 * c + 2] = fmaf(w[i][c], kz, acc[3 * c + 2]);
                     }
-                    const float les = lam * (E0 * dx + E1 * dy + E2 * dz);
-                    ax[i] = fmaf(-kap, E0, fmaf(les, dx, ax[i]));
-                    ay[i] = fmaf(-kap, E1, fmaf(les, dy, ay[i]));
-                    az[i] = fmaf(-kap, E2, fmaf(les, dz, az[i]));
+                    if constexpr (DX) {
+                        const float les = lam * (E0 * dx + E1 * dy + E2 * dz);
+                        ax[i] = fmaf(-kap, E0, fmaf(les, dx, ax[i]));
+                        ay[i] = fmaf(-kap, E1, fmaf(les, dy, ay[i]));
+                        az[i] = fmaf(-kap, E2, fmaf(les, dz, az[i]));
+                    }
                 }
             }
             scatter_add_node(acc, lane, &G[((size_t)t * C + c0) * 3]);
@@ -505,21 +519,24 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                         if (open[i]) {
                             const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
                             const float r2 = dx * dx + dy * dy + dz * dz;
-                            float kap, lam;
-                            if (radial(r2, kp, kap, lam)) {
+                            float kap, lam = 0.0f;
+                            const bool term = DX ? radial(r2, kp, kap, lam) : radial_k(r2, kp, kap);
+                            if (term) {
                                 const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
                                 const float ks = kap * sa;
                                 float wm = 0.0f;
 #pragma unroll
                                 for (int c = 0; c < CB; ++c) {
-                                    wm += w[i][c] * mu[c];
+                                    if constexpr (DX) wm += w[i][c] * mu[c];
                                     acc[c] += w[i][c] * ks;
                                 }
-                                const float les = lam * sa * wm;
-                                const float kw = kap * wm;
-                                ax[i] = fmaf(-kw, pr.anx, fmaf(les, dx, ax[i]));
-                                ay[i] = fmaf(-kw, pr.any, fmaf(les, dy, ay[i]));
-                                az[i] = fmaf(-kw, pr.anz, fmaf(les, dz, az[i]));
+                                if constexpr (DX) {
+                                    const float les = lam * sa * wm;
+                                    const float kw = kap * wm;
+                                    ax[i] = fmaf(-kw, pr.anx, fmaf(les, dx, ax[i]));
+                                    ay[i] = fmaf(-kw, pr.any, fmaf(les, dy, ay[i]));
+                                    az[i] = fmaf(-kw, pr.anz, fmaf(les, dz, az[i]));
+                                }
                             }
                         }
                     }
@@ -538,6 +555,19 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         for (int i = 0; i < K; ++i) {
             const int64_t q = q0 + 64 * i;
             if (q < Q) {
+                if constexpr (!DX) {  // sum_c df_c grad D_c from the forward's gradients
+                    const float *gq = gin + 3 * (q * ldo + co);
+                    float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) {
+                        gx = fmaf(w[i][c], gq[3 * c], gx);
+                        gy = fmaf(w[i][c], gq[3 * c + 1], gy);
+                        gz = fmaf(w[i][c], gq[3 * c + 2], gz);
+                    }
+                    ax[i] = gx;
+                    ay[i] = gy;
+                    az[i] = gz;
+                }
                 if (dx_mode == 1) {
                     dxout[3 * q] = ax[i];
                     dxout[3 * q + 1] = ay[i];
@@ -552,15 +582,17 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
     }
 }
 
-template <int CB, bool BF16, int K>
+template <int CB, bool BF16, int K, bool DX>
 __global__ __launch_bounds__(kThreads) void k_adjoint(DPS_KERN_PARAMS, int C, const float *__restrict__ df,
                                                       double *__restrict__ G, double *__restrict__ P,
-                                                      float *__restrict__ dxout, int dx_mode, int xcd_remap) {
+                                                      float *__restrict__ dxout, int dx_mode,
+                                                      const float *__restrict__ gin, int xcd_remap) {
     DPS_ROWS;
     const int64_t blk = remap_block(xcd_remap);
     if (blk < 0 || blk * (int64_t)blockDim.x * K >= Q) return;  // whole block past the rows
     const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
-    adjoint_body<CB, BF16, K>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout, dx_mode);
+    adjoint_body<CB, BF16, K, DX>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout, dx_mode,
+                                  gin);
 }
 
 // resident waves per SIMD requested for the 4-query, 4-channel persistent
@@ -568,12 +600,17 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(DPS_KERN_PARAMS, int C, co
 #ifndef DPS_ADJOINT_WAVES
 #define DPS_ADJOINT_WAVES 5
 #endif
+// the same without the in-walk dL/dx (fewer live registers)
+#ifndef DPS_ADJOINT_WAVES_NODX
+#define DPS_ADJOINT_WAVES_NODX 5
+#endif
 
-template <int CB, bool BF16, int K>
-__global__ __launch_bounds__(kThreads, (CB == 4 && K == 4) ? DPS_ADJOINT_WAVES : 1) void k_adjoint_persistent(DPS_KERN_PARAMS, int C,
+template <int CB, bool BF16, int K, bool DX>
+__global__ __launch_bounds__(kThreads, (CB == 4 && K == 4) ? (DX ? DPS_ADJOINT_WAVES : DPS_ADJOINT_WAVES_NODX) : 1) void k_adjoint_persistent(DPS_KERN_PARAMS, int C,
                                                                  const float *__restrict__ df,
                                                                  double *__restrict__ G, double *__restrict__ P,
                                                                  float *__restrict__ dxout, int dx_mode,
+                                                                 const float *__restrict__ gin,
                                                                  uint32_t *__restrict__ ctr) {
     DPS_ROWS;
     const int64_t ntiles = (Q + 64 * K - 1) / (64 * K);
@@ -581,7 +618,8 @@ __global__ __launch_bounds__(kThreads, (CB == 4 && K == 4) ? DPS_ADJOINT_WAVES :
     for (;;) {
         const int64_t tile = next_tile(ctr, ntiles, part);
         if (tile < 0) break;
-        adjoint_body<CB, BF16, K>(tile * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout, dx_mode);
+        adjoint_body<CB, BF16, K, DX>(tile * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout,
+                                      dx_mode, gin);
     }
 }
 
@@ -630,7 +668,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float D[3 * CB];
-    load_moments<CB, BF16>(mom, ms, 0, c0, D);
+    load_moments<CB, BF16>(mom, ms, 0, c0, D, kp.nhi);
     uint32_t steps = 0;
     for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
@@ -657,7 +695,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         const uint32_t pf = next == kEnd ? t : next;
         const NodeRec nn = nodes[pf];
         float Dn[3 * CB];
-        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+        load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far) {
             float acc[3 * CB];
 #pragma unroll
@@ -875,7 +913,7 @@ __global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ 
 
 // new normals: A n of every point record (sorted order), from caller order
 __global__ void k_set_normals(const float *__restrict__ n, const uint32_t *__restrict__ perm, int64_t M,
-                              PointRec *__restrict__ pts) {
+                              PointRec *__restrict__ pts, float *__restrict__ nrm) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
     const int64_t i = perm[j];
@@ -883,6 +921,9 @@ __global__ void k_set_normals(const float *__restrict__ n, const uint32_t *__res
     pts[j].anx = mul_rn(a, n[3 * i]);
     pts[j].any = mul_rn(a, n[3 * i + 1]);
     pts[j].anz = mul_rn(a, n[3 * i + 2]);
+    nrm[3 * j] = n[3 * i];
+    nrm[3 * j + 1] = n[3 * i + 1];
+    nrm[3 * j + 2] = n[3 * i + 2];
 }
 
 
@@ -953,7 +994,7 @@ __global__ void k_export_nodes(int64_t N, const int32_t *__restrict__ lvl, const
 }
 
 template <bool BF16>
-__global__ void k_export_moments(int64_t N, int C, int kw, int ms, const void *__restrict__ mom,
+__global__ void k_export_moments(int64_t N, int C, int kw, int ms, int64_t nhi, const void *__restrict__ mom,
                                  float *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t w3 = 3 * (int64_t)C;
@@ -964,9 +1005,9 @@ __global__ void k_export_moments(int64_t N, int C, int kw, int ms, const void *_
         out[i] = 0.0f;
         return;
     }
-    const int64_t e = t * ms + (kw == 1 ? k / 3 : k);
-    if (BF16) out[i] = __uint_as_float((uint32_t)((const uint16_t *)mom)[e] << 16);
-    else out[i] = ((const float *)mom)[e];
+    const int64_t e = (kw == 1 ? k / 3 : k);
+    if (BF16 && t >= nhi) out[i] = __uint_as_float((uint32_t)((const uint16_t *)mom)[(t + nhi) * ms + e] << 16);
+    else out[i] = ((const float *)mom)[t * ms + e];
 }
 
 
@@ -984,7 +1025,7 @@ inline int clamp_packet(int k, int cb, bool grad) {
 template <int CB, bool BF, bool GR, int K>
 dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
                         float *f, float *g, hipStream_t s) {
-    const uint32_t lim = (uint32_t)t->N;
+    const uint32_t lim = walk_limit(t);
     if (t->launch_flags & kFlagPersistentQuery) {
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_query_persistent<CB, BF, GR, K>);
@@ -1035,7 +1076,7 @@ dps_status grid_launch(dps_tree_s *t, const GridSpec &gs, int64_t Q, float b2, K
     const void *fn = reinterpret_cast<const void *>(&k_query_grid<CB, BF, GR, K>);
     k_query_grid<CB, BF, GR, K><<<persistent_grid(fn), kThreads, 0, s>>>(
         t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, nullptr, Q, nullptr, b2, kp, sb.c0, sb.ldo,
-        sb.co, (uint32_t)t->N, t->err, f, g, gs, t->ctr);
+        sb.co, walk_limit(t), t->err, f, g, gs, t->ctr);
     return hip_status(hipGetLastError(), "grid query launch");
 }
 
@@ -1064,47 +1105,55 @@ dps_status grid_block(dps_tree_s *t, const GridSpec &gs, int64_t Q, float b2, Ke
     return grid_k<CB, false, false>(t, gs, Q, b2, kp, sb, f, g, s);
 }
 
-template <int CB, bool BF, int K>
+template <int CB, bool BF, int K, bool DX>
 dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
-                          const float *df, float *dx, int dx_mode, hipStream_t s) {
-    const uint32_t lim = (uint32_t)t->N;
+                          const float *df, float *dx, int dx_mode, const float *gin, hipStream_t s) {
+    const uint32_t lim = walk_limit(t);
     if (t->launch_flags & kFlagPersistentAdjoint) {
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
-        const void *fn = reinterpret_cast<const void *>(&k_adjoint_persistent<CB, BF, K>);
-        k_adjoint_persistent<CB, BF, K><<<persistent_grid(fn), kThreads, 0, s>>>(
+        const void *fn = reinterpret_cast<const void *>(&k_adjoint_persistent<CB, BF, K, DX>);
+        k_adjoint_persistent<CB, BF, K, DX><<<persistent_grid(fn), kThreads, 0, s>>>(
             t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
-            lim, t->err, t->C, df, t->G, t->P, dx, dx_mode, t->ctr + 8);
+            lim, t->err, t->C, df, t->G, t->P, dx, dx_mode, gin, t->ctr + 8);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdAdjoint) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
-        k_adjoint<CB, BF, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
-                                                     t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co, lim,
-                                                     t->err, t->C, df, t->G, t->P, dx, dx_mode,
-                                                     remap ? (int)nb : 0);
+        k_adjoint<CB, BF, K, DX><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+                                                         t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co, lim,
+                                                         t->err, t->C, df, t->G, t->P, dx, dx_mode, gin,
+                                                         remap ? (int)nb : 0);
     }
     return hip_status(hipGetLastError(), "adjoint launch");
 }
 
+// dL/dx in the walk (DX) only when it is wanted and no forward gradients are given
+template <int CB, bool BF, int K>
+dps_status adjoint_launch_dx(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp,
+                             Sub sb, const float *df, float *dx, int dx_mode, const float *gin, hipStream_t s) {
+    if (dx_mode != 0 && !gin) return adjoint_launch<CB, BF, K, true>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
+    return adjoint_launch<CB, BF, K, false>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
+}
+
 template <int CB>
 dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
-                         const float *df, float *dx, int dx_mode, hipStream_t s) {
+                         const float *df, float *dx, int dx_mode, const float *gin, hipStream_t s) {
     const int k = clamp_packet(t->packet_adjoint, CB, false);
     if (t->storage == DPS_STORE_BF16) {
-        if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, true, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); }
-        if (k >= 2) return adjoint_launch<CB, true, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
-        return adjoint_launch<CB, true, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
+        if (k == 4) { if constexpr (CB <= 4) return adjoint_launch_dx<CB, true, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); }
+        if (k >= 2) return adjoint_launch_dx<CB, true, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
+        return adjoint_launch_dx<CB, true, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
     }
-    if (k == 4) { if constexpr (CB <= 4) return adjoint_launch<CB, false, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); }
-    if (k >= 2) return adjoint_launch<CB, false, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
-    return adjoint_launch<CB, false, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s);
+    if (k == 4) { if constexpr (CB <= 4) return adjoint_launch_dx<CB, false, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); }
+    if (k >= 2) return adjoint_launch_dx<CB, false, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
+    return adjoint_launch_dx<CB, false, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
 }
 
 template <int CB, bool BF, int K, bool DF, bool EXT>
 dps_status adjoint_g_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp,
                             Sub sb, const float *df, const float *dg, float *dx, int dx_mode, double *pn,
                             double *eacc, hipStream_t s) {
-    const uint32_t lim = (uint32_t)t->N;
+    const uint32_t lim = walk_limit(t);
     if (t->launch_flags & kFlagPersistentAdjoint) {
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_adjoint_g_persistent<CB, BF, K, DF, EXT>);
@@ -1161,7 +1210,7 @@ dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, const int64_t 
                         int cbegin, int nc, float *f, float *g, hipStream_t s) {
     if (t->kernel == DPS_KERNEL_MONOPOLE) return launch_query_mono(t, x, Q, qdev, beta, eps, cbegin, nc, f, g, s);
     const float b2 = mul_rn(beta, beta);
-    const KernelParams kp = make_kernel_params(eps);
+    const KernelParams kp = tree_kernel_params(t, eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
         const int cb = next_block(cbegin + nc - c0);
         const Sub sb{c0, nc, c0 - cbegin};
@@ -1181,26 +1230,26 @@ dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, const int64_t 
 
 dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta, int32_t *counts,
                          hipStream_t s) {
-    k_counts<<<grid(Q), kThreads, 0, s>>>(t->nodes, x, Q, mul_rn(beta, beta), counts, (uint32_t)t->N, t->err);
+    k_counts<<<grid(Q), kThreads, 0, s>>>(t->nodes, x, Q, mul_rn(beta, beta), counts, walk_limit(t), t->err);
     return hip_status(hipGetLastError(), "counts launch");
 }
 
 dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
-                          int cbegin, int nc, const float *df, float *dx, hipStream_t s) {
+                          int cbegin, int nc, const float *df, float *dx, const float *gin, hipStream_t s) {
     if (t->kernel == DPS_KERNEL_MONOPOLE) return launch_adjoint_mono(t, x, Q, qdev, beta, eps, cbegin, nc, df, dx, s);
     const float b2 = mul_rn(beta, beta);
-    const KernelParams kp = make_kernel_params(eps);
+    const KernelParams kp = tree_kernel_params(t, eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
         const int cb = next_block(cbegin + nc - c0);
         const int dx_mode = dx ? (c0 == cbegin ? 1 : 2) : 0;
         const Sub sb{c0, nc, c0 - cbegin};
         dps_status st;
         switch (cb) {
-            case 8: st = adjoint_block<8>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
-            case 4: st = adjoint_block<4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
-            case 3: st = adjoint_block<3>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
-            case 2: st = adjoint_block<2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
-            default: st = adjoint_block<1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, s); break;
+            case 8: st = adjoint_block<8>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
+            case 4: st = adjoint_block<4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
+            case 3: st = adjoint_block<3>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
+            case 2: st = adjoint_block<2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
+            default: st = adjoint_block<1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
         }
         if (st != DPS_OK) return st;
         c0 += cb;
@@ -1236,10 +1285,10 @@ dps_status launch_export(dps_tree_s *t, int32_t *nodes, float *geom, float *mome
     }
     if (moments) {
         if (t->storage == DPS_STORE_BF16)
-            k_export_moments<true><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->kw, t->mom_stride, t->mom,
-                                                                                moments);
+            k_export_moments<true><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->kw, t->mom_stride,
+                                                                                t->n_top, t->mom, moments);
         else
-            k_export_moments<false><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->kw, t->mom_stride,
+            k_export_moments<false><<<grid(t->N * 3 * t->C), kThreads, 0, s>>>(t->N, t->C, t->kw, t->mom_stride, 0,
                                                                                  t->mom, moments);
         dps_status st = hip_status(hipGetLastError(), "export moments");
         if (st != DPS_OK) return st;
@@ -1251,7 +1300,7 @@ dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int6
                             int cbegin, int nc, const float *df, const float *dg, int want, float *dx,
                             hipStream_t s) {
     const float b2 = mul_rn(beta, beta);
-    const KernelParams kp = make_kernel_params(eps);
+    const KernelParams kp = tree_kernel_params(t, eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
         // blocks of at most 4 channels: each carries 4 floats per channel and query
         const int rem = cbegin + nc - c0;
@@ -1309,7 +1358,7 @@ dps_status launch_finalize_ext(dps_tree_s *t, float *dattrs, float *dnormals, do
 }
 
 dps_status launch_set_normals(dps_tree_s *t, const float *n, hipStream_t s) {
-    k_set_normals<<<grid(t->M), kThreads, 0, s>>>(n, t->perm, t->M, t->pts);
+    k_set_normals<<<grid(t->M), kThreads, 0, s>>>(n, t->perm, t->M, t->pts, t->nrm);
     return hip_status(hipGetLastError(), "set normals");
 }
 
@@ -1324,7 +1373,7 @@ dps_status launch_query_grid(dps_tree_s *t, const float origin[3], const float s
     }
     const int64_t Q = gs.nb[0] * gs.nb[1] * gs.nb[2] * 64;
     const float b2 = mul_rn(beta, beta);
-    const KernelParams kp = make_kernel_params(eps);
+    const KernelParams kp = tree_kernel_params(t, eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
         const int cb = next_block(cbegin + nc - c0);
         const Sub sb{c0, nc, c0 - cbegin};

@@ -25,11 +25,12 @@ struct dps_tree_s {
     int mom_stride;   // elements per node row of `mom`
     int attr_stride;  // elements per point row of `attr`
     int64_t level_start[dps::kLevels + 2];  // nodes of level l: [level_start[l], level_start[l+1])
-    int64_t n_top;    // nodes with level <= kTopLevels
+    int64_t n_top;    // nodes with level <= kTopLevels (FP32 moment rows of BF16 storage)
     bool wide_top;    // FP64 accumulation of top-level moments
     int packet_query;    // queries per lane in dps_query (1, 2, 4)
     int packet_adjoint;  // queries per lane in dps_adjoint_accumulate (1, 2, 4)
     int launch_flags;    // kFlag* bits: XCD-contiguous order / persistent launch per kernel
+    uint32_t step_limit; // nodes one traversal may walk (dps_set_step_limit; default N)
     uint32_t *ctr;       // [16] tile counters of the persistent launches (query, adjoint)
 
     uint64_t *codes;          // [M] sorted Morton codes
@@ -38,9 +39,12 @@ struct dps_tree_s {
     dps::NodeRec *nodes;      // [N]
     int32_t *level, *parent, *first_child, *nchild, *ptb, *ptc;  // [N] topology
     int32_t *leaf_of;         // [M] leaf holding each sorted point
-    void *mom;                // [N][mom_stride] FP32 or BF16
+    void *mom;                // moments, moment_bytes(): [N][mom_stride] FP32, or for BF16
+                              // storage n_top FP32 rows then BF16 rows (dps_internal.h)
     void *attr;               // [M][attr_stride] FP32 or BF16
-    float *momw;              // [N][kw C] FP32 working sums of the refit
+    float *nrm;               // [M][3] point normals as given (sorted order; the refit's exact products)
+    float *momw;              // [N][kw C] FP32 working sums of the refit (high parts)
+    float *momw_lo;           // [N][kw C] their low parts (compensated FP32 sums)
     double *momw64;           // [n_top][kw C] FP64 working sums (wide_top only)
     double *G;                // [N][C][kw] node adjoint accumulators
     double *P;                // [M][C] point adjoint accumulators
@@ -49,7 +53,8 @@ struct dps_tree_s {
     double *EACC;             // [1] dL/deps accumulator
     uint32_t *err;            // sticky device error word (traversal guard)
 
-    int64_t bytes;
+    int64_t bytes;            // device bytes held by the tree
+    int64_t scratch_bytes;    // device bytes of the build's temporary buffers (while building)
     std::vector<void *> allocs;
 };
 
@@ -60,11 +65,19 @@ constexpr uint64_t kMagic = 0x6470732d74726565ull;
 void set_error(const char *fmt, ...);
 dps_status hip_status(hipError_t e, const char *what);
 
+// dps_set_memory_limit: device bytes one build may hold (tree plus build
+// scratch); 0 = no cap.  True if `more` bytes fit beside what t holds.
+bool memory_fits(const dps_tree_s *t, size_t more);
+
 // Allocates `count` elements on the current device and records the block in the tree.
 template <class T>
 dps_status tree_alloc(dps_tree_s *t, T **ptr, size_t count) {
     *ptr = nullptr;
     if (count == 0) count = 1;
+    if (!memory_fits(t, count * sizeof(T))) {
+        set_error("device memory limit of dps_set_memory_limit reached");
+        return DPS_ERR_OOM;
+    }
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, count * sizeof(T));
     if (e != hipSuccess) return hip_status(e, "hipMalloc");
@@ -94,8 +107,9 @@ dps_status launch_ray_resample(const float *o, const float *d, const float *tn, 
                                hipStream_t s);
 dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta,
                          int32_t *counts, hipStream_t s);
+// gin: the forward query's gradients at x ([Q][nc][3]) to form dL/dx from, or NULL
 dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
-                          int cbegin, int nc, const float *df, float *dx, hipStream_t s);
+                          int cbegin, int nc, const float *df, float *dx, const float *gin, hipStream_t s);
 dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                             int cbegin, int nc, const float *df, const float *dg, int want, float *dx,
                             hipStream_t s);
@@ -117,5 +131,22 @@ dps_status device_scan(const uint32_t *in, uint32_t *out, int64_t n, bool inclus
                        uint32_t *tmp, hipStream_t s);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// the step guard of every traversal: a well-formed tree is walked in at most
+// N steps
+inline uint32_t walk_limit(const dps_tree_s *t) { return t->step_limit ? t->step_limit : (uint32_t)t->N; }
+
+// kernel parameters of a traversal on tree t at regularisation eps
+inline KernelParams tree_kernel_params(const dps_tree_s *t, float eps) {
+    KernelParams kp = make_kernel_params(eps);
+    kp.nhi = t->storage == DPS_STORE_BF16 ? (uint32_t)t->n_top : 0u;
+    return kp;
+}
+
+// bytes of the moment array
+inline size_t moment_bytes(const dps_tree_s *t) {
+    return t->storage == DPS_STORE_BF16 ? (size_t)(t->N + t->n_top) * t->mom_stride * 2
+                                        : (size_t)t->N * t->mom_stride * 4;
+}
 
 }  // namespace dps

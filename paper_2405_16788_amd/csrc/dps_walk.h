@@ -64,7 +64,7 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float D[3 * CB];
-    load_moments<CB, BF16>(mom, ms, 0, c0, D);
+    load_moments<CB, BF16>(mom, ms, 0, c0, D, kp.nhi);
     uint32_t steps = 0;
     for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
@@ -91,7 +91,7 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
         const uint32_t pf = next == kEnd ? t : next;
         const NodeRec nn = nodes[pf];
         float Dn[3 * CB];
-        load_moments<CB, BF16>(mom, ms, pf, c0, Dn);
+        load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far) {
             // predicated rather than branched per point: a lane's terms are
             // computed under the wavefront's mask either way, and selects

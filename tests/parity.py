@@ -8,8 +8,10 @@ TOL_FP32 = 1e-5
 # BF16-stored: round-to-nearest-even to 8 significant bits leaves each stored
 # value within 2^-8 of itself (relative), and |dD.d| <= 2^-8 |D||d|
 # (Cauchy-Schwarz), so the normalised error is bounded by 2^-8 (plus the FP32
-# part).  Queries dominated by one source approach that bound; the 2e-3 figure
-# is met by the bulk of queries and reported as a percentile.
+# part) whatever the workload: the guaranteed bound.  With the top-level node
+# moments kept in FP32, the stated 2e-3 target (TARGET_BF16) holds for every
+# query of the 4M-point precision workloads; results computed from BF16 values
+# are also held to the FP32 bar against an oracle fed the same rounded values.
 TOL_BF16 = 2.0 ** -8 + TOL_FP32
 TARGET_BF16 = 2e-3
 
@@ -54,3 +56,11 @@ def node_abs_sums(perm, nodes, A, mu):
     b = nodes[:, 4].astype(np.int64)
     e = b + nodes[:, 5].astype(np.int64)
     return cs[e] - cs[b]
+
+
+def normwise(got, ref):
+    """||got - ref||_2 / ||ref||_2 over all elements (0 for an empty or zero reference)."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    den = float(np.linalg.norm(ref))
+    return float(np.linalg.norm(got - ref)) / den if den > 0 else 0.0

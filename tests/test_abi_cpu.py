@@ -89,3 +89,13 @@ def test_calls_on_unknown_handles(lib):
     assert lib.dps_tree_info(bogus, ct.byref(n), None, None, None, None) == 4
     lib.dps_destroy(None)   # no-op
     lib.dps_destroy(bogus)  # unknown handles are ignored
+
+
+def test_limits_validate_without_a_device(lib):
+    bogus = ct.c_void_p(0xdead0000)
+    assert lib.dps_set_step_limit(bogus, 5) == 4
+    assert lib.dps_set_step_limit(None, 0) == 4
+    assert lib.dps_set_memory_limit(-1) == 1
+    assert lib.dps_last_error().startswith(b"dps_set_memory_limit")
+    assert lib.dps_set_memory_limit(1 << 30) == 0
+    assert lib.dps_set_memory_limit(0) == 0

@@ -495,3 +495,149 @@ def test_sfm_8m_batched(P, orc):
         rs = T.query(xs, BETA, EPS, want_grad=False)
         assert norm_err(to_host(fs)[:, 0], rs["f"][:, 0], rs["sf"][:, 0]) <= TOL_BF16
     P.dps_check(tree)
+
+
+def test_sfm_8m_subbatch_against_oracle(P, orc):
+    """The batched workload's kernels in the benchmark's configuration
+    (8,388,608 points, BF16 storage, autotuned persistent launch) on a
+    multi-view, tile-aligned sub-batch, element by element against the
+    oracle: 6 tiles near the image centre of each of the 8 views (primary rows
+    in [tile, sample, lane] order), the shadow rows of the oracle's own hits
+    (64 samples, the compacted [group, sample, lane] layout, a device row
+    count) and one hit-point row per hit.  Forward values and the adjoint with
+    seeded cotangents -- values of the primaries, channel 0 of the shadow
+    rows, values and gradients of the hit points -- run in one captured graph;
+    two replays are each compared with the oracle (dL/dmu and dL/dx exactly
+    against the FP64 sums, values and dL/dx against the sums of the values as
+    stored)."""
+    import torch
+    print("[sfm-8m sub] generating the scene", flush=True)
+    p, n, A, mu = workloads.sfm_8m_cloud()
+    batch = workloads.make_ray_batch()
+    S, K, C = batch.S, batch.S_shadow, mu.shape[1]
+    G = 64
+    tiles = []
+    for v, res in enumerate(batch.res):
+        side = res // 8
+        t0 = batch.ray_offsets[v] // G
+        mid = (side // 2) * side + side // 2
+        # four tiles at the image centre (rays that hit) and the two first
+        # tiles of the view (a corner: rays that miss)
+        tiles += [t0 + mid + k for k in (-side - 1, -side, -1, 0)] + [t0, t0 + 1]
+    tiles = np.array(sorted(tiles))
+    rows = ((tiles[:, None] * S + np.arange(S)[None, :]) * G)[:, :, None] + np.arange(G)[None, None, :]
+    rows_t = torch.from_numpy(rows.reshape(-1)).cuda()
+    xp = to_host(batch.x[rows_t])  # primary rows of the sub-batch, [tile, sample, lane]
+    ray_ids = (tiles[:, None] * G + np.arange(G)[None, :]).reshape(-1)
+    light = to_host(batch.ray_light[torch.from_numpy(ray_ids).cuda()]).astype(np.float64)
+    su = to_host(batch.shadow_u[torch.from_numpy(ray_ids).cuda()]).astype(np.float64)
+    del batch
+    torch.cuda.empty_cache()
+
+    print(f"[sfm-8m sub] oracle tree, {xp.shape[0]} primary rows", flush=True)
+    T = orc.Tree(p, n, A, mu, 16)
+    T.set_storage("bf16", 3)
+    nt = tiles.size
+    f0 = T.query(xp, BETA, EPS, want_grad=False)["f"][:, 0].reshape(nt, S, G).transpose(0, 2, 1).reshape(-1, S)
+    xr = xp.reshape(nt, S, G, 3).transpose(0, 2, 1, 3).reshape(-1, S, 3).astype(np.float64)
+    has, _, hit = R.primary_hits_numpy(f0, xr)
+    n_hits = int(has.sum())
+    print(f"[sfm-8m sub] oracle hits {n_hits} of {has.size} rays", flush=True)
+    assert 64 <= n_hits < has.size
+    # shadow rows: hit rays in ray order, groups of 64 rays, [sample, lane] inside a group
+    hr = np.flatnonzero(has)
+    xs = R.shadow_samples_numpy(hit[hr], np.ones(n_hits, bool), light[hr], su[hr])  # [n_hits, K, 3]
+    n_groups = (n_hits + G - 1) // G
+    cap = n_groups * G
+    xs_pad = np.concatenate([xs, np.broadcast_to(light[hr[:1]][:, None, :], (cap - n_hits, K, 3))])
+    xs_rows = xs_pad.reshape(n_groups, G, K, 3).transpose(0, 2, 1, 3).reshape(-1, 3).astype(np.float32)
+    xh = np.concatenate([hit[hr], np.broadcast_to(hit[hr[:1]], (cap - n_hits, 3))]).astype(np.float32)
+    rng = np.random.default_rng(62)
+    dfp = rng.standard_normal((xp.shape[0], C)).astype(np.float32)
+    dfs = rng.standard_normal((xs_rows.shape[0], 1)).astype(np.float32)
+    dfh = rng.standard_normal((cap, C)).astype(np.float32)
+    dgh = rng.standard_normal((cap, C, 3)).astype(np.float32)
+    # only the evaluated rows carry cotangents: shadow rows up to the last
+    # started group (the device count), hit rows up to n_hits
+    qs_count, qh_count = xs_rows.shape[0], n_hits
+    dfh[n_hits:] = 0.0
+    dgh[n_hits:] = 0.0
+
+    print("[sfm-8m sub] oracle forward and adjoint", flush=True)
+    rf = T.query(xp, BETA, EPS)
+    rs = T.query(xs_rows, BETA, EPS, want_grad=False)
+    rh = T.query(xh[:n_hits], BETA, EPS)
+    dfs_full = np.zeros((xs_rows.shape[0], C), np.float32)
+    dfs_full[:, 0] = dfs[:, 0]
+    a1 = T.adjoint(xp, BETA, EPS, dfp)
+    a2 = T.adjoint(xs_rows, BETA, EPS, dfs_full)
+    a3 = T.adjoint(xh[:n_hits], BETA, EPS, dfh[:n_hits], dg=dgh[:n_hits])
+    dmu = a1["dmu"] + a2["dmu"] + a3["dmu"]
+    sdmu = a1["sdmu"] + a2["sdmu"] + a3["sdmu"]
+
+    pd, nd, Ad, mud = to_dev(p, n, A, mu)
+    tree = P.dps_build(pd, nd, Ad, mud, leaf_size=16, storage="bf16")
+    xpd, xsd, xhd, dfpd, dfsd, dfhd, dghd = to_dev(xp, xs_rows, xh, dfp, dfs, dfh, dgh)
+    qs = torch.tensor([qs_count], dtype=torch.int64, device="cuda")
+    qh = torch.tensor([qh_count], dtype=torch.int64, device="cuda")
+    Qp, Qs = xp.shape[0], xs_rows.shape[0]
+    out = {"f": torch.empty((Qp, C), device="cuda"), "g": torch.empty((Qp, C, 3), device="cuda"),
+           "fs": torch.empty((Qs, 1), device="cuda"), "fh": torch.empty((cap, C), device="cuda"),
+           "gh": torch.empty((cap, C, 3), device="cuda"), "dxp": torch.empty((Qp, 3), device="cuda"),
+           "dxs": torch.empty((Qs, 3), device="cuda"), "dxh": torch.empty((cap, 3), device="cuda"),
+           "da": torch.empty((p.shape[0], C), device="cuda")}
+
+    def step():
+        P.dps_set_attributes(tree, mud)
+        P.dps_query(tree, xpd, BETA, EPS, f_out=out["f"], g_out=out["g"])
+        P.dps_query_channels(tree, xsd, BETA, EPS, 0, 1, grad=False, f_out=out["fs"], q_count=qs)
+        P.dps_query_channels(tree, xhd, BETA, EPS, 0, C, f_out=out["fh"], g_out=out["gh"], q_count=qh)
+        P.dps_adjoint_zero(tree)
+        P.dps_adjoint_accumulate(tree, xpd, BETA, EPS, dfpd, dx_out=out["dxp"])
+        P.dps_adjoint_accumulate_channels(tree, xsd, BETA, EPS, 0, 1, dfsd, dx_out=out["dxs"], q_count=qs)
+        P.dps_adjoint_accumulate_grad(tree, xhd, BETA, EPS, dghd, df=dfhd, dx_out=out["dxh"], q_count=qh)
+        P.dps_adjoint_finalize(tree, dattrs_out=out["da"])
+
+    # the launch the autotuner picks for the whole batch (persistent tile
+    # queue, 4 queries per lane in the query, 2 in the adjoint), and a plain
+    # grid with one query per lane
+    for launch in ((4, 2, P.LAUNCH_PERSISTENT_QUERY | P.LAUNCH_PERSISTENT_ADJOINT), (1, 1, 0)):
+        P.dps_set_launch(tree, *launch)
+        print(f"[sfm-8m sub] launch {launch}", flush=True)
+        _subbatch_replays(P, tree, step, out, n_hits, rf, rs, rh, a1, a2, a3, dmu, sdmu)
+    P.dps_destroy(tree)
+
+
+def _subbatch_replays(P, tree, step, out, n_hits, rf, rs, rh, a1, a2, a3, dmu, sdmu):
+    import torch
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()  # warm-up outside the capture
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=side):
+            step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        for v in out.values():
+            v.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        P.dps_check(tree)
+        h = {k: to_host(v) for k, v in out.items()}
+        checks = {
+            "primary f": norm_err_all(h["f"], rf["f"], rf["sf"]),
+            "primary grad": norm_err_all(h["g"], rf["g"], rf["sg"]),
+            "shadow f": norm_err_all(h["fs"][:, 0], rs["f"][:, 0], rs["sf"][:, 0]),
+            "hit f": norm_err_all(h["fh"][:n_hits], rh["f"], rh["sf"]),
+            "hit grad": norm_err_all(h["gh"][:n_hits], rh["g"], rh["sg"]),
+            "dL/dmu": norm_err_all(h["da"], dmu, sdmu),
+            "primary dL/dx": norm_err_all(h["dxp"], a1["dx"], a1["sdx"]),
+            "shadow dL/dx": norm_err_all(h["dxs"], a2["dx"], a2["sdx"]),
+            "hit dL/dx": norm_err_all(h["dxh"][:n_hits], a3["dx"], a3["sdx"]),
+        }
+        for k, e in checks.items():
+            print(f"[sfm-8m sub] replay {rep} {k}: max {e.max():.3g}", flush=True)
+        bad = {k: float(e.max()) for k, e in checks.items() if not e.max() <= TOL_FP32}
+        assert not bad, bad

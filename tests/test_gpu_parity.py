@@ -315,3 +315,71 @@ def test_values_only_one_channel(dps, orc, storage, eps):
             assert norm_err(fv, ref["f"][:, :1], ref["sf"][:, :1]) <= tol, (k, flags)
             assert norm_err(fv, fg, ref["sf"][:, :1]) <= 1e-6, (k, flags)
     dps.dps_check(tree)
+
+
+@pytest.mark.parametrize("name", ["sphere-8k", "random-3001", "random-3001-c5", "random-2000-c1"])
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+@pytest.mark.parametrize("flags", [0, 12])
+def test_adjoint_from_forward_gradients(dps, orc, name, storage, flags):
+    """dL/dx formed from the forward query's gradients (the walk then adds
+    only the node and point increments) equals the oracle's adjoint, and so
+    does dL/dmu; an adjoint without dL/dx (NULL dx) accumulates the same
+    dL/dmu."""
+    p, n, A, mu = CLOUDS[name]()
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16, storage)
+    dps.dps_set_launch(tree, 4, 4, flags)
+    x = workloads.sphere_queries(3001, 12)
+    x = np.concatenate([x, p[:37]])  # queries exactly at points
+    C = mu.shape[1]
+    df = workloads.cotangents(x.shape[0], C, 17)
+    xd, dfd = to_dev(x, df)
+    f, g = dps.dps_query(tree, xd, 2.0, 0.05)
+    ref = T.adjoint(x, 2.0, 0.05, df)
+    tol = TOL_BF16 if storage == "bf16" else TOL_FP32
+    dps.dps_adjoint_zero(tree)
+    dx = dps.dps_adjoint_accumulate_from_forward(tree, xd, 2.0, 0.05, dfd, g)
+    da = dps.dps_adjoint_finalize(tree)
+    e1 = norm_err(to_host(da), ref["dmu"], ref["sdmu"])
+    e2 = norm_err(to_host(dx), ref["dx"], ref["sdx"])
+    print(f"[from-forward] {name} {storage} flags={flags}: dattrs {e1:.3g} dx {e2:.3g}", flush=True)
+    assert e1 <= TOL_FP32 and e2 <= tol
+    # the same sum as the walk's dL/dx
+    dps.dps_adjoint_zero(tree)
+    dx_walk = dps.dps_adjoint_accumulate(tree, xd, 2.0, 0.05, dfd)
+    da_walk = dps.dps_adjoint_finalize(tree)
+    assert norm_err(to_host(dx), to_host(dx_walk), ref["sdx"]) <= 2 * TOL_FP32
+    assert norm_err(to_host(da), to_host(da_walk), ref["sdmu"]) <= 2 * TOL_FP32
+    # without dL/dx
+    dps.dps_adjoint_zero(tree)
+    assert dps.dps_adjoint_accumulate(tree, xd, 2.0, 0.05, dfd, want_dx=False) is None
+    da_nodx = dps.dps_adjoint_finalize(tree)
+    assert norm_err(to_host(da_nodx), ref["dmu"], ref["sdmu"]) <= TOL_FP32
+    dps.dps_check(tree)
+
+
+@pytest.mark.parametrize("c_begin,nc", [(0, 1), (1, 3), (0, 5), (4, 1)])
+def test_adjoint_from_forward_channel_subsets(dps, orc, c_begin, nc):
+    import torch
+    p, n, A, mu = CLOUDS["random-3001-c5"]()
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16)
+    x = workloads.sphere_queries(2000, 41)
+    Q = x.shape[0]
+    (xd,) = to_dev(x)
+    f, g = dps.dps_query_channels(tree, xd, 2.0, 0.05, c_begin, nc)
+    dfs = workloads.cotangents(Q, nc, 43)
+    dffull = np.zeros((Q, mu.shape[1]), np.float32)
+    dffull[:, c_begin:c_begin + nc] = dfs
+    (dfsd,) = to_dev(dfs)
+    qc = torch.tensor([1500], dtype=torch.int64, device="cuda")
+    dx = torch.full((Q, 3), float("nan"), device="cuda")
+    dps.dps_adjoint_zero(tree)
+    dps.dps_adjoint_accumulate_from_forward(tree, xd, 2.0, 0.05, dfsd, g, c_begin=c_begin, n_channels=nc,
+                                            dx_out=dx, q_count=qc)
+    da = dps.dps_adjoint_finalize(tree)
+    adj = T.adjoint(x[:1500], 2.0, 0.05, dffull[:1500])
+    dxh = to_host(dx)
+    assert np.isnan(dxh[1500:]).all()
+    assert norm_err(dxh[:1500], adj["dx"], adj["sdx"]) <= TOL_FP32
+    assert norm_err(to_host(da), adj["dmu"], adj["sdmu"] + 1e-30) <= TOL_FP32
+    with pytest.raises(dps.DpsError):
+        dps.dps_adjoint_accumulate_from_forward(tree, xd, 2.0, 0.05, dfsd, None, c_begin=c_begin, n_channels=nc)

@@ -1,16 +1,17 @@
 """GPU parity at the benchmark's full size (sfm-1m: 1,000,000 points,
 512x512 rays x 128 samples = 33,554,432 queries), in the launch
 configurations the benchmark times: the whole query set in one call, with
-the library's default launch and with the autotuned one the benchmark uses,
-outputs compared on a seeded sample that the oracle evaluates one by one,
-plus properties that hold at any size."""
+the library's default launch and with the autotuned one the benchmark uses.
+Forward outputs are compared on a seeded sample that the oracle evaluates one
+by one; the adjoint of all 33.5M queries is compared element by element with
+the oracle's adjoint of all of them; plus properties that hold at any size."""
 import math
 
 import numpy as np
 import pytest
 
 import workloads
-from parity import TARGET_BF16, TOL_BF16, TOL_FP32, norm_err, norm_err_all, to_dev, to_host
+from parity import TARGET_BF16, TOL_BF16, TOL_FP32, norm_err, norm_err_all, normwise, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -71,49 +72,52 @@ def test_sfm_1m_full_query(scene, storage, launch):
     print(f"[scale] {storage}: max normalised error f {ef:.3g} grad {eg:.3g}; 99.9th pct f {pf:.3g}", flush=True)
     assert ef <= tol and eg <= tol
     if storage == "bf16":
-        assert pf <= TARGET_BF16
+        assert max(ef, eg) <= TARGET_BF16
     assert np.array_equal(to_host(counts[it]), ref["counts"])
     assert torch.isfinite(f).all() and torch.isfinite(g).all()
     P.dps_destroy(tree)
 
 
+@pytest.fixture(scope="module")
+def oracle_adjoint(scene):
+    """The oracle's Barnes-Hut adjoint of all 33,554,432 queries (stage 1 and
+    the push-down, Algorithm 1 AdjointQuery and eq. farfield_features_gradient)
+    with N(0,1) cotangents (seed 17): about a minute on the host's cores."""
+    import time
+    P, T, (p, n, A, mu, x), d = scene
+    df = workloads.cotangents(x.shape[0], mu.shape[1], 17)
+    print(f"[scale] oracle adjoint of all {x.shape[0]} queries", flush=True)
+    t0 = time.time()
+    ref = T.adjoint(x, BETA, EPS, df)
+    print(f"[scale] oracle adjoint took {time.time() - t0:.1f} s", flush=True)
+    return df, ref
+
+
 @pytest.mark.parametrize("launch", ["default", "tuned"])
-def test_sfm_1m_adjoint(scene, launch):
+def test_sfm_1m_adjoint(scene, oracle_adjoint, launch):
+    """The full-size adjoint (33.5M queries in one launch, the contention the
+    benchmark runs under) element by element against the oracle: dL/dmu of
+    every point and channel, dL/dx of every query."""
     import torch
     P, T, (p, n, A, mu, x), d = scene
+    df, ref = oracle_adjoint
     tree = P.dps_build(d["p"], d["n"], d["A"], d["mu"], leaf_size=16)
     print(f"[scale] adjoint launch {_launch(P, tree, d, launch)}", flush=True)
-    Q = x.shape[0]
-    df = workloads.cotangents(Q, mu.shape[1], 17)
     (dfd,) = to_dev(df)
-    # full-size adjoint, checked through a property that holds at any size:
-    # L = sum df . f is linear in the attributes, so sum df . f = sum dattrs . mu
     f, _ = P.dps_query(tree, d["x"], BETA, EPS, grad=False)
     dattrs, dx = P.dps_adjoint(tree, d["x"], BETA, EPS, dfd)
     P.dps_check(tree)
+    e1 = norm_err_all(to_host(dattrs), ref["dmu"], ref["sdmu"])
+    e2 = norm_err_all(to_host(dx), ref["dx"], ref["sdx"])
+    print(f"[scale] full adjoint: dattrs max {e1.max():.3g} (normwise {normwise(to_host(dattrs), ref['dmu']):.3g}), "
+          f"dx max {e2.max():.3g} (normwise {normwise(to_host(dx), ref['dx']):.3g})", flush=True)
+    assert e1.max() <= TOL_FP32 and e2.max() <= TOL_FP32
+    # and a property that holds at any size: L = sum df . f is linear in the
+    # attributes, so sum df . f = sum dattrs . mu
     lhs = torch.sum(dfd.double() * f.double(), dim=0)
     rhs = torch.sum(dattrs.double() * d["mu"].double(), dim=0)
     scale = torch.sum((dfd.double() * f.double()).abs(), dim=0)
     rel = ((lhs - rhs).abs() / scale).max().item()
     print(f"[scale] dot-product identity, relative to sum |df f|: {rel:.3g}", flush=True)
     assert rel < 1e-4
-    # dL/dx of the full launch on sampled queries
-    idx = np.sort(np.random.default_rng(19).choice(Q, 3000, replace=False))
-    g = T.query(x[idx], BETA, EPS)["g"]
-    want = np.einsum("qc,qck->qk", df[idx].astype(np.float64), g)
-    sdx = np.sum(np.abs(df[idx]).astype(np.float64) * T.query(x[idx], BETA, EPS)["sg"], axis=1)
-    e = norm_err(to_host(dx[torch.from_numpy(idx).cuda()]), want, sdx)
-    print(f"[scale] dx sampled error {e:.3g}", flush=True)
-    assert e <= TOL_FP32
-    # dL/dattrs against the oracle adjoint on a tile-aligned sub-batch (the
-    # oracle cannot run all 33.5M queries in a test)
-    sub = slice(64 * 128 * 2000, 64 * 128 * 2000 + 64 * 128 * 6)
-    xs, dfs = x[sub], df[sub]
-    xsd, dfsd = to_dev(xs, dfs)
-    da, dxs = P.dps_adjoint(tree, xsd, BETA, EPS, dfsd)
-    ref = T.adjoint(xs, BETA, EPS, dfs)
-    e1 = norm_err(to_host(da), ref["dmu"], ref["sdmu"])
-    e2 = norm_err(to_host(dxs), ref["dx"], ref["sdx"])
-    print(f"[scale] sub-batch adjoint errors dattrs {e1:.3g} dx {e2:.3g}", flush=True)
-    assert e1 <= TOL_FP32 and e2 <= TOL_FP32
     P.dps_destroy(tree)
