@@ -427,6 +427,26 @@ dps_status dps_ray_resample(const float *o, const float *d, const float *tnear, 
                             const float *jitter, int32_t n_before, int32_t n_dense, int32_t n_after, float window,
                             int32_t tile_layout, float *t_out, float *x_out, void *stream);
 
+/*
+ * dps_adjoint_noalloc -- for callers that cannot allocate device memory
+ * (code under graph capture, serving loops, harnesses that forbid it): the
+ * result of dps_adjoint (same arguments, outputs and errors; dattrs [M][C] in
+ * caller order, dx [Q][3] or NULL) computed with its working buffers -- the
+ * FP64 node and point accumulators and the tile counters -- in a static
+ * per-device workspace of DPS_NOALLOC_SCRATCH_BYTES instead of the tree's.
+ * Calls no allocating routine.  Each device the library runs on holds one
+ * copy of the workspace until the process ends; every call on that device
+ * uses the same copy and clears it first, so calls that overlap in time on
+ * one device (other streams, other threads, other trees) race and give wrong
+ * results: order them.  Leaves the tree's own adjoint accumulators untouched.
+ * Needs 8 (N * 3C + M * C) bytes plus 64 (rounded to 256-byte blocks) to
+ * fit the workspace (e.g. 1M points, 264k nodes, C = 4: 58 MB); larger trees
+ * get DPS_ERR_INVALID.  Dipole-kernel trees only.  Graph-safe.
+ */
+#define DPS_NOALLOC_SCRATCH_BYTES (64 << 20)
+dps_status dps_adjoint_noalloc(dps_tree t, const float *x, int64_t Q, float beta, float eps, const float *df,
+                               float *dattrs, float *dx, void *stream);
+
 /* dps_check -- synchronises `stream` and reports device-side failures recorded
  * by earlier calls on this tree (DPS_ERR_DEVICE; sticky until destroyed).  A
  * traversal that would walk more than N nodes stops and sets this flag; its

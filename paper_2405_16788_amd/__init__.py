@@ -7,7 +7,7 @@ streams only.
 """
 from .binding import (  # noqa: F401
     DpsError, Tree, dps_build, dps_get_kernel, dps_set_attributes, dps_query, dps_query_counts,
-    dps_adjoint_zero, dps_adjoint_accumulate, dps_adjoint_finalize, dps_adjoint,
+    dps_adjoint_zero, dps_adjoint_accumulate, dps_adjoint_finalize, dps_adjoint, dps_adjoint_noalloc,
     dps_export_tree, dps_tree_info, dps_set_launch, dps_get_launch, dps_query_channels,
     dps_adjoint_accumulate_channels, dps_adjoint_accumulate_grad, dps_adjoint_accumulate_ext,
     dps_adjoint_accumulate_from_forward,

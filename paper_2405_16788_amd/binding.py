@@ -27,7 +27,7 @@ EXPORTED = (
     "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_adjoint_accumulate_ext",
     "dps_adjoint_accumulate_from_forward",
     "dps_adjoint_finalize_ext", "dps_set_normals", "dps_query_grid", "dps_ray_march", "dps_ray_resample",
-    "dps_check", "dps_set_step_limit", "dps_set_memory_limit", "dps_destroy",
+    "dps_adjoint_noalloc", "dps_check", "dps_set_step_limit", "dps_set_memory_limit", "dps_destroy",
     "dps_status_string", "dps_last_error",
 )
 
@@ -77,6 +77,7 @@ def load():
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
         "dps_adjoint": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
+        "dps_adjoint_noalloc": [vp, vp, i64, f32, f32, vp, vp, vp, vp],
         "dps_export_tree": [vp, vp, vp, vp, vp, vp, vp],
         "dps_tree_info": [vp, ct.POINTER(i64), ct.POINTER(i32), ct.POINTER(i64), ct.POINTER(i64),
                           ct.POINTER(i32)],
@@ -245,6 +246,20 @@ def dps_adjoint(tree: Tree, x, beta: float, eps: float, df, want_dx: bool = True
                               _ptr(d, torch.float32), _ptr(dx, torch.float32), _stream(tree.device)),
            "dps_adjoint")
     return d, dx
+
+
+def dps_adjoint_noalloc(tree: Tree, x, beta: float, eps: float, df, dattrs_out, dx_out=None):
+    """dps_adjoint with its working buffers in the library's static per-device
+    workspace (allocates nothing; outputs must be given).  Calls that overlap
+    in time on one device race."""
+    import torch
+    Q = x.shape[0]
+    _check(load().dps_adjoint_noalloc(tree.handle, _ptr(x, torch.float32, (Q, 3), tree.device, "x"), Q,
+                                      float(beta), float(eps), _ptr(df, torch.float32, (Q, tree.C), tree.device, "df"),
+                                      _ptr(dattrs_out, torch.float32, (tree.M, tree.C), tree.device, "dattrs"),
+                                      _ptr(dx_out, torch.float32, (Q, 3), tree.device, "dx"), _stream(tree.device)),
+           "dps_adjoint_noalloc")
+    return dattrs_out, dx_out
 
 
 def dps_tree_info(tree: Tree) -> dict:

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <mutex>
 #include <new>
+#include <unordered_map>
 #include <unordered_set>
 
 #include "dps_tree.h"
@@ -76,6 +77,42 @@ struct DeviceGuard {
 }  // namespace dps
 
 using namespace dps;
+
+// ---------------------------------------------------------------------------
+// Working memory of dps_adjoint_noalloc: a static device array (each device
+// the library runs on holds its own copy until the process ends), so that
+// entry point never allocates.  Host code refers to it only through the
+// per-device address hipGetSymbolAddress returns: the array's name is a host
+// stand-in, not a device address.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchBytes = (size_t)DPS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::unordered_map<int, unsigned char *> g_scratch_ptr;  // device -> its copy
+
+// address of device dev's copy (dev current); looked up once per device
+dps_status scratch_address(int dev, unsigned char **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return DPS_OK;
+    }
+    unsigned char *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        dps::set_error("dps_adjoint_noalloc: hipGetSymbolAddress of the workspace failed on device %d: %s", dev,
+                       hipGetErrorString(e));
+        return DPS_ERR_DEVICE;
+    }
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return DPS_OK;
+}
+
+inline size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+}  // namespace
 
 extern "C" {
 
@@ -397,6 +434,36 @@ dps_status dps_adjoint(dps_tree t, const float *x, int64_t Q, float beta, float 
     if ((st = dps_adjoint_zero(t, stream)) != DPS_OK) return st;
     if (Q > 0 && (st = dps_adjoint_accumulate(t, x, Q, beta, eps, df, dx, stream)) != DPS_OK) return st;
     return dps_adjoint_finalize(t, dattrs, stream);
+}
+
+dps_status dps_adjoint_noalloc(dps_tree t, const float *x, int64_t Q, float beta, float eps, const float *df,
+                               float *dattrs, float *dx, void *stream) {
+    dps_status st = check_tree(t, "dps_adjoint_noalloc");
+    if (st != DPS_OK) return st;
+    if ((st = need_dipole(t, "dps_adjoint_noalloc")) != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_adjoint_noalloc")) != DPS_OK) return st;
+    if (Q < 0 || Q > kMaxRows) return invalid("dps_adjoint_noalloc: Q out of range");
+    if (!dattrs) return invalid("dps_adjoint_noalloc: dattrs is NULL");
+    if (Q > 0 && (!x || !df)) return invalid("dps_adjoint_noalloc: NULL x or df");
+    // node accumulators (also the push-down sums), point accumulators, tile counters
+    const size_t gb = align256((size_t)t->N * t->kw * t->C * sizeof(double));
+    const size_t pb = align256((size_t)t->M * t->C * sizeof(double));
+    const size_t cb = 16 * sizeof(uint32_t);
+    if (gb + pb + cb > kScratchBytes) {
+        set_error("dps_adjoint_noalloc: this tree needs %zu bytes of workspace (N = %lld nodes, M = %lld points, "
+                  "C = %d), more than the %zu of DPS_NOALLOC_SCRATCH_BYTES; use dps_adjoint",
+                  gb + pb + cb, (long long)t->N, (long long)t->M, t->C, kScratchBytes);
+        return DPS_ERR_INVALID;
+    }
+    DeviceGuard dg(t->device);
+    unsigned char *base = nullptr;
+    if ((st = scratch_address(t->device, &base)) != DPS_OK) return st;
+    const AccBuffers ab{(double *)base, (double *)(base + gb), (double *)base, (uint32_t *)(base + gb + pb)};
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = launch_zero_acc(t, ab, s)) != DPS_OK) return st;  // fill kernels, no memset
+    if (Q > 0 && (st = launch_adjoint(t, x, Q, nullptr, beta, eps, 0, t->C, df, dx, nullptr, s, &ab)) != DPS_OK)
+        return st;
+    return launch_finalize_acc(t, dattrs, ab, s);
 }
 
 dps_status dps_export_tree(dps_tree t, uint64_t *codes, uint32_t *perm, int32_t *nodes, float *geom,

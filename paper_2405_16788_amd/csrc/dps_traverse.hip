@@ -602,7 +602,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(DPS_KERN_PARAMS, int C, co
 #endif
 // the same without the in-walk dL/dx (fewer live registers)
 #ifndef DPS_ADJOINT_WAVES_NODX
-#define DPS_ADJOINT_WAVES_NODX 5
+#define DPS_ADJOINT_WAVES_NODX 6
 #endif
 
 template <int CB, bool BF16, int K, bool DX>
@@ -945,6 +945,20 @@ __global__ void k_leaf_sums(int64_t N, int64_t W, const NodeRec *__restrict__ no
     S[t * W + k] = sum;
 }
 
+// the same sums written over the leaf's own node accumulators (the leaf entry
+// is read before it is overwritten; internal entries are only read)
+__global__ void k_leaf_sums_inplace(int64_t N, int64_t W, const NodeRec *__restrict__ nodes,
+                                    const int32_t *__restrict__ parent, double *G) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N * W) return;
+    const int64_t t = i / W;
+    const int64_t k = i - t * W;
+    if (!(nodes[t].meta & kLeafFlag)) return;
+    double sum = G[t * W + k];
+    for (int64_t a = parent[t]; a >= 0; a = parent[a]) sum += G[a * W + k];
+    G[t * W + k] = sum;
+}
+
 // dL/dmu_mc = P_mc + A_m n_m . S_lc (dipole) or P_mc + A_m S_lc (monopole)
 template <bool MONO>
 __global__ void k_points_out(int64_t M, int C, const int32_t *__restrict__ leaf_of,
@@ -1107,21 +1121,22 @@ dps_status grid_block(dps_tree_s *t, const GridSpec &gs, int64_t Q, float b2, Ke
 
 template <int CB, bool BF, int K, bool DX>
 dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
-                          const float *df, float *dx, int dx_mode, const float *gin, hipStream_t s) {
+                          const float *df, float *dx, int dx_mode, const float *gin, const AccBuffers &ab,
+                          hipStream_t s) {
     const uint32_t lim = walk_limit(t);
     if (t->launch_flags & kFlagPersistentAdjoint) {
-        k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
+        k_fill_u32<<<1, 64, 0, s>>>(ab.ctr + 8, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_adjoint_persistent<CB, BF, K, DX>);
         k_adjoint_persistent<CB, BF, K, DX><<<persistent_grid(fn), kThreads, 0, s>>>(
             t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
-            lim, t->err, t->C, df, t->G, t->P, dx, dx_mode, gin, t->ctr + 8);
+            lim, t->err, t->C, df, ab.G, ab.P, dx, dx_mode, gin, ab.ctr + 8);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdAdjoint) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
         k_adjoint<CB, BF, K, DX><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
                                                          t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co, lim,
-                                                         t->err, t->C, df, t->G, t->P, dx, dx_mode, gin,
+                                                         t->err, t->C, df, ab.G, ab.P, dx, dx_mode, gin,
                                                          remap ? (int)nb : 0);
     }
     return hip_status(hipGetLastError(), "adjoint launch");
@@ -1130,23 +1145,26 @@ dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_
 // dL/dx in the walk (DX) only when it is wanted and no forward gradients are given
 template <int CB, bool BF, int K>
 dps_status adjoint_launch_dx(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp,
-                             Sub sb, const float *df, float *dx, int dx_mode, const float *gin, hipStream_t s) {
-    if (dx_mode != 0 && !gin) return adjoint_launch<CB, BF, K, true>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
-    return adjoint_launch<CB, BF, K, false>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
+                             Sub sb, const float *df, float *dx, int dx_mode, const float *gin, const AccBuffers &ab,
+                             hipStream_t s) {
+    if (dx_mode != 0 && !gin)
+        return adjoint_launch<CB, BF, K, true>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s);
+    return adjoint_launch<CB, BF, K, false>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s);
 }
 
 template <int CB>
 dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
-                         const float *df, float *dx, int dx_mode, const float *gin, hipStream_t s) {
+                         const float *df, float *dx, int dx_mode, const float *gin, const AccBuffers &ab,
+                         hipStream_t s) {
     const int k = clamp_packet(t->packet_adjoint, CB, false);
     if (t->storage == DPS_STORE_BF16) {
-        if (k == 4) { if constexpr (CB <= 4) return adjoint_launch_dx<CB, true, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); }
-        if (k >= 2) return adjoint_launch_dx<CB, true, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
-        return adjoint_launch_dx<CB, true, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
+        if (k == 4) { if constexpr (CB <= 4) return adjoint_launch_dx<CB, true, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s); }
+        if (k >= 2) return adjoint_launch_dx<CB, true, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s);
+        return adjoint_launch_dx<CB, true, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s);
     }
-    if (k == 4) { if constexpr (CB <= 4) return adjoint_launch_dx<CB, false, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); }
-    if (k >= 2) return adjoint_launch_dx<CB, false, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
-    return adjoint_launch_dx<CB, false, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s);
+    if (k == 4) { if constexpr (CB <= 4) return adjoint_launch_dx<CB, false, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s); }
+    if (k >= 2) return adjoint_launch_dx<CB, false, 2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s);
+    return adjoint_launch_dx<CB, false, 1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s);
 }
 
 template <int CB, bool BF, int K, bool DF, bool EXT>
@@ -1235,8 +1253,10 @@ dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta, i
 }
 
 dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
-                          int cbegin, int nc, const float *df, float *dx, const float *gin, hipStream_t s) {
+                          int cbegin, int nc, const float *df, float *dx, const float *gin, hipStream_t s,
+                          const AccBuffers *abp) {
     if (t->kernel == DPS_KERNEL_MONOPOLE) return launch_adjoint_mono(t, x, Q, qdev, beta, eps, cbegin, nc, df, dx, s);
+    const AccBuffers ab = abp ? *abp : tree_buffers(t);
     const float b2 = mul_rn(beta, beta);
     const KernelParams kp = tree_kernel_params(t, eps);
     for (int c0 = cbegin; c0 < cbegin + nc;) {
@@ -1245,11 +1265,11 @@ dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_
         const Sub sb{c0, nc, c0 - cbegin};
         dps_status st;
         switch (cb) {
-            case 8: st = adjoint_block<8>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
-            case 4: st = adjoint_block<4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
-            case 3: st = adjoint_block<3>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
-            case 2: st = adjoint_block<2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
-            default: st = adjoint_block<1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, s); break;
+            case 8: st = adjoint_block<8>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s); break;
+            case 4: st = adjoint_block<4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s); break;
+            case 3: st = adjoint_block<3>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s); break;
+            case 2: st = adjoint_block<2>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s); break;
+            default: st = adjoint_block<1>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s); break;
         }
         if (st != DPS_OK) return st;
         c0 += cb;
@@ -1270,6 +1290,30 @@ dps_status launch_zero(dps_tree_s *t, hipStream_t s) {
     if (st != DPS_OK) return st;
     k_fill_f64<<<1, 64, 0, s>>>(t->EACC, 1);
     return hip_status(hipGetLastError(), "zero eps accumulator");
+}
+
+dps_status launch_zero_acc(dps_tree_s *t, const AccBuffers &ab, hipStream_t s) {
+    const int64_t ng = t->N * t->kw * t->C, np = t->M * t->C;
+    k_fill_f64<<<(unsigned)std::min<int64_t>(cdiv(ng, kThreads), 4096), kThreads, 0, s>>>(ab.G, ng);
+    dps_status st = hip_status(hipGetLastError(), "zero node accumulators");
+    if (st != DPS_OK) return st;
+    k_fill_f64<<<(unsigned)std::min<int64_t>(cdiv(np, kThreads), 4096), kThreads, 0, s>>>(ab.P, np);
+    return hip_status(hipGetLastError(), "zero point accumulators");
+}
+
+dps_status launch_finalize_acc(dps_tree_s *t, float *dattrs, const AccBuffers &ab, hipStream_t s) {
+    const int64_t w = (int64_t)t->kw * t->C;
+    if (ab.S == ab.G) k_leaf_sums_inplace<<<grid(t->N * w), kThreads, 0, s>>>(t->N, w, t->nodes, t->parent, ab.G);
+    else k_leaf_sums<<<grid(t->N * w), kThreads, 0, s>>>(t->N, w, t->nodes, t->parent, ab.G, ab.S);
+    dps_status st = hip_status(hipGetLastError(), "leaf sums");
+    if (st != DPS_OK) return st;
+    if (t->kernel == DPS_KERNEL_MONOPOLE)
+        k_points_out<true><<<grid(t->M * t->C), kThreads, 0, s>>>(t->M, t->C, t->leaf_of, t->perm, t->pts, ab.P,
+                                                                  ab.S, dattrs);
+    else
+        k_points_out<false><<<grid(t->M * t->C), kThreads, 0, s>>>(t->M, t->C, t->leaf_of, t->perm, t->pts, ab.P,
+                                                                   ab.S, dattrs);
+    return hip_status(hipGetLastError(), "point gradients");
 }
 
 dps_status launch_finalize(dps_tree_s *t, float *dattrs, hipStream_t s) {

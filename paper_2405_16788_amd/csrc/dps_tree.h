@@ -107,9 +107,24 @@ dps_status launch_ray_resample(const float *o, const float *d, const float *tn, 
                                hipStream_t s);
 dps_status launch_counts(dps_tree_s *t, const float *x, int64_t Q, float beta,
                          int32_t *counts, hipStream_t s);
+// Working buffers of a value adjoint: node accumulators G [N][C][kw], point
+// accumulators P [M][C], push-down sums S (may alias G: the push-down reads
+// a leaf's own entry before overwriting it and never writes an ancestor's),
+// and 16 tile counters.  By default the tree's own.
+struct AccBuffers {
+    double *G, *P, *S;
+    uint32_t *ctr;
+};
+inline AccBuffers tree_buffers(const dps_tree_s *t) { return AccBuffers{t->G, t->P, t->S, t->ctr}; }
+
 // gin: the forward query's gradients at x ([Q][nc][3]) to form dL/dx from, or NULL
+// ab: the working buffers, or NULL for the tree's own
 dps_status launch_adjoint(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
-                          int cbegin, int nc, const float *df, float *dx, const float *gin, hipStream_t s);
+                          int cbegin, int nc, const float *df, float *dx, const float *gin, hipStream_t s,
+                          const AccBuffers *ab = nullptr);
+// clears G and P of ab (fill kernels); dattrs [M][C] from ab (dipole trees)
+dps_status launch_zero_acc(dps_tree_s *t, const AccBuffers &ab, hipStream_t s);
+dps_status launch_finalize_acc(dps_tree_s *t, float *dattrs, const AccBuffers &ab, hipStream_t s);
 dps_status launch_adjoint_g(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float beta, float eps,
                             int cbegin, int nc, const float *df, const float *dg, int want, float *dx,
                             hipStream_t s);
