@@ -9,8 +9,11 @@ in HBM before timing starts.
 
 One step = one training iteration of the hot path: moment refit from the
 attributes (dps_set_attributes), primal query with gradients (dps_query), and
-the two-stage adjoint (dps_adjoint_zero / _accumulate / _finalize) with
-dL/df ~ N(0,1).  The adjoint that also takes cotangents of the gradients
+the two-stage adjoint (dps_adjoint_zero / _accumulate_from_forward /
+_finalize) with dL/df ~ N(0,1): dL/dmu from the adjoint walk, dL/dx =
+sum_c dL/df_c grad D_c from the query's gradients.  The adjoint that forms
+dL/dx in its own walk (dps_adjoint_accumulate) is timed beside it and
+reported in kernel_ms.  The adjoint that also takes cotangents of the gradients
 (dps_adjoint_accumulate_grad, N(0,1)) is timed beside it and reported in
 kernel_ms.  The tree itself is built once (points are fixed) and its
 build time is reported separately.  value = Q / (time per step), FP32-stored
@@ -77,6 +80,16 @@ def flops_fwd(C):
 
 def flops_adj(C):
     return {"test": 10, "far": 27 + 13 * C, "near": 35 + 5 * C}
+
+
+# the adjoint walk whose dL/dx comes from the forward's gradients:
+#   far source:  d (3), rsqrt + r^-3 + kappa (4), kappa d (3), per channel
+#                w kappa d (6) + wavefront sum (3)
+#   near point:  d (3), r^2 (5), rsqrt + kappa (4), An.d (5), kappa s (1),
+#                per channel w kappa s (2) + wavefront sum (1)
+#   per query:   dL/dx = sum_c w_c grad_c (6 C)
+def flops_adj_fwdgrad(C):
+    return {"test": 10, "far": 10 + 9 * C, "near": 18 + 3 * C, "query": 6 * C}
 
 
 # monopole kernel (appearance channels, foreshortening dropped), same
@@ -230,7 +243,9 @@ def time_storage(P, dev_in, storage, steps, warmup, packet, graph=False):
         P.dps_query(tree, x, BETA, EPS, f_out=f, g_out=g)
         if record: e[2].record()
         P.dps_adjoint_zero(tree)
-        P.dps_adjoint_accumulate(tree, x, BETA, EPS, df, dx_out=dx)
+        # dL/dx from the gradients the query just returned; the walk adds the
+        # node and point increments
+        P.dps_adjoint_accumulate_from_forward(tree, x, BETA, EPS, df, g, dx_out=dx)
         if record: e[3].record()
         P.dps_adjoint_finalize(tree, dattrs_out=dattrs)
         if record: e[4].record()
@@ -290,11 +305,22 @@ def time_storage(P, dev_in, storage, steps, warmup, packet, graph=False):
         torch.cuda.synchronize()
         gms.append(a.elapsed_time(b))
     del dg
+    # the adjoint that forms dL/dx in its own walk (no forward gradients at hand)
+    wms = []
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        P.dps_adjoint_zero(tree)
+        a.record()
+        P.dps_adjoint_accumulate(tree, x, BETA, EPS, df, dx_out=dx)
+        b.record()
+        torch.cuda.synchronize()
+        wms.append(a.elapsed_time(b))
     counts = P.dps_query_counts(tree, x, BETA)
     csum = counts.to(torch.int64).sum(0).tolist()
     info = P.dps_tree_info(tree)
     P.dps_destroy(tree)
     per["adjoint_accumulate_with_grad_cotangents"] = sorted(gms)[1]
+    per["adjoint_accumulate_dx_in_walk"] = sorted(wms)[1]
     return {"ms_per_step": total_ms / steps, "graph_ms_per_step": graph_ms, "build_ms": build_ms, "kernel_ms": per,
             "counts_total": csum, "tree": info, "packet": {"query": tuned["query"], "adjoint": tuned["adjoint"], "flags": tuned["flags"]}}
 
@@ -688,9 +714,9 @@ def main():
     main_st = "fp32" if "fp32" in res else storages[0]
     r = res[main_st]
     visits, nfar, leaves, near = r["counts_total"]
-    ffw, fad = flops_fwd(C), flops_adj(C)
+    ffw, fad = flops_fwd(C), flops_adj_fwdgrad(C)
     fl_q = ffw["test"] * visits + ffw["far"] * nfar + ffw["near"] * near
-    fl_a = fad["test"] * visits + fad["far"] * nfar + fad["near"] * near
+    fl_a = fad["test"] * visits + fad["far"] * nfar + fad["near"] * near + fad["query"] * Q
     bfw, bad = bytes_fwd(C), bytes_adj(C)
     by_q = bfw["visit"] * visits + bfw["far"] * nfar + bfw["near"] * near + bfw["io"] * Q
     by_a = bad["visit"] * visits + bad["far"] * nfar + bad["near"] * near + bad["io"] * Q
@@ -720,8 +746,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"sfm-1m: {p.shape[0]} points, {args.res}x{args.res} rays x {SAMPLES} samples "
                                f"= {Q} queries, C={C}, beta={BETA}, eps={EPS:.5f}, leaf {LEAF}",
-                   "storage": main_st, "step": "refit + query(values, gradients) + adjoint(zero, "
-                                               "accumulate, finalize)"},
+                   "storage": main_st, "step": "refit + query(values, gradients) + adjoint(zero, accumulate "
+                                               "with dL/dx from the query's gradients, finalize)"},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": MI355X_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MI355X_FP32_VECTOR_TFLOPS, "traffic": traffic,
                      "traffic_source": traffic_src, "flops_per_launch": fl, "avg_launch_ms": ms,
@@ -742,6 +768,12 @@ def main():
             "note": "the paper gives no kernel-level query rate, so there is no number for this metric to compare "
                     "against (vs_baseline null)"},
     }
+    fw = flops_adj(C)
+    fl_w = fw["test"] * visits + fw["far"] * nfar + fw["near"] * near
+    out["roofline"]["adjoint_dx_in_walk"] = {
+        "note": "dps_adjoint_accumulate forming dL/dx in its own walk (no forward gradients at hand)",
+        "avg_launch_ms": r["kernel_ms"]["adjoint_accumulate_dx_in_walk"], "flops_per_launch": fl_w,
+        "achieved": fl_w / (r["kernel_ms"]["adjoint_accumulate_dx_in_walk"] * 1e-3) / 1e12}
     for st, rr in res.items():
         out[f"{st}_stored"] = {"value": Q / (rr["ms_per_step"] * 1e-3), "ms_per_step": rr["ms_per_step"],
                                "kernel_ms": rr["kernel_ms"], "build_ms": rr["build_ms"],

@@ -1,8 +1,10 @@
 """Autotuner for the traversal launch shape: queries per lane (1 / 2 / 4) and
 the schedule (plain grid, XCD-contiguous grid, persistent tile queue).
 
-Times dps_query and dps_adjoint_accumulate for each shape on a slice of the
-caller's own queries (HIP events on the current stream), keeps the fastest
+Times dps_query and the adjoint's stage 1 (after a query with gradients the
+walk that forms dL/dx from them, dps_adjoint_accumulate_from_forward;
+otherwise dps_adjoint_accumulate) for each shape on a slice of the caller's
+own queries (HIP events on the current stream), keeps the fastest
 per kernel, and applies it with dps_set_launch.  Results are cached in a JSON file
 keyed by the workload shape, so later runs skip the sweep.
 """
@@ -10,6 +12,7 @@ from __future__ import annotations
 
 import json
 import os
+import sys
 
 from . import binding as B
 
@@ -22,7 +25,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dps_autotune.js
 
 def _key(tree, Q, beta, eps, grad):
     kind = getattr(tree, "kernel", "dipole")
-    return f"M{tree.M}_C{tree.C}_{tree.storage}_{kind}_Q{Q}_b{beta:g}_e{eps:g}" + ("" if grad else "_values")
+    return f"M{tree.M}_C{tree.C}_{tree.storage}_{kind}_Q{Q}_b{beta:g}_e{eps:g}" + ("_fwdgrad" if grad else "_values")
 
 
 def _time(fn, reps):
@@ -72,11 +75,16 @@ def tune(tree, x, df, beta, eps, sample=1 << 26, reps=2, cache=None, verbose=Fal
             ms["query"][(k, mode)] = _time(
                 lambda: B.dps_query(tree, xs, beta, eps, grad=grad, f_out=f, g_out=g), reps)
             B.dps_adjoint_zero(tree)
-            ms["adjoint"][(k, mode)] = _time(
-                lambda: B.dps_adjoint_accumulate(tree, xs, beta, eps, dfs, dx_out=dx), reps)
+            if grad and getattr(tree, "kernel", "dipole") == "dipole":
+                # the adjoint the caller will run after a query with gradients
+                ms["adjoint"][(k, mode)] = _time(
+                    lambda: B.dps_adjoint_accumulate_from_forward(tree, xs, beta, eps, dfs, g, dx_out=dx), reps)
+            else:
+                ms["adjoint"][(k, mode)] = _time(
+                    lambda: B.dps_adjoint_accumulate(tree, xs, beta, eps, dfs, dx_out=dx), reps)
             if verbose:
                 print(f"[autotune] k={k} {mode}: query {ms['query'][(k, mode)]:.3f} ms, "
-                      f"adjoint {ms['adjoint'][(k, mode)]:.3f} ms", flush=True)
+                      f"adjoint {ms['adjoint'][(k, mode)]:.3f} ms", file=sys.stderr, flush=True)
     B.dps_adjoint_zero(tree)
     bq = min(ms["query"], key=ms["query"].get)
     ba = min(ms["adjoint"], key=ms["adjoint"].get)

@@ -5,9 +5,9 @@
 //   PointRec [M]      32 B: position, A*n, A (one 8-dword scalar load)
 //   moments  [N][ms]  node dipoles D_t = sum A_m mu_m n_m, channel-major 3-vectors,
 //                     FP32 (ms = 3C), or with BF16 storage (ms = 3C rounded up to
-//                     even) the first nhi nodes (levels <= kTopLevels) as FP32 rows of
-//                     ms floats followed by BF16 rows: node t >= nhi at bf16 element
-//                     (t + nhi) * ms
+//                     even) FP32 rows of ms floats for the first nhi nodes (levels
+//                     <= kTopLevels) followed by a bfloat16 row for every node, node
+//                     t at bfloat16 element (t + 2 nhi) * ms
 //   attrs    [M][as]  point attributes, FP32 (as = C) or BF16 (as = C rounded up to even)
 #pragma once
 
@@ -235,7 +235,7 @@ __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &
 
 // kappa alone, same branches as radial() (the adjoint's node and point
 // increments need no lambda when dL/dx comes from the forward's gradients)
-__device__ __forceinline__ bool radial_k(float r2, const KernelParams &kp, float &kappa) {
+__device__ __forceinline__ bool radial_kappa(float r2, const KernelParams &kp, float &kappa) {
     if (kp.eps == 0.0f && !(r2 > 0.0f)) return false;
     const float ir = __builtin_amdgcn_rsqf(r2);
     const float ir2 = ir * ir;

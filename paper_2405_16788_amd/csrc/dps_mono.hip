@@ -88,6 +88,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
         float Qn[CB];
         load_charges<CB, BF16>(mom, ms, pf, c0, Qn, kp.nhi);
         if (any_far) {
+            refine_charges<CB, BF16>(mom, ms, t, c0, Qc, kp.nhi);
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 if (far[i]) {  // s > 0 here
@@ -247,6 +248,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
         float Qn[CB];
         load_charges<CB, BF16>(mom, ms, pf, c0, Qn, kp.nhi);
         if (any_far) {
+            refine_charges<CB, BF16>(mom, ms, t, c0, Qc, kp.nhi);
             // node increment sum_q df_c m, first over the lane's queries
             float acc[CB];
 #pragma unroll
@@ -403,13 +405,13 @@ dps_status mono_query_launch(dps_tree_s *t, const float *x, int64_t Q, const int
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_mono_query_persistent<CB, BF, GR, K>);
         k_mono_query_persistent<CB, BF, GR, K><<<persistent_grid(fn), kThreads, 0, s>>>(
-            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
+            t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
             lim, t->err, f, g, t->ctr);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdQuery) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
-        k_mono_query<CB, BF, GR, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+        k_mono_query<CB, BF, GR, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride,
                                                             t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
                                                             lim, t->err, f, g, remap ? (int)nb : 0);
     }
@@ -456,13 +458,13 @@ dps_status mono_adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, const i
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_mono_adjoint_persistent<CB, BF, K>);
         k_mono_adjoint_persistent<CB, BF, K><<<persistent_grid(fn), kThreads, 0, s>>>(
-            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
+            t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
             lim, t->err, t->C, df, t->G, t->P, dx, dx_mode, t->ctr + 8);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdAdjoint) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
-        k_mono_adjoint<CB, BF, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+        k_mono_adjoint<CB, BF, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride,
                                                           t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
                                                           lim, t->err, t->C, df, t->G, t->P, dx, dx_mode,
                                                           remap ? (int)nb : 0);

@@ -262,7 +262,7 @@ dps_status march_launch(dps_tree_s *t, const float *o, const float *d, const flo
     k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
     const void *fn = reinterpret_cast<const void *>(&k_ray_march<BF16, K>);
     k_ray_march<BF16, K><<<persistent_grid(fn), kThreads, 0, s>>>(
-        t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, walk_limit(t), t->err,
+        t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, walk_limit(t), t->err,
         o, d, tn, tf, R, n, level, hit, hv, t->ctr);
     return hip_status(hipGetLastError(), "ray march launch");
 }
@@ -279,14 +279,14 @@ dps_status march_along_launch(dps_tree_s *t, const float *o, const float *d, con
     }
     k_fill_i32_max<<<(unsigned)std::min<int64_t>(cdiv(R, kThreads), 4096), kThreads, 0, s>>>(hit, R);
     k_ray_march_along<BF16, K><<<(unsigned)wgs, kThreads, 0, s>>>(
-        t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, walk_limit(t), t->err,
+        t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, walk_limit(t), t->err,
         o, d, tn, tf, R, n, nitems, level, hit);
     dps_status st = hip_status(hipGetLastError(), "ray-major march launch");
     if (st != DPS_OK) return st;
     int G = 1;  // rays per wavefront of the values pass: at least 16384 wavefronts
     while (G < 32 && R / (2 * G) >= 16384) G *= 2;
     k_ray_hit_values<BF16><<<(unsigned)cdiv(cdiv(R, G), kThreads / 64), kThreads, 0, s>>>(
-        t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, walk_limit(t), t->err, o,
+        t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, walk_limit(t), t->err, o,
         d, tn, tf, R, n, G, hit, hv);
     return hip_status(hipGetLastError(), "ray hit values launch");
 }

@@ -65,8 +65,8 @@ __device__ __forceinline__ void prod3(float a, float b, float c, float &hi, floa
 // unit normal, not from the rounded A n of the point records), internal nodes
 // their children's working sums, in a fixed order, compensated in FP32 (or in
 // FP64 for the top levels of large trees, `wide`).  The stored value is the
-// working sum rounded once to FP32, and then to BF16 for nodes past the nhi
-// FP32 rows of BF16 storage.
+// working sum rounded once to FP32, and with BF16 storage also to BF16 (the
+// first nhi nodes keep their FP32 value as well, for the far field).
 template <bool BF16, int KW>
 __global__ void k_moments(int64_t nb, int64_t ne, int C, int ms, bool wide, int64_t n_top, int64_t nhi,
                           const float *__restrict__ attrs, const uint32_t *__restrict__ perm,
@@ -131,6 +131,8 @@ __global__ void k_moments(int64_t nb, int64_t ne, int C, int ms, bool wide, int6
             }
         }
     }
+    // FP32 storage: row t.  BF16 storage: the bfloat16 row t + 2 nhi of every
+    // node, and for the first nhi nodes also the FP32 row t.
     const bool f32row = !BF16 || t < nhi;
     for (int k = 0; k < KW; ++k) {
         momw[o + k] = hi[k];
@@ -142,11 +144,11 @@ __global__ void k_moments(int64_t nb, int64_t ne, int C, int ms, bool wide, int6
             v = hi[k] + lo[k];
         }
         if (f32row) ((float *)mom)[t * ms + KW * c + k] = v;
-        else ((uint16_t *)mom)[(t + nhi) * ms + KW * c + k] = f32_to_bf16(v);
+        if (BF16) ((uint16_t *)mom)[(t + 2 * nhi) * ms + KW * c + k] = f32_to_bf16(v);
     }
     if (c == C - 1 && ms > KW * C) {  // row padding
         if (f32row) ((float *)mom)[t * ms + KW * C] = 0.0f;
-        else ((uint16_t *)mom)[(t + nhi) * ms + KW * C] = 0;
+        if (BF16) ((uint16_t *)mom)[(t + 2 * nhi) * ms + KW * C] = 0;
     }
 }
 

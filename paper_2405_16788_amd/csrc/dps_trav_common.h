@@ -15,17 +15,22 @@ namespace {
 constexpr int kThreads = 256;
 
 // Node moments of channels [c0, c0 + CB) of node t (wave-uniform), as
-// floats.  BF16 storage keeps the first nhi nodes (the top levels, whose
-// moments dominate queries that use few far-field sources) as FP32 rows.
+// floats.  BF16 storage holds a bfloat16 row for every node, after the FP32
+// rows of the first nhi nodes (the top levels, whose moments dominate
+// queries that take few far-field sources); the traversals get `mom`
+// pointing at the first bfloat16 row, so FP32 row t < nhi sits (nhi - t)
+// rows of ms floats before it.  load_moments reads the bfloat16 row,
+// branch-free, and a far-field block refines the moments of a top-level node
+// to its FP32 row with refine_moments.
 template <int CB, bool BF16>
 __device__ __forceinline__ void load_moments(const void *__restrict__ mom, int ms, uint32_t t, int c0,
                                              float (&D)[3 * CB], uint32_t nhi) {
-    if (!BF16 || t < nhi) {
+    if constexpr (!BF16) {
         const float *b = (const float *)mom + (size_t)t * ms + 3 * c0;
 #pragma unroll
         for (int i = 0; i < 3 * CB; ++i) D[i] = b[i];
     } else {
-        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)(t + nhi) * ms + 3 * c0);
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)t * ms + 3 * c0);
         constexpr int W = (3 * CB + 1) / 2;
         uint32_t w[W];
 #pragma unroll
@@ -35,23 +40,56 @@ __device__ __forceinline__ void load_moments(const void *__restrict__ mom, int m
     }
 }
 
+// Waits for this wave's scalar loads inside the (rare) branch that issued
+// them, so that the common path, which uses moments loaded one node ahead,
+// does not wait on the next node's prefetch at the first use of D.
+__device__ __forceinline__ void wait_scalar_loads() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0); vmcnt, expcnt left at their maxima
+}
+
+template <int CB, bool BF16>
+__device__ __forceinline__ void refine_moments(const void *__restrict__ mom, int ms, uint32_t t, int c0,
+                                               float (&D)[3 * CB], uint32_t nhi) {
+    if constexpr (BF16) {
+        if (t < nhi) {
+            const float *b = (const float *)mom - (size_t)(nhi - t) * ms + 3 * c0;
+#pragma unroll
+            for (int i = 0; i < 3 * CB; ++i) D[i] = b[i];
+            wait_scalar_loads();
+        }
+    }
+}
+
 // Scalar node charges (monopole trees) of channels [c0, c0 + CB), same layout
-// rules as load_moments with one component per channel.
+// with one component per channel.
 template <int CB, bool BF16>
 __device__ __forceinline__ void load_charges(const void *__restrict__ mom, int ms, uint32_t t, int c0,
                                              float (&Q)[CB], uint32_t nhi) {
-    if (!BF16 || t < nhi) {
+    if constexpr (!BF16) {
         const float *b = (const float *)mom + (size_t)t * ms + c0;
 #pragma unroll
         for (int i = 0; i < CB; ++i) Q[i] = b[i];
     } else {
-        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)(t + nhi) * ms + c0);
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)t * ms + c0);
         constexpr int W = (CB + 1) / 2;
         uint32_t w[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) w[i] = b[i];
 #pragma unroll
         for (int i = 0; i < CB; ++i) Q[i] = (i & 1) ? bf16_hi(w[i >> 1]) : bf16_lo(w[i >> 1]);
+    }
+}
+
+template <int CB, bool BF16>
+__device__ __forceinline__ void refine_charges(const void *__restrict__ mom, int ms, uint32_t t, int c0,
+                                               float (&Q)[CB], uint32_t nhi) {
+    if constexpr (BF16) {
+        if (t < nhi) {
+            const float *b = (const float *)mom - (size_t)(nhi - t) * ms + c0;
+#pragma unroll
+            for (int i = 0; i < CB; ++i) Q[i] = b[i];
+            wait_scalar_loads();
+        }
     }
 }
 

@@ -79,6 +79,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         float Dn[3 * CB];
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far && far) {
+            refine_moments<CB, BF16>(mom, ms, t, c0, D, kp.nhi);
             float kap, lam;
             radial(s, kp, kap, lam);
             const float dx = nd.cx - px, dy = nd.cy - py, dz = nd.cz - pz;
@@ -221,6 +222,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
             float Dn[3 * CB];
             load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
             if (any_far) {
+                refine_moments<CB, BF16>(mom, ms, t, c0, D, kp.nhi);
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
                     if (far[i]) {
@@ -465,6 +467,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         float Dn[3 * CB];
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far) {
+            refine_moments<CB, BF16>(mom, ms, t, c0, D, kp.nhi);
             // node increment sum_q df_c kappa (p_t - x_q), first over the lane's queries
             float acc[3 * CB];
 #pragma unroll
@@ -474,7 +477,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                 if (far[i]) {
                     float kap, lam = 0.0f;
                     if constexpr (DX) radial(s[i], kp, kap, lam);
-                    else radial_k(s[i], kp, kap);
+                    else radial_kappa(s[i], kp, kap);
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
                     float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
                     // kappa (p_t - x_q) once, then one FMA per channel and axis
@@ -520,7 +523,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                             const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
                             const float r2 = dx * dx + dy * dy + dz * dz;
                             float kap, lam = 0.0f;
-                            const bool term = DX ? radial(r2, kp, kap, lam) : radial_k(r2, kp, kap);
+                            const bool term = DX ? radial(r2, kp, kap, lam) : radial_kappa(r2, kp, kap);
                             if (term) {
                                 const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
                                 const float ks = kap * sa;
@@ -602,7 +605,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(DPS_KERN_PARAMS, int C, co
 #endif
 // the same without the in-walk dL/dx (fewer live registers)
 #ifndef DPS_ADJOINT_WAVES_NODX
-#define DPS_ADJOINT_WAVES_NODX 6
+#define DPS_ADJOINT_WAVES_NODX 5
 #endif
 
 template <int CB, bool BF16, int K, bool DX>
@@ -697,6 +700,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         float Dn[3 * CB];
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far) {
+            refine_moments<CB, BF16>(mom, ms, t, c0, D, kp.nhi);
             float acc[3 * CB];
 #pragma unroll
             for (int v = 0; v < 3 * CB; ++v) acc[v] = 0.0f;
@@ -1020,7 +1024,7 @@ __global__ void k_export_moments(int64_t N, int C, int kw, int ms, int64_t nhi, 
         return;
     }
     const int64_t e = (kw == 1 ? k / 3 : k);
-    if (BF16 && t >= nhi) out[i] = __uint_as_float((uint32_t)((const uint16_t *)mom)[(t + nhi) * ms + e] << 16);
+    if (BF16 && t >= nhi) out[i] = __uint_as_float((uint32_t)((const uint16_t *)mom)[(t + 2 * nhi) * ms + e] << 16);
     else out[i] = ((const float *)mom)[t * ms + e];
 }
 
@@ -1044,13 +1048,13 @@ dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t 
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_query_persistent<CB, BF, GR, K>);
         k_query_persistent<CB, BF, GR, K><<<persistent_grid(fn), kThreads, 0, s>>>(
-            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
+            t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
             lim, t->err, f, g, t->ctr);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdQuery) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
-        k_query<CB, BF, GR, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+        k_query<CB, BF, GR, K><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride,
                                                        t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co, lim,
                                                        t->err, f, g, remap ? (int)nb : 0);
     }
@@ -1089,7 +1093,7 @@ dps_status grid_launch(dps_tree_s *t, const GridSpec &gs, int64_t Q, float b2, K
     k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
     const void *fn = reinterpret_cast<const void *>(&k_query_grid<CB, BF, GR, K>);
     k_query_grid<CB, BF, GR, K><<<persistent_grid(fn), kThreads, 0, s>>>(
-        t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, nullptr, Q, nullptr, b2, kp, sb.c0, sb.ldo,
+        t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, nullptr, Q, nullptr, b2, kp, sb.c0, sb.ldo,
         sb.co, walk_limit(t), t->err, f, g, gs, t->ctr);
     return hip_status(hipGetLastError(), "grid query launch");
 }
@@ -1128,13 +1132,13 @@ dps_status adjoint_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_
         k_fill_u32<<<1, 64, 0, s>>>(ab.ctr + 8, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_adjoint_persistent<CB, BF, K, DX>);
         k_adjoint_persistent<CB, BF, K, DX><<<persistent_grid(fn), kThreads, 0, s>>>(
-            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
+            t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
             lim, t->err, t->C, df, ab.G, ab.P, dx, dx_mode, gin, ab.ctr + 8);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdAdjoint) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
-        k_adjoint<CB, BF, K, DX><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+        k_adjoint<CB, BF, K, DX><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride,
                                                          t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co, lim,
                                                          t->err, t->C, df, ab.G, ab.P, dx, dx_mode, gin,
                                                          remap ? (int)nb : 0);
@@ -1176,13 +1180,13 @@ dps_status adjoint_g_launch(dps_tree_s *t, const float *x, int64_t Q, const int6
         k_fill_u32<<<1, 64, 0, s>>>(t->ctr + 8, 8, 0u);
         const void *fn = reinterpret_cast<const void *>(&k_adjoint_g_persistent<CB, BF, K, DF, EXT>);
         k_adjoint_g_persistent<CB, BF, K, DF, EXT><<<persistent_grid(fn), kThreads, 0, s>>>(
-            t->nodes, t->pts, t->mom, t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
+            t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
             lim, t->err, t->C, df, dg, t->G, t->P, dx, dx_mode, pn, eacc, t->ctr + 8);
     } else {
         const unsigned nb = grid(cdiv(Q, K));
         const bool remap = (t->launch_flags & kFlagXcdAdjoint) != 0;
         const unsigned gr = remap ? (unsigned)(8 * cdiv(nb, 8)) : nb;
-        k_adjoint_g<CB, BF, K, DF, EXT><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, t->mom, t->attr, t->mom_stride,
+        k_adjoint_g<CB, BF, K, DF, EXT><<<gr, kThreads, 0, s>>>(t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride,
                                                                 t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo,
                                                                 sb.co, lim, t->err, t->C, df, dg, t->G, t->P, dx,
                                                                 dx_mode, pn, eacc, remap ? (int)nb : 0);

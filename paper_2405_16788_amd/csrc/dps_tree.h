@@ -40,7 +40,7 @@ struct dps_tree_s {
     int32_t *level, *parent, *first_child, *nchild, *ptb, *ptc;  // [N] topology
     int32_t *leaf_of;         // [M] leaf holding each sorted point
     void *mom;                // moments, moment_bytes(): [N][mom_stride] FP32, or for BF16
-                              // storage n_top FP32 rows then BF16 rows (dps_internal.h)
+                              // storage n_top FP32 rows then N BF16 rows (dps_internal.h)
     void *attr;               // [M][attr_stride] FP32 or BF16
     float *nrm;               // [M][3] point normals as given (sorted order; the refit's exact products)
     float *momw;              // [N][kw C] FP32 working sums of the refit (high parts)
@@ -158,9 +158,16 @@ inline KernelParams tree_kernel_params(const dps_tree_s *t, float eps) {
     return kp;
 }
 
+// the moment pointer the traversal kernels take: with BF16 storage the first
+// bfloat16 row (the FP32 rows of the top nodes sit just before it)
+inline const void *trav_mom(const dps_tree_s *t) {
+    return t->storage == DPS_STORE_BF16 ? (const void *)((const uint16_t *)t->mom + 2 * t->n_top * t->mom_stride)
+                                        : (const void *)t->mom;
+}
+
 // bytes of the moment array
 inline size_t moment_bytes(const dps_tree_s *t) {
-    return t->storage == DPS_STORE_BF16 ? (size_t)(t->N + t->n_top) * t->mom_stride * 2
+    return t->storage == DPS_STORE_BF16 ? (size_t)(t->N + 2 * t->n_top) * t->mom_stride * 2
                                         : (size_t)t->N * t->mom_stride * 4;
 }
 

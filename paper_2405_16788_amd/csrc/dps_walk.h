@@ -93,6 +93,7 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
         float Dn[3 * CB];
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far) {
+            refine_moments<CB, BF16>(mom, ms, t, c0, D, kp.nhi);
             // predicated rather than branched per point: a lane's terms are
             // computed under the wavefront's mask either way, and selects
             // spare the scalar unit the exec-mask updates of a branch.  A
