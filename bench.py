@@ -540,7 +540,10 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=Non
     od, dd, tnd, tfd = dev[4:]
     R, C, S = o.shape[0], attrs.shape[1], sum(counts)
     sparse = n_rays is not None
-    march_k = 2
+    # measured on this workload: a batch of 4096 rays marches fastest with 1
+    # sample per lane (64-sample chunks balance better over few rays), a whole
+    # view with 2
+    march_k = 1 if sparse else 2
     query_k, tile_layout = (1, False) if sparse else (2, True)
     gen = torch.Generator(device="cuda").manual_seed(78)
     u = torch.rand((R, S), device="cuda", generator=gen)
@@ -573,9 +576,10 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=Non
         P.dps_query(tree, x, BETA, EPS, f_out=f, g_out=g)
         if record: e[3].record()
         if sparse:
+            # dL/dx from the query's gradients; the walk adds the increments
             P.dps_set_launch(tree, 0, 1, 0)
             P.dps_adjoint_zero(tree)
-            P.dps_adjoint_accumulate(tree, x, BETA, EPS, df, dx_out=dx)
+            P.dps_adjoint_accumulate_from_forward(tree, x, BETA, EPS, df, g, dx_out=dx)
             P.dps_adjoint_finalize(tree, dattrs_out=dattrs)
             if record: e[4].record()
         if record:
@@ -633,43 +637,84 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=Non
                         + f"{'/'.join(map(str, counts))} samples placed "
                         f"(or {S} uniform), query of the {R * S} placed samples (values + gradients, C={C}, "
                         f"k={query_k}, {'[tile, sample, lane]' if tile_layout else 'ray-major'} order)"
-                        + (", adjoint of the placed samples (N(0,1) cotangents, k=1)" if sparse else "")
+                        + (", adjoint of the placed samples (N(0,1) cotangents, k=1, dL/dx from the query's "
+                           "gradients)" if sparse else "")
                         + ", FP32 storage",
             "step": "ray march + resample + query of the placed samples"
                     + (" + their adjoint (zero, accumulate, finalize)" if sparse else "")}
 
 
+def host_cpu():
+    """CPU model, logical CPUs, the CPUs this process may run on, and the
+    threads the oracle legs use: the affinity set, capped by OMP_NUM_THREADS
+    when that is set (the share of the host that goes with one GPU)."""
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    threads = aff
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        threads = min(threads, int(omp))
+    return {"model": model, "nproc": os.cpu_count(), "affinity": aff, "threads": threads,
+            "omp_num_threads": omp or None}
+
+
 def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
+    """The FP64 oracle on the host's cores: Barnes-Hut forward + adjoint on a
+    bounded sample of the workload's queries (all threads, and one thread),
+    and the direct O(Q M) sum + its adjoint on 512 of the queries."""
     import oracle
     oracle.build(force=False)
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+    host = host_cpu()
+    cores = host["threads"]
     T = oracle.Tree(p, n, A, attrs, LEAF)
     rng = np.random.default_rng(18)
 
-    def run(k):
+    def run(k, nt):
         idx = np.sort(rng.choice(x.shape[0], size=k, replace=False))
         xs, dfs = x[idx], df[idx]
         t0 = time.perf_counter()
-        T.query(xs, BETA, EPS, nthreads=cores)
-        T.adjoint(xs, BETA, EPS, dfs, nthreads=cores)
+        T.query(xs, BETA, EPS, nthreads=nt)
+        T.adjoint(xs, BETA, EPS, dfs, nthreads=nt)
         return time.perf_counter() - t0
 
     # the oracle adjoint has a fixed cost (thread-private accumulators over all
     # nodes and points), so calibrate time = a + b k on two sample sizes
     k1, k2 = 8192, 32768
-    t1, t2 = run(k1), run(k2)
+    t1, t2 = run(k1, cores), run(k2, cores)
     b = max((t2 - t1) / (k2 - k1), 1e-9)
     a = max(t1 - b * k1, 0.0)
     k = int(min(x.shape[0], max(k2, (seconds - a) / b)))
-    dt = run(k)
+    dt = run(k, cores)
+    k_one = 65536
+    dt_one = run(k_one, 1)
+    # direct sum (eq. dipole_sum, no tree) and its exact adjoint on 512 queries
+    # of the same seeded draw
+    n_dir = 512
+    idx = np.sort(np.random.default_rng(18).choice(x.shape[0], size=n_dir, replace=False))
+    t0 = time.perf_counter()
+    oracle.direct(p, n, A, attrs, x[idx], EPS, nthreads=cores)
+    oracle.direct_adjoint(p, n, A, attrs, x[idx], EPS, df[idx], nthreads=cores)
+    dt_dir = time.perf_counter() - t0
     return {"value": k / dt, "unit": "queries/s", "cores": cores, "kind": "oracle",
             "sample": f"{k} queries drawn (seed 18) from the {x.shape[0]}-query set; FP64 Barnes-Hut "
                       f"forward (values+gradients) + adjoint on the full {p.shape[0]}-point tree, "
-                      f"{dt:.1f} s wall on {cores} threads; tree build excluded"}
+                      f"{dt:.1f} s wall on {cores} threads; tree build excluded",
+            "host": host,
+            "one_thread": {"value": k_one / dt_one, "unit": "queries/s", "sample": f"{k_one} queries, {dt_one:.1f} s"},
+            "direct_sum": {"value": n_dir / dt_dir, "unit": "queries/s", "cores": cores,
+                           "sample": f"{n_dir} queries (seed 18), FP64 direct sum over all {p.shape[0]} points "
+                                     f"(values + gradients) + its adjoint, {dt_dir:.1f} s wall",
+                           "extrapolated_s_for_all_queries": x.shape[0] / n_dir * dt_dir}}
 
 
 def main():

@@ -12,7 +12,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dps_oracle.c")
-_LIB = os.path.join(_HERE, "libdps_oracle.so")
+# DPS_ORACLE_SANITIZE=1 selects a separate build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (the process must preload the ASan runtime)
+_SANITIZE = os.environ.get("DPS_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "libdps_oracle_san.so" if _SANITIZE else "libdps_oracle.so")
 _lib = None
 
 _f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
@@ -23,7 +26,9 @@ def build(force: bool = True) -> str:
     """Compile the reference with gcc (FP64, no floating-point contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+        opt = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+               "-fno-omit-frame-pointer"] if _SANITIZE else ["-O2"]
+        cmd = ["gcc", *opt, "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(tmp, _LIB)
