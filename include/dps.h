@@ -256,6 +256,36 @@ dps_status dps_set_launch(dps_tree t, int32_t query_k, int32_t adjoint_k, int32_
 dps_status dps_get_launch(dps_tree t, int32_t *query_k, int32_t *adjoint_k, int32_t *flags);
 
 /*
+ * dps_set_split -- subtree-split walks, for batches too small to fill the GPU
+ * (the few hundred thousand samples of a 4096-ray training batch make a few
+ * wavefronts per SIMD, each waiting on its own chain of node fetches).  With
+ * P > 1 parts the walk of each 64-query tile (one query per lane) is divided
+ * over P wavefronts.  Nodes are numbered level by level in Morton order, and
+ * node t of level <= cut_level belongs to part t mod P.  Every part tests the
+ * nodes above the cut level that its queries reach (each part opens the same
+ * ones) but adds a node's far-field term only if it owns the node; a node of
+ * the cut level, or a leaf above it, that the part does not own is skipped
+ * with its whole subtree.  Each source term of Algorithm 1 is therefore added
+ * by exactly one part.
+ *  query_parts  (0 keeps) 1, 2, 4 or 8, for dps_query and dps_query_channels
+ *      on dipole trees.  The call zeroes the f (and grad) rows and the parts
+ *      add their sums into them with FP32 atomics: with 2 parts the result
+ *      does not depend on their order; with more it can change between runs
+ *      in the last bit.  Summation order differs from the unsplit walk.
+ *  adjoint_parts  (0 keeps) 1, 2, 4 or 8, for the dipole adjoint accumulation
+ *      when dL/dx is not formed in the walk (dx NULL, or
+ *      dps_adjoint_accumulate_from_forward); part 0 writes dL/dx.  The
+ *      accumulators are FP64 atomic sums either way.
+ *  cut_level  (-1 keeps) 0 to 21.
+ * The packet sizes and flags of dps_set_launch do not apply to split walks;
+ * grid queries, ray marches, the gradient-cotangent adjoint and monopole
+ * trees are never split.  Host-only; applies to later launches.  Default 1, 1
+ * (unsplit), cut level 6.  Errors: DPS_ERR_INVALID for other values.
+ */
+dps_status dps_set_split(dps_tree t, int32_t query_parts, int32_t adjoint_parts, int32_t cut_level);
+dps_status dps_get_split(dps_tree t, int32_t *query_parts, int32_t *adjoint_parts, int32_t *cut_level);
+
+/*
  * dps_query_channels / dps_adjoint_accumulate_channels -- as dps_query /
  * dps_adjoint_accumulate for the channel range [c_begin, c_begin+n_channels)
  * only (e.g. the geometry channel alone for shadow rays).  f, grad and df rows

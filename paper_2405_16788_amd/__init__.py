@@ -8,7 +8,8 @@ streams only.
 from .binding import (  # noqa: F401
     DpsError, Tree, dps_build, dps_get_kernel, dps_set_attributes, dps_query, dps_query_counts,
     dps_adjoint_zero, dps_adjoint_accumulate, dps_adjoint_finalize, dps_adjoint, dps_adjoint_noalloc,
-    dps_export_tree, dps_tree_info, dps_set_launch, dps_get_launch, dps_query_channels,
+    dps_export_tree, dps_tree_info, dps_set_launch, dps_get_launch, dps_set_split, dps_get_split,
+    dps_query_channels,
     dps_adjoint_accumulate_channels, dps_adjoint_accumulate_grad, dps_adjoint_accumulate_ext,
     dps_adjoint_accumulate_from_forward,
     dps_adjoint_finalize_ext, dps_set_normals, dps_query_grid, dps_ray_march, dps_ray_resample, WANT_NORMALS, WANT_EPS, dps_check, dps_set_step_limit,

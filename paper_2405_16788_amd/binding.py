@@ -23,7 +23,7 @@ KERNEL = {"dipole": DPS_KERNEL_DIPOLE, "monopole": DPS_KERNEL_MONOPOLE}
 EXPORTED = (
     "dps_build", "dps_build_kernel", "dps_get_kernel", "dps_set_attributes", "dps_query", "dps_query_counts", "dps_adjoint_zero",
     "dps_adjoint_accumulate", "dps_adjoint_finalize", "dps_adjoint", "dps_export_tree",
-    "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_query_channels",
+    "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_set_split", "dps_get_split", "dps_query_channels",
     "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_adjoint_accumulate_ext",
     "dps_adjoint_accumulate_from_forward",
     "dps_adjoint_finalize_ext", "dps_set_normals", "dps_query_grid", "dps_ray_march", "dps_ray_resample",
@@ -64,6 +64,8 @@ def load():
         "dps_check": [vp, vp],
         "dps_set_launch": [vp, i32, i32, i32],
         "dps_get_launch": [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)],
+        "dps_set_split": [vp, i32, i32, i32],
+        "dps_get_split": [vp, ct.POINTER(i32), ct.POINTER(i32), ct.POINTER(i32)],
         "dps_query_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate_channels": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_adjoint_accumulate_grad": [vp, vp, i64, vp, f32, f32, i32, i32, vp, vp, vp, vp],
@@ -301,6 +303,19 @@ def dps_get_launch(tree: Tree):
     a, b, c = ct.c_int32(), ct.c_int32(), ct.c_int32()
     _check(load().dps_get_launch(tree.handle, ct.byref(a), ct.byref(b), ct.byref(c)), "dps_get_launch")
     return {"query": a.value, "adjoint": b.value, "flags": c.value}
+
+
+def dps_set_split(tree: Tree, query_parts: int = 0, adjoint_parts: int = 0, cut_level: int = -1):
+    """Subtree-split walks for small batches: parts (1, 2, 4, 8; 0 keeps)
+    for the query and the adjoint accumulation, and the cut level (-1
+    keeps)."""
+    _check(load().dps_set_split(tree.handle, int(query_parts), int(adjoint_parts), int(cut_level)), "dps_set_split")
+
+
+def dps_get_split(tree: Tree):
+    a, b, c = ct.c_int32(), ct.c_int32(), ct.c_int32()
+    _check(load().dps_get_split(tree.handle, ct.byref(a), ct.byref(b), ct.byref(c)), "dps_get_split")
+    return {"query": a.value, "adjoint": b.value, "cut": c.value}
 
 
 def dps_query_channels(tree: Tree, x, beta: float, eps: float, c_begin: int, n_channels: int,

@@ -169,6 +169,9 @@ dps_status dps_build_kernel(const float *p, const float *n, const float *A, cons
     t->packet_query = kDefaultPacketQuery;
     t->packet_adjoint = kDefaultPacketAdjoint;
     t->launch_flags = kDefaultLaunchFlags;
+    t->split_query = 1;
+    t->split_adjoint = 1;
+    t->split_cut = kDefaultSplitCut;
     const bool bf = storage == DPS_STORE_BF16;
     const int kw = t->kw;
     t->mom_stride = bf ? ((kw * C + 1) & ~1) : kw * C;
@@ -553,6 +556,28 @@ dps_status dps_get_launch(dps_tree t, int32_t *query_k, int32_t *adjoint_k, int3
     if (query_k) *query_k = t->packet_query;
     if (adjoint_k) *adjoint_k = t->packet_adjoint;
     if (flags) *flags = t->launch_flags;
+    return DPS_OK;
+}
+
+dps_status dps_set_split(dps_tree t, int32_t query_parts, int32_t adjoint_parts, int32_t cut_level) {
+    dps_status st = check_tree(t, "dps_set_split");
+    if (st != DPS_OK) return st;
+    auto ok = [](int32_t p) { return p == 0 || p == 1 || p == 2 || p == 4 || p == 8; };
+    if (!ok(query_parts) || !ok(adjoint_parts))
+        return invalid("dps_set_split: parts must be 0 (keep), 1, 2, 4 or 8");
+    if (cut_level < -1 || cut_level > kLevels) return invalid("dps_set_split: cut_level must be -1 (keep) or a level in [0, 21]");
+    if (query_parts) t->split_query = query_parts;
+    if (adjoint_parts) t->split_adjoint = adjoint_parts;
+    if (cut_level >= 0) t->split_cut = cut_level;
+    return DPS_OK;
+}
+
+dps_status dps_get_split(dps_tree t, int32_t *query_parts, int32_t *adjoint_parts, int32_t *cut_level) {
+    dps_status st = check_tree(t, "dps_get_split");
+    if (st != DPS_OK) return st;
+    if (query_parts) *query_parts = t->split_query;
+    if (adjoint_parts) *adjoint_parts = t->split_adjoint;
+    if (cut_level) *cut_level = t->split_cut;
     return DPS_OK;
 }
 

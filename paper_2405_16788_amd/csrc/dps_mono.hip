@@ -114,11 +114,8 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                const uint32_t je = nd.first + nd.count;
-                for (uint32_t j = nd.first; j < je; ++j) {
-                    const PointRec pr = pts[j];
-                    float mu[CB];
-                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                                          [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
 #pragma unroll
                     for (int i = 0; i < K; ++i) {
                         if (open[i]) {
@@ -142,7 +139,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
                             }
                         }
                     }
-                }
+                });
             }
         }
         if (next == kEnd) break;
@@ -279,11 +276,8 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                const uint32_t je = nd.first + nd.count;
-                for (uint32_t j = nd.first; j < je; ++j) {
-                    const PointRec pr = pts[j];
-                    float mu[CB];
-                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                                          [&](uint32_t j, const PointRec &pr, const float (&mu)[CB]) {
                     float acc[CB];
 #pragma unroll
                     for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
@@ -310,7 +304,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
                         }
                     }
                     scatter_add_node(acc, lane, &P[(size_t)j * C + c0]);
-                }
+                });
             }
         }
         if (next == kEnd) break;

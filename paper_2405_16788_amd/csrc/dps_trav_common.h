@@ -111,6 +111,48 @@ __device__ __forceinline__ void load_attrs(const void *__restrict__ attr, int as
     }
 }
 
+// The points [first, first + count) of a bucket leaf in order, fn(j, rec, mu)
+// once per point.  The record and attributes of point j + 1 are requested as
+// soon as those of point j have arrived, so their latency runs under point j's
+// arithmetic instead of before it.  Scalar loads may return out of order and a
+// wait covers every load in flight, so each wait is placed explicitly, before
+// the next point's loads are issued (a wait the compiler put at the first use
+// of the current point's registers would also wait for them).  Two register
+// sets alternate, so no record is copied.  Blocks of more than 4 channels
+// keep the plain loop: a second set of their attributes does not fit in the
+// scalar registers.
+template <int CB, bool BF16, class Fn>
+__device__ __forceinline__ void for_leaf_points(const PointRec *__restrict__ pts, const void *__restrict__ attr,
+                                                int as, int c0, uint32_t first, uint32_t count, Fn &&fn) {
+    const uint32_t je = first + count;
+    if constexpr (CB > 4) {
+        for (uint32_t j = first; j < je; ++j) {
+            const PointRec r = pts[j];
+            float m[CB];
+            load_attrs<CB, BF16>(attr, as, j, c0, m);
+            fn(j, r, m);
+        }
+        return;
+    }
+    PointRec ra = pts[first];
+    float ma[CB];
+    load_attrs<CB, BF16>(attr, as, first, c0, ma);
+    for (uint32_t j = first; j < je; j += 2) {
+        wait_scalar_loads();
+        const uint32_t j1 = j + 1 < je ? j + 1 : j;
+        const PointRec rb = pts[j1];
+        float mb[CB];
+        load_attrs<CB, BF16>(attr, as, j1, c0, mb);
+        fn(j, ra, ma);
+        if (j + 1 >= je) break;
+        wait_scalar_loads();
+        const uint32_t j2 = j + 2 < je ? j + 2 : j1;
+        ra = pts[j2];
+        load_attrs<CB, BF16>(attr, as, j2, c0, ma);
+        fn(j1, rb, mb);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launch shapes
 //
@@ -153,6 +195,33 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t
         }
     }
     return -1;
+}
+
+// ---------------------------------------------------------------------------
+// Subtree split: the walk of one 64-query tile divided over `parts`
+// wavefronts, for batches too small to fill the GPU with one wavefront per
+// tile.  Nodes are stored level by level in Morton order, so the nodes of one
+// level that lie next to each other in space have consecutive indices; node t
+// of level <= cut belongs to part t mod parts.  Every part tests every node
+// above the cut level that its queries reach (the decision to open it is the
+// same in each) but adds the far-field term of a node only if it owns it;
+// a node of the cut level, or a leaf above it, that it does not own is
+// skipped with its whole subtree, and inside an owned one the walk is the
+// plain one.  So every term of every query is added by exactly one part, the
+// one that owns its node's ancestor (or itself) at the cut level.
+// ---------------------------------------------------------------------------
+struct Split {
+    uint32_t part;   // this wavefront's part
+    uint32_t mask;   // parts - 1 (parts a power of two)
+    uint32_t cut;    // the cut level
+};
+
+// whether this part takes node t (level lvl): own -- adds its far-field term;
+// skip -- neither tests nor enters it
+__device__ __forceinline__ void split_node(const Split &sp, uint32_t t, uint32_t lvl, bool leaf, bool &own,
+                                           bool &skip) {
+    own = lvl > sp.cut || (t & sp.mask) == sp.part;
+    skip = !own && (leaf || lvl == sp.cut);
 }
 
 // Shared parameters of the traversal bodies.  f / grad / df rows have `ldo`

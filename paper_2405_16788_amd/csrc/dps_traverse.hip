@@ -35,9 +35,10 @@ namespace {
 // next node is known right after the ballots, so its record and moments are
 // fetched before the far-field / leaf work of the current node.
 // ---------------------------------------------------------------------------
-template <int CB, bool BF16, bool GRAD, bool GRID = false>
+template <int CB, bool BF16, bool GRAD, bool GRID = false, bool SPLIT = false>
 __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *__restrict__ fout,
-                                            float *__restrict__ gout, const GridSpec &gs = GridSpec{}) {
+                                            float *__restrict__ gout, const GridSpec &gs = GridSpec{},
+                                            const Split &sp = Split{}) {
     bool valid = q < Q;
     float px = 0.0f, py = 0.0f, pz = 0.0f;
     int64_t row = q;
@@ -67,10 +68,13 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         }
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
-        const bool in = (bits >> lvl) & 1u;
+        bool own = true, skip = false;
+        if constexpr (SPLIT) split_node(sp, t, lvl, leaf, own, skip);
+        const bool in = !skip && ((bits >> lvl) & 1u);
         const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
-        const bool far = in && (s > mul_rn(b2, nd.r2));
-        const bool open = in && !far;
+        const bool accept = in && (s > mul_rn(b2, nd.r2));
+        const bool far = accept && own;
+        const bool open = in && !accept;
         const bool any_far = __ballot(far) != 0;
         const bool any_open = __ballot(open) != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
@@ -99,11 +103,8 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
             if (!leaf) {
                 bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
             } else {
-                const uint32_t je = nd.first + nd.count;
-                for (uint32_t j = nd.first; j < je; ++j) {
-                    const PointRec pr = pts[j];
-                    float mu[CB];
-                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                                          [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
                     if (open) {
                         const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
                         const float r2 = dx * dx + dy * dy + dz * dz;
@@ -126,7 +127,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
                             }
                         }
                     }
-                }
+                });
             }
         }
         if (next == kEnd) break;
@@ -139,11 +140,20 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             const int64_t o = row * ldo + co + c;
-            fout[o] = f[c];
-            if (GRAD) {
-                gout[3 * o] = g[c][0];
-                gout[3 * o + 1] = g[c][1];
-                gout[3 * o + 2] = g[c][2];
+            if constexpr (SPLIT) {  // the parts' sums meet in the zero-filled outputs
+                atomicAdd(&fout[o], f[c]);
+                if (GRAD) {
+                    atomicAdd(&gout[3 * o], g[c][0]);
+                    atomicAdd(&gout[3 * o + 1], g[c][1]);
+                    atomicAdd(&gout[3 * o + 2], g[c][2]);
+                }
+            } else {
+                fout[o] = f[c];
+                if (GRAD) {
+                    gout[3 * o] = g[c][0];
+                    gout[3 * o + 1] = g[c][1];
+                    gout[3 * o + 2] = g[c][2];
+                }
             }
         }
     }
@@ -249,11 +259,8 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
                     for (int i = 0; i < K; ++i)
                         bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
                 } else {
-                    const uint32_t je = nd.first + nd.count;
-                    for (uint32_t j = nd.first; j < je; ++j) {
-                        const PointRec pr = pts[j];
-                        float mu[CB];
-                        load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                    for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                                              [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
 #pragma unroll
                         for (int i = 0; i < K; ++i) {
                             if (open[i]) {
@@ -279,7 +286,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
                                 }
                             }
                         }
-                    }
+                    });
                 }
             }
             if (next == kEnd) break;
@@ -321,6 +328,20 @@ __global__ __launch_bounds__(kThreads) void k_query(DPS_KERN_PARAMS, float *__re
     if (blk < 0 || blk * (int64_t)blockDim.x * K >= Q) return;  // whole block past the rows
     const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
     query_body<CB, BF16, GRAD, K>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, fout, gout);
+}
+
+// subtree-split query: wavefront w takes part w mod parts of tile w / parts,
+// one query per lane, and adds its sums into zero-filled outputs
+template <int CB, bool BF16, bool GRAD>
+__global__ __launch_bounds__(kThreads) void k_query_split(DPS_KERN_PARAMS, float *__restrict__ fout,
+                                                          float *__restrict__ gout, Split sp, int shift) {
+    DPS_ROWS;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t tile = wave >> shift;
+    if (tile * 64 >= Q) return;  // wave-uniform
+    sp.part = (uint32_t)wave & sp.mask;
+    query1_body<CB, BF16, GRAD, false, true>(tile * 64 + (threadIdx.x & 63), DPS_TRAV_ARGS, fout, gout, GridSpec{},
+                                             sp);
 }
 
 template <int CB, bool BF16, bool GRAD, int K>
@@ -415,11 +436,11 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
 // the identical sum, 3 CB multiply-adds per query instead of a second
 // evaluation of every term's gradient.
 // ---------------------------------------------------------------------------
-template <int CB, bool BF16, int K, bool DX>
+template <int CB, bool BF16, int K, bool DX, bool SPLIT = false>
 __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C, const float *__restrict__ df,
                                              double *__restrict__ G, double *__restrict__ P,
                                              float *__restrict__ dxout, int dx_mode,
-                                             const float *__restrict__ gin) {
+                                             const float *__restrict__ gin, const Split &sp = Split{}) {
     const int lane = lane_id();
     float px[K], py[K], pz[K], w[K][CB], ax[K], ay[K], az[K];
     uint32_t bits[K];
@@ -448,14 +469,17 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
         const float lim = mul_rn(b2, nd.r2);
+        bool own = true, skip = false;
+        if constexpr (SPLIT) split_node(sp, t, lvl, leaf, own, skip);
         bool far[K], open[K], lane_far = false, lane_open = false;
         float s[K];
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const bool in = (bits[i] >> lvl) & 1u;
+            const bool in = !skip && ((bits[i] >> lvl) & 1u);
             s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
-            far[i] = in && (s[i] > lim);
-            open[i] = in && !far[i];
+            const bool accept = in && (s[i] > lim);
+            far[i] = accept && own;
+            open[i] = in && !accept;
             lane_far |= far[i];
             lane_open |= open[i];
         }
@@ -509,11 +533,8 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                const uint32_t je = nd.first + nd.count;
-                for (uint32_t j = nd.first; j < je; ++j) {
-                    const PointRec pr = pts[j];
-                    float mu[CB];
-                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                                          [&](uint32_t j, const PointRec &pr, const float (&mu)[CB]) {
                     float acc[CB];
 #pragma unroll
                     for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
@@ -544,7 +565,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                         }
                     }
                     scatter_add_node(acc, lane, &P[(size_t)j * C + c0]);
-                }
+                });
             }
         }
         if (next == kEnd) break;
@@ -553,7 +574,8 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
 #pragma unroll
         for (int v = 0; v < 3 * CB; ++v) D[v] = Dn[v];
     }
-    if (dx_mode != 0) {
+    static_assert(!(SPLIT && DX), "a split walk forms no dL/dx");
+    if (dx_mode != 0 && (!SPLIT || sp.part == 0)) {  // one part writes dL/dx
 #pragma unroll
         for (int i = 0; i < K; ++i) {
             const int64_t q = q0 + 64 * i;
@@ -596,6 +618,22 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(DPS_KERN_PARAMS, int C, co
     const int64_t wave = (blk * blockDim.x + threadIdx.x) >> 6;
     adjoint_body<CB, BF16, K, DX>(wave * 64 * K + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout, dx_mode,
                                   gin);
+}
+
+// subtree-split adjoint (accumulators only, dL/dx if wanted from the
+// forward's gradients): wavefront w takes part w mod parts of tile w / parts
+template <int CB, bool BF16>
+__global__ __launch_bounds__(kThreads) void k_adjoint_split(DPS_KERN_PARAMS, int C, const float *__restrict__ df,
+                                                            double *__restrict__ G, double *__restrict__ P,
+                                                            float *__restrict__ dxout, int dx_mode,
+                                                            const float *__restrict__ gin, Split sp, int shift) {
+    DPS_ROWS;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t tile = wave >> shift;
+    if (tile * 64 >= Q) return;  // wave-uniform
+    sp.part = (uint32_t)wave & sp.mask;
+    adjoint_body<CB, BF16, 1, false, true>(tile * 64 + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout,
+                                           dx_mode, gin, sp);
 }
 
 // resident waves per SIMD requested for the 4-query, 4-channel persistent
@@ -753,11 +791,8 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                const uint32_t je = nd.first + nd.count;
-                for (uint32_t j = nd.first; j < je; ++j) {
-                    const PointRec pr = pts[j];
-                    float mu[CB];
-                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                                          [&](uint32_t j, const PointRec &pr, const float (&mu)[CB]) {
                     float acc[CB];
                     float nacc[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -816,7 +851,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                     if constexpr (EXT) {
                         if (pn) scatter_add_node(nacc, lane, &pn[(size_t)j * 3]);
                     }
-                }
+                });
             }
         }
         if (next == kEnd) break;
@@ -1061,9 +1096,55 @@ dps_status query_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t 
     return hip_status(hipGetLastError(), "query launch");
 }
 
+// zeroes the first min(Qcap, *qdev) rows of f (and g), `row` floats per f row
+__global__ void k_zero_rows(float *__restrict__ f, float *__restrict__ g, int64_t Qcap,
+                            const int64_t *__restrict__ qdev, int64_t row) {
+    DPS_ROWS;
+    const int64_t nf = Q * row;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nf; i += (int64_t)gridDim.x * blockDim.x) {
+        f[i] = 0.0f;
+        if (g) {
+            g[3 * i] = 0.0f;
+            g[3 * i + 1] = 0.0f;
+            g[3 * i + 2] = 0.0f;
+        }
+    }
+}
+
+inline int split_shift(int parts) {
+    int sh = 0;
+    while ((1 << sh) < parts) ++sh;
+    return sh;
+}
+
+inline dps_status split_grid(int64_t Q, int parts, unsigned &wgs) {
+    const int64_t n = cdiv(std::max<int64_t>(Q, 1), 64) * parts;
+    const int64_t w = cdiv(n, kThreads / 64);
+    if (w > INT32_MAX) {
+        set_error("split launch: %lld workgroups exceed the launch grid", (long long)w);
+        return DPS_ERR_INVALID;
+    }
+    wgs = (unsigned)w;
+    return DPS_OK;
+}
+
+template <int CB, bool BF, bool GR>
+dps_status query_split_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp,
+                              Sub sb, float *f, float *g, hipStream_t s) {
+    unsigned wgs = 0;
+    dps_status st = split_grid(Q, t->split_query, wgs);
+    if (st != DPS_OK) return st;
+    const Split sp{0u, (uint32_t)t->split_query - 1u, (uint32_t)t->split_cut};
+    k_query_split<CB, BF, GR><<<wgs, kThreads, 0, s>>>(t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride,
+                                                       t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
+                                                       walk_limit(t), t->err, f, g, sp, split_shift(t->split_query));
+    return hip_status(hipGetLastError(), "split query launch");
+}
+
 template <int CB, bool BF, bool GR>
 dps_status query_k(dps_tree_s *t, int k, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
                    float *f, float *g, hipStream_t s) {
+    if (t->split_query > 1) return query_split_launch<CB, BF, GR>(t, x, Q, qdev, b2, kp, sb, f, g, s);
     switch (clamp_packet(k, CB, GR)) {
         case 4:
             if constexpr ((GR && CB <= 2) || (!GR && CB <= 4)) return query_launch<CB, BF, GR, 4>(t, x, Q, qdev, b2, kp, sb, f, g, s);
@@ -1156,10 +1237,31 @@ dps_status adjoint_launch_dx(dps_tree_s *t, const float *x, int64_t Q, const int
     return adjoint_launch<CB, BF, K, false>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s);
 }
 
+template <int CB, bool BF>
+dps_status adjoint_split_launch(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2,
+                                KernelParams kp, Sub sb, const float *df, float *dx, int dx_mode, const float *gin,
+                                const AccBuffers &ab, hipStream_t s) {
+    unsigned wgs = 0;
+    dps_status st = split_grid(Q, t->split_adjoint, wgs);
+    if (st != DPS_OK) return st;
+    const Split sp{0u, (uint32_t)t->split_adjoint - 1u, (uint32_t)t->split_cut};
+    k_adjoint_split<CB, BF><<<wgs, kThreads, 0, s>>>(t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride,
+                                                     t->attr_stride, x, Q, qdev, b2, kp, sb.c0, sb.ldo, sb.co,
+                                                     walk_limit(t), t->err, t->C, df, ab.G, ab.P, dx, dx_mode, gin,
+                                                     sp, split_shift(t->split_adjoint));
+    return hip_status(hipGetLastError(), "split adjoint launch");
+}
+
 template <int CB>
 dps_status adjoint_block(dps_tree_s *t, const float *x, int64_t Q, const int64_t *qdev, float b2, KernelParams kp, Sub sb,
                          const float *df, float *dx, int dx_mode, const float *gin, const AccBuffers &ab,
                          hipStream_t s) {
+    // the split walk when no dL/dx has to be formed in it
+    if (t->split_adjoint > 1 && (dx_mode == 0 || gin)) {
+        if (t->storage == DPS_STORE_BF16)
+            return adjoint_split_launch<CB, true>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s);
+        return adjoint_split_launch<CB, false>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s);
+    }
     const int k = clamp_packet(t->packet_adjoint, CB, false);
     if (t->storage == DPS_STORE_BF16) {
         if (k == 4) { if constexpr (CB <= 4) return adjoint_launch_dx<CB, true, 4>(t, x, Q, qdev, b2, kp, sb, df, dx, dx_mode, gin, ab, s); }
@@ -1233,6 +1335,11 @@ dps_status launch_query(dps_tree_s *t, const float *x, int64_t Q, const int64_t 
     if (t->kernel == DPS_KERNEL_MONOPOLE) return launch_query_mono(t, x, Q, qdev, beta, eps, cbegin, nc, f, g, s);
     const float b2 = mul_rn(beta, beta);
     const KernelParams kp = tree_kernel_params(t, eps);
+    if (t->split_query > 1) {  // the parts add into zeroed rows
+        k_zero_rows<<<std::min<unsigned>(grid(Q * nc), 4096u), kThreads, 0, s>>>(f, g, Q, qdev, nc);
+        dps_status st = hip_status(hipGetLastError(), "split query zero fill");
+        if (st != DPS_OK) return st;
+    }
     for (int c0 = cbegin; c0 < cbegin + nc;) {
         const int cb = next_block(cbegin + nc - c0);
         const Sub sb{c0, nc, c0 - cbegin};

@@ -30,6 +30,9 @@ struct dps_tree_s {
     int packet_query;    // queries per lane in dps_query (1, 2, 4)
     int packet_adjoint;  // queries per lane in dps_adjoint_accumulate (1, 2, 4)
     int launch_flags;    // kFlag* bits: XCD-contiguous order / persistent launch per kernel
+    int split_query;     // parts of the subtree-split query walk (1: unsplit; dps_set_split)
+    int split_adjoint;   // the same for the adjoint accumulation
+    int split_cut;       // level at which the split walks divide the tree
     uint32_t step_limit; // nodes one traversal may walk (dps_set_step_limit; default N)
     uint32_t *ctr;       // [16] tile counters of the persistent launches (query, adjoint)
 

@@ -127,11 +127,8 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                const uint32_t je = nd.first + nd.count;
-                for (uint32_t j = nd.first; j < je; ++j) {
-                    const PointRec pr = pts[j];
-                    float mu[CB];
-                    load_attrs<CB, BF16>(attr, as, j, c0, mu);
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                                          [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
                     float dx[K], dy[K], dz[K], r2[K], kap[K], lam[K];
                     bool on[K];
 #pragma unroll
@@ -163,7 +160,7 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
                             }
                         }
                     }
-                }
+                });
             }
         }
         if (next == kEnd) break;
