@@ -428,8 +428,17 @@ dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing
  *   of dps_set_launch instead gives each lane one ray, walking its samples in
  *   order up to its crossing (consecutive rays should then be neighbouring
  *   pixels, e.g. 8 x 8 tiles); results are identical either way.  The
- *   ray-major march uses hit_index itself as its working buffer (an atomic
- *   minimum over chunks), so no memory beyond the caller's is needed.
+ *   ray-major march keeps the crossing index in hit_index (an atomic minimum
+ *   over chunks) and the two field values of each chunk's first crossing in
+ *   a workspace held by the tree (R x chunks x 8 bytes, chunks =
+ *   ceil((n_samples - 1) / (64 k - 1)) for query packet k), from which the
+ *   values of the ray's crossing are gathered.  The first call that needs a
+ *   larger workspace allocates it (counted in the tree's bytes and under
+ *   dps_set_memory_limit); an outgrown workspace stays allocated until
+ *   dps_destroy, because a graph captured earlier may use it.  A call being
+ *   captured into a graph that would need a larger workspace, or one the
+ *   memory limit or an allocation failure refuses, evaluates the field at
+ *   j and j + 1 in a second pass instead: the same values bit for bit.
  *   n_samples in [2, 2^20]; dipole-kernel trees only; with BF16 storage the
  *   channel must be even.  R = 0 is a no-op.  DPS_ERR_INVALID (nothing
  *   launched) for a bad argument or NULL array, or for more rays x samples

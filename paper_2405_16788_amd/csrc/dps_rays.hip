@@ -118,14 +118,18 @@ __global__ __launch_bounds__(kThreads) void k_ray_march(
 // [c P, c P + P), P = 64 K - 1, the last lane's last sample being the next
 // chunk's first.  The wavefront lowers hit[r] to its first crossing (atomic
 // min; hit starts at INT32_MAX) and skips its chunk when hit[r] already lies
-// before it.
+// before it.  With `slots` ([R][nchunks][2]) it also stores the field at its
+// first crossing j and at j + 1 in its own slot: the chunk holding the ray's
+// final (smallest) crossing always runs (hit[r] never drops below it) and
+// finds that crossing first, so k_ray_hit_gather reads the values from the
+// slot of chunk j / P.
 template <bool BF16, int K>
 __global__ __launch_bounds__(kThreads) void k_ray_march_along(
     const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
     const void *__restrict__ attr, int ms, int as, float b2, KernelParams kp, int c0, uint32_t limit,
     uint32_t *__restrict__ err, const float *__restrict__ o, const float *__restrict__ d,
     const float *__restrict__ tnear, const float *__restrict__ tfar, int64_t R, int n, int64_t nitems, float level,
-    int32_t *__restrict__ hit) {
+    int32_t *__restrict__ hit, float *__restrict__ slots, int nchunks) {
     constexpr int P = 64 * K - 1;
     const int lane = lane_id();
     const int64_t item = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
@@ -152,15 +156,46 @@ __global__ __launch_bounds__(kThreads) void k_ray_march_along(
     dipole_walk<1, BF16, false, K>(px, py, pz, bits, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit, err);
     const float next = __shfl_down(f[0][0], 1);  // the next lane's first sample
     int32_t j = INT32_MAX;
+    float v0 = 0.0f, v1 = 0.0f;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int s = s0 + lane * K + i;
         const bool pair = s + 1 < n && (lane < 63 || i < K - 1);
         const float w = i + 1 < K ? f[i + 1 < K ? i + 1 : i][0] : next;
-        if (j == INT32_MAX && pair && ((f[i][0] >= level) != (w >= level))) j = s;
+        if (j == INT32_MAX && pair && ((f[i][0] >= level) != (w >= level))) {
+            j = s;
+            v0 = f[i][0];
+            v1 = w;
+        }
     }
     const uint64_t m = __ballot(j != INT32_MAX);
-    if (m != 0 && lane == __ffsll((unsigned long long)m) - 1) atomicMin(&hit[r], j);
+    if (m != 0 && lane == __ffsll((unsigned long long)m) - 1) {
+        atomicMin(&hit[r], j);
+        if (slots) {
+            float *sl = slots + 2 * (r * nchunks + c);
+            sl[0] = v0;
+            sl[1] = v1;
+        }
+    }
+}
+
+// After the ray-major march with crossing slots: hit = -1 and zero values
+// without a crossing, else the values the chunk of the crossing stored.
+__global__ void k_ray_hit_gather(int64_t R, int nchunks, int P, int32_t *__restrict__ hit, float *__restrict__ hv,
+                                 const float *__restrict__ slots) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const int32_t j = hit[r];
+    float v0 = 0.0f, v1 = 0.0f;
+    if (j == INT32_MAX) {
+        hit[r] = -1;
+    } else {
+        const float *sl = slots + 2 * (r * nchunks + j / P);
+        v0 = sl[0];
+        v1 = sl[1];
+    }
+    hv[2 * r] = v0;
+    hv[2 * r + 1] = v1;
 }
 
 // After the ray-major march: the field at samples j and j + 1 of each ray
@@ -255,6 +290,31 @@ __global__ void k_ray_resample(const float *__restrict__ o, const float *__restr
     x_out[3 * row + 2] = ray_at(o[3 * r + 2], t, d[3 * r + 2]);
 }
 
+// The tree's crossing-slot workspace with at least `bytes`: a larger one is
+// allocated when a call is not being captured into a graph and the memory
+// limit allows it; nullptr otherwise (the march then takes the values in a
+// second pass).  A workspace that is outgrown stays allocated with the tree,
+// since a graph captured earlier may still write to it.
+float *crossing_slots(dps_tree_s *t, int64_t bytes, hipStream_t s) {
+    if (bytes <= t->ray_ws_bytes) return t->ray_ws;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (!memory_fits(t, (size_t)bytes)) return nullptr;
+    void *p = nullptr;
+    if (hipMalloc(&p, (size_t)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    t->allocs.push_back(p);
+    t->bytes += bytes;
+    t->ray_ws = (float *)p;
+    t->ray_ws_bytes = bytes;
+    return t->ray_ws;
+}
+
 template <bool BF16, int K>
 dps_status march_launch(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf, int64_t R,
                         int n, float b2, KernelParams kp, int channel, float level, int32_t *hit, float *hv,
@@ -271,18 +331,24 @@ template <bool BF16, int K>
 dps_status march_along_launch(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf,
                               int64_t R, int n, float b2, KernelParams kp, int channel, float level, int32_t *hit,
                               float *hv, hipStream_t s) {
-    const int64_t nitems = cdiv(n - 1, 64 * K - 1) * R;
+    const int nchunks = (int)cdiv(n - 1, 64 * K - 1);
+    const int64_t nitems = nchunks * R;
     const int64_t wgs = cdiv(nitems, kThreads / 64);
     if (wgs > INT32_MAX) {
         set_error("ray march: %lld workgroups exceed the launch grid", (long long)wgs);
         return DPS_ERR_INVALID;
     }
+    float *slots = crossing_slots(t, nitems * 2 * (int64_t)sizeof(float), s);
     k_fill_i32_max<<<(unsigned)std::min<int64_t>(cdiv(R, kThreads), 4096), kThreads, 0, s>>>(hit, R);
     k_ray_march_along<BF16, K><<<(unsigned)wgs, kThreads, 0, s>>>(
         t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, walk_limit(t), t->err,
-        o, d, tn, tf, R, n, nitems, level, hit);
+        o, d, tn, tf, R, n, nitems, level, hit, slots, nchunks);
     dps_status st = hip_status(hipGetLastError(), "ray-major march launch");
     if (st != DPS_OK) return st;
+    if (slots) {
+        k_ray_hit_gather<<<grid(R), kThreads, 0, s>>>(R, nchunks, 64 * K - 1, hit, hv, slots);
+        return hip_status(hipGetLastError(), "ray hit gather launch");
+    }
     int G = 1;  // rays per wavefront of the values pass: at least 16384 wavefronts
     while (G < 32 && R / (2 * G) >= 16384) G *= 2;
     k_ray_hit_values<BF16><<<(unsigned)cdiv(cdiv(R, G), kThreads / 64), kThreads, 0, s>>>(

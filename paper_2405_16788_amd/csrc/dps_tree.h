@@ -55,6 +55,8 @@ struct dps_tree_s {
     double *PN;               // [M][3] near-field dL/dn accumulators (sorted order)
     double *EACC;             // [1] dL/deps accumulator
     uint32_t *err;            // sticky device error word (traversal guard)
+    float *ray_ws;            // [rays][chunks][2] crossing values of the ray-major march (one of allocs)
+    int64_t ray_ws_bytes;     // its size
 
     int64_t bytes;            // device bytes held by the tree
     int64_t scratch_bytes;    // device bytes of the build's temporary buffers (while building)

@@ -307,3 +307,77 @@ def test_march_ray_major_equals_ray_per_lane(P, storage, R, n_s):
         if R >= 200:
             assert int((hs >= 0).sum()) > 0
     P.dps_check(tree)
+
+
+def test_march_crossing_values_without_workspace(P):
+    """The march's crossing values come from the chunk that found the crossing
+    when the tree's workspace is there; captured into a graph before any
+    workspace exists, or under a memory limit that refuses it, the march
+    evaluates them in a second pass: the same bits every way."""
+    import torch
+    p, n, A, mu = workloads.winding_cloud(20000, 1000, 90)
+    o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(91), 64)
+    R = 1000
+    o, d, tn, tf = o[:R].copy(), d[:R].copy(), tn[:R].copy(), tf[:R].copy()
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    results = {}
+    for k in (1, 2):
+        # a fresh tree: the captured march has no workspace and takes the second pass
+        tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+        P.dps_set_launch(tree, k, 0, 0)
+        bytes0 = P.dps_tree_info(tree)["bytes"]
+        hit = torch.empty(R, device="cuda", dtype=torch.int32)
+        hv = torch.empty((R, 2), device="cuda")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph):
+                P.dps_ray_march(tree, od, dd, tnd, tfd, 300, BETA, EPS, hit_out=hit, values_out=hv)
+        torch.cuda.current_stream().wait_stream(side)
+        assert P.dps_tree_info(tree)["bytes"] == bytes0  # nothing allocated under capture
+        hit.fill_(-7)
+        hv.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        captured = (to_host(hit).copy(), to_host(hv).copy())
+        # eager: allocates the workspace and gathers the values from it
+        he, ve = P.dps_ray_march(tree, od, dd, tnd, tfd, 300, BETA, EPS)
+        chunks = -(-(300 - 1) // (64 * k - 1))
+        assert P.dps_tree_info(tree)["bytes"] == bytes0 + R * chunks * 8
+        eager = (to_host(he).copy(), to_host(ve).copy())
+        # captured with the workspace in place: the graph gathers from it
+        with torch.cuda.stream(side):
+            torch.cuda.synchronize()
+            graph2 = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph2):
+                P.dps_ray_march(tree, od, dd, tnd, tfd, 300, BETA, EPS, hit_out=hit, values_out=hv)
+        torch.cuda.current_stream().wait_stream(side)
+        # a larger march outgrows the workspace; both graphs keep working
+        P.dps_ray_march(tree, od, dd, tnd, tfd, 1024, BETA, EPS)
+        for gr in (graph, graph2):
+            hit.fill_(-7)
+            hv.fill_(float("nan"))
+            gr.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(to_host(hit), eager[0]) and np.array_equal(to_host(hv), eager[1])
+        assert np.array_equal(captured[0], eager[0]) and np.array_equal(captured[1], eager[1])
+        assert 0 < int((eager[0] >= 0).sum()) < R
+        P.dps_check(tree)
+        P.dps_destroy(tree)
+        # a memory limit that leaves no room for the workspace
+        tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+        P.dps_set_launch(tree, k, 0, 0)
+        b = P.dps_tree_info(tree)["bytes"]
+        P.dps_set_memory_limit(b + 64)
+        try:
+            hl, vl = P.dps_ray_march(tree, od, dd, tnd, tfd, 300, BETA, EPS)
+            torch.cuda.synchronize()
+            assert P.dps_tree_info(tree)["bytes"] == b
+        finally:
+            P.dps_set_memory_limit(0)
+        assert np.array_equal(to_host(hl), eager[0]) and np.array_equal(to_host(vl), eager[1])
+        P.dps_destroy(tree)
+        results[k] = eager
+    assert np.array_equal(results[1][0], results[2][0]) and np.array_equal(results[1][1], results[2][1])
