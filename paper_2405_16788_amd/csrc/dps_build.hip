@@ -464,9 +464,10 @@ __global__ void k_records(int64_t N, const int32_t *__restrict__ lvl,
     if (t >= N) return;
     const bool leaf = nchild[t] == 0;
     nodes[t].first = (uint32_t)(leaf ? ptb[t] : first_child[t]);
-    nodes[t].count = (uint32_t)(leaf ? ptc[t] : nchild[t]);
+    nodes[t].down = leaf ? esc[t] : (uint32_t)first_child[t];
     nodes[t].escape = esc[t];
-    nodes[t].meta = (uint32_t)lvl[t] | (leaf ? kLeafFlag : 0u);
+    nodes[t].meta = (uint32_t)lvl[t] | (leaf ? kLeafFlag : 0u) |
+                    ((uint32_t)(leaf ? ptc[t] : nchild[t]) << kCountShift);
 }
 
 // structural invariants every later kernel relies on for its indexing

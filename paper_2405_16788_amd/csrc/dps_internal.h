@@ -18,8 +18,11 @@
 
 namespace dps {
 
-constexpr uint32_t kEnd = 0xffffffffu;   // escape pointer past the last subtree
+// escape pointer past the last subtree: the root, which no walk returns to,
+// so a walk may fetch the record of the node it moves to next without a test
+constexpr uint32_t kEnd = 0u;
 constexpr uint32_t kLeafFlag = 0x100u;   // NodeRec::meta bit: node is a leaf
+constexpr int kCountShift = 16;          // NodeRec::meta bits 16..31: children or points
 constexpr int kLevels = DPS_LEVELS;      // 21 levels below the root
 constexpr int kTopLevels = 3;            // "top-level" nodes: depth <= 3
 constexpr int64_t kWideTopPoints = 4194304;  // FP64 top-level moment sums from this size on
@@ -35,10 +38,15 @@ constexpr int kDefaultSplitCut = 6;        // cut level of the subtree-split wal
 struct alignas(32) NodeRec {
     float cx, cy, cz, r2;  // FP32 centroid and squared radius
     uint32_t first;        // first child (internal) or first point (leaf)
-    uint32_t count;        // number of children (internal) or points (leaf)
+    uint32_t down;         // where a walk that opens the node goes next: its first
+                           // child, or for a leaf its escape (the march's walk
+                           // selects with it; in the other walks the compiler
+                           // keeps fewer copies selecting on the leaf flag)
     uint32_t escape;       // next node in depth-first order after this subtree
-    uint32_t meta;         // level | kLeafFlag
+    uint32_t meta;         // level | kLeafFlag | children or points << kCountShift
 };
+
+__host__ __device__ inline uint32_t node_count(const NodeRec &nd) { return nd.meta >> kCountShift; }
 
 struct alignas(32) PointRec {
     float x, y, z;         // position as given
@@ -46,6 +54,13 @@ struct alignas(32) PointRec {
     float a;               // A_m
     float pad;
 };
+
+// a0 b0 + a1 b1 + a2 b2 as one fixed chain of fused operations, so that every
+// kernel forms a dot product with the same roundings (left to contraction,
+// the compiler may fuse a different product in each kernel)
+__device__ __forceinline__ float dot3(float a0, float a1, float a2, float b0, float b1, float b2) {
+    return fmaf(a2, b2, fmaf(a1, b1, a0 * b0));
+}
 
 // 1/(4 pi), 2/sqrt(pi), 4/sqrt(pi)
 constexpr float kInv4Pi = 0.0795774715459476679f;

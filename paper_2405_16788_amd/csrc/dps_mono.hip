@@ -83,7 +83,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
         const bool any_far = __ballot(lane_far) != 0;
         const bool any_open = __ballot(lane_open) != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
-        const uint32_t pf = next == kEnd ? t : next;
+        const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
         float Qn[CB];
         load_charges<CB, BF16>(mom, ms, pf, c0, Qn, kp.nhi);
@@ -114,13 +114,13 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
 #pragma unroll
                     for (int i = 0; i < K; ++i) {
                         if (open[i]) {
                             const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
-                            const float r2 = dx * dx + dy * dy + dz * dz;
+                            const float r2 = dot3(dx, dy, dz, dx, dy, dz);
                             if (r2 > 0.0f) {
                                 float m, gv;
                                 mono_radial(r2, kp, m, gv);
@@ -240,7 +240,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
         const bool any_far = __ballot(lane_far) != 0;
         const bool any_open = __ballot(lane_open) != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
-        const uint32_t pf = next == kEnd ? t : next;
+        const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
         float Qn[CB];
         load_charges<CB, BF16>(mom, ms, pf, c0, Qn, kp.nhi);
@@ -276,7 +276,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t j, const PointRec &pr, const float (&mu)[CB]) {
                     float acc[CB];
 #pragma unroll
@@ -285,7 +285,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
                     for (int i = 0; i < K; ++i) {
                         if (open[i]) {
                             const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
-                            const float r2 = dx * dx + dy * dy + dz * dz;
+                            const float r2 = dot3(dx, dy, dz, dx, dy, dz);
                             if (r2 > 0.0f) {
                                 float m, gv;
                                 mono_radial(r2, kp, m, gv);

@@ -14,6 +14,12 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Row i of an array of rows of `row_bytes` bytes: a 32 x 32-bit product, so
+// the address costs two scalar multiplies and a 64-bit add.
+__device__ __forceinline__ const void *row_at(const void *base, uint32_t i, uint32_t row_bytes) {
+    return (const char *)base + (uint64_t)i * row_bytes;
+}
+
 // Node moments of channels [c0, c0 + CB) of node t (wave-uniform), as
 // floats.  BF16 storage holds a bfloat16 row for every node, after the FP32
 // rows of the first nhi nodes (the top levels, whose moments dominate
@@ -26,11 +32,11 @@ template <int CB, bool BF16>
 __device__ __forceinline__ void load_moments(const void *__restrict__ mom, int ms, uint32_t t, int c0,
                                              float (&D)[3 * CB], uint32_t nhi) {
     if constexpr (!BF16) {
-        const float *b = (const float *)mom + (size_t)t * ms + 3 * c0;
+        const float *b = (const float *)row_at(mom, t, (uint32_t)ms * 4u) + 3 * c0;
 #pragma unroll
         for (int i = 0; i < 3 * CB; ++i) D[i] = b[i];
     } else {
-        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)t * ms + 3 * c0);
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)row_at(mom, t, (uint32_t)ms * 2u) + 3 * c0);
         constexpr int W = (3 * CB + 1) / 2;
         uint32_t w[W];
 #pragma unroll
@@ -66,11 +72,11 @@ template <int CB, bool BF16>
 __device__ __forceinline__ void load_charges(const void *__restrict__ mom, int ms, uint32_t t, int c0,
                                              float (&Q)[CB], uint32_t nhi) {
     if constexpr (!BF16) {
-        const float *b = (const float *)mom + (size_t)t * ms + c0;
+        const float *b = (const float *)row_at(mom, t, (uint32_t)ms * 4u) + c0;
 #pragma unroll
         for (int i = 0; i < CB; ++i) Q[i] = b[i];
     } else {
-        const uint32_t *b = (const uint32_t *)((const uint16_t *)mom + (size_t)t * ms + c0);
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)row_at(mom, t, (uint32_t)ms * 2u) + c0);
         constexpr int W = (CB + 1) / 2;
         uint32_t w[W];
 #pragma unroll
@@ -97,11 +103,11 @@ template <int CB, bool BF16>
 __device__ __forceinline__ void load_attrs(const void *__restrict__ attr, int as, uint32_t j, int c0,
                                            float (&mu)[CB]) {
     if constexpr (!BF16) {
-        const float *b = (const float *)attr + (size_t)j * as + c0;
+        const float *b = (const float *)row_at(attr, j, (uint32_t)as * 4u) + c0;
 #pragma unroll
         for (int i = 0; i < CB; ++i) mu[i] = b[i];
     } else {
-        const uint32_t *b = (const uint32_t *)((const uint16_t *)attr + (size_t)j * as + c0);
+        const uint32_t *b = (const uint32_t *)((const uint16_t *)row_at(attr, j, (uint32_t)as * 2u) + c0);
         constexpr int W = (CB + 1) / 2;
         uint32_t w[W];
 #pragma unroll
@@ -119,25 +125,29 @@ __device__ __forceinline__ void load_attrs(const void *__restrict__ attr, int as
 // the next point's loads are issued (a wait the compiler put at the first use
 // of the current point's registers would also wait for them).  Two register
 // sets alternate, so no record is copied.  Blocks of more than 4 channels
-// keep the plain loop: a second set of their attributes does not fit in the
-// scalar registers.
-template <int CB, bool BF16, class Fn>
+// keep the plain loop (PIPE = false): a second set of their attributes does
+// not fit in the scalar registers.  So do packets of several queries per
+// lane: they have other wavefronts to cover the latency, and the pipelined
+// loop made the compiler copy their accumulators on every leaf.
+// A leaf holds at least one point (count >= 1), so the loops test at the end.
+template <int CB, bool BF16, bool PIPE = (CB <= 4), class Fn>
 __device__ __forceinline__ void for_leaf_points(const PointRec *__restrict__ pts, const void *__restrict__ attr,
                                                 int as, int c0, uint32_t first, uint32_t count, Fn &&fn) {
     const uint32_t je = first + count;
-    if constexpr (CB > 4) {
-        for (uint32_t j = first; j < je; ++j) {
+    uint32_t j = first;
+    if constexpr (!PIPE) {
+        do {
             const PointRec r = pts[j];
             float m[CB];
             load_attrs<CB, BF16>(attr, as, j, c0, m);
             fn(j, r, m);
-        }
+        } while (++j < je);
         return;
     }
     PointRec ra = pts[first];
     float ma[CB];
     load_attrs<CB, BF16>(attr, as, first, c0, ma);
-    for (uint32_t j = first; j < je; j += 2) {
+    do {
         wait_scalar_loads();
         const uint32_t j1 = j + 1 < je ? j + 1 : j;
         const PointRec rb = pts[j1];
@@ -150,7 +160,8 @@ __device__ __forceinline__ void for_leaf_points(const PointRec *__restrict__ pts
         ra = pts[j2];
         load_attrs<CB, BF16>(attr, as, j2, c0, ma);
         fn(j1, rb, mb);
-    }
+        j += 2;
+    } while (j < je);
 }
 
 // ---------------------------------------------------------------------------

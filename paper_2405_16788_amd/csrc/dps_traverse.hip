@@ -78,7 +78,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         const bool any_far = __ballot(far) != 0;
         const bool any_open = __ballot(open) != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
-        const uint32_t pf = next == kEnd ? t : next;
+        const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
         float Dn[3 * CB];
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
@@ -89,7 +89,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
             const float dx = nd.cx - px, dy = nd.cy - py, dz = nd.cz - pz;
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
-                const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
+                const float sd = dot3(D[3 * c], D[3 * c + 1], D[3 * c + 2], dx, dy, dz);
                 f[c] = fmaf(kap, sd, f[c]);
                 if (GRAD) {
                     const float ls = lam * sd;
@@ -103,14 +103,14 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
             if (!leaf) {
                 bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
             } else {
-                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
                     if (open) {
                         const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
-                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        const float r2 = dot3(dx, dy, dz, dx, dy, dz);
                         float kap, lam;
                         if (radial(r2, kp, kap, lam)) {
-                            const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                            const float sa = dot3(pr.anx, pr.any, pr.anz, dx, dy, dz);
                             const float ks = kap * sa;
                             const float ls = lam * sa;
                             const float G0 = fmaf(ls, dx, -kap * pr.anx);
@@ -227,7 +227,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
             const bool any_far = __ballot(lane_far) != 0;
             const bool any_open = __ballot(lane_open) != 0;
             const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
-            const uint32_t pf = next == kEnd ? t : next;
+            const uint32_t pf = next;  // kEnd is the root: a valid record
             const NodeRec nn = nodes[pf];
             float Dn[3 * CB];
             load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
@@ -241,7 +241,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
                         const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
 #pragma unroll
                         for (int c = 0; c < CB; ++c) {
-                            const float sd = D[3 * c] * dx + D[3 * c + 1] * dy + D[3 * c + 2] * dz;
+                            const float sd = dot3(D[3 * c], D[3 * c + 1], D[3 * c + 2], dx, dy, dz);
                             f[i][c] = fmaf(kap, sd, f[i][c]);
                             if (GRAD) {
                                 const float ls = lam * sd;
@@ -259,16 +259,16 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
                     for (int i = 0; i < K; ++i)
                         bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
                 } else {
-                    for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                    for_leaf_points<CB, BF16, false>(pts, attr, as, c0, nd.first, node_count(nd),
                                               [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
 #pragma unroll
                         for (int i = 0; i < K; ++i) {
                             if (open[i]) {
                                 const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
-                                const float r2 = dx * dx + dy * dy + dz * dz;
+                                const float r2 = dot3(dx, dy, dz, dx, dy, dz);
                                 float kap, lam;
                                 if (radial(r2, kp, kap, lam)) {
-                                    const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                                    const float sa = dot3(pr.anx, pr.any, pr.anz, dx, dy, dz);
                                     const float ks = kap * sa;
                                     const float ls = lam * sa;
                                     const float G0 = fmaf(ls, dx, -kap * pr.anx);
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
     uint32_t bits = valid ? 1u : 0u;
     uint32_t t = 0;
     uint32_t steps = 0;
-    while (t != kEnd) {
+    for (;;) {
         if (++steps > limit) {  // a well-formed tree is walked in at most N steps
             if (threadIdx.x % 64 == 0) atomicOr(err, 1u);
             break;
@@ -405,16 +405,18 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
         const bool open = in && !far;
         visits += in;
         nfar += far;
+        uint32_t next = nd.escape;
         if (__ballot(open)) {
             if (!(nd.meta & kLeafFlag)) {
                 bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
-                t = nd.first;
-                continue;
+            } else {
+                leaves += open;
+                near += open ? (int32_t)node_count(nd) : 0;
             }
-            leaves += open;
-            near += open ? (int32_t)nd.count : 0;
+            next = nd.down;
         }
-        t = nd.escape;
+        if (next == kEnd) break;
+        t = next;
     }
     if (valid) {
         counts[4 * q] = visits;
@@ -486,7 +488,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         const bool any_far = __ballot(lane_far) != 0;
         const bool any_open = __ballot(lane_open) != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
-        const uint32_t pf = next == kEnd ? t : next;
+        const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
         float Dn[3 * CB];
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
@@ -518,7 +520,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                         acc[3 * c + 2] = fmaf(w[i][c], kz, acc[3 * c + 2]);
                     }
                     if constexpr (DX) {
-                        const float les = lam * (E0 * dx + E1 * dy + E2 * dz);
+                        const float les = lam * dot3(E0, E1, E2, dx, dy, dz);
                         ax[i] = fmaf(-kap, E0, fmaf(les, dx, ax[i]));
                         ay[i] = fmaf(-kap, E1, fmaf(les, dy, ay[i]));
                         az[i] = fmaf(-kap, E2, fmaf(les, dz, az[i]));
@@ -533,7 +535,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t j, const PointRec &pr, const float (&mu)[CB]) {
                     float acc[CB];
 #pragma unroll
@@ -542,11 +544,11 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                     for (int i = 0; i < K; ++i) {
                         if (open[i]) {
                             const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
-                            const float r2 = dx * dx + dy * dy + dz * dz;
+                            const float r2 = dot3(dx, dy, dz, dx, dy, dz);
                             float kap, lam = 0.0f;
                             const bool term = DX ? radial(r2, kp, kap, lam) : radial_kappa(r2, kp, kap);
                             if (term) {
-                                const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                                const float sa = dot3(pr.anx, pr.any, pr.anz, dx, dy, dz);
                                 const float ks = kap * sa;
                                 float wm = 0.0f;
 #pragma unroll
@@ -733,7 +735,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         const bool any_far = __ballot(lane_far) != 0;
         const bool any_open = __ballot(lane_open) != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
-        const uint32_t pf = next == kEnd ? t : next;
+        const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
         float Dn[3 * CB];
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
@@ -754,9 +756,9 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                     for (int c = 0; c < CB; ++c) {
                         const float Dx = D[3 * c], Dy = D[3 * c + 1], Dz = D[3 * c + 2];
                         const float hx = h[i][c][0], hy = h[i][c][1], hz = h[i][c][2];
-                        const float sc = Dx * dx + Dy * dy + Dz * dz;
-                        const float dh = dx * hx + dy * hy + dz * hz;
-                        const float Dh = Dx * hx + Dy * hy + Dz * hz;
+                        const float sc = dot3(Dx, Dy, Dz, dx, dy, dz);
+                        const float dh = dot3(dx, dy, dz, hx, hy, hz);
+                        const float Dh = dot3(Dx, Dy, Dz, hx, hy, hz);
                         const float be = fmaf(kap, w[i][c], lam * dh);
                         al = fmaf(sc, fmaf(lam, w[i][c], nu * dh), fmaf(-lam, Dh, al));
                         const float ls = lam * sc;
@@ -791,7 +793,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t j, const PointRec &pr, const float (&mu)[CB]) {
                     float acc[CB];
                     float nacc[3] = {0.0f, 0.0f, 0.0f};
@@ -801,17 +803,17 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                     for (int i = 0; i < K; ++i) {
                         if (open[i]) {
                             const float dx = pr.x - px[i], dy = pr.y - py[i], dz = pr.z - pz[i];
-                            const float r2 = dx * dx + dy * dy + dz * dz;
+                            const float r2 = dot3(dx, dy, dz, dx, dy, dz);
                             float kap, lam, nu;
                             if (radial3(r2, kp, kap, lam, nu)) {
-                                const float sa = pr.anx * dx + pr.any * dy + pr.anz * dz;
+                                const float sa = dot3(pr.anx, pr.any, pr.anz, dx, dy, dz);
                                 float al = 0.0f, bsum = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
                                 float hmx = 0.0f, hmy = 0.0f, hmz = 0.0f, e1 = 0.0f, e2 = 0.0f;
 #pragma unroll
                                 for (int c = 0; c < CB; ++c) {
                                     const float hx = h[i][c][0], hy = h[i][c][1], hz = h[i][c][2];
-                                    const float dh = dx * hx + dy * hy + dz * hz;
-                                    const float Ah = pr.anx * hx + pr.any * hy + pr.anz * hz;
+                                    const float dh = dot3(dx, dy, dz, hx, hy, hz);
+                                    const float Ah = dot3(pr.anx, pr.any, pr.anz, hx, hy, hz);
                                     const float be = fmaf(kap, w[i][c], lam * dh);
                                     // point accumulator: (d g_c / d mu_c) . h_c and the value part
                                     acc[c] = fmaf(be, sa, fmaf(-kap, Ah, acc[c]));

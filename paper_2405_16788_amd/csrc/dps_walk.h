@@ -87,8 +87,8 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
         }
         const bool any_far = __ballot(lane_far) != 0;
         const bool any_open = __ballot(lane_open) != 0;
-        const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
-        const uint32_t pf = next == kEnd ? t : next;
+        const uint32_t next = any_open ? nd.down : nd.escape;
+        const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
         float Dn[3 * CB];
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
@@ -127,7 +127,7 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
                 for (int i = 0; i < K; ++i)
                     bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
             } else {
-                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, nd.count,
+                for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
                     float dx[K], dy[K], dz[K], r2[K], kap[K], lam[K];
                     bool on[K];
