@@ -577,8 +577,8 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=Non
             # measured on this workload: the walks of a batch this small are
             # bound by its heaviest wavefronts; dividing each tile's walk over
             # 2 (query, still order-independent) / 4 (adjoint) wavefronts at
-            # tree level 2 shortens them
-            P.dps_set_split(tree, 2, 4, 2)
+            # tree level 3 shortens them
+            P.dps_set_split(tree, 2, 4, 3)
         P.dps_query(tree, x, BETA, EPS, f_out=f, g_out=g)
         if record: e[3].record()
         if sparse:
@@ -645,7 +645,7 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=Non
                         f"k={query_k}, {'[tile, sample, lane]' if tile_layout else 'ray-major'} order)"
                         + (", adjoint of the placed samples (N(0,1) cotangents, k=1, dL/dx from the query's "
                            "gradients); query and adjoint walks split over 2 / 4 wavefronts per tile at tree "
-                           "level 2" if sparse else "")
+                           "level 3" if sparse else "")
                         + ", FP32 storage",
             "step": "ray march + resample + query of the placed samples"
                     + (" + their adjoint (zero, accumulate, finalize)" if sparse else "")}
