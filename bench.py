@@ -704,9 +704,9 @@ def cpu_baseline(np, p, n, A, attrs, x, df, seconds):
     dt = run(k, cores)
     k_one = 65536
     dt_one = run(k_one, 1)
-    # direct sum (eq. dipole_sum, no tree) and its exact adjoint on 512 queries
-    # of the same seeded draw
-    n_dir = 512
+    # direct sum (eq. dipole_sum, no tree) and its exact adjoint on a fixed
+    # 4096-query subset (seed 18), the O(Q M) reference cost
+    n_dir = min(4096, x.shape[0])
     idx = np.sort(np.random.default_rng(18).choice(x.shape[0], size=n_dir, replace=False))
     t0 = time.perf_counter()
     oracle.direct(p, n, A, attrs, x[idx], EPS, nthreads=cores)

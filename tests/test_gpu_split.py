@@ -180,3 +180,36 @@ def test_set_split_rejects_bad_values(dps):
             dps.dps_set_split(tree, 2, 2, cut)
     dps.dps_set_split(tree, 0, 4)
     assert dps.dps_get_split(tree) == {"query": 1, "adjoint": 4, "cut": 6}
+
+
+def test_autotune_chooses_and_caches_a_split(dps, sphere, tmp_path):
+    """On a batch small enough for the split candidates the autotuner returns
+    and applies a valid split (query parts 1 or 2, so its result does not
+    depend on the order of the parts), the results still match the oracle,
+    and a cached entry re-applies the same split."""
+    from paper_2405_16788_amd import autotune
+    p, n, A, mu, x, df, T, ref, adj = sphere
+    tree = dps.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    xd, dfd = to_dev(x, df)
+    cache = str(tmp_path / "tune.json")
+    best = autotune.tune(tree, xd, dfd, 2.0, 0.05, reps=1, cache=cache)
+    sq, sa, cut = best["split"]
+    assert sq in (1, 2) and sa in (1, 2, 4, 8)
+    got = dps.dps_get_split(tree)
+    assert got["query"] == sq and got["adjoint"] == sa and (cut == -1 or got["cut"] == cut)
+    assert any(str(k).startswith("split") for k in best["ms"]["adjoint"])
+    f, g = dps.dps_query(tree, xd, 2.0, 0.05)
+    assert norm_err(to_host(f), ref["f"], ref["sf"]) <= TOL_FP32
+    assert norm_err(to_host(g), ref["g"], ref["sg"]) <= TOL_FP32
+    dps.dps_adjoint_zero(tree)
+    dx = dps.dps_adjoint_accumulate_from_forward(tree, xd, 2.0, 0.05, dfd, g)
+    da = dps.dps_adjoint_finalize(tree)
+    assert norm_err(to_host(da), adj["dmu"], adj["sdmu"]) <= TOL_FP32
+    assert norm_err(to_host(dx), adj["dx"], adj["sdx"]) <= TOL_FP32
+    # a fresh tree takes the cached choice
+    tree2 = dps.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    again = autotune.tune(tree2, xd, dfd, 2.0, 0.05, reps=1, cache=cache)
+    assert again["split"] == best["split"]
+    got2 = dps.dps_get_split(tree2)
+    assert got2["query"] == sq and got2["adjoint"] == sa
+    dps.dps_check(tree)
