@@ -623,9 +623,28 @@ def time_frontend(P, steps, warmup, n_march=1024, counts=(24, 48, 8), n_rays=Non
     fv = flops_values(1)
     fl = total * (fv["test"] * c[0] + fv["far"] * c[1] + fv["near"] * c[3]) / m
     ach = fl / (per["march"] * 1e-3) / 1e12
+    # the Harnack-accelerated march beside it (same outputs where its bound
+    # holds; not part of the step): one warm-up and one timed launch
+    P.dps_set_launch(tree, march_k, 0, 0)
+    hh = torch.empty_like(hit)
+    vh = torch.empty_like(hv)
+    evh = torch.empty_like(hit)
+    P.dps_ray_march(tree, od, dd, tnd, tfd, n_march, BETA, EPS, hit_out=hit, values_out=hv)
+    P.dps_ray_march_harnack(tree, od, dd, tnd, tfd, n_march, BETA, EPS, lower=-0.25, hit_out=hh, values_out=vh,
+                            evals_out=evh)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    P.dps_ray_march_harnack(tree, od, dd, tnd, tfd, n_march, BETA, EPS, lower=-0.25, hit_out=hh, values_out=vh,
+                            evals_out=evh)
+    e1.record()
+    torch.cuda.synchronize()
+    harnack = {"ms": e0.elapsed_time(e1), "lower": -0.25, "evaluations_per_ray": float(evh.float().mean().item()),
+               "dense_samples_per_ray": total / R,
+               "same_as_dense_march": bool(torch.equal(hh, hit) and torch.equal(vh, hv))}
     P.dps_check(tree)
     P.dps_destroy(tree)
     return {"value": R / (ms * 1e-3), "unit": "rays/s", "ms_per_step": ms, "steps": steps, "kernel_ms": per,
+            "harnack_march": harnack,
             "march": {"samples_evaluated": total, "samples_per_s": total / (per["march"] * 1e-3),
                       "hit_fraction": hit_frac, "per_sample": {"nodes_visited": c[0] / m, "far_nodes": c[1] / m,
                                                                 "near_points": c[3] / m},
@@ -852,6 +871,11 @@ def main():
             f"kernels {out['ray_frontend']['kernel_ms']}")
         log(f"[bench] ray front-end, 4096-ray batch: {out['ray_frontend_batch']['ms_per_step']:.2f} ms, "
             f"kernels {out['ray_frontend_batch']['kernel_ms']}")
+        for key in ("ray_frontend", "ray_frontend_batch"):
+            hm = out[key]["harnack_march"]
+            log(f"[bench] {key}: Harnack-accelerated march {hm['ms']:.1f} ms, {hm['evaluations_per_ray']:.0f} "
+                f"evaluations per ray (dense {hm['dense_samples_per_ray']:.0f}), same as the dense march: "
+                f"{hm['same_as_dense_march']}")
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(np, p, n, A, attrs, x, df, args.cpu_seconds)

@@ -467,6 +467,37 @@ dps_status dps_ray_resample(const float *o, const float *d, const float *tnear, 
                             int32_t tile_layout, float *t_out, float *x_out, void *stream);
 
 /*
+ * dps_ray_march_harnack -- the march of dps_ray_march (same samples x_k, same
+ * crossing definition, same outputs) accelerated by Harnack tracing (Sec.
+ * 7.1, following Gillespie et al. 2024): Harnack's inequality bounds how fast
+ * a positive harmonic function can change within a ball around a point, so
+ * from an evaluated sample many of the next ones can be skipped.  The field
+ * shifted by `lower` (u = D - lower, assumed > 0) is harmonic within
+ * R = (distance to the nearest point) - 4.5 eps of a sample x_k (the kernel's
+ * regularisation ends there: rho(4.5) = 1 - 8e-9); with a = (level - lower) /
+ * (D(x_k) - lower) the field stays on D(x_k)'s side of the level within
+ * s R, s = |sqrt(8a + 1) - (2a + 1)| / (2a) (the root of (1 - s) = a (1 + s)^2
+ * or of (1 + s) = a (1 - s)^2).  The samples strictly within 0.99 s R are
+ * skipped, the next one is evaluated and, if it lies on the other side of the
+ * level, the one before it: on D(x_k)'s side it closes the crossing pair,
+ * otherwise (the field did not obey the bound, e.g. because `lower` is not a
+ * bound or the Barnes-Hut switch between far field and points moved the
+ * value) the ray continues sample by sample from x_k.  So wherever the bound
+ * holds, hit_index and hit_values equal dps_ray_march's, bit for bit (same
+ * walk at the same FP32 positions).  One ray per lane (a persistent tile
+ * queue over 64-ray tiles); each step runs a nearest-point walk and a value
+ * walk.
+ *  lower   a lower bound of the field (finite, < level); the geometry field
+ *          of a closed surface lies in [0, 1] up to noise, e.g. -0.25
+ *  evals   [R] int32 output: field evaluations per ray, or NULL
+ * Other arguments, errors and ordering as dps_ray_march (uses the tree's tile
+ * counters).  Graph-safe: no allocation, no memory set or copy.
+ */
+dps_status dps_ray_march_harnack(dps_tree t, const float *o, const float *d, const float *tnear, const float *tfar,
+                                 int64_t R, int32_t n_samples, float beta, float eps, int32_t channel, float level,
+                                 float lower, int32_t *hit_index, float *hit_values, int32_t *evals, void *stream);
+
+/*
  * dps_adjoint_noalloc -- for callers that cannot allocate device memory
  * (code under graph capture, serving loops, harnesses that forbid it): the
  * result of dps_adjoint (same arguments, outputs and errors; dattrs [M][C] in

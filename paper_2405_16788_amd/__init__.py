@@ -12,7 +12,7 @@ from .binding import (  # noqa: F401
     dps_query_channels,
     dps_adjoint_accumulate_channels, dps_adjoint_accumulate_grad, dps_adjoint_accumulate_ext,
     dps_adjoint_accumulate_from_forward,
-    dps_adjoint_finalize_ext, dps_set_normals, dps_query_grid, dps_ray_march, dps_ray_resample, WANT_NORMALS, WANT_EPS, dps_check, dps_set_step_limit,
+    dps_adjoint_finalize_ext, dps_set_normals, dps_query_grid, dps_ray_march, dps_ray_march_harnack, dps_ray_resample, WANT_NORMALS, WANT_EPS, dps_check, dps_set_step_limit,
     dps_set_memory_limit, dps_destroy, LAUNCH_XCD_QUERY,
     LAUNCH_XCD_ADJOINT,
     LAUNCH_PERSISTENT_QUERY, LAUNCH_PERSISTENT_ADJOINT, LAUNCH_MARCH_WHOLE, dps_status_string, dps_last_error,

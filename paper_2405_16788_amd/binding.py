@@ -26,7 +26,7 @@ EXPORTED = (
     "dps_tree_info", "dps_set_launch", "dps_get_launch", "dps_set_split", "dps_get_split", "dps_query_channels",
     "dps_adjoint_accumulate_channels", "dps_adjoint_accumulate_grad", "dps_adjoint_accumulate_ext",
     "dps_adjoint_accumulate_from_forward",
-    "dps_adjoint_finalize_ext", "dps_set_normals", "dps_query_grid", "dps_ray_march", "dps_ray_resample",
+    "dps_adjoint_finalize_ext", "dps_set_normals", "dps_query_grid", "dps_ray_march", "dps_ray_march_harnack", "dps_ray_resample",
     "dps_adjoint_noalloc", "dps_check", "dps_set_step_limit", "dps_set_memory_limit", "dps_destroy",
     "dps_status_string", "dps_last_error",
 )
@@ -75,6 +75,7 @@ def load():
         "dps_set_normals": [vp, vp, vp],
         "dps_query_grid": [vp, vp, vp, vp, f32, f32, i32, i32, vp, vp, vp],
         "dps_ray_march": [vp, vp, vp, vp, vp, i64, i32, f32, f32, i32, f32, vp, vp, vp],
+        "dps_ray_march_harnack": [vp, vp, vp, vp, vp, i64, i32, f32, f32, i32, f32, f32, vp, vp, vp, vp],
         "dps_ray_resample": [vp, vp, vp, vp, i64, i32, vp, vp, f32, vp, i32, i32, i32, f32, i32, vp, vp, vp],
         "dps_adjoint_accumulate": [vp, vp, i64, f32, f32, vp, vp, vp],
         "dps_adjoint_finalize": [vp, vp, vp],
@@ -476,6 +477,28 @@ def dps_ray_march(tree: Tree, o, d, tnear, tfar, n_samples: int = 1024, beta: fl
                                 _ptr(hit, torch.int32, (R,), dev, "hit_index"), _ptr(hv, f, (R, 2), dev, "hit_values"),
                                 _stream(dev)), "dps_ray_march")
     return hit, hv
+
+
+def dps_ray_march_harnack(tree: Tree, o, d, tnear, tfar, n_samples: int = 1024, beta: float = 2.0, eps: float = 0.0,
+                          channel: int = 0, level: float = 0.5, lower: float = -0.25, hit_out=None, values_out=None,
+                          evals_out=None, want_evals: bool = False):
+    """dps_ray_march's outputs through the Harnack-accelerated march
+    (``dps_ray_march_harnack``); ``lower`` bounds the field from below.
+    Returns (hit_index, hit_values, evals int32[R] or None)."""
+    import torch
+    R = o.shape[0]
+    dev = tree.device
+    hit = hit_out if hit_out is not None else torch.empty(R, device=dev, dtype=torch.int32)
+    hv = values_out if values_out is not None else torch.empty((R, 2), device=dev, dtype=torch.float32)
+    ev = evals_out if evals_out is not None else (
+        torch.empty(R, device=dev, dtype=torch.int32) if want_evals else None)
+    f = torch.float32
+    _check(load().dps_ray_march_harnack(
+        tree.handle, _ptr(o, f, (R, 3), dev, "o"), _ptr(d, f, (R, 3), dev, "d"), _ptr(tnear, f, (R,), dev, "tnear"),
+        _ptr(tfar, f, (R,), dev, "tfar"), R, int(n_samples), float(beta), float(eps), int(channel), float(level),
+        float(lower), _ptr(hit, torch.int32, (R,), dev, "hit_index"), _ptr(hv, f, (R, 2), dev, "hit_values"),
+        _ptr(ev, torch.int32, (R,), dev, "evals"), _stream(dev)), "dps_ray_march_harnack")
+    return hit, hv, ev
 
 
 def dps_ray_resample(o, d, tnear, tfar, n_march: int, hit_index, hit_values, jitter, level: float = 0.5,

@@ -511,6 +511,26 @@ dps_status dps_ray_march(dps_tree t, const float *o, const float *d, const float
                             (hipStream_t)stream);
 }
 
+dps_status dps_ray_march_harnack(dps_tree t, const float *o, const float *d, const float *tnear, const float *tfar,
+                                 int64_t R, int32_t n_samples, float beta, float eps, int32_t channel, float level,
+                                 float lower, int32_t *hit_index, float *hit_values, int32_t *evals, void *stream) {
+    dps_status st = check_tree(t, "dps_ray_march_harnack");
+    if (st != DPS_OK) return st;
+    if ((st = need_dipole(t, "dps_ray_march_harnack")) != DPS_OK) return st;
+    if ((st = check_beta_eps(beta, eps, "dps_ray_march_harnack")) != DPS_OK) return st;
+    if ((st = check_channels(t, channel, 1, "dps_ray_march_harnack")) != DPS_OK) return st;
+    if (n_samples < 2 || n_samples > (1 << 20)) return invalid("dps_ray_march_harnack: n_samples must be in [2, 2^20]");
+    if (!isfinite(level) || !isfinite(lower) || !(lower < level))
+        return invalid("dps_ray_march_harnack: level and lower must be finite with lower < level");
+    if (R < 0 || R > kMaxRows) return invalid("dps_ray_march_harnack: R out of range");
+    if (R == 0) return DPS_OK;
+    if (!o || !d || !tnear || !tfar || !hit_index || !hit_values)
+        return invalid("dps_ray_march_harnack: NULL array");
+    DeviceGuard guard(t->device);
+    return launch_ray_march_harnack(t, o, d, tnear, tfar, R, n_samples, beta, eps, channel, level, lower, hit_index,
+                                    hit_values, evals, (hipStream_t)stream);
+}
+
 dps_status dps_ray_resample(const float *o, const float *d, const float *tnear, const float *tfar, int64_t R,
                             int32_t n_march, const int32_t *hit_index, const float *hit_values, float level,
                             const float *jitter, int32_t n_before, int32_t n_dense, int32_t n_after, float window,

@@ -237,6 +237,147 @@ __global__ __launch_bounds__(kThreads) void k_ray_hit_values(
     if (on) hv[2 * r + side] = f[0][0];
 }
 
+// Harnack-accelerated march (Sec. 7.1: the first crossing found by Harnack
+// tracing).  Lane = ray over the persistent tile queue.  From an evaluated
+// sample k with value v_k, Harnack's inequality for the field shifted by its
+// lower bound (u = D - lower > 0, harmonic outside the regularised zones,
+// i.e. within R = nearest point - 4.5 eps of x_k) keeps D on v_k's side of
+// the level within s(a) R, a = (level - lower) / (v_k - lower),
+// s = |sqrt(8a + 1) - (2a + 1)| / (2a).  The samples strictly within
+// safety * s R of x_k are skipped; the first one past them is evaluated and,
+// if it lies on the other side, the one before it: on v_k's side it closes
+// the crossing pair, otherwise (the field did not obey the bound) the lane
+// goes on sample by sample from k.  Modes: 0 step from k, 1 candidate k2,
+// 2 confirm k2 - 1, 3 one sample at a time, 4 done.  Every evaluated value
+// comes from the march's walk at the march's FP32 positions, so a crossing
+// found here carries the dense march's values bit for bit.
+template <bool BF16>
+__global__ __launch_bounds__(kThreads) void k_ray_march_harnack(
+    const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts, const void *__restrict__ mom,
+    const void *__restrict__ attr, int ms, int as, float b2, KernelParams kp, int c0, uint32_t limit,
+    uint32_t *__restrict__ err, const float *__restrict__ o, const float *__restrict__ d,
+    const float *__restrict__ tnear, const float *__restrict__ tfar, int64_t R, int n, float level, float lower,
+    float reg, int32_t *__restrict__ hit, float *__restrict__ hv, int32_t *__restrict__ evals,
+    uint32_t *__restrict__ ctr) {
+    constexpr float kSafety = 0.99f;
+    const int lane = lane_id();
+    const int64_t ntiles = (R + 63) / 64;
+    int part = xcc_id();
+    for (;;) {
+        const int64_t tile = next_tile(ctr, ntiles, part);
+        if (tile < 0) break;
+        const int64_t r = tile * 64 + lane;
+        const bool live = r < R;
+        float ox = 0.0f, oy = 0.0f, oz = 0.0f, dx = 0.0f, dy = 0.0f, dz = 0.0f, tn = 0.0f, h = 0.0f;
+        if (live) {
+            ox = o[3 * r];
+            oy = o[3 * r + 1];
+            oz = o[3 * r + 2];
+            dx = d[3 * r];
+            dy = d[3 * r + 1];
+            dz = d[3 * r + 2];
+            tn = tnear[r];
+            h = (tfar[r] - tn) / (float)n;
+        }
+        const float spacing = h * __builtin_sqrtf(dot3(dx, dy, dz, dx, dy, dz));  // between samples, in space
+        auto value = [&](int k, bool on) {
+            const float t = march_param(tn, k, h);
+            float px[1] = {ray_at(ox, t, dx)}, py[1] = {ray_at(oy, t, dy)}, pz[1] = {ray_at(oz, t, dz)};
+            float f[1][1] = {{0.0f}}, g[1][1][3] = {{{0.0f, 0.0f, 0.0f}}};
+            uint32_t bits[1] = {on ? 1u : 0u};
+            dipole_walk<1, BF16, false, 1>(px, py, pz, bits, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit,
+                                           err);
+            return f[0][0];
+        };
+        int k = 0, k2 = 0, mode = live ? 0 : 4, nev = 1;
+        float vk = value(0, live), v2 = 0.0f;
+        float near = __builtin_inff();
+        int near_k = 0;
+        int32_t j = -1;
+        float vj = 0.0f, vj1 = 0.0f;
+        // every pass advances k or ends the lane, at most 3 passes per sample
+        for (int pass = 0; __ballot(mode != 4) != 0; ++pass) {
+            if (pass > 3 * n + 3) {  // cannot happen; guards the loop like the walks' step bound
+                if (lane == 0) atomicOr(err, 1u);
+                break;
+            }
+            const bool stepping = mode == 0;
+            if (__ballot(stepping) != 0) {
+                const float t = march_param(tn, k, h);
+                const float px = ray_at(ox, t, dx), py = ray_at(oy, t, dy), pz = ray_at(oz, t, dz);
+                // the nearest point lies within the last one's distance plus the way moved
+                const float bound = near_k >= 0 && near < __builtin_inff()
+                                        ? (near + (float)(k - near_k) * spacing) * 1.0001f + 1e-30f
+                                        : __builtin_inff();
+                const float dist = nearest_walk(px, py, pz, stepping, bound, nodes, pts, limit, err);
+                if (stepping) {
+                    near = dist;
+                    near_k = k;
+                    const float rad = dist - reg;
+                    float rho = 0.0f;
+                    if (vk > lower && rad > 0.0f) {
+                        const float a = (level - lower) / (vk - lower);
+                        const float sa = fabsf(__builtin_sqrtf(fmaf(8.0f, a, 1.0f)) - fmaf(2.0f, a, 1.0f)) / (2.0f * a);
+                        rho = sa * rad;
+                    }
+                    const float skip = spacing > 0.0f ? floorf(kSafety * rho / spacing) : (float)n;
+                    const int m = skip < (float)n ? (int)skip : n;
+                    k2 = min(k + m + 1, n - 1);
+                    mode = 1;
+                }
+            }
+            const bool evaluating = mode == 1 || mode == 2 || mode == 3;
+            const int e = mode == 1 ? k2 : (mode == 2 ? k2 - 1 : k + 1);
+            const float w = value(evaluating ? e : 0, evaluating);
+            if (evaluating) {
+                ++nev;
+                const bool side = vk >= level;
+                if (mode == 1) {
+                    if ((w >= level) == side) {
+                        k = k2;
+                        vk = w;
+                        mode = k >= n - 1 ? 4 : 0;
+                    } else if (k2 == k + 1) {
+                        j = k;
+                        vj = vk;
+                        vj1 = w;
+                        mode = 4;
+                    } else {
+                        v2 = w;
+                        mode = 2;
+                    }
+                } else if (mode == 2) {
+                    if ((w >= level) == side) {
+                        j = k2 - 1;
+                        vj = w;
+                        vj1 = v2;
+                        mode = 4;
+                    } else {
+                        mode = 3;
+                    }
+                } else {
+                    if ((w >= level) != side) {
+                        j = k;
+                        vj = vk;
+                        vj1 = w;
+                        mode = 4;
+                    } else {
+                        ++k;
+                        vk = w;
+                        if (k >= n - 1) mode = 4;
+                    }
+                }
+            }
+        }
+        if (live) {
+            hit[r] = j;
+            hv[2 * r] = vj;
+            hv[2 * r + 1] = vj1;
+            if (evals) evals[r] = nev;
+        }
+    }
+}
+
 __global__ void k_fill_i32_max(int32_t *__restrict__ a, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         a[i] = INT32_MAX;
@@ -372,7 +513,30 @@ dps_status march_k(dps_tree_s *t, const float *o, const float *d, const float *t
     return march_along_launch<BF16, 1>(t, o, d, tn, tf, R, n, b2, kp, channel, level, hit, hv, s);
 }
 
+template <bool BF16>
+dps_status harnack_launch(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf, int64_t R,
+                          int n, float b2, KernelParams kp, int channel, float level, float lower, float reg,
+                          int32_t *hit, float *hv, int32_t *evals, hipStream_t s) {
+    k_fill_u32<<<1, 64, 0, s>>>(t->ctr, 8, 0u);
+    const void *fn = reinterpret_cast<const void *>(&k_ray_march_harnack<BF16>);
+    k_ray_march_harnack<BF16><<<persistent_grid(fn), kThreads, 0, s>>>(
+        t->nodes, t->pts, trav_mom(t), t->attr, t->mom_stride, t->attr_stride, b2, kp, channel, walk_limit(t), t->err,
+        o, d, tn, tf, R, n, level, lower, reg, hit, hv, evals, t->ctr);
+    return hip_status(hipGetLastError(), "Harnack march launch");
+}
+
 }  // namespace
+
+dps_status launch_ray_march_harnack(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf,
+                                    int64_t R, int n, float beta, float eps, int channel, float level, float lower,
+                                    int32_t *hit, float *hv, int32_t *evals, hipStream_t s) {
+    const float b2 = mul_rn(beta, beta);
+    const KernelParams kp = tree_kernel_params(t, eps);
+    const float reg = eps > 0.0f ? 4.5f * eps : 0.0f;  // rho(t) = 1 to 8e-9 beyond t = 4.5
+    if (t->storage == DPS_STORE_BF16)
+        return harnack_launch<true>(t, o, d, tn, tf, R, n, b2, kp, channel, level, lower, reg, hit, hv, evals, s);
+    return harnack_launch<false>(t, o, d, tn, tf, R, n, b2, kp, channel, level, lower, reg, hit, hv, evals, s);
+}
 
 dps_status launch_ray_march(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf,
                             int64_t R, int n, float beta, float eps, int channel, float level, int32_t *hit,

@@ -106,6 +106,9 @@ dps_status launch_adjoint_mono(dps_tree_s *t, const float *x, int64_t Q, const i
 dps_status launch_ray_march(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf,
                             int64_t R, int n, float beta, float eps, int channel, float level, int32_t *hit,
                             float *hv, hipStream_t s);
+dps_status launch_ray_march_harnack(dps_tree_s *t, const float *o, const float *d, const float *tn, const float *tf,
+                                    int64_t R, int n, float beta, float eps, int channel, float level, float lower,
+                                    int32_t *hit, float *hv, int32_t *evals, hipStream_t s);
 dps_status launch_ray_resample(const float *o, const float *d, const float *tn, const float *tf, int64_t R,
                                int n_march, const int32_t *hit, const float *hv, float level, const float *u, int nb,
                                int nd, int na, float window, int tile_layout, float *t_out, float *x_out,

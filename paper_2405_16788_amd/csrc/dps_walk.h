@@ -171,5 +171,54 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
     }
 }
 
+// Distance from each lane's point to the nearest point of the cloud, for the
+// lanes with `on` (others return `bound`): a union walk that opens a node
+// while its bounding sphere may hold a point nearer than the lane's best so
+// far, starting from `bound` (a distance the nearest point is known to lie
+// within, or infinity).  The sphere radius gets a relative slack of 1e-4 so
+// that rounding cannot prune the node holding the nearest point; where no
+// point lies within `bound` the result is `bound`.
+__device__ __forceinline__ float nearest_walk(float px, float py, float pz, bool on, float bound,
+                                              const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts,
+                                              uint32_t limit, uint32_t *__restrict__ err) {
+    float best2 = bound * bound;
+    float best = bound;
+    uint32_t bits = on ? 1u : 0u;
+    NodeRec nd = nodes[0];
+    uint32_t steps = 0;
+    for (;;) {
+        if (++steps > limit) {  // a well-formed tree is walked in at most N steps
+            if ((threadIdx.x & 63) == 0) atomicOr(err, 1u);
+            break;
+        }
+        const uint32_t lvl = nd.meta & 0xffu;
+        const bool leaf = (nd.meta & kLeafFlag) != 0;
+        const bool in = (bits >> lvl) & 1u;
+        const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
+        const float reach = (best + __builtin_sqrtf(nd.r2)) * 1.0001f;
+        const bool open = in && s < reach * reach;
+        const bool any_open = __ballot(open) != 0;
+        const uint32_t next = any_open ? nd.down : nd.escape;
+        const NodeRec nn = nodes[next];  // kEnd is the root: a valid record
+        if (any_open) {
+            if (!leaf) {
+                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
+            } else {
+                const uint32_t je = nd.first + node_count(nd);
+                for (uint32_t j = nd.first; j < je; ++j) {
+                    const PointRec pr = pts[j];
+                    const float dx = pr.x - px, dy = pr.y - py, dz = pr.z - pz;
+                    const float d2 = dot3(dx, dy, dz, dx, dy, dz);
+                    best2 = open ? fminf(best2, d2) : best2;
+                }
+                best = __builtin_sqrtf(best2);
+            }
+        }
+        if (next == kEnd) break;
+        nd = nn;
+    }
+    return best;
+}
+
 }  // namespace
 }  // namespace dps

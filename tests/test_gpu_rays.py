@@ -381,3 +381,80 @@ def test_march_crossing_values_without_workspace(P):
         P.dps_destroy(tree)
         results[k] = eager
     assert np.array_equal(results[1][0], results[2][0]) and np.array_equal(results[1][1], results[2][1])
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+@pytest.mark.parametrize("cloud", ["winding", "sphere"])
+def test_harnack_march_equals_the_dense_march(P, orc, storage, cloud):
+    """The Harnack-accelerated march returns the dense march's crossing index
+    and values bit for bit (same walk at the same FP32 positions) on every
+    ray, matches the oracle's Harnack march (whose index equals the oracle's
+    dense march) to the precision of the field, and evaluates the field far
+    fewer times than the dense march needs."""
+    from oracle import rays
+    if cloud == "winding":
+        p, n, A, mu = workloads.winding_cloud(20000, 1000, 90)
+        o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(91), 64)
+        eps = EPS
+    else:
+        p, n, A = workloads.fibonacci_sphere(40000)
+        mu = np.ones((p.shape[0], 1), np.float32)
+        o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(92), 32)
+        eps = 0.05
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16, storage=storage)
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    R = o.shape[0]
+    print(f"[rays] Harnack march {cloud} {storage} R={R}", flush=True)
+    hit, hv = P.dps_ray_march(tree, od, dd, tnd, tfd, N_MARCH, BETA, eps)
+    hh, vh, ev = P.dps_ray_march_harnack(tree, od, dd, tnd, tfd, N_MARCH, BETA, eps, lower=-0.25, want_evals=True)
+    P.dps_check(tree)
+    hit, hv, hh, vh, ev = (to_host(a) for a in (hit, hv, hh, vh, ev))
+    assert np.array_equal(hh, hit), np.nonzero(hh != hit)
+    assert np.array_equal(vh.view(np.int32), hv.view(np.int32))
+    crossing = hit >= 0
+    assert 0 < crossing.sum() < R
+    needed = np.where(crossing, hit + 2, N_MARCH)
+    print(f"[rays] {crossing.sum()} of {R} cross; evaluations {ev.mean():.1f} per ray (dense {needed.mean():.1f}), "
+          f"max {ev.max()}", flush=True)
+    assert np.all(ev >= 1) and ev.mean() < 0.5 * needed.mean()
+    # the oracle's Harnack march on a subset of the rays
+    sel = np.arange(0, R, max(1, R // 256))
+    T = orc.Tree(p, n, A, mu, 16)
+    ho = rays.harnack_march(T, p, o[sel], d[sel], tn[sel], tf[sel], N_MARCH, BETA, eps, level=0.5, lower=-0.25)
+    ref = rays.march(T, o[sel], d[sel], tn[sel], tf[sel], N_MARCH, BETA, eps)
+    assert np.array_equal(ho["j"], ref["j"])
+    _check_march(hh[sel], vh[sel], ref, TOL_BF16 if storage == "bf16" else TOL_FP32)
+
+
+def test_harnack_march_edge_cases(P):
+    """Two samples, zero-length rays, a ray count that is not a multiple of
+    64, a bound that is no bound at all (the march then falls back to single
+    steps and still returns the dense march's crossing), no evaluation
+    counts, and argument errors."""
+    import torch
+    p, n, A, mu = workloads.winding_cloud(20000, 1000, 90)
+    o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(91), 16)
+    R = 200
+    o, d, tn, tf = o[:R].copy(), d[:R].copy(), tn[:R].copy(), tf[:R].copy()
+    tf[::7] = tn[::7]
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    for n_s, lower in ((2, -0.25), (3, -0.25), (97, -0.25), (300, -0.25), (300, 0.49), (300, -5.0)):
+        print(f"[rays] Harnack edge case n={n_s} lower={lower}", flush=True)
+        hit, hv = P.dps_ray_march(tree, od, dd, tnd, tfd, n_s, BETA, EPS)
+        hh, vh, ev = P.dps_ray_march_harnack(tree, od, dd, tnd, tfd, n_s, BETA, EPS, lower=lower)
+        assert ev is None
+        hit, hv, hh, vh = (to_host(a) for a in (hit, hv, hh, vh))
+        assert np.array_equal(hh, hit) and np.array_equal(vh.view(np.int32), hv.view(np.int32))
+        assert np.all(hh[::7] == -1)
+    P.dps_check(tree)
+    x0 = torch.empty((0, 3), device="cuda")
+    t0 = torch.empty(0, device="cuda")
+    h0, v0, _ = P.dps_ray_march_harnack(tree, x0, x0, t0, t0, 64, BETA, EPS)
+    assert h0.shape == (0,)
+    for bad in (dict(lower=0.5), dict(lower=0.7), dict(lower=float("nan")), dict(n_samples=1), dict(channel=4)):
+        kw = dict(n_samples=64, lower=-0.25)
+        kw.update(bad)
+        with pytest.raises(P.DpsError):
+            P.dps_ray_march_harnack(tree, od, dd, tnd, tfd, kw["n_samples"], BETA, EPS, lower=kw["lower"],
+                                    channel=kw.get("channel", 0))

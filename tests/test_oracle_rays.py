@@ -148,3 +148,76 @@ def test_resample_placement_properties(orc):
                 assert abs(t64[r, off + i] - (lo + (i + u[r, off + i]) * step)) <= 2 * ulp[r]
     on = o.astype(np.float64)[:, None, :] + t64[..., None] * d.astype(np.float64)[:, None, :]
     assert np.max(np.abs(x - on)) <= 4 * 2.0 ** -24 * 4.0
+
+
+def test_harnack_step_solves_its_equations(orc):
+    """s(a) is the root in [0, 1) of (1 - s) = a (1 + s)^2 for a < 1 (the
+    field above the level, Harnack's lower bound) and of (1 + s) = a (1 - s)^2
+    for a > 1 (below it, the upper bound); s(1) = 0."""
+    from oracle import rays
+    a = np.concatenate([np.geomspace(1e-3, 0.999, 200), np.geomspace(1.001, 1e3, 200)])
+    s = rays.harnack_s(a)
+    assert np.all((s >= 0) & (s < 1))
+    lo = a < 1
+    np.testing.assert_allclose((1 - s[lo]) / (1 + s[lo]) ** 2, a[lo], rtol=1e-10)
+    np.testing.assert_allclose((1 + s[~lo]) / (1 - s[~lo]) ** 2, a[~lo], rtol=1e-10)
+    assert rays.harnack_s(1.0) == 0.0
+    assert np.all(rays.harnack_radius([0.1, -0.3], 0.5, -0.25, [1.0, 1.0]) == [rays.harnack_radius(0.1, 0.5, -0.25, 1.0), 0.0])
+
+
+def test_harnack_radius_is_safe_for_a_harmonic_function(orc):
+    """u(y) = 1/|y - p0| is positive and harmonic away from p0.  From a point
+    at distance R of p0, u changes fastest along the line through p0, so the
+    Harnack radius must keep u on its side of the level along that line:
+    1/(R - rho) < level above u, 1/(R + rho) > level below it, and the same on
+    random directions."""
+    from oracle import rays
+    rng = np.random.default_rng(7)
+    for _ in range(400):
+        R = rng.uniform(0.2, 3.0)
+        u0 = 1.0 / R
+        level = u0 * (rng.uniform(1.05, 6.0) if rng.random() < 0.5 else rng.uniform(0.1, 0.95))
+        rho = float(rays.harnack_radius(u0, level, 0.0, R))
+        assert 0 < rho < R
+        if level > u0:
+            assert 1.0 / (R - rho) < level
+        else:
+            assert 1.0 / (R + rho) > level
+        x = np.array([R, 0.0, 0.0])
+        dirs = rng.standard_normal((64, 3))
+        dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+        for r in (0.25 * rho, 0.5 * rho, 0.999 * rho):
+            u = 1.0 / np.linalg.norm(x[None, :] + r * dirs, axis=1)
+            assert np.all((u >= level) == (u0 >= level))
+
+
+@pytest.mark.parametrize("scene", ["sphere", "winding"])
+def test_harnack_march_matches_the_dense_march(orc, scene):
+    """The Harnack-accelerated march returns the dense march's first crossing
+    and the same values there on every ray (rays that cross and rays that
+    miss), with far fewer field evaluations."""
+    from oracle import rays
+    if scene == "sphere":
+        p, n, A = workloads.fibonacci_sphere(40000)
+        mu = np.ones((p.shape[0], 1), F)
+        o, d, tn, tf = _rays(48, 11, impact=(0.0, 1.6))
+        eps = 0.05
+    else:
+        p, n, A, mu = workloads.winding_cloud(20000, 1000, 90)
+        o, d, tn, tf = workloads.tile_camera_rays(workloads.sfm_camera(91), 16)
+        sel = np.arange(0, o.shape[0], 4)
+        o, d, tn, tf = o[sel], d[sel], tn[sel], tf[sel]
+        eps = 0.01414
+    T = orc.Tree(p, n, A, mu, 16)
+    dense = rays.march(T, o, d, tn, tf, 1024, 2.0, eps)
+    hm = rays.harnack_march(T, p, o, d, tn, tf, 1024, 2.0, eps, level=0.5, lower=-0.25)
+    assert np.array_equal(hm["j"], dense["j"]), np.nonzero(hm["j"] != dense["j"])
+    hit = dense["j"] >= 0
+    assert 0 < hit.sum() < len(hit)
+    rr = np.nonzero(hit)[0]
+    assert np.array_equal(hm["vj"][rr], dense["v"][rr, dense["j"][rr]])
+    assert np.array_equal(hm["vj1"][rr], dense["v"][rr, dense["j"][rr] + 1])
+    needed = np.where(hit, dense["j"] + 2, 1024)
+    print(f"[harnack] {scene}: {len(hit)} rays, {hit.sum()} cross; evaluations {hm['evals'].mean():.1f} per ray "
+          f"(dense march needs {needed.mean():.1f})", flush=True)
+    assert hm["evals"].mean() < 0.5 * needed.mean()
