@@ -280,7 +280,7 @@ dps_status dps_get_launch(dps_tree t, int32_t *query_k, int32_t *adjoint_k, int3
  * The packet sizes and flags of dps_set_launch do not apply to split walks;
  * grid queries, ray marches, the gradient-cotangent adjoint and monopole
  * trees are never split.  Host-only; applies to later launches.  Default 1, 1
- * (unsplit), cut level 6.  Errors: DPS_ERR_INVALID for other values.
+ * (unsplit), cut level 3.  Errors: DPS_ERR_INVALID for other values.
  */
 dps_status dps_set_split(dps_tree t, int32_t query_parts, int32_t adjoint_parts, int32_t cut_level);
 dps_status dps_get_split(dps_tree t, int32_t *query_parts, int32_t *adjoint_parts, int32_t *cut_level);

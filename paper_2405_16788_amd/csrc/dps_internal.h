@@ -33,7 +33,6 @@ constexpr int kFlagXcdAdjoint = 2;
 constexpr int kFlagPersistentQuery = 4;
 constexpr int kFlagPersistentAdjoint = 8;
 constexpr int kDefaultLaunchFlags = kFlagXcdQuery | kFlagXcdAdjoint;
-constexpr int kDefaultSplitCut = 6;        // cut level of the subtree-split walks (dps_set_split)
 
 struct alignas(32) NodeRec {
     float cx, cy, cz, r2;  // FP32 centroid and squared radius

@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void k_ray_march_harnack(
                 const float t = march_param(tn, k, h);
                 const float px = ray_at(ox, t, dx), py = ray_at(oy, t, dy), pz = ray_at(oz, t, dz);
                 // the nearest point lies within the last one's distance plus the way moved
-                const float bound = near_k >= 0 && near < __builtin_inff()
+                const float bound = near < __builtin_inff()
                                         ? (near + (float)(k - near_k) * spacing) * 1.0001f + 1e-30f
                                         : __builtin_inff();
                 const float dist = nearest_walk(px, py, pz, stepping, bound, nodes, pts, limit, err);

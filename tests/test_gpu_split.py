@@ -169,7 +169,7 @@ def test_split_empty_and_tiny(dps, orc):
 def test_set_split_rejects_bad_values(dps):
     p, n, A, mu = workloads.sphere_cloud(256, 1)
     tree = dps.dps_build(*to_dev(p, n, A, mu))
-    assert dps.dps_get_split(tree) == {"query": 1, "adjoint": 1, "cut": 6}
+    assert dps.dps_get_split(tree) == {"query": 1, "adjoint": 1, "cut": 3}
     for parts in (3, 16, -1):
         with pytest.raises(dps.DpsError):
             dps.dps_set_split(tree, parts, 1)
@@ -179,7 +179,7 @@ def test_set_split_rejects_bad_values(dps):
         with pytest.raises(dps.DpsError):
             dps.dps_set_split(tree, 2, 2, cut)
     dps.dps_set_split(tree, 0, 4)
-    assert dps.dps_get_split(tree) == {"query": 1, "adjoint": 4, "cut": 6}
+    assert dps.dps_get_split(tree) == {"query": 1, "adjoint": 4, "cut": 3}
 
 
 def test_autotune_chooses_and_caches_a_split(dps, sphere, tmp_path):
