@@ -225,8 +225,11 @@ __device__ __forceinline__ float series_chi_t7(float u) {  // u = t^2
 // with the hardware reciprocal square root (1 ulp).  Inside the regularised
 // zone t < 4.5 (near points and the nearest far nodes) the factors are
 // recomputed: series below t = 1 (finite at r = 0), the erfcx form above.
+// FAR: r2 > 0 is known (a far-field node lies beyond beta r_t of the query),
+// so the test for a source at the query point is left out.
+template <bool FAR = false>
 __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &kappa, float &lambda) {
-    if (kp.eps == 0.0f && !(r2 > 0.0f)) return false;
+    if (!FAR && kp.eps == 0.0f && !(r2 > 0.0f)) return false;
     const float ir = __builtin_amdgcn_rsqf(r2);
     const float ir2 = ir * ir;
     kappa = kInv4Pi * ir * ir2;
@@ -250,8 +253,9 @@ __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &
 
 // kappa alone, same branches as radial() (the adjoint's node and point
 // increments need no lambda when dL/dx comes from the forward's gradients)
+template <bool FAR = false>
 __device__ __forceinline__ bool radial_kappa(float r2, const KernelParams &kp, float &kappa) {
-    if (kp.eps == 0.0f && !(r2 > 0.0f)) return false;
+    if (!FAR && kp.eps == 0.0f && !(r2 > 0.0f)) return false;
     const float ir = __builtin_amdgcn_rsqf(r2);
     const float ir2 = ir * ir;
     kappa = kInv4Pi * ir * ir2;
@@ -267,6 +271,47 @@ __device__ __forceinline__ bool radial_kappa(float r2, const KernelParams &kp, f
         }
     }
     return true;
+}
+
+// radial<true>() / radial_kappa<true>() for the K queries of a lane that a
+// far-field node serves (far[i]: r2[i] > 0): the plain factors for every
+// slot, and the regularised ones (same values as radial()) only when some
+// far query of the wavefront lies in the regularised zone, behind one
+// wave-uniform branch instead of a divergent branch per query.
+template <int K>
+__device__ __forceinline__ void radial_far(const float (&r2)[K], const bool (&far)[K], const KernelParams &kp,
+                                           float (&kappa)[K], float (&lambda)[K]) {
+    bool slow = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const float ir = __builtin_amdgcn_rsqf(r2[i]);
+        const float ir2 = ir * ir;
+        kappa[i] = kInv4Pi * ir * ir2;
+        lambda[i] = 3.0f * kappa[i] * ir2;
+        slow |= far[i] && kp.eps > 0.0f && r2[i] * kp.ieps2 < kFarT2;
+    }
+    if (__ballot(slow) != 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (far[i]) radial<true>(r2[i], kp, kappa[i], lambda[i]);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void radial_kappa_far(const float (&r2)[K], const bool (&far)[K], const KernelParams &kp,
+                                                 float (&kappa)[K]) {
+    bool slow = false;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        const float ir = __builtin_amdgcn_rsqf(r2[i]);
+        kappa[i] = kInv4Pi * ir * (ir * ir);
+        slow |= far[i] && kp.eps > 0.0f && r2[i] * kp.ieps2 < kFarT2;
+    }
+    if (__ballot(slow) != 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            if (far[i]) radial_kappa<true>(r2[i], kp, kappa[i]);
+    }
 }
 
 // kappa, lambda and the Hessian factor nu = chi(t)/(4 pi r^7), same branches

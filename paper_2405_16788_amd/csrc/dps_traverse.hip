@@ -85,7 +85,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         if (any_far && far) {
             refine_moments<CB, BF16>(mom, ms, t, c0, D, kp.nhi);
             float kap, lam;
-            radial(s, kp, kap, lam);
+            radial<true>(s, kp, kap, lam);
             const float dx = nd.cx - px, dy = nd.cy - py, dz = nd.cz - pz;
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
@@ -237,7 +237,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
                 for (int i = 0; i < K; ++i) {
                     if (far[i]) {
                         float kap, lam;
-                        radial(s[i], kp, kap, lam);
+                        radial<true>(s[i], kp, kap, lam);
                         const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
 #pragma unroll
                         for (int c = 0; c < CB; ++c) {
@@ -502,8 +502,8 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
             for (int i = 0; i < K; ++i) {
                 if (far[i]) {
                     float kap, lam = 0.0f;
-                    if constexpr (DX) radial(s[i], kp, kap, lam);
-                    else radial_kappa(s[i], kp, kap);
+                    if constexpr (DX) radial<true>(s[i], kp, kap, lam);
+                    else radial_kappa<true>(s[i], kp, kap);
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
                     float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
                     // kappa (p_t - x_q) once, then one FMA per channel and axis
