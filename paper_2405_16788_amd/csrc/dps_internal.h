@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "dps.h"
 
 namespace dps {
@@ -138,6 +140,7 @@ struct KernelParams {
     float k7;        // 1/(4 pi eps^7)
     float ke4;       // 1/(pi^1.5 eps^4):   d kappa / d eps = -exp(-t^2) ke4
     float ke6;       // 2/(pi^1.5 eps^6):   d lambda / d eps = -exp(-t^2) ke6
+    float zone_r2;   // r2 < zone_r2 iff r2 * ieps2 < kFarT2 (the regularised zone); 0 without eps
     uint32_t nhi;    // BF16 storage: nodes [0, nhi) keep FP32 moments (0 otherwise)
 };
 
@@ -154,6 +157,13 @@ __host__ inline KernelParams make_kernel_params(float eps) {
         kp.k7 = (float)(0.0795774715459476679 / (e * e * e * e * e * e * e));
         kp.ke4 = (float)(0.179587122125166564 / (e * e * e * e));
         kp.ke6 = (float)(0.359174244250333128 / (e * e * e * e * e * e));
+        // the smallest float r2 whose FP32 product r2 * ieps2 reaches kFarT2
+        // (the product is monotone in r2): one compare of r2 then takes the
+        // same decision as forming the product and comparing it
+        float z = (float)((double)kFarT2 / (double)kp.ieps2);
+        while (z > 0.0f && z * kp.ieps2 >= kFarT2) z = std::nextafter(z, 0.0f);
+        while (z * kp.ieps2 < kFarT2) z = std::nextafter(z, HUGE_VALF);
+        kp.zone_r2 = z;
     } else {
         kp.ieps = 0.0f;
         kp.ieps2 = 0.0f;
@@ -162,6 +172,7 @@ __host__ inline KernelParams make_kernel_params(float eps) {
         kp.k7 = 0.0f;
         kp.ke4 = 0.0f;
         kp.ke6 = 0.0f;
+        kp.zone_r2 = 0.0f;  // no r2 lies below it
     }
     return kp;
 }
@@ -223,8 +234,9 @@ __device__ __forceinline__ float series_chi_t7(float u) {  // u = t^2
 // r2 = |d|^2.  Returns false when the term is excluded (r = 0 with eps = 0).
 // Common case first, without branches: rho = 1, psi = 3 (t >= 4.5 or eps = 0),
 // with the hardware reciprocal square root (1 ulp).  Inside the regularised
-// zone t < 4.5 (near points and the nearest far nodes) the factors are
-// recomputed: series below t = 1 (finite at r = 0), the erfcx form above.
+// zone t < 4.5 (near points and the nearest far nodes; r2 < zone_r2, never
+// without eps) the factors are recomputed: series below t = 1 (finite at
+// r = 0), the erfcx form above.
 // FAR: r2 > 0 is known (a far-field node lies beyond beta r_t of the query),
 // so the test for a source at the query point is left out.
 template <bool FAR = false>
@@ -234,18 +246,16 @@ __device__ __forceinline__ bool radial(float r2, const KernelParams &kp, float &
     const float ir2 = ir * ir;
     kappa = kInv4Pi * ir * ir2;
     lambda = 3.0f * kappa * ir2;
-    if (kp.eps > 0.0f) {
+    if (r2 < kp.zone_r2) {
         const float u = r2 * kp.ieps2;
-        if (u < kFarT2) {
-            if (u < kSeriesWideT2) {
-                kappa = kp.k3 * series_rho_t3(u);
-                lambda = kp.k5 * series_psi_t5(u);
-            } else {
-                float rho, psi, e;
-                rho_psi_erfcx(u, r2 * ir * kp.ieps, rho, psi, e);
-                kappa = kappa * rho;
-                lambda = kInv4Pi * ir * ir2 * ir2 * psi;
-            }
+        if (u < kSeriesWideT2) {
+            kappa = kp.k3 * series_rho_t3(u);
+            lambda = kp.k5 * series_psi_t5(u);
+        } else {
+            float rho, psi, e;
+            rho_psi_erfcx(u, r2 * ir * kp.ieps, rho, psi, e);
+            kappa = kappa * rho;
+            lambda = kInv4Pi * ir * ir2 * ir2 * psi;
         }
     }
     return true;
@@ -259,59 +269,16 @@ __device__ __forceinline__ bool radial_kappa(float r2, const KernelParams &kp, f
     const float ir = __builtin_amdgcn_rsqf(r2);
     const float ir2 = ir * ir;
     kappa = kInv4Pi * ir * ir2;
-    if (kp.eps > 0.0f) {
+    if (r2 < kp.zone_r2) {
         const float u = r2 * kp.ieps2;
-        if (u < kFarT2) {
-            if (u < kSeriesWideT2) {
-                kappa = kp.k3 * series_rho_t3(u);
-            } else {
-                float e;
-                kappa = kappa * rho_erfcx(u, r2 * ir * kp.ieps, e);
-            }
+        if (u < kSeriesWideT2) {
+            kappa = kp.k3 * series_rho_t3(u);
+        } else {
+            float e;
+            kappa = kappa * rho_erfcx(u, r2 * ir * kp.ieps, e);
         }
     }
     return true;
-}
-
-// radial<true>() / radial_kappa<true>() for the K queries of a lane that a
-// far-field node serves (far[i]: r2[i] > 0): the plain factors for every
-// slot, and the regularised ones (same values as radial()) only when some
-// far query of the wavefront lies in the regularised zone, behind one
-// wave-uniform branch instead of a divergent branch per query.
-template <int K>
-__device__ __forceinline__ void radial_far(const float (&r2)[K], const bool (&far)[K], const KernelParams &kp,
-                                           float (&kappa)[K], float (&lambda)[K]) {
-    bool slow = false;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const float ir = __builtin_amdgcn_rsqf(r2[i]);
-        const float ir2 = ir * ir;
-        kappa[i] = kInv4Pi * ir * ir2;
-        lambda[i] = 3.0f * kappa[i] * ir2;
-        slow |= far[i] && kp.eps > 0.0f && r2[i] * kp.ieps2 < kFarT2;
-    }
-    if (__ballot(slow) != 0) {
-#pragma unroll
-        for (int i = 0; i < K; ++i)
-            if (far[i]) radial<true>(r2[i], kp, kappa[i], lambda[i]);
-    }
-}
-
-template <int K>
-__device__ __forceinline__ void radial_kappa_far(const float (&r2)[K], const bool (&far)[K], const KernelParams &kp,
-                                                 float (&kappa)[K]) {
-    bool slow = false;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-        const float ir = __builtin_amdgcn_rsqf(r2[i]);
-        kappa[i] = kInv4Pi * ir * (ir * ir);
-        slow |= far[i] && kp.eps > 0.0f && r2[i] * kp.ieps2 < kFarT2;
-    }
-    if (__ballot(slow) != 0) {
-#pragma unroll
-        for (int i = 0; i < K; ++i)
-            if (far[i]) radial_kappa<true>(r2[i], kp, kappa[i]);
-    }
 }
 
 // kappa, lambda and the Hessian factor nu = chi(t)/(4 pi r^7), same branches
@@ -324,11 +291,12 @@ __device__ __forceinline__ bool radial3(float r2, const KernelParams &kp, float 
     kappa = kInv4Pi * ir * ir2;
     lambda = 3.0f * kappa * ir2;
     nu = 5.0f * lambda * ir2;
-    if (kp.eps > 0.0f) {
+    {
+        const bool zone = r2 < kp.zone_r2;
         const float u = r2 * kp.ieps2;
         // the wavefront-uniform test keeps the branch-free block below a real
         // branch: without it the compiler evaluated it for every term
-        if (__ballot(u < kFarT2) != 0 && u < kFarT2) {
+        if (__ballot(zone) != 0 && zone) {
             if (u < kSeriesWideT2) {
                 kappa = kp.k3 * series_rho_t3(u);
                 lambda = kp.k5 * series_psi_t5(u);

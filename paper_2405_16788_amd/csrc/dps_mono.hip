@@ -24,10 +24,12 @@ namespace dps {
 
 namespace {
 
-// m = kappa r and gv = r lambda - kappa / r for r^2 > 0
+// m = kappa r and gv = r lambda - kappa / r for r^2 > 0 (FAR: a far-field
+// node, as in radial())
+template <bool FAR = false>
 __device__ __forceinline__ void mono_radial(float r2, const KernelParams &kp, float &m, float &gv) {
     float kap, lam;
-    radial(r2, kp, kap, lam);
+    radial<FAR>(r2, kp, kap, lam);
     const float ir = __builtin_amdgcn_rsqf(r2);
     m = kap * (r2 * ir);
     gv = fmaf(lam, r2, -kap) * ir;
@@ -93,7 +95,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
             for (int i = 0; i < K; ++i) {
                 if (far[i]) {  // s > 0 here
                     float m, gv;
-                    mono_radial(s[i], kp, m, gv);
+                    mono_radial<true>(s[i], kp, m, gv);
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
 #pragma unroll
                     for (int c = 0; c < CB; ++c) {
@@ -254,7 +256,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
             for (int i = 0; i < K; ++i) {
                 if (far[i]) {
                     float m, gv;
-                    mono_radial(s[i], kp, m, gv);
+                    mono_radial<true>(s[i], kp, m, gv);
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
                     float wq = 0.0f;
 #pragma unroll

@@ -221,6 +221,32 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t
 // plain one.  So every term of every query is added by exactly one part, the
 // one that owns its node's ancestor (or itself) at the cut level.
 // ---------------------------------------------------------------------------
+// Per-lane walk state.  A lane visits the current node iff it opened every
+// ancestor of it; along the current path those levels form a prefix, so one
+// integer carries them: the lane visits a node of level l iff l <= depth.
+// Descending from a level-l node sets depth = min(depth, l) + opened;
+// following an escape pointer (to a level <= l) leaves it unchanged, since
+// levels above the new node's are never read before the next descent
+// rewrites them.  -1: the lane has no query.
+__device__ __forceinline__ bool visits(int32_t depth, uint32_t lvl) { return depth >= (int32_t)lvl; }
+
+__device__ __forceinline__ int32_t descend(int32_t depth, uint32_t lvl, bool opened) {
+    return min(depth, (int32_t)lvl) + (opened ? 1 : 0);
+}
+
+// Wavefront-wide "some lane" tests are formed from the ballots of the plain
+// compares (visits, beyond beta r_t): a ballot of a compare is its lane mask
+// as it stands, a ballot of a combined predicate is rebuilt with two vector
+// instructions.
+struct WaveMasks {
+    uint64_t far = 0, open = 0;
+    __device__ __forceinline__ void add(bool in, bool beyond) {
+        const uint64_t bi = __ballot(in), bb = __ballot(beyond);
+        far |= bi & bb;
+        open |= bi & ~bb;
+    }
+};
+
 struct Split {
     uint32_t part;   // this wavefront's part
     uint32_t mask;   // parts - 1 (parts a power of two)

@@ -10,11 +10,12 @@
 // traversals once, in depth-first order, without a stack:
 //   - `t` (the current node) is wave-uniform, so node records, moments and leaf
 //     points are fetched with scalar loads and broadcast to all lanes;
-//   - each lane keeps one bit per level: bit l set means the lane opened every
-//     ancestor of the current level-l node, i.e. Algorithm 1 would visit it;
+//   - each lane keeps the depth of the deepest level on the current path whose
+//     ancestors it all opened: it visits the current node (Algorithm 1 would)
+//     iff the node's level is at most that depth;
 //   - after a node, the wave descends to its first child if any lane opened it
-//     (setting bit l+1 to "opened"), otherwise follows the node's escape
-//     pointer (next sibling, or the parent's escape).
+//     (lanes that did not fall back to the node's level), otherwise follows the
+//     node's escape pointer (next sibling, or the parent's escape).
 // Every lane therefore makes exactly the decisions of the recursive algorithm,
 // in the same depth-first order; lanes not visiting a node are masked off.
 //
@@ -55,7 +56,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         f[c] = 0.0f;
         g[c][0] = g[c][1] = g[c][2] = 0.0f;
     }
-    uint32_t bits = valid ? 1u : 0u;
+    int32_t depth = valid ? 0 : -1;
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float D[3 * CB];
@@ -70,13 +71,15 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         const bool leaf = (nd.meta & kLeafFlag) != 0;
         bool own = true, skip = false;
         if constexpr (SPLIT) split_node(sp, t, lvl, leaf, own, skip);
-        const bool in = !skip && ((bits >> lvl) & 1u);
+        const bool in = !skip && visits(depth, lvl);
         const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
-        const bool accept = in && (s > mul_rn(b2, nd.r2));
-        const bool far = accept && own;
-        const bool open = in && !accept;
-        const bool any_far = __ballot(far) != 0;
-        const bool any_open = __ballot(open) != 0;
+        const bool beyond = s > mul_rn(b2, nd.r2);
+        const bool far = in && beyond && own;
+        const bool open = in && !beyond;
+        WaveMasks wm;
+        if (!skip) wm.add(visits(depth, lvl), beyond);
+        const bool any_far = own && wm.far != 0;
+        const bool any_open = wm.open != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
         const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
@@ -101,7 +104,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         }
         if (any_open) {
             if (!leaf) {
-                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
+                depth = descend(depth, lvl, open);
             } else {
                 for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
@@ -168,7 +171,8 @@ template <int CB, bool BF16, bool GRAD, int K, bool GRID = false>
 __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *__restrict__ fout,
                                             float *__restrict__ gout, const GridSpec &gs = GridSpec{}) {
     float px[K], py[K], pz[K];
-    uint32_t bits[K];
+    uint32_t bits[K];  // level bits of the predicated one-channel walk
+    int32_t depth[K];
     float f[K][CB], g[K][CB][3];
     int64_t row[K];
     bool vld[K];
@@ -187,6 +191,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
             pz[i] = valid ? x[3 * q + 2] : 0.0f;
         }
         bits[i] = valid ? 1u : 0u;
+        depth[i] = valid ? 0 : -1;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             f[i][c] = 0.0f;
@@ -213,19 +218,20 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
             const uint32_t lvl = nd.meta & 0xffu;
             const bool leaf = (nd.meta & kLeafFlag) != 0;
             const float lim = mul_rn(b2, nd.r2);
-            bool far[K], open[K], lane_far = false, lane_open = false;
+            bool far[K], open[K];
             float s[K];
+            WaveMasks wm;
 #pragma unroll
             for (int i = 0; i < K; ++i) {
-                const bool in = (bits[i] >> lvl) & 1u;
+                const bool in = visits(depth[i], lvl);
                 s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
-                far[i] = in && (s[i] > lim);
-                open[i] = in && !far[i];
-                lane_far |= far[i];
-                lane_open |= open[i];
+                const bool beyond = s[i] > lim;
+                far[i] = in && beyond;
+                open[i] = in && !beyond;
+                wm.add(in, beyond);
             }
-            const bool any_far = __ballot(lane_far) != 0;
-            const bool any_open = __ballot(lane_open) != 0;
+            const bool any_far = wm.far != 0;
+            const bool any_open = wm.open != 0;
             const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
             const uint32_t pf = next;  // kEnd is the root: a valid record
             const NodeRec nn = nodes[pf];
@@ -256,8 +262,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
             if (any_open) {
                 if (!leaf) {
 #pragma unroll
-                    for (int i = 0; i < K; ++i)
-                        bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
+                    for (int i = 0; i < K; ++i) depth[i] = descend(depth[i], lvl, open[i]);
                 } else {
                     for_leaf_points<CB, BF16, false>(pts, attr, as, c0, nd.first, node_count(nd),
                                               [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_query_split(DPS_KERN_PARAMS, float
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t tile = wave >> shift;
     if (tile * 64 >= Q) return;  // wave-uniform
-    sp.part = (uint32_t)wave & sp.mask;
+    sp.part = __builtin_amdgcn_readfirstlane((uint32_t)wave & sp.mask);  // wave-uniform
     query1_body<CB, BF16, GRAD, false, true>(tile * 64 + (threadIdx.x & 63), DPS_TRAV_ARGS, fout, gout, GridSpec{},
                                              sp);
 }
@@ -445,7 +450,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                                              const float *__restrict__ gin, const Split &sp = Split{}) {
     const int lane = lane_id();
     float px[K], py[K], pz[K], w[K][CB], ax[K], ay[K], az[K];
-    uint32_t bits[K];
+    int32_t depth[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int64_t q = q0 + 64 * i;
@@ -453,7 +458,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         px[i] = valid ? x[3 * q] : 0.0f;
         py[i] = valid ? x[3 * q + 1] : 0.0f;
         pz[i] = valid ? x[3 * q + 2] : 0.0f;
-        bits[i] = valid ? 1u : 0u;
+        depth[i] = valid ? 0 : -1;
         ax[i] = ay[i] = az[i] = 0.0f;
 #pragma unroll
         for (int c = 0; c < CB; ++c) w[i][c] = valid ? df[q * ldo + co + c] : 0.0f;
@@ -473,20 +478,20 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         const float lim = mul_rn(b2, nd.r2);
         bool own = true, skip = false;
         if constexpr (SPLIT) split_node(sp, t, lvl, leaf, own, skip);
-        bool far[K], open[K], lane_far = false, lane_open = false;
+        bool far[K], open[K];
         float s[K];
+        WaveMasks wm;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const bool in = !skip && ((bits[i] >> lvl) & 1u);
+            const bool in = !skip && visits(depth[i], lvl);
             s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
-            const bool accept = in && (s[i] > lim);
-            far[i] = accept && own;
-            open[i] = in && !accept;
-            lane_far |= far[i];
-            lane_open |= open[i];
+            const bool beyond = s[i] > lim;
+            far[i] = in && beyond && own;
+            open[i] = in && !beyond;
+            if (!skip) wm.add(visits(depth[i], lvl), beyond);
         }
-        const bool any_far = __ballot(lane_far) != 0;
-        const bool any_open = __ballot(lane_open) != 0;
+        const bool any_far = own && wm.far != 0;
+        const bool any_open = wm.open != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
         const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
@@ -532,8 +537,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         if (any_open) {
             if (!leaf) {
 #pragma unroll
-                for (int i = 0; i < K; ++i)
-                    bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
+                for (int i = 0; i < K; ++i) depth[i] = descend(depth[i], lvl, open[i]);
             } else {
                 for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t j, const PointRec &pr, const float (&mu)[CB]) {
@@ -633,7 +637,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_split(DPS_KERN_PARAMS, int
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t tile = wave >> shift;
     if (tile * 64 >= Q) return;  // wave-uniform
-    sp.part = (uint32_t)wave & sp.mask;
+    sp.part = __builtin_amdgcn_readfirstlane((uint32_t)wave & sp.mask);  // wave-uniform
     adjoint_body<CB, BF16, 1, false, true>(tile * 64 + (threadIdx.x & 63), DPS_TRAV_ARGS, C, df, G, P, dxout,
                                            dx_mode, gin, sp);
 }
@@ -690,7 +694,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                                                double *__restrict__ pn, double *__restrict__ eacc) {
     const int lane = lane_id();
     float px[K], py[K], pz[K], w[K][CB], h[K][CB][3], ax[K], ay[K], az[K];
-    uint32_t bits[K];
+    int32_t depth[K];
     float deps = 0.0f;
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -699,7 +703,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         px[i] = valid ? x[3 * q] : 0.0f;
         py[i] = valid ? x[3 * q + 1] : 0.0f;
         pz[i] = valid ? x[3 * q + 2] : 0.0f;
-        bits[i] = valid ? 1u : 0u;
+        depth[i] = valid ? 0 : -1;
         ax[i] = ay[i] = az[i] = 0.0f;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
@@ -721,19 +725,20 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
         const float lim = mul_rn(b2, nd.r2);
-        bool far[K], open[K], lane_far = false, lane_open = false;
+        bool far[K], open[K];
         float s2[K];
+        WaveMasks wm;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const bool in = (bits[i] >> lvl) & 1u;
+            const bool in = visits(depth[i], lvl);
             s2[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
-            far[i] = in && (s2[i] > lim);
-            open[i] = in && !far[i];
-            lane_far |= far[i];
-            lane_open |= open[i];
+            const bool beyond = s2[i] > lim;
+            far[i] = in && beyond;
+            open[i] = in && !beyond;
+            wm.add(in, beyond);
         }
-        const bool any_far = __ballot(lane_far) != 0;
-        const bool any_open = __ballot(lane_open) != 0;
+        const bool any_far = wm.far != 0;
+        const bool any_open = wm.open != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
         const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
@@ -777,9 +782,8 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                     ay[i] += fmaf(al, dy, -vy);
                     az[i] += fmaf(al, dz, -vz);
                     if constexpr (EXT) {
-                        const float u = s2[i] * kp.ieps2;
-                        if (eacc && kp.eps > 0.0f && u < kFarT2) {
-                            const float e = expf(-u);
+                        if (eacc && s2[i] < kp.zone_r2) {
+                            const float e = expf(-(s2[i] * kp.ieps2));
                             deps = fmaf(-e, fmaf(kp.ke4, e1, kp.ke6 * e2), deps);
                         }
                     }
@@ -790,8 +794,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         if (any_open) {
             if (!leaf) {
 #pragma unroll
-                for (int i = 0; i < K; ++i)
-                    bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
+                for (int i = 0; i < K; ++i) depth[i] = descend(depth[i], lvl, open[i]);
             } else {
                 for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t j, const PointRec &pr, const float (&mu)[CB]) {
@@ -840,9 +843,8 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                                     nacc[0] += pr.a * fmaf(bsum, dx, -kap * hmx);
                                     nacc[1] += pr.a * fmaf(bsum, dy, -kap * hmy);
                                     nacc[2] += pr.a * fmaf(bsum, dz, -kap * hmz);
-                                    const float u = r2 * kp.ieps2;
-                                    if (eacc && kp.eps > 0.0f && u < kFarT2) {
-                                        const float e = expf(-u);
+                                    if (eacc && r2 < kp.zone_r2) {
+                                        const float e = expf(-(r2 * kp.ieps2));
                                         deps = fmaf(-e, fmaf(kp.ke4, e1, kp.ke6 * e2), deps);
                                     }
                                 }

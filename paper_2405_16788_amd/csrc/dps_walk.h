@@ -45,7 +45,7 @@ __device__ __forceinline__ void radial_k(const float (&r2)[K], const bool (&take
         kap[i] = kInv4Pi * ir * ir2;
         lam[i] = 3.0f * kap[i] * ir2;
         on[i] = take[i] && (kp.eps != 0.0f || x > 0.0f);
-        slow |= take[i] && kp.eps > 0.0f && x * kp.ieps2 < kFarT2;
+        slow |= take[i] && x < kp.zone_r2;
     }
     if (__ballot(slow) != 0) {
 #pragma unroll
