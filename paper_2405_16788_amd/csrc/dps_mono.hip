@@ -42,7 +42,7 @@ template <int CB, bool BF16, bool GRAD, int K>
 __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, float *__restrict__ fout,
                                                 float *__restrict__ gout) {
     float px[K], py[K], pz[K];
-    uint32_t bits[K];
+    int32_t depth[K];
     float f[K][CB], g[K][CB][3];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
@@ -51,7 +51,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
         px[i] = valid ? x[3 * q] : 0.0f;
         py[i] = valid ? x[3 * q + 1] : 0.0f;
         pz[i] = valid ? x[3 * q + 2] : 0.0f;
-        bits[i] = valid ? 1u : 0u;
+        depth[i] = valid ? 0 : -1;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
             f[i][c] = 0.0f;
@@ -71,19 +71,20 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
         const float lim = mul_rn(b2, nd.r2);
-        bool far[K], open[K], lane_far = false, lane_open = false;
+        bool far[K], open[K];
         float s[K];
+        WaveMasks wm;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const bool in = (bits[i] >> lvl) & 1u;
+            const bool in = visits(depth[i], lvl);
             s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
-            far[i] = in && (s[i] > lim);
-            open[i] = in && !far[i];
-            lane_far |= far[i];
-            lane_open |= open[i];
+            const bool beyond = s[i] > lim;
+            far[i] = in && beyond;
+            open[i] = in && !beyond;
+            wm.add(in, beyond);
         }
-        const bool any_far = __ballot(lane_far) != 0;
-        const bool any_open = __ballot(lane_open) != 0;
+        const bool any_far = wm.far != 0;
+        const bool any_open = wm.open != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
         const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
@@ -113,8 +114,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
         if (any_open) {
             if (!leaf) {
 #pragma unroll
-                for (int i = 0; i < K; ++i)
-                    bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
+                for (int i = 0; i < K; ++i) depth[i] = descend(depth[i], lvl, open[i]);
             } else {
                 for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
@@ -202,7 +202,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
                                                   float *__restrict__ dxout, int dx_mode) {
     const int lane = lane_id();
     float px[K], py[K], pz[K], w[K][CB], ax[K], ay[K], az[K];
-    uint32_t bits[K];
+    int32_t depth[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int64_t q = q0 + 64 * i;
@@ -210,7 +210,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
         px[i] = valid ? x[3 * q] : 0.0f;
         py[i] = valid ? x[3 * q + 1] : 0.0f;
         pz[i] = valid ? x[3 * q + 2] : 0.0f;
-        bits[i] = valid ? 1u : 0u;
+        depth[i] = valid ? 0 : -1;
         ax[i] = ay[i] = az[i] = 0.0f;
 #pragma unroll
         for (int c = 0; c < CB; ++c) w[i][c] = valid ? df[q * ldo + co + c] : 0.0f;
@@ -228,19 +228,20 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
         const float lim = mul_rn(b2, nd.r2);
-        bool far[K], open[K], lane_far = false, lane_open = false;
+        bool far[K], open[K];
         float s[K];
+        WaveMasks wm;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const bool in = (bits[i] >> lvl) & 1u;
+            const bool in = visits(depth[i], lvl);
             s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
-            far[i] = in && (s[i] > lim);
-            open[i] = in && !far[i];
-            lane_far |= far[i];
-            lane_open |= open[i];
+            const bool beyond = s[i] > lim;
+            far[i] = in && beyond;
+            open[i] = in && !beyond;
+            wm.add(in, beyond);
         }
-        const bool any_far = __ballot(lane_far) != 0;
-        const bool any_open = __ballot(lane_open) != 0;
+        const bool any_far = wm.far != 0;
+        const bool any_open = wm.open != 0;
         const uint32_t next = (any_open && !leaf) ? nd.first : nd.escape;
         const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
@@ -275,8 +276,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
         if (any_open) {
             if (!leaf) {
 #pragma unroll
-                for (int i = 0; i < K; ++i)
-                    bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
+                for (int i = 0; i < K; ++i) depth[i] = descend(depth[i], lvl, open[i]);
             } else {
                 for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t j, const PointRec &pr, const float (&mu)[CB]) {

@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void k_ray_march(
         // wave-uniform: every lane evaluates the ballot; at most ceil(n / K) passes
         for (int k = 0; __ballot(active) != 0; k += K) {
             float px[K], py[K], pz[K], f[K][1], g[K][1][3];
-            uint32_t bits[K];
+            int32_t depth[K];
 #pragma unroll
             for (int i = 0; i < K; ++i) {
                 const int s = k + i;
@@ -80,11 +80,11 @@ __global__ __launch_bounds__(kThreads) void k_ray_march(
                 px[i] = ray_at(ox, t, dx);
                 py[i] = ray_at(oy, t, dy);
                 pz[i] = ray_at(oz, t, dz);
-                bits[i] = (active && s < n) ? 1u : 0u;
+                depth[i] = (active && s < n) ? 0 : -1;
                 f[i][0] = 0.0f;
                 g[i][0][0] = g[i][0][1] = g[i][0][2] = 0.0f;
             }
-            dipole_walk<1, BF16, false, K>(px, py, pz, bits, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit,
+            dipole_walk<1, BF16, false, K>(px, py, pz, depth, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit,
                                            err);
 #pragma unroll
             for (int i = 0; i < K; ++i) {
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(kThreads) void k_ray_march_along(
     const float dx = d[3 * r], dy = d[3 * r + 1], dz = d[3 * r + 2];
     const float tn = tnear[r], h = (tfar[r] - tn) / (float)n;
     float px[K], py[K], pz[K], f[K][1], g[K][1][3];
-    uint32_t bits[K];
+    int32_t depth[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
         const int s = s0 + lane * K + i;
@@ -149,11 +149,11 @@ __global__ __launch_bounds__(kThreads) void k_ray_march_along(
         px[i] = ray_at(ox, t, dx);
         py[i] = ray_at(oy, t, dy);
         pz[i] = ray_at(oz, t, dz);
-        bits[i] = s < n ? 1u : 0u;
+        depth[i] = s < n ? 0 : -1;
         f[i][0] = 0.0f;
         g[i][0][0] = g[i][0][1] = g[i][0][2] = 0.0f;
     }
-    dipole_walk<1, BF16, false, K>(px, py, pz, bits, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit, err);
+    dipole_walk<1, BF16, false, K>(px, py, pz, depth, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit, err);
     const float next = __shfl_down(f[0][0], 1);  // the next lane's first sample
     int32_t j = INT32_MAX;
     float v0 = 0.0f, v1 = 0.0f;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_ray_hit_values(
     }
     if (__ballot(on) == 0) return;  // wave-uniform
     float px[1] = {0.0f}, py[1] = {0.0f}, pz[1] = {0.0f}, f[1][1] = {{0.0f}}, g[1][1][3] = {{{0.0f, 0.0f, 0.0f}}};
-    uint32_t bits[1] = {on ? 1u : 0u};
+    int32_t depth[1] = {on ? 0 : -1};
     if (on) {
         const float tn = tnear[r], h = (tfar[r] - tn) / (float)n;
         const float t = march_param(tn, j + side, h);
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_ray_hit_values(
         py[0] = ray_at(o[3 * r + 1], t, d[3 * r + 1]);
         pz[0] = ray_at(o[3 * r + 2], t, d[3 * r + 2]);
     }
-    dipole_walk<1, BF16, false, 1>(px, py, pz, bits, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit, err);
+    dipole_walk<1, BF16, false, 1>(px, py, pz, depth, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit, err);
     if (on) hv[2 * r + side] = f[0][0];
 }
 
@@ -284,8 +284,8 @@ __global__ __launch_bounds__(kThreads) void k_ray_march_harnack(
             const float t = march_param(tn, k, h);
             float px[1] = {ray_at(ox, t, dx)}, py[1] = {ray_at(oy, t, dy)}, pz[1] = {ray_at(oz, t, dz)};
             float f[1][1] = {{0.0f}}, g[1][1][3] = {{{0.0f, 0.0f, 0.0f}}};
-            uint32_t bits[1] = {on ? 1u : 0u};
-            dipole_walk<1, BF16, false, 1>(px, py, pz, bits, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit,
+            int32_t depth[1] = {on ? 0 : -1};
+            dipole_walk<1, BF16, false, 1>(px, py, pz, depth, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit,
                                            err);
             return f[0][0];
         };

@@ -171,7 +171,6 @@ template <int CB, bool BF16, bool GRAD, int K, bool GRID = false>
 __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *__restrict__ fout,
                                             float *__restrict__ gout, const GridSpec &gs = GridSpec{}) {
     float px[K], py[K], pz[K];
-    uint32_t bits[K];  // level bits of the predicated one-channel walk
     int32_t depth[K];
     float f[K][CB], g[K][CB][3];
     int64_t row[K];
@@ -190,7 +189,6 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
             py[i] = valid ? x[3 * q + 1] : 0.0f;
             pz[i] = valid ? x[3 * q + 2] : 0.0f;
         }
-        bits[i] = valid ? 1u : 0u;
         depth[i] = valid ? 0 : -1;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
@@ -202,7 +200,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
         // one channel without gradients (grids, level-set values): the
         // predicated walk of the ray march, the same values bit for bit with
         // fewer scalar instructions per node
-        dipole_walk<1, BF16, false, K>(px, py, pz, bits, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit,
+        dipole_walk<1, BF16, false, K>(px, py, pz, depth, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit,
                                        err);
     } else {
         uint32_t t = 0;
@@ -393,8 +391,8 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
         py = x[3 * q + 1];
         pz = x[3 * q + 2];
     }
-    int32_t visits = 0, nfar = 0, leaves = 0, near = 0;
-    uint32_t bits = valid ? 1u : 0u;
+    int32_t nvisit = 0, nfar = 0, leaves = 0, near = 0;
+    int32_t depth = valid ? 0 : -1;
     uint32_t t = 0;
     uint32_t steps = 0;
     for (;;) {
@@ -404,16 +402,16 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
         }
         const NodeRec nd = nodes[t];
         const uint32_t lvl = nd.meta & 0xffu;
-        const bool in = (bits >> lvl) & 1u;
+        const bool in = visits(depth, lvl);
         const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
         const bool far = in && (s > mul_rn(b2, nd.r2));
         const bool open = in && !far;
-        visits += in;
+        nvisit += in;
         nfar += far;
         uint32_t next = nd.escape;
         if (__ballot(open)) {
             if (!(nd.meta & kLeafFlag)) {
-                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
+                depth = descend(depth, lvl, open);
             } else {
                 leaves += open;
                 near += open ? (int32_t)node_count(nd) : 0;
@@ -424,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void k_counts(const NodeRec *__restrict__
         t = next;
     }
     if (valid) {
-        counts[4 * q] = visits;
+        counts[4 * q] = nvisit;
         counts[4 * q + 1] = nfar;
         counts[4 * q + 2] = leaves;
         counts[4 * q + 3] = near;

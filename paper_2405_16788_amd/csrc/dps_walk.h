@@ -3,12 +3,12 @@
 // (and gradients) of CB channels accumulated in registers.
 //
 // Algorithm 1 (PrimalQuery) for every active point, as the union walk of the
-// wavefront: the current node is wave-uniform, bit l of bits[i] means that
-// point i opened every ancestor of the current level-l node, the far test
-// comes before the leaf test and bucket leaves sum their points exactly.
+// wavefront: the current node is wave-uniform, point i visits it iff its
+// level is at most depth[i] (the walk state of the traversal kernels), the far
+// test comes before the leaf test and bucket leaves sum their points exactly.
 // The next node's record and moments are fetched before the current node's
-// far-field and leaf work (software pipelining).  Points with bits[i] = 0 take
-// no part; f and g are accumulated into (the caller zeroes them).  The
+// far-field and leaf work (software pipelining).  Points with depth[i] = -1
+// take no part; f and g are accumulated into (the caller zeroes them).  The
 // arithmetic per point is that of the point-query kernels, with its dot
 // products written as explicit fused chains: left to contraction, the
 // compiler may fuse a different product of a sum of products in each kernel,
@@ -56,7 +56,7 @@ __device__ __forceinline__ void radial_k(const float (&r2)[K], const bool (&take
 
 template <int CB, bool BF16, bool GRAD, int K>
 __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&py)[K], const float (&pz)[K],
-                                            uint32_t (&bits)[K], float (&f)[K][CB], float (&g)[K][CB][3],
+                                            int32_t (&depth)[K], float (&f)[K][CB], float (&g)[K][CB][3],
                                             const NodeRec *__restrict__ nodes, const PointRec *__restrict__ pts,
                                             const void *__restrict__ mom, const void *__restrict__ attr, int ms,
                                             int as, float b2, KernelParams kp, int c0, uint32_t limit,
@@ -74,19 +74,20 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
         const float lim = mul_rn(b2, nd.r2);
-        bool far[K], open[K], lane_far = false, lane_open = false;
+        bool far[K], open[K];
         float s[K];
+        WaveMasks wm;
 #pragma unroll
         for (int i = 0; i < K; ++i) {
-            const bool in = (bits[i] >> lvl) & 1u;
+            const bool in = visits(depth[i], lvl);
             s[i] = dist2_rn(nd.cx, nd.cy, nd.cz, px[i], py[i], pz[i]);
-            far[i] = in && (s[i] > lim);
-            open[i] = in && !far[i];
-            lane_far |= far[i];
-            lane_open |= open[i];
+            const bool beyond = s[i] > lim;
+            far[i] = in && beyond;
+            open[i] = in && !beyond;
+            wm.add(in, beyond);
         }
-        const bool any_far = __ballot(lane_far) != 0;
-        const bool any_open = __ballot(lane_open) != 0;
+        const bool any_far = wm.far != 0;
+        const bool any_open = wm.open != 0;
         const uint32_t next = any_open ? nd.down : nd.escape;
         const uint32_t pf = next;  // kEnd is the root: a valid record
         const NodeRec nn = nodes[pf];
@@ -124,8 +125,7 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
         if (any_open) {
             if (!leaf) {
 #pragma unroll
-                for (int i = 0; i < K; ++i)
-                    bits[i] = (bits[i] & ~(2u << lvl)) | ((uint32_t)open[i] << (lvl + 1));
+                for (int i = 0; i < K; ++i) depth[i] = descend(depth[i], lvl, open[i]);
             } else {
                 for_leaf_points<CB, BF16>(pts, attr, as, c0, nd.first, node_count(nd),
                                           [&](uint32_t, const PointRec &pr, const float (&mu)[CB]) {
@@ -183,7 +183,7 @@ __device__ __forceinline__ float nearest_walk(float px, float py, float pz, bool
                                               uint32_t limit, uint32_t *__restrict__ err) {
     float best2 = bound * bound;
     float best = bound;
-    uint32_t bits = on ? 1u : 0u;
+    int32_t depth = on ? 0 : -1;
     NodeRec nd = nodes[0];
     uint32_t steps = 0;
     for (;;) {
@@ -193,16 +193,19 @@ __device__ __forceinline__ float nearest_walk(float px, float py, float pz, bool
         }
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
-        const bool in = (bits >> lvl) & 1u;
+        const bool in = visits(depth, lvl);
         const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
         const float reach = (best + __builtin_sqrtf(nd.r2)) * 1.0001f;
-        const bool open = in && s < reach * reach;
-        const bool any_open = __ballot(open) != 0;
+        const bool beyond = !(s < reach * reach);
+        const bool open = in && !beyond;
+        WaveMasks wm;
+        wm.add(in, beyond);
+        const bool any_open = wm.open != 0;
         const uint32_t next = any_open ? nd.down : nd.escape;
         const NodeRec nn = nodes[next];  // kEnd is the root: a valid record
         if (any_open) {
             if (!leaf) {
-                bits = (bits & ~(2u << lvl)) | ((uint32_t)open << (lvl + 1));
+                depth = descend(depth, lvl, open);
             } else {
                 const uint32_t je = nd.first + node_count(nd);
                 for (uint32_t j = nd.first; j < je; ++j) {
