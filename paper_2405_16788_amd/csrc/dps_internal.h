@@ -340,98 +340,86 @@ __device__ __forceinline__ float wave_sum(float v) {
 // ---------------------------------------------------------------------------
 // Reduce-scatter of N <= 16 per-lane values over the 64 lanes.
 //
-// Pairs of lanes exchange half of their partial sums at each of the four
-// in-row DPP steps (partners lane^1, lane^2, lane^7, lane^15 inside a row of
-// 16), so the number of values a lane carries halves at each step instead of
-// every value being reduced separately; the four rows are then summed with
-// the gfx950 row-swap permutes.  Every lane ends with the total of one value
-// index, wave_slot<N>(lane); lanes 0 .. P-1 (P the power of two >= N) hold
-// distinct indices.  The "upper half" bit of step s is the parity of the lane
-// bits in a_s = {0,2}, {1,2}, {2,3}, {3}: partners differ in it, and agree in
-// the bits of the earlier steps, so they always hold the same index set.
+// The values are taken as 4R registers, R = ceil(N / 4) (zeros past N).  The
+// first two halvings use the gfx950 lane swaps, which exchange whole halves
+// of two registers in one instruction: after permlane32_swap of registers k
+// and k + 2R and one add, the lower half-wave holds register k summed over
+// the lanes l and l + 32, the upper half register k + 2R; permlane16_swap of
+// k and k + R does the same between the even and odd rows of 16.  A lane then
+// carries R registers, each summed over the 4 lanes of its column (l mod 16),
+// register k standing for value k + R b4 + 2R b5 (b_i: bit i of the lane).
+// Inside a row, the R registers are halved over lane bits 0 and 1 (DPP quad
+// permutes: partners differ in that bit, each keeps one half of the pair and
+// sends the other) and summed over bits 2 and 3 (row rotations by 4 and 8).
+// Lane l ends with the total of value wave_slot<N>(l) =
+// kk + R b4 + 2R b5, where kk = 2 b0 + b1 (R > 2), b0 (R = 2), 0 (R = 1);
+// wave_slot gives -1 where kk >= R or the value is padding, and also for
+// every lane with bit 2 or 3 set, so each value has exactly one lane.
 // ---------------------------------------------------------------------------
 template <int N_>
-constexpr int scatter_width() { return N_ <= 1 ? 1 : N_ <= 2 ? 2 : N_ <= 4 ? 4 : N_ <= 8 ? 8 : 16; }
-
-__device__ __forceinline__ void scatter_bits(int lane, bool &h0, bool &h1, bool &h2, bool &h3) {
-    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
-    h0 = (b0 ^ b2) != 0;
-    h1 = (b1 ^ b2) != 0;
-    h2 = (b2 ^ b3) != 0;
-    h3 = b3 != 0;
-}
+constexpr int scatter_regs() { return (N_ + 3) / 4; }
 
 template <int N_>
 __device__ __forceinline__ int wave_slot(int lane) {
-    constexpr int P = scatter_width<N_>();
-    bool h0, h1, h2, h3;
-    scatter_bits(lane, h0, h1, h2, h3);
-    if (P == 16) return 8 * h0 + 4 * h1 + 2 * h2 + h3;
-    if (P == 8) return 4 * h0 + 2 * h1 + h2;
-    if (P == 4) return 2 * h0 + h1;
-    if (P == 2) return h0;
-    return 0;
+    constexpr int R = scatter_regs<N_>();
+    if (lane & 12) return -1;
+    const int b0 = lane & 1, b1 = (lane >> 1) & 1, b4 = (lane >> 4) & 1, b5 = (lane >> 5) & 1;
+    const int kk = R > 2 ? 2 * b0 + b1 : R == 2 ? (b1 ? R : b0) : (b0 | b1 ? R : 0);
+    const int n = kk + R * b4 + 2 * R * b5;
+    return (kk < R && n < N_) ? n : -1;
 }
 
-// one halving step: W values -> W/2, partner through the DPP control CTRL
-template <int CTRL, int W>
-__device__ __forceinline__ void scatter_step(const float *in, float *out, bool hi) {
-#pragma unroll
-    for (int k = 0; k < W / 2; ++k) {
-        const float keep = hi ? in[k + W / 2] : in[k];
-        const float send = hi ? in[k] : in[k + W / 2];
-        out[k] = keep + dpp_f<CTRL>(send);
-    }
+// pair sums over one lane-swap: lanes whose half (or row parity) is 0 get
+// register a summed with its partner, the others register b
+__device__ __forceinline__ float swap32_add(float a, float b) {
+    const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+
+__device__ __forceinline__ float swap16_add(float a, float b) {
+    const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(s[0]) + __uint_as_float(s[1]);
+}
+
+// one in-row halving with the partner through the DPP control CTRL: lanes
+// with hi keep b and send a, the others keep a and send b
+template <int CTRL>
+__device__ __forceinline__ float dpp_halve(float a, float b, bool hi) {
+    const float keep = hi ? b : a;
+    const float send = hi ? a : b;
+    return keep + dpp_f<CTRL>(send);
 }
 
 template <int N_>
 __device__ __forceinline__ float wave_sum_scatter(const float (&v)[N_]) {
     static_assert(N_ >= 1 && N_ <= 16, "at most 16 values per call");
-    constexpr int P = scatter_width<N_>();
-    bool h0, h1, h2, h3;
-    scatter_bits(lane_id(), h0, h1, h2, h3);
-    float a[16], b[8];
+    constexpr int R = scatter_regs<N_>();
+    float x[4 * R], y[2 * R], z[4];
 #pragma unroll
-    for (int k = 0; k < P; ++k) a[k] = k < N_ ? v[k] : 0.0f;
+    for (int k = 0; k < 4 * R; ++k) x[k] = k < N_ ? v[k] : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) y[k] = swap32_add(x[k], x[k + 2 * R]);
+#pragma unroll
+    for (int k = 0; k < R; ++k) z[k] = swap16_add(y[k], y[k + R]);
+    const int lane = lane_id();
+    const bool h0 = (lane & 1) != 0, h1 = (lane & 2) != 0;
     float r;
-    if constexpr (P == 16) {
-        scatter_step<0xb1, 16>(a, b, h0);
-        scatter_step<0x4e, 8>(b, a, h1);
-        scatter_step<0x141, 4>(a, b, h2);
-        scatter_step<0x140, 2>(b, a, h3);
-        r = a[0];
-    } else if constexpr (P == 8) {
-        scatter_step<0xb1, 8>(a, b, h0);
-        scatter_step<0x4e, 4>(b, a, h1);
-        scatter_step<0x141, 2>(a, b, h2);
-        r = b[0];
-        r += dpp_f<0x140>(r);
-    } else if constexpr (P == 4) {
-        scatter_step<0xb1, 4>(a, b, h0);
-        scatter_step<0x4e, 2>(b, a, h1);
-        r = a[0];
-        r += dpp_f<0x141>(r);
-        r += dpp_f<0x140>(r);
-    } else if constexpr (P == 2) {
-        scatter_step<0xb1, 2>(a, b, h0);
-        r = b[0];
+    if constexpr (R == 1) {
+        r = z[0];
+        r += dpp_f<0xb1>(r);  // quad_perm [1,0,3,2]
+        r += dpp_f<0x4e>(r);  // quad_perm [2,3,0,1]
+    } else if constexpr (R == 2) {
+        r = dpp_halve<0xb1>(z[0], z[1], h0);
         r += dpp_f<0x4e>(r);
-        r += dpp_f<0x141>(r);
-        r += dpp_f<0x140>(r);
     } else {
-        r = a[0];
-        r += dpp_f<0xb1>(r);
-        r += dpp_f<0x4e>(r);
-        r += dpp_f<0x141>(r);
-        r += dpp_f<0x140>(r);
+        if constexpr (R == 3) z[3] = 0.0f;
+        const float w0 = dpp_halve<0xb1>(z[0], z[2], h0);
+        const float w1 = dpp_halve<0xb1>(z[1], z[3], h0);
+        r = dpp_halve<0x4e>(w0, w1, h1);
     }
-    // rows of 16 -> the whole wavefront: swap odd / even rows, then halves
-    const unsigned u = __float_as_uint(r);
-    const auto s16 = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-    const float r2 = __uint_as_float(s16[0]) + __uint_as_float(s16[1]);
-    const unsigned u2 = __float_as_uint(r2);
-    const auto s32 = __builtin_amdgcn_permlane32_swap(u2, u2, false, false);
-    return __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
+    r += dpp_f<0x124>(r);  // row_ror:4
+    r += dpp_f<0x128>(r);  // row_ror:8
+    return r;
 }
 
 // Max over the 64 lanes of non-negative values.

@@ -311,8 +311,8 @@ __device__ __forceinline__ bool grid_point(const GridSpec &g, int64_t q, float &
 }
 
 // Adds the wavefront totals of v[0..N) to dst[0..N) with one FP64 atomic per
-// value: reduce-scatter in chunks of at most 16 values; in each chunk lanes
-// 0 .. P-1 hold distinct values and issue the atomics.
+// value: reduce-scatter in chunks of at most 16 values; in each chunk the lane
+// wave_slot names for a value holds its total and issues its atomic.
 template <int N_, int B = 0>
 __device__ __forceinline__ void scatter_add_node(const float (&v)[N_], int lane, double *dst) {
     constexpr int W = (N_ - B) < 16 ? (N_ - B) : 16;
@@ -321,7 +321,7 @@ __device__ __forceinline__ void scatter_add_node(const float (&v)[N_], int lane,
     for (int k = 0; k < W; ++k) part[k] = v[B + k];
     const float tot = wave_sum_scatter<W>(part);
     const int slot = wave_slot<W>(lane);
-    if (lane < scatter_width<W>() && slot < W) atomicAdd(&dst[B + slot], (double)tot);
+    if (slot >= 0) atomicAdd(&dst[B + slot], (double)tot);
     if constexpr (B + 16 < N_) scatter_add_node<N_, B + 16>(v, lane, dst);
 }
 
