@@ -641,13 +641,15 @@ __global__ __launch_bounds__(kThreads) void k_adjoint_split(DPS_KERN_PARAMS, int
 }
 
 // resident waves per SIMD requested for the 4-query, 4-channel persistent
-// adjoint (a register budget of 96; measured faster than the unbounded 4)
+// adjoint (register budgets of 96 and 80; measured faster than the unbounded
+// 4 and 5 waves; the 6-wave build keeps 3 spilled values out of the node
+// loop)
 #ifndef DPS_ADJOINT_WAVES
 #define DPS_ADJOINT_WAVES 5
 #endif
 // the same without the in-walk dL/dx (fewer live registers)
 #ifndef DPS_ADJOINT_WAVES_NODX
-#define DPS_ADJOINT_WAVES_NODX 5
+#define DPS_ADJOINT_WAVES_NODX 6
 #endif
 
 template <int CB, bool BF16, int K, bool DX>
