@@ -58,6 +58,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
             g[i][c][0] = g[i][c][1] = g[i][c][2] = 0.0f;
         }
     }
+    const float b2v = in_vgpr(b2);
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float Qc[CB];
@@ -70,7 +71,7 @@ __device__ __forceinline__ void mono_query_body(int64_t q0, DPS_TRAV_PARAMS, flo
         }
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
-        const float lim = mul_rn(b2, nd.r2);
+        const float lim = mul_rn(b2v, nd.r2);
         bool far[K], open[K];
         float s[K];
         WaveMasks wm;
@@ -215,6 +216,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
 #pragma unroll
         for (int c = 0; c < CB; ++c) w[i][c] = valid ? df[q * ldo + co + c] : 0.0f;
     }
+    const float b2v = in_vgpr(b2);
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float Qc[CB];
@@ -227,7 +229,7 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
         }
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
-        const float lim = mul_rn(b2, nd.r2);
+        const float lim = mul_rn(b2v, nd.r2);
         bool far[K], open[K];
         float s[K];
         WaveMasks wm;

@@ -221,6 +221,16 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t
 // plain one.  So every term of every query is added by exactly one part, the
 // one that owns its node's ancestor (or itself) at the cut level.
 // ---------------------------------------------------------------------------
+// A loop-invariant kernel argument held in a vector register.  The far
+// test's product b2 * r_t^2 then takes the node radius as its one scalar
+// operand (a vector instruction reads at most one scalar register here)
+// instead of a copy of the radius made at every node.
+__device__ __forceinline__ float in_vgpr(float v) {
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
+    return r;
+}
+
 // Per-lane walk state.  A lane visits the current node iff it opened every
 // ancestor of it; along the current path those levels form a prefix, so one
 // integer carries them: the lane visits a node of level l iff l <= depth.

@@ -57,6 +57,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         g[c][0] = g[c][1] = g[c][2] = 0.0f;
     }
     int32_t depth = valid ? 0 : -1;
+    const float b2v = in_vgpr(b2);
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float D[3 * CB];
@@ -73,7 +74,7 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
         if constexpr (SPLIT) split_node(sp, t, lvl, leaf, own, skip);
         const bool in = !skip && visits(depth, lvl);
         const float s = dist2_rn(nd.cx, nd.cy, nd.cz, px, py, pz);
-        const bool beyond = s > mul_rn(b2, nd.r2);
+        const bool beyond = s > mul_rn(b2v, nd.r2);
         const bool far = in && beyond && own;
         const bool open = in && !beyond;
         WaveMasks wm;
@@ -203,6 +204,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
         dipole_walk<1, BF16, false, K>(px, py, pz, depth, f, g, nodes, pts, mom, attr, ms, as, b2, kp, c0, limit,
                                        err);
     } else {
+        const float b2v = in_vgpr(b2);
         uint32_t t = 0;
         NodeRec nd = nodes[0];
         float D[3 * CB];
@@ -215,7 +217,7 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
             }
             const uint32_t lvl = nd.meta & 0xffu;
             const bool leaf = (nd.meta & kLeafFlag) != 0;
-            const float lim = mul_rn(b2, nd.r2);
+            const float lim = mul_rn(b2v, nd.r2);
             bool far[K], open[K];
             float s[K];
             WaveMasks wm;
@@ -461,6 +463,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
 #pragma unroll
         for (int c = 0; c < CB; ++c) w[i][c] = valid ? df[q * ldo + co + c] : 0.0f;
     }
+    const float b2v = in_vgpr(b2);
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float D[3 * CB];
@@ -473,7 +476,7 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         }
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
-        const float lim = mul_rn(b2, nd.r2);
+        const float lim = mul_rn(b2v, nd.r2);
         bool own = true, skip = false;
         if constexpr (SPLIT) split_node(sp, t, lvl, leaf, own, skip);
         bool far[K], open[K];
@@ -712,6 +715,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
             for (int j = 0; j < 3; ++j) h[i][c][j] = (dg && valid) ? dg[(q * ldo + co + c) * 3 + j] : 0.0f;
         }
     }
+    const float b2v = in_vgpr(b2);
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float D[3 * CB];
@@ -724,7 +728,7 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         }
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
-        const float lim = mul_rn(b2, nd.r2);
+        const float lim = mul_rn(b2v, nd.r2);
         bool far[K], open[K];
         float s2[K];
         WaveMasks wm;

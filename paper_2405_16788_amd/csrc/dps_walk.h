@@ -61,6 +61,7 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
                                             const void *__restrict__ mom, const void *__restrict__ attr, int ms,
                                             int as, float b2, KernelParams kp, int c0, uint32_t limit,
                                             uint32_t *__restrict__ err) {
+    const float b2v = in_vgpr(b2);
     uint32_t t = 0;
     NodeRec nd = nodes[0];
     float D[3 * CB];
@@ -73,7 +74,7 @@ __device__ __forceinline__ void dipole_walk(const float (&px)[K], const float (&
         }
         const uint32_t lvl = nd.meta & 0xffu;
         const bool leaf = (nd.meta & kLeafFlag) != 0;
-        const float lim = mul_rn(b2, nd.r2);
+        const float lim = mul_rn(b2v, nd.r2);
         bool far[K], open[K];
         float s[K];
         WaveMasks wm;
