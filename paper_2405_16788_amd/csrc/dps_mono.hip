@@ -251,21 +251,24 @@ __device__ __forceinline__ void mono_adjoint_body(int64_t q0, DPS_TRAV_PARAMS, i
         load_charges<CB, BF16>(mom, ms, pf, c0, Qn, kp.nhi);
         if (any_far) {
             refine_charges<CB, BF16>(mom, ms, t, c0, Qc, kp.nhi);
-            // node increment sum_q df_c m, first over the lane's queries
+            // node increment sum_q df_c m, first over the lane's queries; query
+            // slot 0 writes the sums on every lane (zero factors where it is
+            // not far, taken at a huge distance) instead of a zero fill
             float acc[CB];
 #pragma unroll
-            for (int c = 0; c < CB; ++c) acc[c] = 0.0f;
-#pragma unroll
             for (int i = 0; i < K; ++i) {
-                if (far[i]) {
+                if (i == 0 || far[i]) {
+                    const bool off = i == 0 && !far[0];
                     float m, gv;
-                    mono_radial<true>(s[i], kp, m, gv);
+                    mono_radial<true>(off ? kHugeR2 : s[i], kp, m, gv);
+                    m = off ? 0.0f : m;
+                    gv = off ? 0.0f : gv;
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
                     float wq = 0.0f;
 #pragma unroll
                     for (int c = 0; c < CB; ++c) {
                         wq = fmaf(w[i][c], Qc[c], wq);
-                        acc[c] = fmaf(w[i][c], m, acc[c]);
+                        acc[c] = i == 0 ? w[0][c] * m : fmaf(w[i][c], m, acc[c]);
                     }
                     const float gq = gv * wq;
                     ax[i] = fmaf(gq, dx, ax[i]);

@@ -14,6 +14,10 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// squared distance given to the radial factors for a query or point that takes
+// no part in a term: finite factors on the plain path, then replaced by zero
+constexpr float kHugeR2 = 1.0e30f;
+
 // Row i of an array of rows of `row_bytes` bytes: a 32 x 32-bit product, so
 // the address costs two scalar multiplies and a 64-bit add.
 __device__ __forceinline__ const void *row_at(const void *base, uint32_t i, uint32_t row_bytes) {

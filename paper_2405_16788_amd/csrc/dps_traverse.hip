@@ -500,16 +500,21 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far) {
             refine_moments<CB, BF16>(mom, ms, t, c0, D, kp.nhi);
-            // node increment sum_q df_c kappa (p_t - x_q), first over the lane's queries
+            // node increment sum_q df_c kappa (p_t - x_q), first over the lane's
+            // queries.  Query slot 0 writes the sums on every lane, with zero
+            // factors where it is not far (at a huge distance, so it takes the
+            // plain path): no separate zero fill, which the compiler emitted as
+            // 17 moves per node; the other slots add where their query is far.
             float acc[3 * CB];
 #pragma unroll
-            for (int v = 0; v < 3 * CB; ++v) acc[v] = 0.0f;
-#pragma unroll
             for (int i = 0; i < K; ++i) {
-                if (far[i]) {
+                if (i == 0 || far[i]) {
+                    const bool off = i == 0 && !far[0];
                     float kap, lam = 0.0f;
-                    if constexpr (DX) radial<true>(s[i], kp, kap, lam);
-                    else radial_kappa<true>(s[i], kp, kap);
+                    if constexpr (DX) radial<true>(off ? kHugeR2 : s[i], kp, kap, lam);
+                    else radial_kappa<true>(off ? kHugeR2 : s[i], kp, kap);
+                    kap = off ? 0.0f : kap;
+                    lam = off ? 0.0f : lam;
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
                     float E0 = 0.0f, E1 = 0.0f, E2 = 0.0f;
                     // kappa (p_t - x_q) once, then one FMA per channel and axis
@@ -521,9 +526,15 @@ __device__ __forceinline__ void adjoint_body(int64_t q0, DPS_TRAV_PARAMS, int C,
                             E1 += w[i][c] * D[3 * c + 1];
                             E2 += w[i][c] * D[3 * c + 2];
                         }
-                        acc[3 * c] = fmaf(w[i][c], kx, acc[3 * c]);
-                        acc[3 * c + 1] = fmaf(w[i][c], ky, acc[3 * c + 1]);
-                        acc[3 * c + 2] = fmaf(w[i][c], kz, acc[3 * c + 2]);
+                        if (i == 0) {
+                            acc[3 * c] = w[0][c] * kx;
+                            acc[3 * c + 1] = w[0][c] * ky;
+                            acc[3 * c + 2] = w[0][c] * kz;
+                        } else {
+                            acc[3 * c] = fmaf(w[i][c], kx, acc[3 * c]);
+                            acc[3 * c + 1] = fmaf(w[i][c], ky, acc[3 * c + 1]);
+                            acc[3 * c + 2] = fmaf(w[i][c], kz, acc[3 * c + 2]);
+                        }
                     }
                     if constexpr (DX) {
                         const float les = lam * dot3(E0, E1, E2, dx, dy, dz);

@@ -25,9 +25,6 @@
 namespace dps {
 namespace {
 
-// squared distance given to radial() for points that take no part in a term
-constexpr float kHugeR2 = 1.0e30f;
-
 // radial() for the K points of a lane at once, for the points with take[i]:
 // the plain factors 1/(4 pi r^3), 3/(4 pi r^5) without branches, and radial()
 // itself (same values) only when some point of the wavefront lies in the
