@@ -761,14 +761,20 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
         load_moments<CB, BF16>(mom, ms, pf, c0, Dn, kp.nhi);
         if (any_far) {
             refine_moments<CB, BF16>(mom, ms, t, c0, D, kp.nhi);
+            // query slot 0 writes the node sums on every lane (zero factors
+            // where it is not far, taken at a huge distance), the other slots
+            // add where their query is far
             float acc[3 * CB];
 #pragma unroll
-            for (int v = 0; v < 3 * CB; ++v) acc[v] = 0.0f;
-#pragma unroll
             for (int i = 0; i < K; ++i) {
-                if (far[i]) {
+                if (i == 0 || far[i]) {
+                    const bool off = i == 0 && !far[0];
+                    const float si = off ? kHugeR2 : s2[i];
                     float kap, lam, nu;
-                    radial3(s2[i], kp, kap, lam, nu);
+                    radial3(si, kp, kap, lam, nu);
+                    kap = off ? 0.0f : kap;
+                    lam = off ? 0.0f : lam;
+                    nu = off ? 0.0f : nu;
                     const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
                     float al = 0.0f, vx = 0.0f, vy = 0.0f, vz = 0.0f;
                     float e1 = 0.0f, e2 = 0.0f;  // sum_c (w_c s_c - D_c.h_c), sum_c s_c (d.h_c)
@@ -785,9 +791,15 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                         vx = fmaf(be, Dx, fmaf(ls, hx, vx));
                         vy = fmaf(be, Dy, fmaf(ls, hy, vy));
                         vz = fmaf(be, Dz, fmaf(ls, hz, vz));
-                        acc[3 * c] = fmaf(be, dx, fmaf(-kap, hx, acc[3 * c]));
-                        acc[3 * c + 1] = fmaf(be, dy, fmaf(-kap, hy, acc[3 * c + 1]));
-                        acc[3 * c + 2] = fmaf(be, dz, fmaf(-kap, hz, acc[3 * c + 2]));
+                        if (i == 0) {
+                            acc[3 * c] = fmaf(be, dx, -kap * hx);
+                            acc[3 * c + 1] = fmaf(be, dy, -kap * hy);
+                            acc[3 * c + 2] = fmaf(be, dz, -kap * hz);
+                        } else {
+                            acc[3 * c] = fmaf(be, dx, fmaf(-kap, hx, acc[3 * c]));
+                            acc[3 * c + 1] = fmaf(be, dy, fmaf(-kap, hy, acc[3 * c + 1]));
+                            acc[3 * c + 2] = fmaf(be, dz, fmaf(-kap, hz, acc[3 * c + 2]));
+                        }
                         if constexpr (EXT) {
                             e1 = fmaf(w[i][c], sc, e1 - Dh);
                             e2 = fmaf(sc, dh, e2);
@@ -797,8 +809,8 @@ __device__ __forceinline__ void adjoint_g_body(int64_t q0, DPS_TRAV_PARAMS, int 
                     ay[i] += fmaf(al, dy, -vy);
                     az[i] += fmaf(al, dz, -vz);
                     if constexpr (EXT) {
-                        if (eacc && s2[i] < kp.zone_r2) {
-                            const float e = expf(-(s2[i] * kp.ieps2));
+                        if (eacc && si < kp.zone_r2) {
+                            const float e = expf(-(si * kp.ieps2));
                             deps = fmaf(-e, fmaf(kp.ke4, e1, kp.ke6 * e2), deps);
                         }
                     }
