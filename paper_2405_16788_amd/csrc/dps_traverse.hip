@@ -91,15 +91,16 @@ __device__ __forceinline__ void query1_body(int64_t q, DPS_TRAV_PARAMS, float *_
             float kap, lam;
             radial<true>(s, kp, kap, lam);
             const float dx = nd.cx - px, dy = nd.cy - py, dz = nd.cz - pz;
+            // lambda (p_t - x) once, then the gradient is 6 FMAs per channel
+            const float lx = lam * dx, ly = lam * dy, lz = lam * dz;
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
                 const float sd = dot3(D[3 * c], D[3 * c + 1], D[3 * c + 2], dx, dy, dz);
                 f[c] = fmaf(kap, sd, f[c]);
                 if (GRAD) {
-                    const float ls = lam * sd;
-                    g[c][0] = fmaf(-kap, D[3 * c], fmaf(ls, dx, g[c][0]));
-                    g[c][1] = fmaf(-kap, D[3 * c + 1], fmaf(ls, dy, g[c][1]));
-                    g[c][2] = fmaf(-kap, D[3 * c + 2], fmaf(ls, dz, g[c][2]));
+                    g[c][0] = fmaf(-kap, D[3 * c], fmaf(sd, lx, g[c][0]));
+                    g[c][1] = fmaf(-kap, D[3 * c + 1], fmaf(sd, ly, g[c][1]));
+                    g[c][2] = fmaf(-kap, D[3 * c + 2], fmaf(sd, lz, g[c][2]));
                 }
             }
         }
@@ -245,15 +246,16 @@ __device__ __forceinline__ void queryk_body(int64_t q0, DPS_TRAV_PARAMS, float *
                         float kap, lam;
                         radial<true>(s[i], kp, kap, lam);
                         const float dx = nd.cx - px[i], dy = nd.cy - py[i], dz = nd.cz - pz[i];
+                        // lambda (p_t - x) once, then the gradient is 6 FMAs per channel
+                        const float lx = lam * dx, ly = lam * dy, lz = lam * dz;
 #pragma unroll
                         for (int c = 0; c < CB; ++c) {
                             const float sd = dot3(D[3 * c], D[3 * c + 1], D[3 * c + 2], dx, dy, dz);
                             f[i][c] = fmaf(kap, sd, f[i][c]);
                             if (GRAD) {
-                                const float ls = lam * sd;
-                                g[i][c][0] = fmaf(-kap, D[3 * c], fmaf(ls, dx, g[i][c][0]));
-                                g[i][c][1] = fmaf(-kap, D[3 * c + 1], fmaf(ls, dy, g[i][c][1]));
-                                g[i][c][2] = fmaf(-kap, D[3 * c + 2], fmaf(ls, dz, g[i][c][2]));
+                                g[i][c][0] = fmaf(-kap, D[3 * c], fmaf(sd, lx, g[i][c][0]));
+                                g[i][c][1] = fmaf(-kap, D[3 * c + 1], fmaf(sd, ly, g[i][c][1]));
+                                g[i][c][2] = fmaf(-kap, D[3 * c + 2], fmaf(sd, lz, g[i][c][2]));
                             }
                         }
                     }
