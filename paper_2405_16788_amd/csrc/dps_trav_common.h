@@ -213,17 +213,7 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Subtree split: the walk of one 64-query tile divided over `parts`
-// wavefronts, for batches too small to fill the GPU with one wavefront per
-// tile.  Nodes are stored level by level in Morton order, so the nodes of one
-// level that lie next to each other in space have consecutive indices; node t
-// of level <= cut belongs to part t mod parts.  Every part tests every node
-// above the cut level that its queries reach (the decision to open it is the
-// same in each) but adds the far-field term of a node only if it owns it;
-// a node of the cut level, or a leaf above it, that it does not own is
-// skipped with its whole subtree, and inside an owned one the walk is the
-// plain one.  So every term of every query is added by exactly one part, the
-// one that owns its node's ancestor (or itself) at the cut level.
+// walk state and node tests shared by the traversal bodies
 // ---------------------------------------------------------------------------
 // A loop-invariant kernel argument held in a vector register.  The far
 // test's product b2 * r_t^2 then takes the node radius as its one scalar
@@ -261,6 +251,19 @@ struct WaveMasks {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Subtree split: the walk of one 64-query tile divided over `parts`
+// wavefronts, for batches too small to fill the GPU with one wavefront per
+// tile.  Nodes are stored level by level in Morton order, so the nodes of one
+// level that lie next to each other in space have consecutive indices; node t
+// of level <= cut belongs to part t mod parts.  Every part tests every node
+// above the cut level that its queries reach (the decision to open it is the
+// same in each) but adds the far-field term of a node only if it owns it;
+// a node of the cut level, or a leaf above it, that it does not own is
+// skipped with its whole subtree, and inside an owned one the walk is the
+// plain one.  So every term of every query is added by exactly one part, the
+// one that owns its node's ancestor (or itself) at the cut level.
+// ---------------------------------------------------------------------------
 struct Split {
     uint32_t part;   // this wavefront's part
     uint32_t mask;   // parts - 1 (parts a power of two)
