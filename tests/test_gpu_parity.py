@@ -35,8 +35,37 @@ def _random_cloud(M, seed, C=4):
     return p.astype(np.float32), n.astype(np.float32), A.astype(np.float32), mu.astype(np.float32)
 
 
+DEEP_CENTRE = np.array([0.3, -0.2, 0.1])
+
+
+def _deep_cloud(seed, C=4):
+    """A uniform cloud plus clusters of half-width 2^-2 ... 2^-20 around one
+    centre and 20 copies of one point: the octree reaches its last level
+    (21), and the walks carry visit depths and escape pointers down there."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, size=(1500, 3))]
+    for k in range(2, 21, 2):
+        parts.append(DEEP_CENTRE + rng.uniform(-1, 1, size=(24, 3)) * 2.0 ** -k)
+    parts.append(np.repeat(DEEP_CENTRE[None] + 2.0 ** -22, 20, axis=0))
+    p = np.concatenate(parts)
+    M = p.shape[0]
+    n = rng.standard_normal((M, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    A = rng.uniform(0.5, 1.5, size=M) * (4.0 / M)
+    mu = rng.standard_normal((M, C))
+    return p.astype(np.float32), n.astype(np.float32), A.astype(np.float32), mu.astype(np.float32)
+
+
+def _deep_probes(p, seed):
+    """Queries around the deep cluster at every scale, and at its points."""
+    rng = np.random.default_rng(seed)
+    near = [DEEP_CENTRE + rng.uniform(-1, 1, size=(40, 3)) * 2.0 ** -k for k in range(1, 23)]
+    return np.concatenate(near + [p[-60:]]).astype(np.float32)
+
+
 CLOUDS = {
     "sphere-8k": lambda: workloads.sphere_cloud(8192, 1),
+    "deep-cluster": lambda: _deep_cloud(10),
     "random-1": lambda: _random_cloud(1, 5),
     "random-17": lambda: _random_cloud(17, 6),
     "random-3001": lambda: _random_cloud(3001, 7),
@@ -112,6 +141,36 @@ def test_query_parity_beta(dps, orc, beta):
     assert norm_err(to_host(f), ref["f"], ref["sf"]) <= TOL_FP32
     assert norm_err(to_host(g), ref["g"], ref["sg"]) <= TOL_FP32
     assert np.array_equal(to_host(dps.dps_query_counts(tree, xd, beta)), ref["counts"])
+
+
+@pytest.mark.parametrize("eps", [0.05, 0.0])
+def test_deep_tree_parity(dps, orc, eps):
+    """A tree that reaches the last level (21): decisions bit-exact, query,
+    adjoint and the adjoint from forward gradients within the FP32 bar, for
+    queries at every scale around the deep cluster and exactly at its points
+    (FP32 storage: under BF16 a few dominant deep moments carry the format's
+    own 2^-9, checked against emulated storage in test_gpu_storage.py)."""
+    p, n, A, mu = CLOUDS["deep-cluster"]()
+    tree, T = _check_build(dps, orc, p, n, A, mu, 16)
+    assert dps.dps_tree_info(tree)["depth"] == 21
+    x = np.concatenate([workloads.sphere_queries(2000, 41), _deep_probes(p, 42)])
+    df = workloads.cotangents(x.shape[0], mu.shape[1], 43)
+    xd, dfd = to_dev(x, df)
+    f, g = dps.dps_query(tree, xd, 2.0, eps)
+    ref = T.query(x, 2.0, eps)
+    assert np.array_equal(to_host(dps.dps_query_counts(tree, xd, 2.0)), ref["counts"]), "traversal decisions differ"
+    ef, eg = norm_err(to_host(f), ref["f"], ref["sf"]), norm_err(to_host(g), ref["g"], ref["sg"])
+    assert ef <= TOL_FP32 and eg <= TOL_FP32, (ef, eg)
+    adj = T.adjoint(x, 2.0, eps, df)
+    dattrs, dx = dps.dps_adjoint(tree, xd, 2.0, eps, dfd)
+    e1, e2 = norm_err(to_host(dattrs), adj["dmu"], adj["sdmu"]), norm_err(to_host(dx), adj["dx"], adj["sdx"])
+    assert e1 <= TOL_FP32 and e2 <= TOL_FP32, (e1, e2)
+    dps.dps_adjoint_zero(tree)
+    dx2 = dps.dps_adjoint_accumulate_from_forward(tree, xd, 2.0, eps, dfd, g)
+    da2 = dps.dps_adjoint_finalize(tree)
+    e3, e4 = norm_err(to_host(da2), adj["dmu"], adj["sdmu"]), norm_err(to_host(dx2), adj["dx"], adj["sdx"])
+    assert e3 <= TOL_FP32 and e4 <= TOL_FP32, (e3, e4)
+    dps.dps_check(tree)
 
 
 @pytest.mark.parametrize("name", ["sphere-8k", "random-3001", "random-3001-c5", "random-2000-c1"])
@@ -219,7 +278,7 @@ def test_row_counts_beyond_the_limit_rejected(dps):
 @pytest.mark.parametrize("flags", [0, 3, 12])
 @pytest.mark.parametrize("k", [1, 2, 4])
 @pytest.mark.parametrize("name,Q", [("sphere-8k", 4099), ("random-3001-c5", 1000), ("random-2000-c1", 257),
-                                    ("sphere-8k", 70000)])
+                                    ("sphere-8k", 70000), ("deep-cluster", 1000)])
 def test_launch_shapes_parity(dps, orc, k, flags, name, Q):
     # every launch shape (packet size, XCD order, persistent queue) makes the
     # same per-query decisions; ragged tails
@@ -227,6 +286,9 @@ def test_launch_shapes_parity(dps, orc, k, flags, name, Q):
     tree, T = _check_build(dps, orc, p, n, A, mu, 16)
     dps.dps_set_launch(tree, k, k, flags)
     x = workloads.sphere_queries(Q, 31)
+    if name == "deep-cluster":
+        x = np.concatenate([x, _deep_probes(p, 32)])
+        Q = x.shape[0]
     df = workloads.cotangents(Q, mu.shape[1], 17)
     xd, dfd = to_dev(x, df)
     f, g = dps.dps_query(tree, xd, 2.0, 0.05)
