@@ -35,37 +35,9 @@ def _random_cloud(M, seed, C=4):
     return p.astype(np.float32), n.astype(np.float32), A.astype(np.float32), mu.astype(np.float32)
 
 
-DEEP_CENTRE = np.array([0.3, -0.2, 0.1])
-
-
-def _deep_cloud(seed, C=4):
-    """A uniform cloud plus clusters of half-width 2^-2 ... 2^-20 around one
-    centre and 20 copies of one point: the octree reaches its last level
-    (21), and the walks carry visit depths and escape pointers down there."""
-    rng = np.random.default_rng(seed)
-    parts = [rng.uniform(-1, 1, size=(1500, 3))]
-    for k in range(2, 21, 2):
-        parts.append(DEEP_CENTRE + rng.uniform(-1, 1, size=(24, 3)) * 2.0 ** -k)
-    parts.append(np.repeat(DEEP_CENTRE[None] + 2.0 ** -22, 20, axis=0))
-    p = np.concatenate(parts)
-    M = p.shape[0]
-    n = rng.standard_normal((M, 3))
-    n /= np.linalg.norm(n, axis=1, keepdims=True)
-    A = rng.uniform(0.5, 1.5, size=M) * (4.0 / M)
-    mu = rng.standard_normal((M, C))
-    return p.astype(np.float32), n.astype(np.float32), A.astype(np.float32), mu.astype(np.float32)
-
-
-def _deep_probes(p, seed):
-    """Queries around the deep cluster at every scale, and at its points."""
-    rng = np.random.default_rng(seed)
-    near = [DEEP_CENTRE + rng.uniform(-1, 1, size=(40, 3)) * 2.0 ** -k for k in range(1, 23)]
-    return np.concatenate(near + [p[-60:]]).astype(np.float32)
-
-
 CLOUDS = {
     "sphere-8k": lambda: workloads.sphere_cloud(8192, 1),
-    "deep-cluster": lambda: _deep_cloud(10),
+    "deep-cluster": lambda: workloads.deep_cluster_cloud(10),
     "random-1": lambda: _random_cloud(1, 5),
     "random-17": lambda: _random_cloud(17, 6),
     "random-3001": lambda: _random_cloud(3001, 7),
@@ -153,7 +125,7 @@ def test_deep_tree_parity(dps, orc, eps):
     p, n, A, mu = CLOUDS["deep-cluster"]()
     tree, T = _check_build(dps, orc, p, n, A, mu, 16)
     assert dps.dps_tree_info(tree)["depth"] == 21
-    x = np.concatenate([workloads.sphere_queries(2000, 41), _deep_probes(p, 42)])
+    x = np.concatenate([workloads.sphere_queries(2000, 41), workloads.deep_cluster_probes(p, 42)])
     df = workloads.cotangents(x.shape[0], mu.shape[1], 43)
     xd, dfd = to_dev(x, df)
     f, g = dps.dps_query(tree, xd, 2.0, eps)
@@ -287,7 +259,7 @@ def test_launch_shapes_parity(dps, orc, k, flags, name, Q):
     dps.dps_set_launch(tree, k, k, flags)
     x = workloads.sphere_queries(Q, 31)
     if name == "deep-cluster":
-        x = np.concatenate([x, _deep_probes(p, 32)])
+        x = np.concatenate([x, workloads.deep_cluster_probes(p, 32)])
         Q = x.shape[0]
     df = workloads.cotangents(Q, mu.shape[1], 17)
     xd, dfd = to_dev(x, df)

@@ -57,6 +57,38 @@ def test_split_query_parity(dps, sphere, parts, cut, storage):
     dps.dps_check(tree)
 
 
+@pytest.fixture(scope="module")
+def deep(dps, orc):
+    p, n, A, mu = workloads.deep_cluster_cloud(10)
+    x = np.concatenate([workloads.sphere_queries(1000, 44), workloads.deep_cluster_probes(p, 45)])
+    T = orc.Tree(p, n, A, mu, 16)
+    df = workloads.cotangents(x.shape[0], mu.shape[1], 46)
+    return p, n, A, mu, x, df, T, T.query(x, 2.0, 0.05), T.adjoint(x, 2.0, 0.05, df)
+
+
+@pytest.mark.parametrize("parts", [2, 4, 8])
+@pytest.mark.parametrize("cut", [9, 15, 19, 20, 21])
+def test_split_on_a_tree_of_21_levels(dps, deep, parts, cut):
+    """Cuts through the deep levels of a tree that reaches level 21: the
+    query and the adjoint still add every source term once."""
+    p, n, A, mu, x, df, T, ref, adj = deep
+    tree = dps.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    assert dps.dps_tree_info(tree)["depth"] == 21
+    xd, dfd = to_dev(x, df)
+    dps.dps_set_split(tree, parts, parts, cut)
+    f, g = dps.dps_query(tree, xd, 2.0, 0.05)
+    ef = norm_err(to_host(f), ref["f"], ref["sf"])
+    eg = norm_err(to_host(g), ref["g"], ref["sg"])
+    assert ef <= TOL_FP32 and eg <= TOL_FP32, (ef, eg)
+    dps.dps_adjoint_zero(tree)
+    dx = dps.dps_adjoint_accumulate_from_forward(tree, xd, 2.0, 0.05, dfd, g)
+    da = dps.dps_adjoint_finalize(tree)
+    e1 = norm_err(to_host(da), adj["dmu"], adj["sdmu"])
+    e2 = norm_err(to_host(dx), adj["dx"], adj["sdx"])
+    assert e1 <= TOL_FP32 and e2 <= TOL_FP32, (e1, e2)
+    dps.dps_check(tree)
+
+
 def test_split_query_two_parts_reproducible(dps, sphere):
     p, n, A, mu, x, df, T, ref, _ = sphere
     tree = dps.dps_build(*to_dev(p, n, A, mu), leaf_size=16)

@@ -8,7 +8,7 @@ FP64 reference in ``oracle/`` and the GPU library consume exactly the same
 FP32 bits without sharing any of the method's code.
 """
 from .scenes import (  # noqa: F401
-    sphere_cloud, sphere_queries, sphere_probes, sfm_cloud, camera_rays,
+    sphere_cloud, sphere_queries, sphere_probes, sfm_cloud, camera_rays, deep_cluster_cloud, deep_cluster_probes,
     ray_samples, tile_order, cotangents, appearance_attrs, sfm_camera, sfm_1m, fibonacci_sphere, pixel_ray_samples,
     CONFIGS,
     SFM_1M_SURFACE, SFM_1M_OUTLIERS, SFM_4M_SURFACE, SFM_4M_OUTLIERS, SFM_8M_SURFACE, SFM_8M_OUTLIERS,

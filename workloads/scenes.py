@@ -57,6 +57,39 @@ def _unit(v):
 
 
 # ----------------------------------------------------------------------------
+# a cloud whose octree reaches the last level
+# ----------------------------------------------------------------------------
+DEEP_CENTRE = np.array([0.3, -0.2, 0.1])
+
+
+def deep_cluster_cloud(seed: int, C: int = 4):
+    """1500 points uniform in [-1, 1]^3, clusters of 24 points of half-width
+    2^-2, 2^-4, ..., 2^-20 around DEEP_CENTRE and 20 copies of one point next
+    to it: with 21 Morton levels over the cloud's cube, the octree reaches its
+    last level.  Unit normals, areas U(0.5, 1.5) * 4/M, N(0,1) attributes.
+    Returns float32 p[M,3], n[M,3], A[M], attrs[M,C]."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, size=(1500, 3))]
+    for k in range(2, 21, 2):
+        parts.append(DEEP_CENTRE + rng.uniform(-1, 1, size=(24, 3)) * 2.0 ** -k)
+    parts.append(np.repeat(DEEP_CENTRE[None] + 2.0 ** -22, 20, axis=0))
+    p = np.concatenate(parts)
+    M = p.shape[0]
+    n = _unit(rng.standard_normal((M, 3)))
+    A = rng.uniform(0.5, 1.5, size=M) * (4.0 / M)
+    mu = rng.standard_normal((M, C))
+    return p.astype(np.float32), n.astype(np.float32), A.astype(np.float32), mu.astype(np.float32)
+
+
+def deep_cluster_probes(p, seed: int):
+    """Queries around DEEP_CENTRE at every scale 2^-1 .. 2^-22 (40 each) and
+    at the last 60 points of a deep_cluster_cloud p (the duplicates among them)."""
+    rng = np.random.default_rng(seed)
+    near = [DEEP_CENTRE + rng.uniform(-1, 1, size=(40, 3)) * 2.0 ** -k for k in range(1, 23)]
+    return np.concatenate(near + [p[-60:]]).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
 # unit sphere cloud
 # ----------------------------------------------------------------------------
 def sphere_cloud(M: int, seed: int, n_rgb: int = 3):
