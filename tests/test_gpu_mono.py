@@ -121,6 +121,32 @@ def test_mono_adjoint_parity(P, orc, name, storage):
     P.dps_check(tree)
 
 
+def test_mono_tree_of_21_levels(P, orc):
+    """Monopole query and adjoint on a tree that reaches its last level, with
+    queries at every scale around the deep cluster and at its points (FP32
+    storage), in each packet size."""
+    p, n, A, mu = workloads.deep_cluster_cloud(10, C=5)
+    x = np.concatenate([workloads.sphere_queries(1000, 67, half=1.2), workloads.deep_cluster_probes(p, 68)])
+    df = workloads.cotangents(x.shape[0], mu.shape[1], 69)
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16, kernel="monopole")
+    assert P.dps_tree_info(tree)["depth"] == 21
+    T = orc.Tree(p, n, A, mu, 16, kind="monopole")
+    xd, dfd = to_dev(x, df)
+    for eps in (0.05, 0.0):
+        ref = T.query(x, BETA, eps)
+        adj = T.adjoint(x, BETA, eps, df)
+        for k in (1, 2, 4):
+            P.dps_set_launch(tree, k, k, P.LAUNCH_PERSISTENT_QUERY | P.LAUNCH_PERSISTENT_ADJOINT)
+            f, g = P.dps_query(tree, xd, BETA, eps)
+            assert norm_err(to_host(f), ref["f"], ref["sf"]) <= TOL_FP32, (eps, k)
+            assert norm_err(to_host(g), ref["g"], ref["sg"]) <= TOL_FP32, (eps, k)
+            da, dx = P.dps_adjoint(tree, xd, BETA, eps, dfd)
+            assert norm_err(to_host(da), adj["dmu"], adj["sdmu"] + 1e-30) <= TOL_FP32, (eps, k)
+            assert norm_err(to_host(dx), adj["dx"], adj["sdx"][:, None] + 1e-30) <= TOL_FP32, (eps, k)
+    assert np.array_equal(to_host(P.dps_query_counts(tree, xd, BETA)), T.query(x, BETA, 0.05)["counts"])
+    P.dps_check(tree)
+
+
 @pytest.mark.parametrize("storage", ["fp32", "bf16"])
 def test_mono_channel_subsets_and_row_counts(P, orc, storage):
     p, n, A, mu = CLOUDS["sfm-20k-c32"]()

@@ -142,6 +142,12 @@ def test_deep_tree_parity(dps, orc, eps):
     da2 = dps.dps_adjoint_finalize(tree)
     e3, e4 = norm_err(to_host(da2), adj["dmu"], adj["sdmu"]), norm_err(to_host(dx2), adj["dx"], adj["sdx"])
     assert e3 <= TOL_FP32 and e4 <= TOL_FP32, (e3, e4)
+    # one channel without gradients: the predicated walk of the march
+    for k in (1, 2, 4):
+        for flags in (0, dps.LAUNCH_PERSISTENT_QUERY):
+            dps.dps_set_launch(tree, k, 0, flags)
+            fv, _ = dps.dps_query_channels(tree, xd, 2.0, eps, 0, 1, grad=False)
+            assert norm_err(to_host(fv), ref["f"][:, :1], ref["sf"][:, :1]) <= TOL_FP32, (k, flags)
     dps.dps_check(tree)
 
 
