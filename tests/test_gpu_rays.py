@@ -426,6 +426,50 @@ def test_harnack_march_equals_the_dense_march(P, orc, storage, cloud):
     _check_march(hh[sel], vh[sel], ref, TOL_BF16 if storage == "bf16" else TOL_FP32)
 
 
+def _deep_scene(R=256, seed=5):
+    """The deep-cluster cloud (a tree of 21 levels) with every normal pointing
+    away from the cluster centre and unit geometry attributes, and R rays
+    aimed at the centre with offsets of 2^-2 .. 2^-21, so that their samples
+    walk the deepest levels and most of them cross the level set."""
+    p, n, A, mu = workloads.deep_cluster_cloud(10, C=2)
+    c = workloads.scenes.DEEP_CENTRE
+    v = p - c
+    n = (v / np.linalg.norm(v, axis=1, keepdims=True)).astype(np.float32)
+    mu[:, 0] = 1.0
+    rng = np.random.default_rng(seed)
+    u = rng.standard_normal((R, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    off = rng.standard_normal((R, 3)) * (2.0 ** -rng.integers(2, 22, R))[:, None]
+    o = (c - 1.5 * u).astype(np.float32)
+    d = (c + off) - o
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    tn = np.full(R, 1.0, np.float32)
+    tf = np.full(R, 2.0, np.float32)
+    return (p, n, A, mu), (o, d, tn, tf)
+
+
+def test_march_on_a_tree_of_21_levels(P, orc):
+    """The dense march (packets 1, 2, 4) against the oracle's, and the
+    Harnack-accelerated march against the dense one bit for bit, on rays
+    through a cluster whose tree reaches its last level."""
+    from oracle import rays
+    (p, n, A, mu), (o, d, tn, tf) = _deep_scene()
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    assert P.dps_tree_info(tree)["depth"] == 21
+    T = orc.Tree(p, n, A, mu, 16)
+    ref = rays.march(T, o, d, tn, tf, 256, BETA, 0.05)
+    od, dd, tnd, tfd = to_dev(o, d, tn, tf)
+    for k in (1, 2, 4):
+        P.dps_set_launch(tree, k, 0, -1)
+        hit, hv = P.dps_ray_march(tree, od, dd, tnd, tfd, 256, BETA, 0.05)
+        hits = _check_march(to_host(hit), to_host(hv), ref, TOL_FP32)
+        assert hits > o.shape[0] // 2, (k, hits)
+    hh, vh, _ = P.dps_ray_march_harnack(tree, od, dd, tnd, tfd, 256, BETA, 0.05, lower=-0.25)
+    assert np.array_equal(to_host(hh), to_host(hit))
+    assert np.array_equal(to_host(vh).view(np.int32), to_host(hv).view(np.int32))
+    P.dps_check(tree)
+
+
 def test_harnack_march_edge_cases(P):
     """Two samples, zero-length rays, a ray count that is not a multiple of
     64, a bound that is no bound at all (the march then falls back to single
