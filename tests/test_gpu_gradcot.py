@@ -91,6 +91,31 @@ def test_grad_cotangent_launch_shapes(P, orc, k, flags):
     P.dps_check(tree)
 
 
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_grad_cotangent_on_a_tree_of_21_levels(P, orc, k):
+    """The Hessian adjoint on a tree that reaches its last level, with queries
+    at every scale around the deep cluster and at its points (eps = 0.05:
+    without regularisation the Hessian factor 1/r^7 leaves the FP32 range
+    10^-7 from a point)."""
+    p, n, A, mu = workloads.deep_cluster_cloud(10, C=2)
+    x = np.concatenate([workloads.sphere_queries(1000, 35), workloads.deep_cluster_probes(p, 36)])
+    Q = x.shape[0]
+    dg = np.random.default_rng(37).standard_normal((Q, 2, 3)).astype(np.float32)
+    df = workloads.cotangents(Q, 2, 38)
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    assert P.dps_tree_info(tree)["depth"] == 21
+    P.dps_set_launch(tree, k, k, P.LAUNCH_PERSISTENT_ADJOINT)
+    T = orc.Tree(p, n, A, mu, 16)
+    xd, dgd, dfd = to_dev(x, dg, df)
+    P.dps_adjoint_zero(tree)
+    dx = P.dps_adjoint_accumulate_grad(tree, xd, 2.0, 0.05, dgd, df=dfd)
+    da = P.dps_adjoint_finalize(tree)
+    ref = T.adjoint(x, 2.0, 0.05, df, dg=dg)
+    assert norm_err(to_host(da), ref["dmu"], ref["sdmu"] + 1e-30) <= TOL_FP32
+    assert norm_err(to_host(dx), ref["dx"], ref["sdx"][:, None] + 1e-30) <= TOL_FP32
+    P.dps_check(tree)
+
+
 def test_grad_cotangent_subsets_counts_and_accumulation(P, orc):
     import torch
     p, n, A, mu = _random_cloud(3001, 8, C=5)
