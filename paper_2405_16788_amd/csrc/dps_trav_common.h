@@ -218,7 +218,9 @@ __device__ __forceinline__ int64_t next_tile(uint32_t *__restrict__ ctr, int64_t
 // A loop-invariant kernel argument held in a vector register.  The far
 // test's product b2 * r_t^2 then takes the node radius as its one scalar
 // operand (a vector instruction reads at most one scalar register here)
-// instead of a copy of the radius made at every node.
+// instead of a copy of the radius made at every node.  v must be
+// wave-uniform (a kernel argument): the operand is read from a scalar
+// register, so a per-lane value would be taken from one lane.
 __device__ __forceinline__ float in_vgpr(float v) {
     float r;
     asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(v));
