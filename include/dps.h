@@ -158,7 +158,10 @@ dps_status dps_set_attributes(dps_tree t, const float *attrs, void *stream);
 /*
  * dps_query -- Barnes-Hut primal query (Algorithm 1, PrimalQuery; Sec. 6.1,
  * eq. farfield) at Q points, all channels in one traversal.
- *  x     [Q][3] query points
+ *  x     [Q][3] query points, not checked: a non-finite point gets a NaN row
+ *        and leaves the other rows unchanged (a NaN point fails every far test
+ *        and so walks the whole tree); in the adjoint calls such a point makes
+ *        the node and point accumulators it reaches non-finite
  *  beta  > 0, finite: a node is used as far field iff |x - p_t| > beta r_t,
  *        evaluated in FP32 as fma(dz, dz, fma(dy, dy, dx*dx)) > (beta*beta)*r_t^2
  *        with d = p_t - x, each operation rounded once and nothing else fused

@@ -115,6 +115,45 @@ def test_query_parity_beta(dps, orc, beta):
     assert np.array_equal(to_host(dps.dps_query_counts(tree, xd, beta)), ref["counts"])
 
 
+@pytest.mark.parametrize("flags", [0, 12])
+def test_non_finite_queries_poison_only_their_rows(dps, flags):
+    """Query points are not checked: a NaN point fails every far test and walks
+    the whole tree (its visit count is the node count), an infinite one is far
+    at the root; both rows come out NaN, no device error is raised, and every
+    other row has the same bits as in a batch without them, in every packet."""
+    p, n, A, mu = CLOUDS["sphere-8k"]()
+    tree = dps.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    N = dps.dps_tree_info(tree)["n_nodes"]
+    x = workloads.sphere_queries(1000, 50)
+    xb = x.copy()
+    xb[7] = np.nan
+    xb[300, 2] = np.nan
+    xb[64, 0] = np.inf
+    xb[65, 1] = -np.inf
+    xb[999] = np.inf
+    bad = np.array([7, 64, 65, 300, 999])
+    good = np.setdiff1d(np.arange(x.shape[0]), bad)
+    (xg,) = to_dev(np.ascontiguousarray(x[good]))
+    (xbd,) = to_dev(xb)
+    for k in (1, 2, 4):
+        dps.dps_set_launch(tree, k, k, flags)
+        f0, g0 = dps.dps_query(tree, xg, 2.0, 0.05)
+        f, g = dps.dps_query(tree, xbd, 2.0, 0.05)
+        f, g, f0, g0 = (to_host(a) for a in (f, g, f0, g0))
+        assert np.array_equal(f[good].view(np.int32), f0.view(np.int32)), k
+        assert np.array_equal(g[good].view(np.int32), g0.view(np.int32)), k
+        assert np.isnan(f[bad]).all() and np.isnan(g[bad]).all(), k
+        fv, _ = dps.dps_query_channels(tree, xbd, 2.0, 0.05, 0, 1, grad=False)
+        fv0, _ = dps.dps_query_channels(tree, xg, 2.0, 0.05, 0, 1, grad=False)
+        fv, fv0 = to_host(fv), to_host(fv0)
+        assert np.array_equal(fv[good].view(np.int32), fv0.view(np.int32)), k
+        assert np.isnan(fv[bad]).all(), k
+    counts = to_host(dps.dps_query_counts(tree, xbd, 2.0))
+    assert np.all(counts[[7, 300], 0] == N)
+    assert np.all(counts[[64, 65, 999], 0] == 1)
+    dps.dps_check(tree)
+
+
 @pytest.mark.parametrize("eps", [0.05, 0.0])
 def test_deep_tree_parity(dps, orc, eps):
     """A tree that reaches the last level (21): decisions bit-exact, query,
