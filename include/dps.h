@@ -424,7 +424,9 @@ dps_status dps_query_grid(dps_tree t, const float origin[3], const float spacing
  *   one rounding per operation; D is channel `channel` of the tree's dipole
  *   sum (beta, eps as dps_query).  Output hit_index [R] int32: the smallest j
  *   with (D(x_j) >= level) != (D(x_{j+1}) >= level), or -1; hit_values [R][2]
- *   float: D(x_j), D(x_{j+1}) (0, 0 without a crossing).  A wavefront walks
+ *   float: D(x_j), D(x_{j+1}) (0, 0 without a crossing).  Rays are not
+ *   checked: one with a non-finite origin, direction or interval finds no
+ *   crossing (-1; 0, 0) and leaves the other rays unchanged.  A wavefront walks
  *   128 consecutive samples of one ray (64 with query packet 1): all chunks of
  *   all rays run at once and a chunk past a crossing already found is skipped,
  *   so any ray order and any batch size keep the GPU busy.  Launch flag bit 4

@@ -426,6 +426,38 @@ def test_harnack_march_equals_the_dense_march(P, orc, storage, cloud):
     _check_march(hh[sel], vh[sel], ref, TOL_BF16 if storage == "bf16" else TOL_FP32)
 
 
+def test_march_non_finite_rays(P, scene):
+    """Rays with a NaN or infinite origin, direction or interval are not
+    checked: they find no crossing (index -1, values 0), every other ray gets
+    the same bits as in a batch without them, in the dense march (packets 1
+    and 2) and in the Harnack march, and no device error is raised."""
+    (p, n, A, mu), (o, d, tn, tf), _ = scene
+    R = 256
+    o, d, tn, tf = (np.ascontiguousarray(a[:R]).copy() for a in (o, d, tn, tf))
+    ob, db, tnb, tfb = o.copy(), d.copy(), tn.copy(), tf.copy()
+    ob[3] = np.nan
+    db[70, 1] = np.inf
+    tfb[129] = np.inf
+    tnb[200] = np.nan
+    bad = np.array([3, 70, 129, 200])
+    good = np.setdiff1d(np.arange(R), bad)
+    tree = P.dps_build(*to_dev(p, n, A, mu), leaf_size=16)
+    clean = to_dev(*(np.ascontiguousarray(a[good]) for a in (o, d, tn, tf)))
+    dirty = to_dev(ob, db, tnb, tfb)
+    for k in (1, 2):
+        P.dps_set_launch(tree, k, 0, -1)
+        hit0, hv0 = (to_host(a) for a in P.dps_ray_march(tree, *clean, N_MARCH, BETA, EPS))
+        hit, hv = (to_host(a) for a in P.dps_ray_march(tree, *dirty, N_MARCH, BETA, EPS))
+        assert np.array_equal(hit[good], hit0), k
+        assert np.array_equal(hv[good].view(np.int32), hv0.view(np.int32)), k
+        assert np.all(hit[bad] == -1) and np.all(hv[bad] == 0.0), k
+        assert 0 < np.sum(hit0 >= 0) < good.size
+    hh, vh, _ = P.dps_ray_march_harnack(tree, *dirty, N_MARCH, BETA, EPS, lower=-0.25)
+    assert np.array_equal(to_host(hh), hit)
+    assert np.array_equal(to_host(vh).view(np.int32), hv.view(np.int32))
+    P.dps_check(tree)
+
+
 def _deep_scene(R=256, seed=5):
     """The deep-cluster cloud (a tree of 21 levels) with every normal pointing
     away from the cluster centre and unit geometry attributes, and R rays
