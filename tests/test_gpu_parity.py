@@ -115,6 +115,34 @@ def test_query_parity_beta(dps, orc, beta):
     assert np.array_equal(to_host(dps.dps_query_counts(tree, xd, beta)), ref["counts"])
 
 
+@pytest.mark.parametrize("M", [100, 256])
+def test_root_is_the_only_leaf(dps, orc, M):
+    """Leaf size 256 (the maximum) over at most 256 points: the tree is one
+    node, a leaf, and every query that does not accept it as far field sums all
+    points exactly; query, adjoint and decisions against the oracle in every
+    packet and schedule."""
+    p, n, A, mu = _random_cloud(M, 70 + M)
+    tree, T = _check_build(dps, orc, p, n, A, mu, 256)
+    assert dps.dps_tree_info(tree)["n_nodes"] == 1
+    x = np.concatenate([workloads.sphere_queries(777, 71), workloads.sphere_queries(64, 72, half=6.0), p[:9]])
+    df = workloads.cotangents(x.shape[0], mu.shape[1], 73)
+    xd, dfd = to_dev(x, df)
+    ref = T.query(x, 2.0, 0.05)
+    adj = T.adjoint(x, 2.0, 0.05, df)
+    assert np.array_equal(to_host(dps.dps_query_counts(tree, xd, 2.0)), ref["counts"])
+    assert ref["counts"][:, 3].max() == M  # some queries sum every point
+    for k in (1, 2, 4):
+        for flags in (0, 3, 12):
+            dps.dps_set_launch(tree, k, k, flags)
+            f, g = dps.dps_query(tree, xd, 2.0, 0.05)
+            assert norm_err(to_host(f), ref["f"], ref["sf"]) <= TOL_FP32, (k, flags)
+            assert norm_err(to_host(g), ref["g"], ref["sg"]) <= TOL_FP32, (k, flags)
+            dattrs, dx = dps.dps_adjoint(tree, xd, 2.0, 0.05, dfd)
+            assert norm_err(to_host(dattrs), adj["dmu"], adj["sdmu"]) <= TOL_FP32, (k, flags)
+            assert norm_err(to_host(dx), adj["dx"], adj["sdx"]) <= TOL_FP32, (k, flags)
+    dps.dps_check(tree)
+
+
 @pytest.mark.parametrize("flags", [0, 12])
 def test_non_finite_queries_poison_only_their_rows(dps, flags):
     """Query points are not checked: a NaN point fails every far test and walks
