@@ -102,8 +102,10 @@ def test_query_parity(dps, orc, name, eps, storage):
     assert np.array_equal(counts, ref["counts"]), "traversal decisions differ"
 
 
-@pytest.mark.parametrize("beta", [1.0, 1.5, 4.0])
+@pytest.mark.parametrize("beta", [0.25, 1.0, 1.5, 4.0, 1000.0])
 def test_query_parity_beta(dps, orc, beta):
+    # 0.25: nodes accepted with the query inside their bounding sphere;
+    # 1000: only zero-radius nodes are far, the sums are direct through leaves
     p, n, A, mu = workloads.sphere_cloud(8192, 1)
     tree, T = _check_build(dps, orc, p, n, A, mu, 16)
     x = workloads.sphere_queries(3000, 4)
