@@ -117,6 +117,39 @@ def test_query_parity_beta(dps, orc, beta):
     assert np.array_equal(to_host(dps.dps_query_counts(tree, xd, beta)), ref["counts"])
 
 
+@pytest.mark.parametrize("eps", [0.05, 0.0])
+def test_single_point_leaves(dps, orc, eps):
+    """Leaf size 1: a single-point leaf has radius 0, so it is far field for
+    every query not exactly at its point, also inside the regularised zone
+    (the far-field path's rare regularised branch), and a query at the point
+    opens it and takes the near-field path (no term at r = 0 without eps).
+    Query, adjoint and decisions against the oracle, packets 1 and 4."""
+    p, n, A, mu = CLOUDS["random-3001"]()
+    tree, T = _check_build(dps, orc, p, n, A, mu, 1)
+    rng = np.random.default_rng(74)
+    near = np.concatenate([p[:64] + rng.standard_normal((64, 3)) * 10.0 ** -e for e in range(1, 7)])
+    x = np.concatenate([workloads.sphere_queries(1000, 75), near, p[100:164]]).astype(np.float32)
+    df = workloads.cotangents(x.shape[0], mu.shape[1], 76)
+    xd, dfd = to_dev(x, df)
+    ref = T.query(x, 2.0, eps)
+    adj = T.adjoint(x, 2.0, eps, df)
+    assert np.array_equal(to_host(dps.dps_query_counts(tree, xd, 2.0)), ref["counts"])
+    for k in (1, 4):
+        dps.dps_set_launch(tree, k, k, 12)
+        f, g = dps.dps_query(tree, xd, 2.0, eps)
+        assert norm_err(to_host(f), ref["f"], ref["sf"]) <= TOL_FP32, k
+        assert norm_err(to_host(g), ref["g"], ref["sg"]) <= TOL_FP32, k
+        dattrs, dx = dps.dps_adjoint(tree, xd, 2.0, eps, dfd)
+        assert norm_err(to_host(dattrs), adj["dmu"], adj["sdmu"]) <= TOL_FP32, k
+        assert norm_err(to_host(dx), adj["dx"], adj["sdx"]) <= TOL_FP32, k
+        dps.dps_adjoint_zero(tree)
+        dx2 = dps.dps_adjoint_accumulate_from_forward(tree, xd, 2.0, eps, dfd, g)
+        da2 = dps.dps_adjoint_finalize(tree)
+        assert norm_err(to_host(da2), adj["dmu"], adj["sdmu"]) <= TOL_FP32, k
+        assert norm_err(to_host(dx2), adj["dx"], adj["sdx"]) <= TOL_FP32, k
+    dps.dps_check(tree)
+
+
 @pytest.mark.parametrize("M", [100, 256])
 def test_root_is_the_only_leaf(dps, orc, M):
     """Leaf size 256 (the maximum) over at most 256 points: the tree is one
